@@ -1,0 +1,241 @@
+/*
+ * cpd.h -- C ABI of libcpd, an MI355X (gfx950) implementation of the Tensor Fox CPD hot path:
+ * truncated-MLSVD compression of a dense third-order tensor, damped Gauss-Newton (dGN) on the
+ * compressed core with Jacobi-preconditioned conjugate gradients, and uncompression.
+ *
+ * Source of every operation: F. B. Diniz, "Tensor decompositions and algorithms, with
+ * applications to tensor learning" (thesis, 2019), ch.3 and ch.4.  Each entry point below names
+ * the section it implements.
+ *
+ * Conventions shared by every call
+ *  - Array arguments marked (device) are device pointers owned by the caller; the library never
+ *    allocates or frees memory.  Scratch memory comes from a caller workspace `ws` of `ws_bytes`
+ *    bytes (device), sized by the matching *_workspace_bytes query.  Arguments marked (host) are
+ *    host pointers.
+ *  - Tensors are dense, C-ordered T[i1][i2][i3] (i3 fastest).  Matrices are row-major.  Factor
+ *    matrices W^(l) are I_l x R (rank-one terms are columns).  Only third-order tensors (L = 3)
+ *    are supported, as in the thesis's regularisation.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All work is
+ *    stream-ordered; a call returns after enqueueing unless it says it synchronises.
+ *  - Return value: CPD_OK or a negative cpd_status.  On error no output is written, except that
+ *    CPD_E_HIP can leave outputs partially written.  Non-convergence is not an error; it is
+ *    reported as a stop reason.
+ *  - All dGN arithmetic is FP64.  Input tensors may be FP64, FP32 (promoted exactly to FP64) or
+ *    BF16 (Gram and projection with FP32 accumulation, see cpd_params.compute_dtype).
+ */
+#ifndef CPD_H
+#define CPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CPD_OK = 0,
+  CPD_E_INVALID = -1,      /* bad size, rank, dtype, null pointer or parameter */
+  CPD_E_WORKSPACE = -2,    /* workspace missing or smaller than the query returned */
+  CPD_E_HIP = -3,          /* a HIP runtime call failed (message in cpd_last_error) */
+  CPD_E_NONFINITE = -4,    /* NaN or Inf met in the input tensor or initial factors */
+  CPD_E_ZERO_TENSOR = -5,  /* ||T|| = 0: relative errors are undefined */
+  CPD_E_UNSUPPORTED = -6   /* a size beyond the documented limits of a kernel */
+} cpd_status;
+
+typedef enum { CPD_F64 = 0, CPD_F32 = 1, CPD_BF16 = 2 } cpd_dtype;
+
+/* Stopping conditions 1-7 of ch.4 "Stopping conditions", in the thesis's order, then maxiter. */
+typedef enum {
+  CPD_STOP_NONE = 0,
+  CPD_STOP_REL_ERR = 1,      /* ||S - S_k|| / ||S|| < tol */
+  CPD_STOP_STEP = 2,         /* ||x_k|| < tol (dGN step before norm balancing) */
+  CPD_STOP_IMPROVEMENT = 3,  /* |err_{k-1} - err_k| < tol */
+  CPD_STOP_GRAD = 4,         /* ||grad F||_inf < tol */
+  CPD_STOP_AVG_ERR = 5,      /* windowed average error stopped decreasing */
+  CPD_STOP_AVG_IMPR = 6,     /* windowed average improvement < 1e-3 * average error */
+  CPD_STOP_DIVERGED = 7,     /* err_k > max(1, ||T||^2) / (1e-16 + tol) */
+  CPD_STOP_MAXITER = 8
+} cpd_stop;
+
+typedef enum {
+  CPD_INIT_RANDOM = 0,  /* N(0,1) entries (ch.4 "Initialization"); from W0 if given, else the
+                           library's counter-based generator seeded by params.seed */
+  CPD_INIT_MLSVD = 1,   /* R largest-|s| core entries on canonical vectors (ch.4 "Initialization") */
+  CPD_INIT_GIVEN = 2    /* W0 used as is */
+} cpd_init;
+
+typedef struct {
+  int32_t maxiter;          /* dGN iteration limit (thesis default 200) */
+  double tol;               /* tolerance of every stopping condition (thesis default 1e-6) */
+  double mlsvd_tol;         /* compression tolerance: smallest R~_l with tail energy ratio
+                               < mlsvd_tol / 3 (ch.4 Alg. Compression); default 1e-6 */
+  double init_damp;         /* tau; mu_0 = tau * mean|S| (ch.4 "Main parameters"); default 1 */
+  double cg_tol;            /* CG stops when ||r||^2 < cg_tol; <= 0 means tol */
+  int32_t cg_fixed;         /* > 0: fixed CG iteration cap; 0: random cap per iteration k drawn
+                               uniformly from [1 + ceil(k^0.4), 2 + ceil(k^0.9)] (ch.4 CG) */
+  const double* cg_uniforms;/* (host) maxiter uniform draws in [0,1) that select the random cap,
+                               or NULL for the library's SplitMix64(seed, k) stream */
+  uint64_t seed;            /* seed of the library's own random streams */
+  int32_t init;             /* cpd_init */
+  int32_t core_dims[3];     /* all > 0: fixed core size instead of the truncation rule */
+  int32_t compute_dtype;    /* precision of the compression Grams for FP32/FP64 input:
+                               CPD_F64 (default, FP64 accumulation) or CPD_BF16 (BF16 MFMA with
+                               FP32 accumulation; the core is still projected from the input) */
+} cpd_params;
+
+/* Fills the thesis's defaults (maxiter 200, tol 1e-6, mlsvd_tol 1e-6, tau 1, random CG cap). */
+void cpd_default_params(cpd_params* p);
+
+/* Per-iteration record of the dGN (ch.4 "Updates" and "Stopping conditions"). */
+typedef struct {
+  int32_t k;             /* iteration number, 1-based */
+  int32_t cg_iters;      /* CG iterations performed */
+  int32_t cg_cap;        /* CG iteration cap used */
+  int32_t stop;          /* cpd_stop after this iteration (0 = continue) */
+  double rel_err;        /* ||S - S_k|| / ||S|| after the update */
+  double step_norm;      /* ||x_k|| */
+  double grad_inf;       /* ||grad F||_inf at the start point of the iteration */
+  double gain;           /* gain ratio g */
+  double mu;             /* damping parameter after the update rule */
+  double cg_resid;       /* final ||r||^2 of CG */
+} cpd_step_info;
+
+typedef struct {
+  int32_t iters;           /* dGN iterations performed */
+  int32_t stop_reason;     /* cpd_stop */
+  int32_t core_dims[3];    /* R~_l chosen by compression */
+  int32_t tol_iter;        /* first iteration with rel_err < tol, or -1 */
+  double rel_err_core;     /* final ||S - S_k|| / ||S|| */
+  double rel_err_full;     /* ||T - sum_r lambda_r w_r^(1) o w_r^(2) o w_r^(3)|| / ||T|| */
+  double t_norm;           /* ||T|| */
+} cpd_solve_info;
+
+/* Last error message of the calling thread (static storage, never NULL). */
+const char* cpd_last_error(void);
+
+/* Library version string. */
+const char* cpd_version(void);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Compression: ch.2 Alg. MLSVD (left singular vectors via the Gram T_(l) T_(l)^T, App. B),    */
+/* ch.4 Alg. Compression (P_l = min(I_l, R), truncation rule) and the core                    */
+/* S = (U^(1)T, U^(2)T, U^(3)T) . T.                                                           */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Workspace bytes needed by cpd_compress and cpd_solve for this problem. */
+size_t cpd_workspace_bytes(const int64_t dims[3], int32_t R, const cpd_params* p);
+
+/*
+ * cpd_compress: truncated MLSVD of T.
+ *   T          (device) dims[0]*dims[1]*dims[2] elements of `dtype`, C order.
+ *   U_out[l]   (device) capacity dims[l]*P_l doubles, P_l = min(dims[l], R) (or core_dims[l]);
+ *              receives U^(l) as a dims[l] x R~_l row-major matrix with orthonormal columns,
+ *              each column signed so its largest-magnitude entry is positive.
+ *   sigma_out[l] (device, nullable) capacity P_l doubles: leading mode-l singular values.
+ *   S_out      (device) capacity P_1*P_2*P_3 doubles: the core, R~_1 x R~_2 x R~_3, C order.
+ *   core_dims_out (host) receives R~_l.
+ * Synchronises `stream` (the truncation ranks are read back).  Limits: I_l <= 4096,
+ * P_l <= 64 when I_l > 64.
+ */
+cpd_status cpd_compress(const void* T, int32_t dtype, const int64_t dims[3], int32_t R,
+                        const cpd_params* p, double* U_out[3], double* sigma_out[3], double* S_out,
+                        int32_t core_dims_out[3], void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------------------ */
+/* dGN on the core: ch.4 "dGN" (residual, gradient, CG with cap, updates, damping rule,       */
+/* stopping conditions) with J^T J v from ch.3 Thm Hv and D, M from ch.4 "Diagonal            */
+/* regularization".                                                                            */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Bytes of the device state buffer for a core of the given size. */
+size_t cpd_state_bytes(const int32_t core_dims[3], int32_t R, const cpd_params* p);
+
+/*
+ * cpd_state_init: prepares a dGN state in `state` (device, cpd_state_bytes bytes): initial point
+ * (p->init; W0 (device, nullable) holds three core_dims[l] x R row-major matrices packed one
+ * after the other), norm balancing, mu_0 = tau * mean|S|, residual and MTTKRP at the start point.
+ *   S (device) core, core_dims C order.  t_norm2: ||T||^2 for the divergence test (<= 0: ||S||^2).
+ * Does not synchronise.
+ */
+cpd_status cpd_state_init(void* state, const double* S, const int32_t core_dims[3], int32_t R,
+                          const double* W0, double t_norm2, const cpd_params* p, void* stream);
+
+/*
+ * cpd_dgn_step: one dGN iteration on the state; fills `info` (host).  Synchronises `stream`.
+ * Calling it after a stop condition fired returns CPD_OK with info->stop set and changes nothing.
+ */
+cpd_status cpd_dgn_step(void* state, const double* S, const cpd_params* p, cpd_step_info* info,
+                        void* stream);
+
+/*
+ * cpd_dgn_run: iterates until a stopping condition fires, all on the device (one persistent
+ * workgroup).  `log` (host, nullable) receives up to `log_cap` per-iteration records.
+ * Synchronises `stream`; returns the number of iterations in *iters and the reason in *stop.
+ */
+cpd_status cpd_dgn_run(void* state, const double* S, const cpd_params* p, int32_t* iters,
+                       int32_t* stop, cpd_step_info* log, int32_t log_cap, void* stream);
+
+/* Copies the current core factors (three core_dims[l] x R matrices, packed, device) out of the
+ * state, or (set = 1) into it. */
+cpd_status cpd_state_factors(void* state, double* W, int32_t set, void* stream);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Full pipeline: ch.4 flow chart Compress -> Initialize -> dGN -> Uncompress, output with    */
+/* unit columns and lambda.                                                                    */
+/* ------------------------------------------------------------------------------------------ */
+
+/*
+ * cpd_solve:
+ *   W0        (device, nullable) three R~_l x R initial core factors, packed (init RANDOM/GIVEN);
+ *             R~_l must equal the core dims compression chooses (use cpd_compress first).
+ *   W_out[l]  (device) dims[l] x R row-major, unit columns; modes 1, 2 signed so each column's
+ *             largest-|.| entry is positive; terms sorted by decreasing lambda.
+ *   lambda_out(device) R doubles, >= 0.
+ *   info      (host) summary.  Synchronises `stream`.
+ */
+cpd_status cpd_solve(const void* T, int32_t dtype, const int64_t dims[3], int32_t R,
+                     const cpd_params* p, const double* W0, double* W_out[3], double* lambda_out,
+                     cpd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Kernel-level entry points (the pieces of the path, exposed for parity tests and timing).   */
+/* ------------------------------------------------------------------------------------------ */
+
+/* G (device, dims[mode]^2 doubles) = T_(mode) T_(mode)^T, the unfolding Gram of App. B lemma.
+ * ws: cpd_gram_workspace_bytes. */
+size_t cpd_gram_workspace_bytes(const int64_t dims[3], int32_t mode);
+cpd_status cpd_gram(const void* T, int32_t dtype, const int64_t dims[3], int32_t mode,
+                    int32_t compute_dtype, double* G, void* ws, size_t ws_bytes, void* stream);
+
+/* Leading P eigenpairs of a symmetric n x n matrix G (device): U (device, n x P row-major,
+ * columns signed as in cpd_compress) and lam (device, P, descending).  n <= 64 uses cyclic
+ * Jacobi on all of G; larger n uses subspace iteration with Rayleigh-Ritz (P <= 56). */
+size_t cpd_eig_workspace_bytes(int32_t n, int32_t P);
+cpd_status cpd_eig_top(const double* G, int32_t n, int32_t P, double* U, double* lam, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* M (device, dims[mode] x R) = T_(mode) (W^(L) (.) ... (.) W^(1) without W^(mode)), the MTTKRP of
+ * the gradient theorem (ch.4 "Computing the gradient").  W[l] (device) dims[l] x R.
+ * ws: cpd_mttkrp_workspace_bytes. */
+size_t cpd_mttkrp_workspace_bytes(const int64_t dims[3], int32_t R, int32_t mode);
+cpd_status cpd_mttkrp(const void* T, int32_t dtype, const int64_t dims[3], const double* const W[3],
+                      int32_t R, int32_t mode, double* M, void* ws, size_t ws_bytes, void* stream);
+
+/* out (device, 1 double) = ||T - sum_r w_r^(1) o w_r^(2) o w_r^(3)||^2, fused (ch.4 "Computing the
+ * residual" applied to the input tensor).  ws: cpd_residual_workspace_bytes. */
+size_t cpd_residual_workspace_bytes(const int64_t dims[3]);
+cpd_status cpd_residual_norm2(const void* T, int32_t dtype, const int64_t dims[3],
+                              const double* const W[3], int32_t R, double* out, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* out[l] (device, dims[l] x R) = block l of J^T J v (ch.3 Thm Hv) for factors W[l] and direction
+ * V[l] (device, dims[l] x R each).  One workgroup; dims[l] <= 4096, R <= 64. */
+cpd_status cpd_jtj_v(const double* const W[3], const double* const V[3], const int32_t dims[3],
+                     int32_t R, double* const out[3], void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPD_H */

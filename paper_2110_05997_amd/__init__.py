@@ -1,0 +1,227 @@
+"""MI355X (gfx950) implementation of the Tensor Fox CPD hot path (thesis of F. B. Diniz, 2019):
+truncated-MLSVD compression, damped Gauss-Newton with preconditioned CG on the core, and
+uncompression.
+
+The compute runs in ``lib/libcpd.so`` (HIP kernels behind the C ABI of ``include/cpd.h``); this
+package only marshals arguments.  Tensors are ``torch`` CUDA (HIP) tensors; the work is enqueued
+on ``torch.cuda.current_stream()``.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (CPD_BF16, CPD_F32, CPD_F64, CPD_INIT_GIVEN, CPD_INIT_MLSVD, CPD_INIT_RANDOM,
+                   STOP_NAMES, CpdError, Params, SolveInfo, StepInfo)
+
+__all__ = ["params", "gram", "eig_top", "compress", "DgnState", "solve", "mttkrp", "residual_norm2",
+           "jtj_v", "CpdError", "STOP_NAMES"]
+
+_DTYPES = {torch.float64: CPD_F64, torch.float32: CPD_F32, torch.bfloat16: CPD_BF16}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dims(T):
+    return (ctypes.c_int64 * 3)(*T.shape)
+
+
+def _dtype(T):
+    if T.dtype not in _DTYPES:
+        raise TypeError(f"unsupported dtype {T.dtype}")
+    return _DTYPES[T.dtype]
+
+
+def _check_tensor(T):
+    if not (T.is_cuda and T.is_contiguous() and T.dim() == 3):
+        raise ValueError("expected a contiguous 3-way tensor on the GPU")
+
+
+def _ws(nbytes, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def params(maxiter=200, tol=1e-6, mlsvd_tol=1e-6, init_damp=1.0, cg_tol=0.0, cg_fixed=0,
+           cg_uniforms=None, seed=0, init="random", core_dims=None, compute_dtype=CPD_F64):
+    """Build a cpd_params struct (defaults are the thesis's).  ``cg_uniforms`` (host floats) must
+    outlive the call that uses the struct; it is kept on the returned object."""
+    p = Params()
+    _lib.lib().cpd_default_params(ctypes.byref(p))
+    p.maxiter, p.tol, p.mlsvd_tol, p.init_damp = int(maxiter), float(tol), float(mlsvd_tol), float(init_damp)
+    p.cg_tol, p.cg_fixed, p.seed = float(cg_tol), int(cg_fixed), int(seed)
+    p.init = {"random": CPD_INIT_RANDOM, "mlsvd": CPD_INIT_MLSVD, "given": CPD_INIT_GIVEN}[init]
+    if core_dims is not None:
+        p.core_dims = (ctypes.c_int32 * 3)(*core_dims)
+    p.compute_dtype = int(compute_dtype)
+    if cg_uniforms is not None:
+        arr = (ctypes.c_double * len(cg_uniforms))(*[float(u) for u in cg_uniforms])
+        if len(cg_uniforms) < maxiter:
+            raise ValueError("cg_uniforms needs maxiter entries")
+        p.cg_uniforms = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+        p._keep = arr
+    return p
+
+
+def gram(T, mode, compute_dtype=CPD_F64):
+    """G = T_(mode) T_(mode)^T in FP64."""
+    _check_tensor(T)
+    L = _lib.lib()
+    dims = _dims(T)
+    ws = _ws(L.cpd_gram_workspace_bytes(dims, mode), T.device)
+    G = torch.empty((T.shape[mode], T.shape[mode]), dtype=torch.float64, device=T.device)
+    _lib.check(L.cpd_gram(_ptr(T), _dtype(T), dims, mode, compute_dtype, _ptr(G), _ptr(ws), ws.numel(),
+                          _stream()), "cpd_gram")
+    return G
+
+
+def eig_top(G, P):
+    """Leading P eigenpairs (U n x P, lam P) of a symmetric FP64 matrix."""
+    n = G.shape[0]
+    L = _lib.lib()
+    ws = _ws(L.cpd_eig_workspace_bytes(n, P), G.device)
+    U = torch.empty((n, P), dtype=torch.float64, device=G.device)
+    lam = torch.empty(P, dtype=torch.float64, device=G.device)
+    _lib.check(L.cpd_eig_top(_ptr(G.contiguous()), n, P, _ptr(U), _ptr(lam), _ptr(ws), ws.numel(), _stream()),
+               "cpd_eig_top")
+    return U, lam
+
+
+def compress(T, R, p=None):
+    """Truncated MLSVD: returns (U list, sigma list, S, core_dims)."""
+    _check_tensor(T)
+    L = _lib.lib()
+    if p is None:
+        p = params()
+    dims = _dims(T)
+    fixed = all(p.core_dims[l] > 0 for l in range(3))
+    P = [p.core_dims[l] if fixed else min(T.shape[l], R) for l in range(3)]
+    ws = _ws(L.cpd_workspace_bytes(dims, R, ctypes.byref(p)), T.device)
+    Uf = [torch.empty(T.shape[l] * P[l], dtype=torch.float64, device=T.device) for l in range(3)]
+    sg = [torch.empty(P[l], dtype=torch.float64, device=T.device) for l in range(3)]
+    S = torch.empty(P[0] * P[1] * P[2], dtype=torch.float64, device=T.device)
+    core = (ctypes.c_int32 * 3)()
+    _lib.check(L.cpd_compress(_ptr(T), _dtype(T), dims, R, ctypes.byref(p),
+                              (ctypes.c_void_p * 3)(*[u.data_ptr() for u in Uf]),
+                              (ctypes.c_void_p * 3)(*[s.data_ptr() for s in sg]), _ptr(S), core,
+                              _ptr(ws), ws.numel(), _stream()), "cpd_compress")
+    cd = tuple(int(c) for c in core)
+    Us = [Uf[l][: T.shape[l] * cd[l]].view(T.shape[l], cd[l]) for l in range(3)]
+    S = S[: cd[0] * cd[1] * cd[2]].view(*cd)
+    return Us, sg, S, cd
+
+
+class DgnState:
+    """Device-resident dGN state for a core S (see cpd_state_init / cpd_dgn_step / cpd_dgn_run)."""
+
+    def __init__(self, S, R, p=None, W0=None, t_norm2=0.0):
+        L = _lib.lib()
+        self.p = p if p is not None else params()
+        self.S = S.contiguous()
+        self.core = tuple(int(d) for d in S.shape)
+        self.R = int(R)
+        cd = (ctypes.c_int32 * 3)(*self.core)
+        nbytes = L.cpd_state_bytes(cd, self.R, ctypes.byref(self.p))
+        self.buf = torch.zeros(nbytes, dtype=torch.uint8, device=S.device)
+        w0 = None
+        if W0 is not None:
+            w0 = torch.cat([w.reshape(-1) for w in W0]).to(device=S.device, dtype=torch.float64).contiguous()
+        self._w0 = w0
+        _lib.check(L.cpd_state_init(_ptr(self.buf), _ptr(self.S), cd, self.R, _ptr(w0), float(t_norm2),
+                                    ctypes.byref(self.p), _stream()), "cpd_state_init")
+
+    def step(self):
+        info = StepInfo()
+        _lib.check(_lib.lib().cpd_dgn_step(_ptr(self.buf), _ptr(self.S), ctypes.byref(self.p), ctypes.byref(info),
+                                           _stream()), "cpd_dgn_step")
+        return info.as_dict()
+
+    def run(self):
+        it, st = ctypes.c_int32(), ctypes.c_int32()
+        log = (StepInfo * self.p.maxiter)()
+        _lib.check(_lib.lib().cpd_dgn_run(_ptr(self.buf), _ptr(self.S), ctypes.byref(self.p), ctypes.byref(it),
+                                          ctypes.byref(st), log, self.p.maxiter, _stream()), "cpd_dgn_run")
+        return it.value, st.value, [log[i].as_dict() for i in range(it.value)]
+
+    def factors(self):
+        n = sum(self.core) * self.R
+        W = torch.empty(n, dtype=torch.float64, device=self.S.device)
+        _lib.check(_lib.lib().cpd_state_factors(_ptr(self.buf), _ptr(W), 0, _stream()), "cpd_state_factors")
+        out, o = [], 0
+        for d in self.core:
+            out.append(W[o:o + d * self.R].view(d, self.R))
+            o += d * self.R
+        return out
+
+
+def workspace_bytes(shape, R, p=None):
+    if p is None:
+        p = params()
+    return _lib.lib().cpd_workspace_bytes((ctypes.c_int64 * 3)(*shape), R, ctypes.byref(p))
+
+
+def solve(T, R, p=None, W0=None, ws=None):
+    """Full CPD.  Returns dict(W=[3 x (I_l x R)], lam, info) with the C struct's fields."""
+    _check_tensor(T)
+    L = _lib.lib()
+    if p is None:
+        p = params()
+    dims = _dims(T)
+    if ws is None:
+        ws = _ws(L.cpd_workspace_bytes(dims, R, ctypes.byref(p)), T.device)
+    W = [torch.empty((T.shape[l], R), dtype=torch.float64, device=T.device) for l in range(3)]
+    lam = torch.empty(R, dtype=torch.float64, device=T.device)
+    w0 = None
+    if W0 is not None:
+        w0 = torch.cat([w.reshape(-1) for w in W0]).to(device=T.device, dtype=torch.float64).contiguous()
+    info = SolveInfo()
+    _lib.check(L.cpd_solve(_ptr(T), _dtype(T), dims, R, ctypes.byref(p), _ptr(w0),
+                           (ctypes.c_void_p * 3)(*[w.data_ptr() for w in W]), _ptr(lam), ctypes.byref(info),
+                           _ptr(ws), ws.numel(), _stream()), "cpd_solve")
+    d = {f: getattr(info, f) for f, _ in SolveInfo._fields_}
+    d["core_dims"] = tuple(info.core_dims)
+    return dict(W=W, lam=lam, info=d)
+
+
+def mttkrp(T, Ws, mode):
+    _check_tensor(T)
+    L = _lib.lib()
+    R = Ws[0].shape[1]
+    dims = _dims(T)
+    ws = _ws(L.cpd_mttkrp_workspace_bytes(dims, R, mode), T.device)
+    M = torch.empty((T.shape[mode], R), dtype=torch.float64, device=T.device)
+    Wc = [w.contiguous().to(torch.float64) for w in Ws]
+    _lib.check(L.cpd_mttkrp(_ptr(T), _dtype(T), dims, (ctypes.c_void_p * 3)(*[w.data_ptr() for w in Wc]), R, mode,
+                            _ptr(M), _ptr(ws), ws.numel(), _stream()), "cpd_mttkrp")
+    return M
+
+
+def residual_norm2(T, Ws):
+    _check_tensor(T)
+    L = _lib.lib()
+    R = Ws[0].shape[1]
+    dims = _dims(T)
+    ws = _ws(L.cpd_residual_workspace_bytes(dims), T.device)
+    out = torch.empty(1, dtype=torch.float64, device=T.device)
+    Wc = [w.contiguous().to(torch.float64) for w in Ws]
+    _lib.check(L.cpd_residual_norm2(_ptr(T), _dtype(T), dims, (ctypes.c_void_p * 3)(*[w.data_ptr() for w in Wc]),
+                                    R, _ptr(out), _ptr(ws), ws.numel(), _stream()), "cpd_residual_norm2")
+    return out
+
+
+def jtj_v(Ws, Vs):
+    L = _lib.lib()
+    R = Ws[0].shape[1]
+    Wc = [w.contiguous().to(torch.float64) for w in Ws]
+    Vc = [v.contiguous().to(torch.float64) for v in Vs]
+    out = [torch.empty_like(w) for w in Wc]
+    dims = (ctypes.c_int32 * 3)(*[w.shape[0] for w in Wc])
+    _lib.check(L.cpd_jtj_v((ctypes.c_void_p * 3)(*[w.data_ptr() for w in Wc]),
+                           (ctypes.c_void_p * 3)(*[v.data_ptr() for v in Vc]), dims, R,
+                           (ctypes.c_void_p * 3)(*[o.data_ptr() for o in out]), _stream()), "cpd_jtj_v")
+    return out

@@ -1,0 +1,410 @@
+// C ABI of libcpd: argument checking, workspace carving and the host-side sequencing of the
+// Tensor Fox pipeline (ch.4 flow chart: Compress -> Initialize -> dGN -> Uncompress).
+#include "common.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+namespace cpd {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+namespace {
+
+bool dims_ok(const int64_t dims[3]) {
+  if (!dims) return false;
+  for (int l = 0; l < 3; ++l)
+    if (dims[l] < 1 || dims[l] > 4096) return false;
+  return true;
+}
+
+bool dtype_ok(int dt) { return dt == CPD_F64 || dt == CPD_F32 || dt == CPD_BF16; }
+
+void pdims(const int64_t dims[3], int R, const cpd_params* p, int P[3]) {
+  const bool fixed = p && p->core_dims[0] > 0 && p->core_dims[1] > 0 && p->core_dims[2] > 0;
+  for (int l = 0; l < 3; ++l) {
+    if (fixed) P[l] = p->core_dims[l];
+    else P[l] = (int)(dims[l] < R ? dims[l] : R);
+  }
+}
+
+// Truncation rule of Alg. Compression: smallest i with sum_{r >= i} lam_r / sum_r lam_r < tol / 3.
+int truncation_rank(const double* lam, int P, double mlsvd_tol) {
+  double total = 0.0;
+  for (int r = 0; r < P; ++r) total += (lam[r] > 0.0 ? lam[r] : 0.0);
+  if (total == 0.0) return P;
+  for (int i = 1; i <= P; ++i) {
+    double tail = 0.0;
+    for (int r = i; r < P; ++r) tail += (lam[r] > 0.0 ? lam[r] : 0.0);
+    if (tail / total < mlsvd_tol / 3.0) return i;
+  }
+  return P;
+}
+
+struct CompressWs {
+  size_t G, gram, eig, Uf, lam, Y1, Y2;
+};
+
+void compress_sizes(const int64_t dims[3], const int P[3], Sizer& z) {
+  size_t gmax = 0, gram = 0, eig = 0;
+  for (int l = 0; l < 3; ++l) {
+    gmax = gmax > (size_t)(dims[l] * dims[l]) ? gmax : (size_t)(dims[l] * dims[l]);
+    size_t g = gram_ws_bytes(dims, l);
+    gram = gram > g ? gram : g;
+    size_t e = eig_ws_bytes((int)dims[l], P[l]);
+    eig = eig > e ? eig : e;
+  }
+  z.take<double>(gmax);                                  // G
+  z.take<char>(gram);                                    // gram partials
+  z.take<char>(eig);                                     // eigensolver
+  for (int l = 0; l < 3; ++l) z.take<double>((size_t)dims[l] * P[l]);   // U full
+  z.take<double>(P[0] + P[1] + P[2]);                    // eigenvalues
+  z.take<double>((size_t)P[0] * dims[1] * dims[2]);      // Y1
+  z.take<double>((size_t)P[0] * P[1] * dims[2]);         // Y2
+}
+
+// Runs compression with carved workspace; outputs U (compact I_l x R~_l), sigma, S.
+cpd_status run_compress(const void* T, int dtype, const int64_t dims[3], int R, const cpd_params* p,
+                        double* const U_out[3], double* const sigma_out[3], double* S_out,
+                        int core_out[3], Arena& ar, hipStream_t s) {
+  int P[3];
+  pdims(dims, R, p, P);
+  size_t gmax = 0, gram_b = 0, eig_b = 0;
+  for (int l = 0; l < 3; ++l) {
+    if (P[l] < 1 || P[l] > dims[l]) {
+      set_error("compress: core dim %d invalid for mode %d of size %lld", P[l], l, (long long)dims[l]);
+      return CPD_E_INVALID;
+    }
+    if (dims[l] > 64 && P[l] > 56) {
+      set_error("compress: P=%d > 56 for mode size %lld > 64 is not supported", P[l], (long long)dims[l]);
+      return CPD_E_UNSUPPORTED;
+    }
+    gmax = gmax > (size_t)(dims[l] * dims[l]) ? gmax : (size_t)(dims[l] * dims[l]);
+    size_t g = gram_ws_bytes(dims, l);
+    gram_b = gram_b > g ? gram_b : g;
+    size_t e = eig_ws_bytes((int)dims[l], P[l]);
+    eig_b = eig_b > e ? eig_b : e;
+  }
+  double* G = ar.take<double>(gmax);
+  char* gws = ar.take<char>(gram_b);
+  char* ews = ar.take<char>(eig_b);
+  double* Uf[3];
+  for (int l = 0; l < 3; ++l) Uf[l] = ar.take<double>((size_t)dims[l] * P[l]);
+  double* lam = ar.take<double>(P[0] + P[1] + P[2]);
+  double* Y1 = ar.take<double>((size_t)P[0] * dims[1] * dims[2]);
+  double* Y2 = ar.take<double>((size_t)P[0] * P[1] * dims[2]);
+  if (!Y2) {
+    set_error("compress: workspace too small (%zu bytes)", ar.cap);
+    return CPD_E_WORKSPACE;
+  }
+  double* laml[3] = {lam, lam + P[0], lam + P[0] + P[1]};
+  cpd_status st;
+  for (int l = 0; l < 3; ++l) {
+    if ((st = gram(T, dtype, dims, l, p ? p->compute_dtype : CPD_F64, G, gws, gram_b, s))) return st;
+    if ((st = eig_top(G, (int)dims[l], P[l], Uf[l], laml[l], ews, eig_b, s))) return st;
+  }
+  const int ptot = P[0] + P[1] + P[2];
+  std::vector<double> hlv(ptot);
+  double* hlam = hlv.data();
+  CPD_HIP_CHECK(hipMemcpyAsync(hlam, lam, sizeof(double) * ptot, hipMemcpyDeviceToHost, s));
+  CPD_HIP_CHECK(hipStreamSynchronize(s));
+  const bool fixed = p && p->core_dims[0] > 0 && p->core_dims[1] > 0 && p->core_dims[2] > 0;
+  int rk[3];
+  int o = 0;
+  for (int l = 0; l < 3; ++l) {
+    rk[l] = fixed ? P[l] : truncation_rank(hlam + o, P[l], p ? p->mlsvd_tol : 1e-6);
+    o += P[l];
+  }
+  // sigma = sqrt(max(lambda, 0))
+  if (sigma_out) {
+    o = 0;
+    for (int l = 0; l < 3; ++l) {
+      if (sigma_out[l]) {
+        std::vector<double> tmpv(P[l]);
+        double* tmp = tmpv.data();
+        for (int r = 0; r < P[l]; ++r) tmp[r] = sqrt(hlam[o + r] > 0.0 ? hlam[o + r] : 0.0);
+        CPD_HIP_CHECK(hipMemcpyAsync(sigma_out[l], tmp, sizeof(double) * P[l], hipMemcpyHostToDevice, s));
+        CPD_HIP_CHECK(hipStreamSynchronize(s));
+      }
+      o += P[l];
+    }
+  }
+  // compact truncated U
+  for (int l = 0; l < 3; ++l)
+    CPD_HIP_CHECK(hipMemcpy2DAsync(U_out[l], sizeof(double) * rk[l], Uf[l], sizeof(double) * P[l],
+                                   sizeof(double) * rk[l], dims[l], hipMemcpyDeviceToDevice, s));
+  // S = T x1 U1^T x2 U2^T x3 U3^T
+  const int I1 = (int)dims[0], I2 = (int)dims[1], I3 = (int)dims[2];
+  const int r1 = rk[0], r2 = rk[1], r3 = rk[2];
+  if ((st = gemm_f64(r1, I2 * I3, I1, 1.0, U_out[0], r1, 0, true, T, dtype, (long long)I2 * I3, 0, false,
+                     0.0, Y1, (long long)I2 * I3, 0, 1, s)))
+    return st;
+  if ((st = gemm_f64(r2, I3, I2, 1.0, U_out[1], r2, 0, true, Y1, CPD_F64, I3, (long long)I2 * I3, false,
+                     0.0, Y2, I3, (long long)r2 * I3, r1, s)))
+    return st;
+  if ((st = gemm_f64(r1 * r2, r3, I3, 1.0, Y2, I3, 0, false, U_out[2], CPD_F64, r3, 0, false, 0.0, S_out,
+                     r3, 0, 1, s)))
+    return st;
+  for (int l = 0; l < 3; ++l) core_out[l] = rk[l];
+  return CPD_OK;
+}
+
+size_t solve_ws(const int64_t dims[3], int R, const cpd_params* p) {
+  int P[3];
+  pdims(dims, R, p, P);
+  Sizer z;
+  z.take<double>(1);                       // ||T||^2
+  z.take<int>(1);                          // non-finite flag
+  z.take<char>(sumsq_ws_bytes());
+  for (int l = 0; l < 3; ++l) z.take<double>((size_t)dims[l] * P[l]);   // U (compact)
+  z.take<double>((size_t)P[0] * P[1] * P[2]);                            // S
+  const int32_t pc[3] = {P[0], P[1], P[2]};
+  z.take<char>(state_bytes(pc, R, p ? p->maxiter : 200));
+  z.take<double>((size_t)(P[0] + P[1] + P[2]) * R);                      // core factors
+  for (int l = 0; l < 3; ++l) z.take<double>((size_t)dims[l] * R);       // uncompressed
+  z.take<char>(normalize_ws_bytes(R));
+  z.take<char>(residual_ws_bytes(dims));
+  z.take<double>(1);
+  Sizer zc;
+  compress_sizes(dims, P, zc);
+  z.take<char>(zc.off);
+  return z.off;
+}
+
+}  // namespace
+}  // namespace cpd
+
+using namespace cpd;
+
+extern "C" {
+
+const char* cpd_last_error(void) { return g_err; }
+
+const char* cpd_version(void) { return "libcpd 0.1 (gfx950)"; }
+
+void cpd_default_params(cpd_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->maxiter = 200;
+  p->tol = 1e-6;
+  p->mlsvd_tol = 1e-6;
+  p->init_damp = 1.0;
+  p->cg_tol = 0.0;
+  p->cg_fixed = 0;
+  p->cg_uniforms = nullptr;
+  p->seed = 0;
+  p->init = CPD_INIT_RANDOM;
+  p->compute_dtype = CPD_F64;
+}
+
+size_t cpd_workspace_bytes(const int64_t dims[3], int32_t R, const cpd_params* p) {
+  if (!dims_ok(dims) || R < 1) return 0;
+  return solve_ws(dims, R, p);
+}
+
+cpd_status cpd_compress(const void* T, int32_t dtype, const int64_t dims[3], int32_t R,
+                        const cpd_params* p, double* U_out[3], double* sigma_out[3], double* S_out,
+                        int32_t core_dims_out[3], void* ws, size_t ws_bytes, void* stream) {
+  CPD_REQUIRE(T && U_out && U_out[0] && U_out[1] && U_out[2] && S_out && core_dims_out, "cpd_compress: null argument");
+  CPD_REQUIRE(dims_ok(dims) && dtype_ok(dtype) && R >= 1 && R <= 64, "cpd_compress: bad dims/dtype/R");
+  cpd_params def;
+  if (!p) { cpd_default_params(&def); p = &def; }
+  Arena ar(ws, ws_bytes);
+  int core[3];
+  cpd_status st = run_compress(T, dtype, dims, R, p, U_out, sigma_out, S_out, core, ar, (hipStream_t)stream);
+  if (st) return st;
+  CPD_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
+  for (int l = 0; l < 3; ++l) core_dims_out[l] = core[l];
+  return CPD_OK;
+}
+
+size_t cpd_state_bytes(const int32_t core_dims[3], int32_t R, const cpd_params* p) {
+  if (!core_dims || R < 1) return 0;
+  return state_bytes(core_dims, R, p ? p->maxiter : 200);
+}
+
+cpd_status cpd_state_init(void* state, const double* S, const int32_t core_dims[3], int32_t R,
+                          const double* W0, double t_norm2, const cpd_params* p, void* stream) {
+  CPD_REQUIRE(state && S && core_dims, "cpd_state_init: null argument");
+  cpd_params def;
+  if (!p) { cpd_default_params(&def); p = &def; }
+  return state_init(state, S, core_dims, R, W0, t_norm2, p, (hipStream_t)stream);
+}
+
+cpd_status cpd_dgn_step(void* state, const double* S, const cpd_params* p, cpd_step_info* info,
+                        void* stream) {
+  (void)p;
+  CPD_REQUIRE(state && S && info, "cpd_dgn_step: null argument");
+  hipStream_t s = (hipStream_t)stream;
+  cpd_status st = dgn_iterate(state, S, 1, s);
+  if (st) return st;
+  int k = 0, stop = 0, ti = 0;
+  if ((st = state_read(state, &k, &stop, &ti, nullptr, s))) return st;
+  memset(info, 0, sizeof(*info));
+  if (k > 0) {
+    if ((st = state_log(state, k - 1, 1, info, s))) return st;
+  }
+  info->stop = stop;
+  return CPD_OK;
+}
+
+cpd_status cpd_dgn_run(void* state, const double* S, const cpd_params* p, int32_t* iters,
+                       int32_t* stop, cpd_step_info* log, int32_t log_cap, void* stream) {
+  CPD_REQUIRE(state && S, "cpd_dgn_run: null argument");
+  hipStream_t s = (hipStream_t)stream;
+  const int maxiter = p ? p->maxiter : 200;
+  cpd_status st = dgn_iterate(state, S, maxiter, s);
+  if (st) return st;
+  int k = 0, sr = 0, ti = 0;
+  if ((st = state_read(state, &k, &sr, &ti, nullptr, s))) return st;
+  if (iters) *iters = k;
+  if (stop) *stop = sr;
+  if (log && log_cap > 0 && k > 0) {
+    const int n = k < log_cap ? k : log_cap;
+    if ((st = state_log(state, 0, n, log, s))) return st;
+  }
+  return CPD_OK;
+}
+
+cpd_status cpd_state_factors(void* state, double* W, int32_t set, void* stream) {
+  CPD_REQUIRE(state && W, "cpd_state_factors: null argument");
+  return state_factors(state, W, set, (hipStream_t)stream);
+}
+
+cpd_status cpd_solve(const void* T, int32_t dtype, const int64_t dims[3], int32_t R,
+                     const cpd_params* p, const double* W0, double* W_out[3], double* lambda_out,
+                     cpd_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
+  CPD_REQUIRE(T && W_out && W_out[0] && W_out[1] && W_out[2] && lambda_out && info, "cpd_solve: null argument");
+  CPD_REQUIRE(dims_ok(dims) && dtype_ok(dtype) && R >= 1 && R <= 64, "cpd_solve: bad dims/dtype/R");
+  cpd_params def;
+  if (!p) { cpd_default_params(&def); p = &def; }
+  CPD_REQUIRE(p->maxiter >= 1 && p->tol >= 0.0, "cpd_solve: bad parameters");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t need = solve_ws(dims, R, p);
+  if (!ws || ws_bytes < need) {
+    set_error("cpd_solve: workspace %zu < %zu", ws_bytes, need);
+    return CPD_E_WORKSPACE;
+  }
+  int P[3];
+  pdims(dims, R, p, P);
+  Arena ar(ws, ws_bytes);
+  double* tn2 = ar.take<double>(1);
+  int* bad = ar.take<int>(1);
+  char* sws = ar.take<char>(sumsq_ws_bytes());
+  double* U[3];
+  for (int l = 0; l < 3; ++l) U[l] = ar.take<double>((size_t)dims[l] * P[l]);
+  double* S = ar.take<double>((size_t)P[0] * P[1] * P[2]);
+  const int32_t pc[3] = {P[0], P[1], P[2]};
+  char* state = ar.take<char>(state_bytes(pc, R, p->maxiter));
+  double* Wc = ar.take<double>((size_t)(P[0] + P[1] + P[2]) * R);
+  double* Wt[3];
+  for (int l = 0; l < 3; ++l) Wt[l] = ar.take<double>((size_t)dims[l] * R);
+  char* nws = ar.take<char>(normalize_ws_bytes(R));
+  char* rws = ar.take<char>(residual_ws_bytes(dims));
+  double* res = ar.take<double>(1);
+  cpd_status st;
+  const int64_t n = dims[0] * dims[1] * dims[2];
+  if ((st = sumsq_full(T, dtype, n, tn2, bad, sws, sumsq_ws_bytes(), s))) return st;
+  double h_tn2 = 0.0;
+  int h_bad = 0;
+  CPD_HIP_CHECK(hipMemcpyAsync(&h_tn2, tn2, sizeof(double), hipMemcpyDeviceToHost, s));
+  CPD_HIP_CHECK(hipMemcpyAsync(&h_bad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  CPD_HIP_CHECK(hipStreamSynchronize(s));
+  if (h_bad) { set_error("cpd_solve: non-finite entries in T"); return CPD_E_NONFINITE; }
+  if (!(h_tn2 > 0.0)) { set_error("cpd_solve: ||T|| = 0"); return CPD_E_ZERO_TENSOR; }
+  int core[3];
+  if ((st = run_compress(T, dtype, dims, R, p, U, nullptr, S, core, ar, s))) return st;
+  if ((st = state_init(state, S, core, R, W0, h_tn2, p, s))) return st;
+  if ((st = dgn_iterate(state, S, p->maxiter, s))) return st;
+  int k = 0, stop = 0, ti = -1;
+  double err = 0.0;
+  if ((st = state_read(state, &k, &stop, &ti, &err, s))) return st;
+  if ((st = state_factors(state, Wc, 0, s))) return st;
+  // uncompress W~ = U W
+  size_t o = 0;
+  for (int l = 0; l < 3; ++l) {
+    if ((st = gemm_f64((int)dims[l], R, core[l], 1.0, U[l], core[l], 0, false, Wc + o, CPD_F64, R, 0, false,
+                       0.0, Wt[l], R, 0, 1, s)))
+      return st;
+    o += (size_t)core[l] * R;
+  }
+  const double* Wtc[3] = {Wt[0], Wt[1], Wt[2]};
+  if ((st = residual_full(T, dtype, dims, Wtc, R, res, rws, residual_ws_bytes(dims), s))) return st;
+  if ((st = normalize_output(Wtc, dims, R, W_out, lambda_out, nws, normalize_ws_bytes(R), s))) return st;
+  double h_res = 0.0;
+  CPD_HIP_CHECK(hipMemcpyAsync(&h_res, res, sizeof(double), hipMemcpyDeviceToHost, s));
+  CPD_HIP_CHECK(hipStreamSynchronize(s));
+  info->iters = k;
+  info->stop_reason = stop;
+  for (int l = 0; l < 3; ++l) info->core_dims[l] = core[l];
+  info->tol_iter = ti;
+  info->rel_err_core = err;
+  info->t_norm = sqrt(h_tn2);
+  info->rel_err_full = sqrt(h_res > 0.0 ? h_res : 0.0) / sqrt(h_tn2);
+  return CPD_OK;
+}
+
+size_t cpd_gram_workspace_bytes(const int64_t dims[3], int32_t mode) {
+  if (!dims_ok(dims) || mode < 0 || mode > 2) return 0;
+  return gram_ws_bytes(dims, mode);
+}
+
+cpd_status cpd_gram(const void* T, int32_t dtype, const int64_t dims[3], int32_t mode,
+                    int32_t compute_dtype, double* G, void* ws, size_t ws_bytes, void* stream) {
+  CPD_REQUIRE(T && G && dims_ok(dims) && dtype_ok(dtype) && mode >= 0 && mode <= 2, "cpd_gram: bad arguments");
+  return gram(T, dtype, dims, mode, compute_dtype, G, ws, ws_bytes, (hipStream_t)stream);
+}
+
+size_t cpd_eig_workspace_bytes(int32_t n, int32_t P) {
+  if (n < 1 || P < 1 || P > n) return 0;
+  return eig_ws_bytes(n, P);
+}
+
+cpd_status cpd_eig_top(const double* G, int32_t n, int32_t P, double* U, double* lam, void* ws,
+                       size_t ws_bytes, void* stream) {
+  CPD_REQUIRE(G && U && lam && n >= 1 && n <= 4096 && P >= 1 && P <= n, "cpd_eig_top: bad arguments");
+  return eig_top(G, n, P, U, lam, ws, ws_bytes, (hipStream_t)stream);
+}
+
+size_t cpd_mttkrp_workspace_bytes(const int64_t dims[3], int32_t R, int32_t mode) {
+  if (!dims_ok(dims) || R < 1 || mode < 0 || mode > 2) return 0;
+  return mttkrp_ws_bytes(dims, R, mode);
+}
+
+cpd_status cpd_mttkrp(const void* T, int32_t dtype, const int64_t dims[3], const double* const W[3],
+                      int32_t R, int32_t mode, double* M, void* ws, size_t ws_bytes, void* stream) {
+  CPD_REQUIRE(T && W && W[0] && W[1] && W[2] && M && dims_ok(dims) && dtype_ok(dtype) && R >= 1 && R <= 64,
+              "cpd_mttkrp: bad arguments");
+  return mttkrp_full(T, dtype, dims, W, R, mode, M, ws, ws_bytes, (hipStream_t)stream);
+}
+
+size_t cpd_residual_workspace_bytes(const int64_t dims[3]) {
+  if (!dims_ok(dims)) return 0;
+  return residual_ws_bytes(dims);
+}
+
+cpd_status cpd_residual_norm2(const void* T, int32_t dtype, const int64_t dims[3],
+                              const double* const W[3], int32_t R, double* out, void* ws,
+                              size_t ws_bytes, void* stream) {
+  CPD_REQUIRE(T && W && out && dims_ok(dims) && dtype_ok(dtype), "cpd_residual_norm2: bad arguments");
+  return residual_full(T, dtype, dims, W, R, out, ws, ws_bytes, (hipStream_t)stream);
+}
+
+cpd_status cpd_jtj_v(const double* const W[3], const double* const V[3], const int32_t dims[3],
+                     int32_t R, double* const out[3], void* stream) {
+  CPD_REQUIRE(W && V && dims && out, "cpd_jtj_v: null argument");
+  return jtj_v(W, V, dims, R, out, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,725 @@
+// Damped Gauss-Newton on the compressed core, one persistent workgroup per CPD.
+//
+// Restates ch.4 "dGN" of the thesis for L = 3: at iteration k
+//   pi^(l) = W^(l)T W^(l); Pi^(1) = pi2*pi3, Pi^(2) = pi1*pi3, Pi^(3) = pi1*pi2 (Hadamard), and the
+//     pair products Pi^(a,b) = pi^(c) for the third mode c (ch.3 "Dealing with the Hessian");
+//   gradient dF/dW^(l) = W^(l) Pi^(l) - S_(l) (KR of the others)         (gradient theorem)
+//   D from the gammas, M = diag(J^T J) + mu D                          (ch.4 regularization)
+//   CG on M^{-1/2}(J^T J + mu D)M^{-1/2} x_hat = M^{-1/2}(-grad F) with the random cap, the
+//     product J^T J v from ch.3 Thm Hv, x = M^{-1/2} x_hat
+//   predicted ||f + J x||^2 = ||f||^2 + 2 grad.x + x.J^T J x; w <- w + x (always accepted);
+//   norm balancing; fused residual ||S - [[W]]||^2 with the MTTKRP of the next gradient;
+//   gain ratio, damping rule (g < 0.25: 3 mu; g > 0.75: mu / 3), stopping conditions 1-7.
+//
+// Layout: the parameter vector is three row-major blocks W^(l) (d_l x R) back to back.  Every
+// vector of the iteration (W, MTTKRP, gradient, CG x, r, p, z) and the R x R Grams live in LDS;
+// the core S is read from global memory (L2-resident).  All arithmetic is FP64; reductions use
+// a fixed order, so a run is bit-reproducible.
+#include "common.h"
+
+#include <math.h>
+#include <string.h>
+
+namespace cpd {
+namespace {
+
+constexpr int NT = 512;
+constexpr int NW = NT / 64;
+
+struct Hdr {
+  int32_t d[3];
+  int32_t R;
+  int32_t k, stop, maxiter, tol_iter;
+  int32_t np, flags, pad0, pad1;
+  double mu, f2, s_norm, div_ref, tol, cg_tol, init_damp, err0;
+};
+static_assert(sizeof(Hdr) <= 256, "header must fit its slot");
+
+struct Layout {
+  size_t W, MK, errs, caps, log, total;
+};
+
+__host__ __device__ inline Layout layout_of(int np, int maxiter) {
+  Layout L;
+  size_t off = 256;
+  L.W = off; off += (size_t)np * 8;
+  L.MK = off; off += (size_t)np * 8;
+  L.errs = off; off += (size_t)(maxiter + 1) * 8;
+  L.caps = off; off += ((size_t)maxiter * 4 + 7) / 8 * 8;
+  L.log = off; off += (size_t)maxiter * sizeof(cpd_step_info);
+  L.total = (off + 255) / 256 * 256;
+  return L;
+}
+
+// LDS footprint in doubles
+__host__ __device__ inline size_t lds_doubles(int np, int R) {
+  return (size_t)7 * np + (size_t)9 * R * R + (size_t)6 * R + 2 * NW + 16;
+}
+
+struct Ctx {
+  int d[3], off[3], R, np;
+  double *W, *MK, *G, *X, *Rv, *P, *Z;
+  double *pi, *Pown, *Y;   // 3 R^2 each
+  double *msq, *gam;       // 3 R each
+  double *red;             // 2 x NW
+  const double* S;
+};
+
+__device__ __forceinline__ void split_index(const Ctx& c, int e, int& l, int& i, int& r) {
+  l = (e >= c.off[2]) ? 2 : (e >= c.off[1] ? 1 : 0);
+  const int loc = e - c.off[l];
+  i = loc / c.R;
+  r = loc - i * c.R;
+}
+
+__device__ void setup_ctx(Ctx& c, double* lds, const int d[3], int R, const double* S) {
+  c.d[0] = d[0]; c.d[1] = d[1]; c.d[2] = d[2]; c.R = R;
+  c.off[0] = 0; c.off[1] = d[0] * R; c.off[2] = (d[0] + d[1]) * R;
+  c.np = (d[0] + d[1] + d[2]) * R;
+  double* p = lds;
+  c.W = p; p += c.np;
+  c.MK = p; p += c.np;
+  c.G = p; p += c.np;
+  c.X = p; p += c.np;
+  c.Rv = p; p += c.np;
+  c.P = p; p += c.np;
+  c.Z = p; p += c.np;
+  c.pi = p; p += 3 * R * R;
+  c.Pown = p; p += 3 * R * R;
+  c.Y = p; p += 3 * R * R;
+  c.msq = p; p += 3 * R;
+  c.gam = p; p += 3 * R;
+  c.red = p; p += 2 * NW;
+  c.S = S;
+}
+
+// pi^(l) and Pi^(l); ends with a barrier.
+__device__ void grams(Ctx& c) {
+  const int R = c.R, RR = R * R;
+  for (int e = threadIdx.x; e < 3 * RR; e += NT) {
+    const int l = e / RR, rs = e - l * RR, r = rs / R, s = rs - r * R;
+    const double* Wl = c.W + c.off[l];
+    double acc = 0.0;
+    for (int i = 0; i < c.d[l]; ++i) acc += Wl[i * R + r] * Wl[i * R + s];
+    c.pi[e] = acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < RR; e += NT) {
+    const double a = c.pi[e], b = c.pi[RR + e], d = c.pi[2 * RR + e];
+    c.Pown[e] = b * d;
+    c.Pown[RR + e] = a * d;
+    c.Pown[2 * RR + e] = a * b;
+  }
+  __syncthreads();
+}
+
+// gammas of D and msq = M^{-1/2}, M = Pi^(l)_rr + mu gamma_l[r]; ends with a barrier.
+__device__ void precond(Ctx& c, double mu) {
+  const int R = c.R, RR = R * R;
+  if (threadIdx.x < R) {
+    double m = 0.0;
+    for (int r = 0; r < R; ++r) {
+      const double n0 = sqrt(c.pi[r * R + r]), n1 = sqrt(c.pi[RR + r * R + r]),
+                   n2 = sqrt(c.pi[2 * RR + r * R + r]);
+      m = fmax(m, fmax(n1 * n2, fmax(n0 * n2, n0 * n1)));
+    }
+    const int r = threadIdx.x;
+    const double n0 = sqrt(c.pi[r * R + r]), n1 = sqrt(c.pi[RR + r * R + r]),
+                 n2 = sqrt(c.pi[2 * RR + r * R + r]);
+    const double g0 = n1 * n2 * m, g1 = n0 * n2 * m, g2 = n0 * n1 * m;
+    c.gam[r] = g0; c.gam[R + r] = g1; c.gam[2 * R + r] = g2;
+    c.msq[r] = 1.0 / sqrt(c.Pown[r * R + r] + mu * g0);
+    c.msq[R + r] = 1.0 / sqrt(c.Pown[RR + r * R + r] + mu * g1);
+    c.msq[2 * R + r] = 1.0 / sqrt(c.Pown[2 * RR + r * R + r] + mu * g2);
+  }
+  __syncthreads();
+}
+
+// Structured product of Thm Hv.  With scale = true the input is v = msq * V and the output is
+// msq * (J^T J v + mu D v) (the preconditioned CG operator); with scale = false it is J^T J V.
+// Returns this thread's partial of <V, out>.  Writes out[e]; ends without a barrier after phase 2.
+__device__ double hv(Ctx& c, const double* V, double* out, double mu, bool scale) {
+  const int R = c.R, RR = R * R;
+  // phase 1: Q_b[s][r] = <v_b[:, s], w_b[:, r]>, then Y_a = sum over b != a of pi^(third) * Q_b
+  for (int e = threadIdx.x; e < RR; e += NT) {
+    const int s = e / R, r = e - s * R;
+    double q[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const double* Vb = V + c.off[b];
+      const double* Wb = c.W + c.off[b];
+      double acc = 0.0;
+      for (int i = 0; i < c.d[b]; ++i) acc += Vb[i * R + s] * Wb[i * R + r];
+      q[b] = scale ? c.msq[b * R + s] * acc : acc;
+    }
+    const double p0 = c.pi[e], p1 = c.pi[RR + e], p2 = c.pi[2 * RR + e];
+    c.Y[e] = p2 * q[1] + p1 * q[2];
+    c.Y[RR + e] = p2 * q[0] + p0 * q[2];
+    c.Y[2 * RR + e] = p1 * q[0] + p0 * q[1];
+  }
+  __syncthreads();
+  // phase 2: out_a[i][r] = sum_s v_a[i][s] Pi^(a)[s][r] + sum_s W_a[i][s] Y_a[s][r] (+ mu D v)
+  double dotp = 0.0;
+  for (int e = threadIdx.x; e < c.np; e += NT) {
+    int a, i, r;
+    split_index(c, e, a, i, r);
+    const double* Va = V + c.off[a] + i * R;
+    const double* Wa = c.W + c.off[a] + i * R;
+    const double* Pa = c.Pown + a * RR;
+    const double* Ya = c.Y + a * RR;
+    const double* ma = c.msq + a * R;
+    double t1 = 0.0, t2 = 0.0;
+    if (scale) {
+      for (int s = 0; s < R; ++s) t1 += (ma[s] * Va[s]) * Pa[s * R + r];
+    } else {
+      for (int s = 0; s < R; ++s) t1 += Va[s] * Pa[s * R + r];
+    }
+    for (int s = 0; s < R; ++s) t2 += Wa[s] * Ya[s * R + r];
+    double t = t1 + t2;
+    if (scale) t = ma[r] * (t + mu * c.gam[a * R + r] * (ma[r] * Va[r]));
+    out[e] = t;
+    dotp += V[e] * t;
+  }
+  return dotp;
+}
+
+// Norm balancing (ch.4 "Updates"): every rank-one term gets equal column norms.  Uses msq as
+// scratch for the column norms.  Ends with a barrier.
+__device__ void norm_balance(Ctx& c) {
+  const int R = c.R;
+  double* cn = c.msq;   // 3R scratch
+  for (int e = threadIdx.x; e < 3 * R; e += NT) {
+    const int l = e / R, r = e - l * R;
+    const double* Wl = c.W + c.off[l];
+    double acc = 0.0;
+    for (int i = 0; i < c.d[l]; ++i) acc += Wl[i * R + r] * Wl[i * R + r];
+    cn[e] = sqrt(acc);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < c.np; e += NT) {
+    int l, i, r;
+    split_index(c, e, l, i, r);
+    const double n0 = cn[r], n1 = cn[R + r], n2 = cn[2 * R + r];
+    if (fmin(n0, fmin(n1, n2)) == 0.0) continue;
+    const double alpha = pow(n0 * n1 * n2, 1.0 / 3.0);
+    c.W[e] *= alpha / cn[l * R + r];
+  }
+  __syncthreads();
+}
+
+// ||S - [[W]]||^2 and MK = S_(l) KR(others) at the current W (one pass per output; ch.4
+// "Computing the residual" and the MTTKRP of the gradient).  Returns the block-wide f2.
+__device__ double residual_mttkrp(Ctx& c, double* slots) {
+  const int R = c.R, d0 = c.d[0], d1 = c.d[1], d2 = c.d[2];
+  const double* W0 = c.W;
+  const double* W1 = c.W + c.off[1];
+  const double* W2 = c.W + c.off[2];
+  const double* S = c.S;
+  const int n = d0 * d1 * d2;
+  double f2 = 0.0;
+  for (int e = threadIdx.x; e < n; e += NT) {
+    const int i = e / (d1 * d2), jk = e - i * d1 * d2, j = jk / d2, k = jk - j * d2;
+    double model = 0.0;
+    for (int r = 0; r < R; ++r) model += (W0[i * R + r] * W1[j * R + r]) * W2[k * R + r];
+    const double f = S[e] - model;
+    f2 += f * f;
+  }
+  for (int e = threadIdx.x; e < c.np; e += NT) {
+    int l, i, r;
+    split_index(c, e, l, i, r);
+    double acc = 0.0;
+    if (l == 0) {
+      for (int j = 0; j < d1; ++j) {
+        const double wj = W1[j * R + r];
+        const double* Sij = S + ((size_t)i * d1 + j) * d2;
+        double t = 0.0;
+        for (int k = 0; k < d2; ++k) t += Sij[k] * W2[k * R + r];
+        acc += wj * t;
+      }
+    } else if (l == 1) {
+      for (int ii = 0; ii < d0; ++ii) {
+        const double wi = W0[ii * R + r];
+        const double* Sij = S + ((size_t)ii * d1 + i) * d2;
+        double t = 0.0;
+        for (int k = 0; k < d2; ++k) t += Sij[k] * W2[k * R + r];
+        acc += wi * t;
+      }
+    } else {
+      for (int ii = 0; ii < d0; ++ii) {
+        const double wi = W0[ii * R + r];
+        double t = 0.0;
+        for (int j = 0; j < d1; ++j) t += S[((size_t)ii * d1 + j) * d2 + i] * W1[j * R + r];
+        acc += wi * t;
+      }
+    }
+    c.MK[e] = acc;
+  }
+  return block_sum(f2, slots);
+}
+
+__device__ int stop_test(const double* errs, int k, double step, double grad_inf, double tol,
+                         int maxiter, double div_ref) {
+  const double err = errs[k];
+  if (err < tol) return CPD_STOP_REL_ERR;
+  if (step < tol) return CPD_STOP_STEP;
+  if (fabs(errs[k - 1] - err) < tol) return CPD_STOP_IMPROVEMENT;
+  if (grad_inf < tol) return CPD_STOP_GRAD;
+  const int cw = 1 + (maxiter + 9) / 10;
+  if (k % cw == 0 && k > 2 * cw) {
+    double so = 0.0, sn = 0.0, si = 0.0;
+    for (int j = k - 2 * cw + 1; j <= k - cw; ++j) so += errs[j];
+    for (int j = k - cw + 1; j <= k; ++j) sn += errs[j];
+    const double avg_old = so / cw, avg_new = sn / cw;
+    if (avg_old - avg_new < tol) return CPD_STOP_AVG_ERR;
+    for (int j = k - cw + 1; j <= k; ++j) si += fabs(errs[j - 1] - errs[j]);
+    if (si / cw < 1e-3 * avg_new) return CPD_STOP_AVG_IMPR;
+  }
+  if (err > div_ref / (1e-16 + tol)) return CPD_STOP_DIVERGED;
+  if (k >= maxiter) return CPD_STOP_MAXITER;
+  return CPD_STOP_NONE;
+}
+
+// mode 0: initialise the state from the W stored in it; mode 1: run up to max_steps iterations.
+__global__ __launch_bounds__(NT) void dgn_kernel(char* __restrict__ state, const double* __restrict__ S,
+                                                 int mode, int max_steps) {
+  extern __shared__ double lds[];
+  __shared__ int s_stop;
+  Hdr* h = (Hdr*)state;
+  const int R = h->R;
+  int d[3] = {h->d[0], h->d[1], h->d[2]};
+  const int maxiter = h->maxiter;
+  Ctx c;
+  setup_ctx(c, lds, d, R, S);
+  const Layout Lo = layout_of(c.np, maxiter);
+  double* gW = (double*)(state + Lo.W);
+  double* gMK = (double*)(state + Lo.MK);
+  double* errs = (double*)(state + Lo.errs);
+  const int* caps = (const int*)(state + Lo.caps);
+  cpd_step_info* logp = (cpd_step_info*)(state + Lo.log);
+  const int tid = threadIdx.x;
+  double* slotA = c.red;
+  double* slotB = c.red + NW;
+
+  for (int e = tid; e < c.np; e += NT) c.W[e] = gW[e];
+  __syncthreads();
+
+  if (mode == 0) {
+    // non-finite initial point?
+    int bad = 0;
+    for (int e = tid; e < c.np; e += NT) bad |= !isfinite(c.W[e]);
+    const double nb = block_sum((double)bad, slotA);
+    norm_balance(c);
+    const int n = d[0] * d[1] * d[2];
+    double s2 = 0.0, sa = 0.0;
+    for (int e = tid; e < n; e += NT) { s2 += S[e] * S[e]; sa += fabs(S[e]); }
+    s2 = block_sum(s2, slotB);
+    sa = block_sum(sa, slotA);
+    const double f2 = residual_mttkrp(c, slotB);
+    for (int e = tid; e < c.np; e += NT) { gW[e] = c.W[e]; gMK[e] = c.MK[e]; }
+    if (tid == 0) {
+      const double s_norm = sqrt(s2);
+      h->s_norm = s_norm;
+      h->mu = h->init_damp * (sa / (double)n);
+      h->f2 = f2;
+      h->div_ref = fmax(1.0, (h->div_ref > 0.0) ? h->div_ref : s2);
+      h->err0 = (s_norm > 0.0) ? sqrt(f2) / s_norm : 0.0;
+      errs[0] = h->err0;
+      h->k = 0;
+      h->tol_iter = -1;
+      h->stop = (nb > 0.0) ? -1 : CPD_STOP_NONE;
+      h->flags = (nb > 0.0) ? 1 : 0;
+    }
+    return;
+  }
+
+  for (int e = tid; e < c.np; e += NT) c.MK[e] = gMK[e];
+  double mu = h->mu, f2 = h->f2;
+  const double s_norm = h->s_norm, div_ref = h->div_ref, tol = h->tol, cg_tol = h->cg_tol;
+  int k = h->k, stop = h->stop, tol_iter = h->tol_iter;
+  __syncthreads();
+
+  for (int step_i = 0; step_i < max_steps && stop == CPD_STOP_NONE; ++step_i) {
+    ++k;
+    grams(c);
+    precond(c, mu);
+    // gradient, CG start r = p = M^{-1/2}(-grad), x = 0
+    double rr = 0.0, gi = 0.0;
+    for (int e = tid; e < c.np; e += NT) {
+      int l, i, r;
+      split_index(c, e, l, i, r);
+      const double* Wi = c.W + c.off[l] + i * R;
+      const double* Pl = c.Pown + l * R * R;
+      double acc = 0.0;
+      for (int s = 0; s < R; ++s) acc += Wi[s] * Pl[s * R + r];
+      const double g = acc - c.MK[e];
+      c.G[e] = g;
+      gi = fmax(gi, fabs(g));
+      const double r0 = c.msq[l * R + r] * (-g);
+      c.Rv[e] = r0;
+      c.P[e] = r0;
+      c.X[e] = 0.0;
+      rr += r0 * r0;
+    }
+    rr = block_sum(rr, slotA);
+    const double grad_inf = block_max(gi, slotB);
+    const int cap = caps[k - 1];
+    int its = 0;
+    while (its < cap) {
+      if (rr == 0.0) break;
+      const double pz = block_sum(hv(c, c.P, c.Z, mu, true), slotA);
+      if (!(pz > 0.0)) break;
+      const double alpha = rr / pz;
+      double eps = 0.0;
+      for (int e = tid; e < c.np; e += NT) {
+        c.X[e] += alpha * c.P[e];
+        const double rv = c.Rv[e] - alpha * c.Z[e];
+        c.Rv[e] = rv;
+        eps += rv * rv;
+      }
+      eps = block_sum(eps, slotB);
+      const double beta = eps / rr;
+      for (int e = tid; e < c.np; e += NT) c.P[e] = c.Rv[e] + beta * c.P[e];
+      __syncthreads();
+      rr = eps;
+      ++its;
+      if (eps < cg_tol) break;
+    }
+    // x = M^{-1/2} x_hat
+    for (int e = tid; e < c.np; e += NT) {
+      int l, i, r;
+      split_index(c, e, l, i, r);
+      c.X[e] *= c.msq[l * R + r];
+    }
+    __syncthreads();
+    // J^T J x for the predicted residual, into Z
+    const double xjx = block_sum(hv(c, c.X, c.Z, 0.0, false), slotA);
+    double gx = 0.0, xx = 0.0;
+    for (int e = tid; e < c.np; e += NT) {
+      gx += c.G[e] * c.X[e];
+      xx += c.X[e] * c.X[e];
+    }
+    gx = block_sum(gx, slotB);
+    xx = block_sum(xx, slotA);
+    const double f2_pred = f2 + 2.0 * gx + xjx;
+    // update, always accepted, then norm balancing
+    for (int e = tid; e < c.np; e += NT) c.W[e] += c.X[e];
+    __syncthreads();
+    norm_balance(c);
+    const double f2_new = residual_mttkrp(c, slotB);
+    const double err = sqrt(f2_new) / s_norm;
+    const double den = f2 - f2_pred;
+    const double g = (den > 0.0) ? (f2 - f2_new) / den : 0.0;
+    const double mu_new = (g < 0.25) ? 3.0 * mu : ((g > 0.75) ? mu / 3.0 : mu);
+    const double stepn = sqrt(xx);
+    if (tid == 0) {
+      errs[k] = err;
+      const int st = stop_test(errs, k, stepn, grad_inf, tol, maxiter, div_ref);
+      s_stop = st;
+      cpd_step_info inf;
+      inf.k = k; inf.cg_iters = its; inf.cg_cap = cap; inf.stop = st;
+      inf.rel_err = err; inf.step_norm = stepn; inf.grad_inf = grad_inf; inf.gain = g;
+      inf.mu = mu_new; inf.cg_resid = rr;
+      logp[k - 1] = inf;
+    }
+    __syncthreads();
+    stop = s_stop;
+    if (tol_iter < 0 && err < tol) tol_iter = k;
+    mu = mu_new;
+    f2 = f2_new;
+  }
+  for (int e = tid; e < c.np; e += NT) { gW[e] = c.W[e]; gMK[e] = c.MK[e]; }
+  if (tid == 0) {
+    h->mu = mu; h->f2 = f2; h->k = k; h->stop = stop; h->tol_iter = tol_iter;
+  }
+}
+
+// MLSVD-energy initial point (ch.4 "Initialization"): the R entries of largest |s| (ties: smallest
+// C-order index) placed on canonical vectors; W^(1) carries the value.  Extra columns (R larger
+// than the core) come from `extra` (packed like W) when given.
+__global__ __launch_bounds__(256) void smart_init_kernel(const double* __restrict__ S, int d0, int d1,
+                                                         int d2, int R, const double* __restrict__ extra,
+                                                         double* __restrict__ W) {
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  __shared__ int chosen[64];
+  const int tid = threadIdx.x;
+  const int n = d0 * d1 * d2, np = (d0 + d1 + d2) * R;
+  for (int e = tid; e < np; e += 256) W[e] = extra ? extra[e] : 0.0;
+  __syncthreads();
+  const int take = min(R, n);
+  for (int t = 0; t < take; ++t) {
+    double best = -1.0;
+    int besti = 0x7fffffff;
+    for (int e = tid; e < n; e += 256) {
+      bool used = false;
+      for (int u = 0; u < t; ++u) used |= (chosen[u] == e);
+      if (used) continue;
+      const double a = fabs(S[e]);
+      if (a > best || (a == best && e < besti)) { best = a; besti = e; }
+    }
+    bv[tid] = best; bi[tid] = besti;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double a = bv[tid + s];
+        const int ia = bi[tid + s];
+        if (a > bv[tid] || (a == bv[tid] && ia < bi[tid])) { bv[tid] = a; bi[tid] = ia; }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) chosen[t] = bi[0];
+    __syncthreads();
+  }
+  if (tid < take) {
+    const int r = tid, e = chosen[r];
+    const int i = e / (d1 * d2), j = (e / d2) % d1, k = e % d2;
+    for (int x = 0; x < d0; ++x) W[x * R + r] = 0.0;
+    for (int x = 0; x < d1; ++x) W[d0 * R + x * R + r] = 0.0;
+    for (int x = 0; x < d2; ++x) W[(d0 + d1) * R + x * R + r] = 0.0;
+    W[i * R + r] = S[e];
+    W[d0 * R + j * R + r] = 1.0;
+    W[(d0 + d1) * R + k * R + r] = 1.0;
+  }
+}
+
+// N(0,1) entries by Box-Muller on SplitMix64 counters.
+__global__ void randn_kernel(double* W, int n, uint64_t seed) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const uint64_t a = splitmix64(seed * 0x9E3779B97F4A7C15ull + 2 * (uint64_t)e);
+  const uint64_t b = splitmix64(seed * 0x9E3779B97F4A7C15ull + 2 * (uint64_t)e + 1);
+  const double u1 = 1.0 - u01_from_bits(a), u2 = u01_from_bits(b);
+  W[e] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+// Standalone J^T J v (ch.3 Thm Hv) for parity tests; one workgroup.
+__global__ __launch_bounds__(NT) void jtjv_kernel(const double* W0, const double* W1, const double* W2,
+                                                  const double* V0, const double* V1, const double* V2,
+                                                  int d0, int d1, int d2, int R, double* O0, double* O1,
+                                                  double* O2) {
+  extern __shared__ double lds[];
+  Ctx c;
+  int d[3] = {d0, d1, d2};
+  setup_ctx(c, lds, d, R, nullptr);
+  const double* Ws[3] = {W0, W1, W2};
+  const double* Vs[3] = {V0, V1, V2};
+  double* Os[3] = {O0, O1, O2};
+  for (int e = threadIdx.x; e < c.np; e += NT) {
+    int l, i, r;
+    split_index(c, e, l, i, r);
+    c.W[e] = Ws[l][i * R + r];
+    c.X[e] = Vs[l][i * R + r];
+  }
+  __syncthreads();
+  grams(c);
+  hv(c, c.X, c.Z, 0.0, false);
+  __syncthreads();
+  for (int e = threadIdx.x; e < c.np; e += NT) {
+    int l, i, r;
+    split_index(c, e, l, i, r);
+    Os[l][i * R + r] = c.Z[e];
+  }
+}
+
+bool lds_fits(int np, int R, size_t* bytes) {
+  const size_t b = lds_doubles(np, R) * sizeof(double);
+  if (bytes) *bytes = b;
+  return b <= 160 * 1024 - 1024;
+}
+
+}  // namespace
+
+int cg_cap_for(int k, double u) {
+  // exact ceilings: smallest m with m^5 >= k^2 and smallest m with m^10 >= k^9
+  auto ceil_pow = [](long long kk, int p, int q) {
+    unsigned __int128 target = 1;
+    for (int i = 0; i < p; ++i) target *= (unsigned __int128)kk;
+    long long m = (long long)floor(pow((double)kk, (double)p / q));
+    m = m > 2 ? m - 2 : 0;
+    for (;; ++m) {
+      unsigned __int128 v = 1;
+      for (int i = 0; i < q; ++i) v *= (unsigned __int128)m;
+      if (v >= target) return m;
+    }
+  };
+  const long long lo = 1 + ceil_pow(k, 2, 5);
+  const long long hi = 2 + ceil_pow(k, 9, 10);
+  const long long n = hi - lo + 1;
+  long long off = (long long)floor(u * (double)n);
+  if (off > n - 1) off = n - 1;
+  if (off < 0) off = 0;
+  return (int)(lo + off);
+}
+
+size_t state_bytes(const int32_t core[3], int R, int maxiter) {
+  const int np = (core[0] + core[1] + core[2]) * R;
+  return layout_of(np, maxiter).total;
+}
+
+cpd_status state_init(void* state, const double* S, const int32_t core[3], int R,
+                      const double* W0, double t_norm2, const cpd_params* p, hipStream_t s) {
+  if (state == nullptr || S == nullptr || p == nullptr || R < 1 || R > 64 || p->maxiter < 1) {
+    set_error("state_init: bad arguments (R=%d)", R);
+    return CPD_E_INVALID;
+  }
+  for (int l = 0; l < 3; ++l)
+    if (core[l] < 1 || core[l] > 4096) {
+      set_error("state_init: bad core dim %d", core[l]);
+      return CPD_E_INVALID;
+    }
+  const int np = (core[0] + core[1] + core[2]) * R;
+  size_t lb;
+  if (!lds_fits(np, R, &lb)) {
+    set_error("state_init: core %dx%dx%d with R=%d needs %zu bytes of LDS", core[0], core[1],
+              core[2], R, lb);
+    return CPD_E_UNSUPPORTED;
+  }
+  const Layout Lo = layout_of(np, p->maxiter);
+  char* st = (char*)state;
+  // header + caps on the host, then one copy
+  Hdr h;
+  memset(&h, 0, sizeof(h));
+  h.d[0] = core[0]; h.d[1] = core[1]; h.d[2] = core[2]; h.R = R;
+  h.maxiter = p->maxiter; h.np = np; h.tol_iter = -1;
+  h.tol = p->tol; h.cg_tol = (p->cg_tol > 0.0) ? p->cg_tol : p->tol;
+  h.init_damp = p->init_damp; h.div_ref = t_norm2;
+  CPD_HIP_CHECK(hipMemcpyAsync(st, &h, sizeof(h), hipMemcpyHostToDevice, s));
+  int* caps = (int*)malloc(sizeof(int) * p->maxiter);
+  if (!caps) { set_error("state_init: host allocation failed"); return CPD_E_INVALID; }
+  for (int k = 1; k <= p->maxiter; ++k) {
+    if (p->cg_fixed > 0) {
+      caps[k - 1] = p->cg_fixed;
+    } else {
+      const double u = p->cg_uniforms ? p->cg_uniforms[k - 1]
+                                      : u01_from_bits(splitmix64(p->seed * 0xD1B54A32D192ED03ull + (uint64_t)k));
+      caps[k - 1] = cg_cap_for(k, u);
+    }
+  }
+  hipError_t ce = hipMemcpyAsync(st + Lo.caps, caps, sizeof(int) * p->maxiter, hipMemcpyHostToDevice, s);
+  if (ce == hipSuccess) ce = hipStreamSynchronize(s);
+  free(caps);
+  if (ce != hipSuccess) {
+    set_error("state_init: copy failed: %s", hipGetErrorString(ce));
+    return CPD_E_HIP;
+  }
+  double* gW = (double*)(st + Lo.W);
+  if (p->init == CPD_INIT_MLSVD) {
+    hipLaunchKernelGGL(smart_init_kernel, dim3(1), dim3(256), 0, s, S, core[0], core[1], core[2],
+                       R, W0, gW);
+    CPD_LAUNCH_CHECK();
+    if (W0 == nullptr && R > core[0] * core[1] * core[2]) {
+      set_error("state_init: MLSVD init with R > prod(core) needs W0 for the extra columns");
+      return CPD_E_INVALID;
+    }
+  } else if (W0 != nullptr) {
+    CPD_HIP_CHECK(hipMemcpyAsync(gW, W0, sizeof(double) * np, hipMemcpyDeviceToDevice, s));
+  } else if (p->init == CPD_INIT_RANDOM) {
+    hipLaunchKernelGGL(randn_kernel, dim3((np + 255) / 256), dim3(256), 0, s, gW, np, p->seed);
+    CPD_LAUNCH_CHECK();
+  } else {
+    set_error("state_init: CPD_INIT_GIVEN needs W0");
+    return CPD_E_INVALID;
+  }
+  CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
+  hipLaunchKernelGGL(dgn_kernel, dim3(1), dim3(NT), lb, s, st, S, 0, 0);
+  CPD_LAUNCH_CHECK();
+  int flags = 0;
+  CPD_HIP_CHECK(hipMemcpyAsync(&flags, st + offsetof(Hdr, flags), sizeof(int), hipMemcpyDeviceToHost, s));
+  CPD_HIP_CHECK(hipStreamSynchronize(s));
+  if (flags & 1) {
+    set_error("state_init: non-finite initial factors");
+    return CPD_E_NONFINITE;
+  }
+  return CPD_OK;
+}
+
+cpd_status dgn_iterate(void* state, const double* S, int max_steps, hipStream_t s) {
+  Hdr h;
+  CPD_HIP_CHECK(hipMemcpyAsync(&h, state, sizeof(h), hipMemcpyDeviceToHost, s));
+  CPD_HIP_CHECK(hipStreamSynchronize(s));
+  if (h.R < 1 || h.np != (h.d[0] + h.d[1] + h.d[2]) * h.R) {
+    set_error("dgn_iterate: state not initialised");
+    return CPD_E_INVALID;
+  }
+  size_t lb;
+  if (!lds_fits(h.np, h.R, &lb)) {
+    set_error("dgn_iterate: state too large for LDS");
+    return CPD_E_UNSUPPORTED;
+  }
+  CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
+  hipLaunchKernelGGL(dgn_kernel, dim3(1), dim3(NT), lb, s, (char*)state, S, 1, max_steps);
+  CPD_LAUNCH_CHECK();
+  return CPD_OK;
+}
+
+cpd_status state_read(void* state, int* k, int* stop, int* tol_iter, double* err, hipStream_t s) {
+  Hdr h;
+  CPD_HIP_CHECK(hipMemcpyAsync(&h, state, sizeof(h), hipMemcpyDeviceToHost, s));
+  CPD_HIP_CHECK(hipStreamSynchronize(s));
+  if (k) *k = h.k;
+  if (stop) *stop = h.stop;
+  if (tol_iter) *tol_iter = h.tol_iter;
+  if (err) {
+    const Layout Lo = layout_of(h.np, h.maxiter);
+    CPD_HIP_CHECK(hipMemcpyAsync(err, (char*)state + Lo.errs + sizeof(double) * h.k, sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+    CPD_HIP_CHECK(hipStreamSynchronize(s));
+  }
+  return CPD_OK;
+}
+
+cpd_status state_log(void* state, int first, int count, cpd_step_info* out, hipStream_t s) {
+  Hdr h;
+  CPD_HIP_CHECK(hipMemcpyAsync(&h, state, sizeof(h), hipMemcpyDeviceToHost, s));
+  CPD_HIP_CHECK(hipStreamSynchronize(s));
+  if (first < 0 || count < 0 || first + count > h.maxiter) {
+    set_error("state_log: range out of bounds");
+    return CPD_E_INVALID;
+  }
+  const Layout Lo = layout_of(h.np, h.maxiter);
+  if (count > 0) {
+    CPD_HIP_CHECK(hipMemcpyAsync(out, (char*)state + Lo.log + sizeof(cpd_step_info) * first,
+                                 sizeof(cpd_step_info) * count, hipMemcpyDeviceToHost, s));
+    CPD_HIP_CHECK(hipStreamSynchronize(s));
+  }
+  return CPD_OK;
+}
+
+cpd_status state_factors(void* state, double* W, int set, hipStream_t s) {
+  Hdr h;
+  CPD_HIP_CHECK(hipMemcpyAsync(&h, state, sizeof(h), hipMemcpyDeviceToHost, s));
+  CPD_HIP_CHECK(hipStreamSynchronize(s));
+  const Layout Lo = layout_of(h.np, h.maxiter);
+  char* gW = (char*)state + Lo.W;
+  if (set)
+    CPD_HIP_CHECK(hipMemcpyAsync(gW, W, sizeof(double) * h.np, hipMemcpyDeviceToDevice, s));
+  else
+    CPD_HIP_CHECK(hipMemcpyAsync(W, gW, sizeof(double) * h.np, hipMemcpyDeviceToDevice, s));
+  return CPD_OK;
+}
+
+cpd_status jtj_v(const double* const W[3], const double* const V[3], const int32_t dims[3], int R,
+                 double* const out[3], hipStream_t s) {
+  if (R < 1 || R > 64) {
+    set_error("jtj_v: R=%d out of range", R);
+    return CPD_E_INVALID;
+  }
+  for (int l = 0; l < 3; ++l)
+    if (dims[l] < 1 || dims[l] > 4096 || !W[l] || !V[l] || !out[l]) {
+      set_error("jtj_v: bad mode %d", l);
+      return CPD_E_INVALID;
+    }
+  const int np = (dims[0] + dims[1] + dims[2]) * R;
+  size_t lb;
+  if (!lds_fits(np, R, &lb)) {
+    set_error("jtj_v: problem too large for LDS");
+    return CPD_E_UNSUPPORTED;
+  }
+  CPD_HIP_CHECK(hipFuncSetAttribute((const void*)jtjv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
+  hipLaunchKernelGGL(jtjv_kernel, dim3(1), dim3(NT), lb, s, W[0], W[1], W[2], V[0], V[1], V[2],
+                     dims[0], dims[1], dims[2], R, out[0], out[1], out[2]);
+  CPD_LAUNCH_CHECK();
+  return CPD_OK;
+}
+
+}  // namespace cpd
