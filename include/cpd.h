@@ -234,6 +234,31 @@ cpd_status cpd_residual_norm2(const void* T, int32_t dtype, const int64_t dims[3
 cpd_status cpd_jtj_v(const double* const W[3], const double* const V[3], const int32_t dims[3],
                      int32_t R, double* const out[3], void* stream);
 
+/* ------------------------------------------------------------------------------------------ */
+/* Kernel timing: when enabled, HIP events are recorded on the launch stream around the main   */
+/* kernels of the path; cpd_profile_read waits for them and accumulates durations.  Intended   */
+/* for single-threaded measurement runs.                                                        */
+/* ------------------------------------------------------------------------------------------ */
+typedef enum {
+  CPD_PK_GRAM = 0,      /* Gram partial-tile kernel (per mode) */
+  CPD_PK_DGN = 1,       /* persistent dGN kernel (one launch per cpd_dgn_run / cpd_solve) */
+  CPD_PK_PROJECT = 2,   /* first mode product of the core projection (reads T) */
+  CPD_PK_RESIDUAL = 3,  /* full-tensor fused residual kernel */
+  CPD_PK_MTTKRP = 4,    /* full-tensor MTTKRP */
+  CPD_PK_EIG = 5,       /* eigensolver (all kernels of one cpd_eig_top call) */
+  CPD_PK_COUNT = 6
+} cpd_profile_kernel;
+
+typedef struct {
+  int64_t launches;
+  double total_ms;
+} cpd_kernel_time;
+
+void cpd_profile_enable(int32_t on);
+void cpd_profile_reset(void);
+/* Waits for the recorded events, then fills out[CPD_PK_COUNT]. */
+cpd_status cpd_profile_read(cpd_kernel_time* out);
+
 #ifdef __cplusplus
 }
 #endif

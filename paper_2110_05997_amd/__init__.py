@@ -214,6 +214,22 @@ def residual_norm2(T, Ws):
     return out
 
 
+def profile_enable(on=True):
+    """Record HIP events around the path's main kernels (see cpd_profile_* in cpd.h)."""
+    _lib.lib().cpd_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    _lib.lib().cpd_profile_reset()
+
+
+def profile_read():
+    """{kernel: (launches, total_ms)} accumulated since the last reset."""
+    out = (_lib.KernelTime * len(_lib.PROFILE_KERNELS))()
+    _lib.check(_lib.lib().cpd_profile_read(out), "cpd_profile_read")
+    return {name: (int(out[i].launches), float(out[i].total_ms)) for i, name in enumerate(_lib.PROFILE_KERNELS)}
+
+
 def jtj_v(Ws, Vs):
     L = _lib.lib()
     R = Ws[0].shape[1]

@@ -66,6 +66,12 @@ class SolveInfo(ctypes.Structure):
     ]
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+PROFILE_KERNELS = ["gram", "dgn", "project", "residual", "mttkrp", "eig"]
+
 _P = ctypes.c_void_p
 _DP = ctypes.POINTER(ctypes.c_double)
 _I64x3 = ctypes.c_int64 * 3
@@ -101,6 +107,9 @@ SIGNATURES = [
     ("cpd_residual_norm2", ctypes.c_int, [_P, ctypes.c_int32, _I64x3, _Px3, ctypes.c_int32, _P, _P,
                                           ctypes.c_size_t, _P]),
     ("cpd_jtj_v", ctypes.c_int, [_Px3, _Px3, _I32x3, ctypes.c_int32, _Px3, _P]),
+    ("cpd_profile_enable", None, [ctypes.c_int32]),
+    ("cpd_profile_reset", None, []),
+    ("cpd_profile_read", ctypes.c_int, [ctypes.POINTER(KernelTime)]),
 ]
 
 _lib = None

@@ -112,7 +112,10 @@ cpd_status run_compress(const void* T, int dtype, const int64_t dims[3], int R, 
   cpd_status st;
   for (int l = 0; l < 3; ++l) {
     if ((st = gram(T, dtype, dims, l, p ? p->compute_dtype : CPD_F64, G, gws, gram_b, s))) return st;
-    if ((st = eig_top(G, (int)dims[l], P[l], Uf[l], laml[l], ews, eig_b, s))) return st;
+    prof_begin(CPD_PK_EIG, s);
+    st = eig_top(G, (int)dims[l], P[l], Uf[l], laml[l], ews, eig_b, s);
+    prof_end(CPD_PK_EIG, s);
+    if (st) return st;
   }
   const int ptot = P[0] + P[1] + P[2];
   std::vector<double> hlv(ptot);
@@ -147,9 +150,11 @@ cpd_status run_compress(const void* T, int dtype, const int64_t dims[3], int R, 
   // S = T x1 U1^T x2 U2^T x3 U3^T
   const int I1 = (int)dims[0], I2 = (int)dims[1], I3 = (int)dims[2];
   const int r1 = rk[0], r2 = rk[1], r3 = rk[2];
-  if ((st = gemm_f64(r1, I2 * I3, I1, 1.0, U_out[0], r1, 0, true, T, dtype, (long long)I2 * I3, 0, false,
-                     0.0, Y1, (long long)I2 * I3, 0, 1, s)))
-    return st;
+  prof_begin(CPD_PK_PROJECT, s);
+  st = gemm_f64(r1, I2 * I3, I1, 1.0, U_out[0], r1, 0, true, T, dtype, (long long)I2 * I3, 0, false, 0.0, Y1,
+                (long long)I2 * I3, 0, 1, s);
+  prof_end(CPD_PK_PROJECT, s);
+  if (st) return st;
   if ((st = gemm_f64(r2, I3, I2, 1.0, U_out[1], r2, 0, true, Y1, CPD_F64, I3, (long long)I2 * I3, false,
                      0.0, Y2, I3, (long long)r2 * I3, r1, s)))
     return st;

@@ -164,6 +164,10 @@ cpd_status normalize_output(const double* const Wt[3], const int64_t dims[3], in
                             hipStream_t s);
 size_t mttkrp_ws_bytes(const int64_t dims[3], int R, int mode);
 
+// Kernel timing (see cpd_profile_* in cpd.h).  No-ops unless enabled.
+void prof_begin(int which, hipStream_t s);
+void prof_end(int which, hipStream_t s);
+
 // Host-side CG cap schedule (exact integer ceilings).
 int cg_cap_for(int k, double u);
 

@@ -647,7 +647,9 @@ cpd_status dgn_iterate(void* state, const double* S, int max_steps, hipStream_t 
     return CPD_E_UNSUPPORTED;
   }
   CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
+  prof_begin(CPD_PK_DGN, s);
   hipLaunchKernelGGL(dgn_kernel, dim3(1), dim3(NT), lb, s, (char*)state, S, 1, max_steps);
+  prof_end(CPD_PK_DGN, s);
   CPD_LAUNCH_CHECK();
   return CPD_OK;
 }

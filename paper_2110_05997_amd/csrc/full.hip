@@ -186,6 +186,7 @@ cpd_status residual_full(const void* T, int dtype, const int64_t dims[3], const 
   }
   double* part = (double*)ws;
   const int I1 = (int)dims[0], I2 = (int)dims[1], I3 = (int)dims[2];
+  prof_begin(CPD_PK_RESIDUAL, s);
   switch (dtype) {
     case CPD_F64:
       hipLaunchKernelGGL(residual_kernel<double>, dim3(RB), dim3(RNT), 0, s, (const double*)T, I1, I2, I3,
@@ -203,6 +204,7 @@ cpd_status residual_full(const void* T, int dtype, const int64_t dims[3], const 
       set_error("residual_full: bad dtype");
       return CPD_E_INVALID;
   }
+  prof_end(CPD_PK_RESIDUAL, s);
   CPD_LAUNCH_CHECK();
   hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(RNT), 0, s, part, RB, out);
   CPD_LAUNCH_CHECK();
@@ -261,6 +263,7 @@ cpd_status mttkrp_full(const void* T, int dtype, const int64_t dims[3], const do
   const int I1 = (int)dims[0], I2 = (int)dims[1], I3 = (int)dims[2];
   double* buf = (double*)ws;
   cpd_status st;
+  prof_begin(CPD_PK_MTTKRP, s);
   if (mode == 0) {
     // KR[(j,k)][r] = W1[j][r] W2[k][r]; M^T (R x I1) = KR^T (R x I2I3) . T_mat^T, stored transposed
     const long long n = (long long)I2 * I3 * R;
@@ -283,6 +286,7 @@ cpd_status mttkrp_full(const void* T, int dtype, const int64_t dims[3], const do
     CPD_LAUNCH_CHECK();
     st = gemm_f64(R, I3, I1 * I2, 1.0, buf, R, 0, true, T, dtype, I3, 0, false, 0.0, M, R, 0, 1, s, true);
   }
+  prof_end(CPD_PK_MTTKRP, s);
   return st;
 }
 

@@ -208,6 +208,7 @@ cpd_status gram(const void* T, int dtype, const int64_t dims[3], int mode, int c
   }
   double* part = (double*)ws;
   const int nblocks = g.nupper * g.nsplit;
+  prof_begin(CPD_PK_GRAM, s);
   switch (dtype) {
     case CPD_F64:
       hipLaunchKernelGGL(gram_partial_kernel<double>, dim3(nblocks), dim3(NT), 0, s,
@@ -225,6 +226,7 @@ cpd_status gram(const void* T, int dtype, const int64_t dims[3], int mode, int c
       set_error("gram: bad dtype %d", dtype);
       return CPD_E_INVALID;
   }
+  prof_end(CPD_PK_GRAM, s);
   CPD_LAUNCH_CHECK();
   const long long nel = (long long)g.nupper * TILE * TILE;
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, s,
