@@ -13,8 +13,10 @@
 //
 // Layout: the parameter vector is three row-major blocks W^(l) (d_l x R) back to back.  Every
 // vector of the iteration (W, MTTKRP, gradient, CG x, r, p, z) and the R x R Grams live in LDS;
-// the core S is read from global memory (L2-resident).  All arithmetic is FP64; reductions use
-// a fixed order, so a run is bit-reproducible.
+// the core S is read from global memory (L2-resident).  The dense contractions (Grams, the two
+// products of Thm Hv, the three MTTKRPs and the residual model W^(1) (W^(3) (.) W^(2))^T) run on
+// the FP64 matrix cores in 16x16 tiles spread over the waves, Khatri-Rao rows formed on the fly.
+// All arithmetic is FP64; reductions use a fixed order, so a run is bit-reproducible.
 #include "common.h"
 
 #include <math.h>
@@ -53,28 +55,68 @@ __host__ __device__ inline Layout layout_of(int np, int maxiter) {
 
 // LDS footprint in doubles
 __host__ __device__ inline size_t lds_doubles(int np, int R) {
-  return (size_t)7 * np + (size_t)9 * R * R + (size_t)6 * R + 2 * NW + 16;
+  return (size_t)7 * np + (size_t)12 * R * R + (size_t)6 * R + 2 * NW + 16;
 }
 
 struct Ctx {
-  int d[3], off[3], R, np;
+  int d0, d1, d2, off1, off2, R, np;
   double *W, *MK, *G, *X, *Rv, *P, *Z;
-  double *pi, *Pown, *Y;   // 3 R^2 each
+  double *pi, *Pown, *Y, *Qb;   // 3 R^2 each
   double *msq, *gam;       // 3 R each
   double *red;             // 2 x NW
   const double* S;
 };
 
+// mode sizes and block offsets by selects (a dynamically indexed local array would live in
+// scratch memory)
+__device__ __forceinline__ int dimof(const Ctx& c, int a) { return a == 0 ? c.d0 : (a == 1 ? c.d1 : c.d2); }
+__device__ __forceinline__ int offof(const Ctx& c, int a) { return a == 0 ? 0 : (a == 1 ? c.off1 : c.off2); }
+
 __device__ __forceinline__ void split_index(const Ctx& c, int e, int& l, int& i, int& r) {
-  l = (e >= c.off[2]) ? 2 : (e >= c.off[1] ? 1 : 0);
-  const int loc = e - c.off[l];
+  l = (e >= c.off2) ? 2 : (e >= c.off1 ? 1 : 0);
+  const int loc = e - offof(c, l);
   i = loc / c.R;
   r = loc - i * c.R;
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// One 16x16 output tile C[m0.., n0..] = sum_k A(m, k) B(k, n) on v_mfma_f64_16x16x4f64.
+// Lane layout: A fragment A[lane%16][lane/16], B fragment B[lane/16][lane%16], result
+// D[4v + lane/16][lane%16] in acc[v].  fa / fb return 0 outside the operands.
+template <class FA, class FB>
+__device__ __forceinline__ dbl4 mfma_tile(int m0, int n0, int K, FA fa, FB fb) {
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  // fragments of four k-steps are loaded before their MFMAs, which alternate between two
+  // accumulators, so LDS latency and the MFMA dependency chain overlap
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + 4 * u + kq;
+      a[u] = fa(m0 + r16, k);
+      b[u] = fb(k, n0 + r16);
+    }
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], b[2], acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], b[3], acc1, 0, 0, 0);
+  }
+  return acc0 + acc1;
+}
+
+__device__ __forceinline__ int tiles16(int n) { return (n + 15) >> 4; }
+
+// q = floor(x / d) for 0 <= x < 2^26 through a double reciprocal (exact: the error of
+// (x + 0.5) * inv is far below the distance 0.5 / d to an integer).
+__device__ __forceinline__ int div_by(int x, double inv) { return (int)(((double)x + 0.5) * inv); }
+
+__device__ __forceinline__ double sel(bool ok, double v) { return ok ? v : 0.0; }
+
 __device__ void setup_ctx(Ctx& c, double* lds, const int d[3], int R, const double* S) {
-  c.d[0] = d[0]; c.d[1] = d[1]; c.d[2] = d[2]; c.R = R;
-  c.off[0] = 0; c.off[1] = d[0] * R; c.off[2] = (d[0] + d[1]) * R;
+  c.d0 = d[0]; c.d1 = d[1]; c.d2 = d[2]; c.R = R;
+  c.off1 = d[0] * R; c.off2 = (d[0] + d[1]) * R;
   c.np = (d[0] + d[1] + d[2]) * R;
   double* p = lds;
   c.W = p; p += c.np;
@@ -87,21 +129,29 @@ __device__ void setup_ctx(Ctx& c, double* lds, const int d[3], int R, const doub
   c.pi = p; p += 3 * R * R;
   c.Pown = p; p += 3 * R * R;
   c.Y = p; p += 3 * R * R;
+  c.Qb = p; p += 3 * R * R;
   c.msq = p; p += 3 * R;
   c.gam = p; p += 3 * R;
   c.red = p; p += 2 * NW;
   c.S = S;
 }
 
-// pi^(l) and Pi^(l); ends with a barrier.
+// pi^(l) = W^(l)T W^(l) on the matrix cores, then Pi^(l); ends with a barrier.
 __device__ void grams(Ctx& c) {
-  const int R = c.R, RR = R * R;
-  for (int e = threadIdx.x; e < 3 * RR; e += NT) {
-    const int l = e / RR, rs = e - l * RR, r = rs / R, s = rs - r * R;
-    const double* Wl = c.W + c.off[l];
-    double acc = 0.0;
-    for (int i = 0; i < c.d[l]; ++i) acc += Wl[i * R + r] * Wl[i * R + s];
-    c.pi[e] = acc;
+  const int R = c.R, RR = R * R, tr = tiles16(R);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r16 = lane & 15, kq = lane >> 4;
+  for (int t = w; t < 3 * tr * tr; t += NW) {
+    const int l = t / (tr * tr), tt = t - l * tr * tr, tm = tt / tr, tn = tt - tm * tr;
+    const double* Wl = c.W + offof(c, l);
+    const int dl = dimof(c, l);
+    const dbl4 acc = mfma_tile(tm * 16, tn * 16, dl,
+        [&](int r, int i) { return sel(r < R && i < dl, Wl[min(i, dl - 1) * R + min(r, R - 1)]); },
+        [&](int i, int q) { return sel(q < R && i < dl, Wl[min(i, dl - 1) * R + min(q, R - 1)]); });
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = tm * 16 + 4 * v + kq, q = tn * 16 + r16;
+      if (r < R && q < R) c.pi[l * RR + r * R + q] = acc[v];
+    }
   }
   __syncthreads();
   for (int e = threadIdx.x; e < RR; e += NT) {
@@ -137,48 +187,70 @@ __device__ void precond(Ctx& c, double mu) {
 
 // Structured product of Thm Hv.  With scale = true the input is v = msq * V and the output is
 // msq * (J^T J v + mu D v) (the preconditioned CG operator); with scale = false it is J^T J V.
-// Returns this thread's partial of <V, out>.  Writes out[e]; ends without a barrier after phase 2.
+// Phase 1: Q_b = v_b^T W_b (R x R) for the three modes.  Phase 2, block a:
+//   out_a = [v_a | W_a] [Pi^(a) ; Y_a],  Y_a = pi^(b2) * Q_b1 + pi^(b1) * Q_b2 ({b1, b2} = other modes),
+// with Y formed inside the B-fragment loads.  Returns this thread's partial of <V, out>; ends
+// without a barrier after phase 2.
 __device__ double hv(Ctx& c, const double* V, double* out, double mu, bool scale) {
-  const int R = c.R, RR = R * R;
-  // phase 1: Q_b[s][r] = <v_b[:, s], w_b[:, r]>, then Y_a = sum over b != a of pi^(third) * Q_b
-  for (int e = threadIdx.x; e < RR; e += NT) {
-    const int s = e / R, r = e - s * R;
-    double q[3];
+  const int R = c.R, RR = R * R, tr = tiles16(R);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r16 = lane & 15, kq = lane >> 4;
+  for (int t = w; t < 3 * tr * tr; t += NW) {
+    const int b = t / (tr * tr), tt = t - b * tr * tr, tm = tt / tr, tn = tt - tm * tr;
+    const double* Vb = V + offof(c, b);
+    const double* Wb = c.W + offof(c, b);
+    const int db = dimof(c, b);
+    const dbl4 acc = mfma_tile(tm * 16, tn * 16, db,
+        [&](int sidx, int i) { return sel(sidx < R && i < db, Vb[min(i, db - 1) * R + min(sidx, R - 1)]); },
+        [&](int i, int r) { return sel(r < R && i < db, Wb[min(i, db - 1) * R + min(r, R - 1)]); });
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const double* Vb = V + c.off[b];
-      const double* Wb = c.W + c.off[b];
-      double acc = 0.0;
-      for (int i = 0; i < c.d[b]; ++i) acc += Vb[i * R + s] * Wb[i * R + r];
-      q[b] = scale ? c.msq[b * R + s] * acc : acc;
+    for (int v = 0; v < 4; ++v) {
+      const int sidx = tm * 16 + 4 * v + kq, r = tn * 16 + r16;
+      if (sidx < R && r < R) c.Qb[b * RR + sidx * R + r] = scale ? c.msq[b * R + sidx] * acc[v] : acc[v];
     }
-    const double p0 = c.pi[e], p1 = c.pi[RR + e], p2 = c.pi[2 * RR + e];
-    c.Y[e] = p2 * q[1] + p1 * q[2];
-    c.Y[RR + e] = p2 * q[0] + p0 * q[2];
-    c.Y[2 * RR + e] = p1 * q[0] + p0 * q[1];
   }
   __syncthreads();
-  // phase 2: out_a[i][r] = sum_s v_a[i][s] Pi^(a)[s][r] + sum_s W_a[i][s] Y_a[s][r] (+ mu D v)
+  for (int e = threadIdx.x; e < RR; e += NT) {
+    const double q0 = c.Qb[e], q1 = c.Qb[RR + e], q2 = c.Qb[2 * RR + e];
+    const double p0 = c.pi[e], p1 = c.pi[RR + e], p2 = c.pi[2 * RR + e];
+    c.Y[e] = p2 * q1 + p1 * q2;
+    c.Y[RR + e] = p2 * q0 + p0 * q2;
+    c.Y[2 * RR + e] = p1 * q0 + p0 * q1;
+  }
+  __syncthreads();
   double dotp = 0.0;
-  for (int e = threadIdx.x; e < c.np; e += NT) {
-    int a, i, r;
-    split_index(c, e, a, i, r);
-    const double* Va = V + c.off[a] + i * R;
-    const double* Wa = c.W + c.off[a] + i * R;
+  const int t0 = tiles16(c.d0) * tr, t1 = t0 + tiles16(c.d1) * tr, t2 = t1 + tiles16(c.d2) * tr;
+  for (int t = w; t < t2; t += NW) {
+    const int a = (t >= t1) ? 2 : (t >= t0 ? 1 : 0);
+    const int tt = t - (a == 0 ? 0 : (a == 1 ? t0 : t1));
+    const int tm = tt / tr, tn = tt - tm * tr;
+    const int da = dimof(c, a);
+    const double* Va = V + offof(c, a);
+    const double* Wa = c.W + offof(c, a);
     const double* Pa = c.Pown + a * RR;
     const double* Ya = c.Y + a * RR;
     const double* ma = c.msq + a * R;
-    double t1 = 0.0, t2 = 0.0;
-    if (scale) {
-      for (int s = 0; s < R; ++s) t1 += (ma[s] * Va[s]) * Pa[s * R + r];
-    } else {
-      for (int s = 0; s < R; ++s) t1 += Va[s] * Pa[s * R + r];
+    // v_a Pi^(a) then W_a Y_a, accumulated into one tile
+    const dbl4 acc1 = mfma_tile(tm * 16, tn * 16, R,
+        [&](int i, int k) {
+          const int kk = min(k, R - 1);
+          const double v = Va[min(i, da - 1) * R + kk];
+          return sel(i < da && k < R, scale ? ma[kk] * v : v);
+        },
+        [&](int k, int r) { return sel(r < R && k < R, Pa[min(k, R - 1) * R + min(r, R - 1)]); });
+    const dbl4 acc2 = mfma_tile(tm * 16, tn * 16, R,
+        [&](int i, int k) { return sel(i < da && k < R, Wa[min(i, da - 1) * R + min(k, R - 1)]); },
+        [&](int k, int r) { return sel(r < R && k < R, Ya[min(k, R - 1) * R + min(r, R - 1)]); });
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = tm * 16 + 4 * v + kq, r = tn * 16 + r16;
+      if (i < da && r < R) {
+        const int e = offof(c, a) + i * R + r;
+        double tv = acc1[v] + acc2[v];
+        if (scale) tv = ma[r] * (tv + mu * c.gam[a * R + r] * (ma[r] * V[e]));
+        out[e] = tv;
+        dotp += V[e] * tv;
+      }
     }
-    for (int s = 0; s < R; ++s) t2 += Wa[s] * Ya[s * R + r];
-    double t = t1 + t2;
-    if (scale) t = ma[r] * (t + mu * c.gam[a * R + r] * (ma[r] * Va[r]));
-    out[e] = t;
-    dotp += V[e] * t;
   }
   return dotp;
 }
@@ -190,9 +262,9 @@ __device__ void norm_balance(Ctx& c) {
   double* cn = c.msq;   // 3R scratch
   for (int e = threadIdx.x; e < 3 * R; e += NT) {
     const int l = e / R, r = e - l * R;
-    const double* Wl = c.W + c.off[l];
+    const double* Wl = c.W + offof(c, l);
     double acc = 0.0;
-    for (int i = 0; i < c.d[l]; ++i) acc += Wl[i * R + r] * Wl[i * R + r];
+    for (int i = 0; i < dimof(c, l); ++i) acc += Wl[i * R + r] * Wl[i * R + r];
     cn[e] = sqrt(acc);
   }
   __syncthreads();
@@ -207,52 +279,79 @@ __device__ void norm_balance(Ctx& c) {
   __syncthreads();
 }
 
-// ||S - [[W]]||^2 and MK = S_(l) KR(others) at the current W (one pass per output; ch.4
-// "Computing the residual" and the MTTKRP of the gradient).  Returns the block-wide f2.
+// ||S - [[W]]||^2 and MK = S_(l) KR(others) at the current W (ch.4 "Computing the residual" and
+// the MTTKRP of the gradient), on the matrix cores:
+//   MK_0 = S_(0) KR(W2, W1) over (j, k);  MK_1 over (i, k);  MK_2 over (i, j);
+//   model = W0 KR12^T (d0 x d1 d2), and f = S - model squared and summed in the tile epilogue.
+// Returns the block-wide ||f||^2.
 __device__ double residual_mttkrp(Ctx& c, double* slots) {
-  const int R = c.R, d0 = c.d[0], d1 = c.d[1], d2 = c.d[2];
+  const int R = c.R, d0 = c.d0, d1 = c.d1, d2 = c.d2, tr = tiles16(R);
+  const int d12 = d1 * d2, d02 = d0 * d2, d01 = d0 * d1;
+  const double inv1 = 1.0 / d1, inv2 = 1.0 / d2;
   const double* W0 = c.W;
-  const double* W1 = c.W + c.off[1];
-  const double* W2 = c.W + c.off[2];
+  const double* W1 = c.W + c.off1;
+  const double* W2 = c.W + c.off2;
   const double* S = c.S;
-  const int n = d0 * d1 * d2;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r16 = lane & 15, kq = lane >> 4;
+  const int n0 = tiles16(d0) * tr, n1 = n0 + tiles16(d1) * tr, n2 = n1 + tiles16(d2) * tr;
+  const int nres = tiles16(d0) * tiles16(d12);
+  const int R1 = R - 1;
   double f2 = 0.0;
-  for (int e = threadIdx.x; e < n; e += NT) {
-    const int i = e / (d1 * d2), jk = e - i * d1 * d2, j = jk / d2, k = jk - j * d2;
-    double model = 0.0;
-    for (int r = 0; r < R; ++r) model += (W0[i * R + r] * W1[j * R + r]) * W2[k * R + r];
-    const double f = S[e] - model;
-    f2 += f * f;
-  }
-  for (int e = threadIdx.x; e < c.np; e += NT) {
-    int l, i, r;
-    split_index(c, e, l, i, r);
-    double acc = 0.0;
-    if (l == 0) {
-      for (int j = 0; j < d1; ++j) {
-        const double wj = W1[j * R + r];
-        const double* Sij = S + ((size_t)i * d1 + j) * d2;
-        double t = 0.0;
-        for (int k = 0; k < d2; ++k) t += Sij[k] * W2[k * R + r];
-        acc += wj * t;
+  for (int t = w; t < n2 + nres; t += NW) {
+    if (t < n2) {
+      const int l = (t >= n1) ? 2 : (t >= n0 ? 1 : 0);
+      const int tt = t - (l == 0 ? 0 : (l == 1 ? n0 : n1));
+      const int tm = tt / tr, tn = tt - tm * tr;
+      const int dl = dimof(c, l);
+      dbl4 acc;
+      if (l == 0) {
+        acc = mfma_tile(tm * 16, tn * 16, d12,
+            [&](int i, int jk) { return sel(i < d0 && jk < d12, S[min(i, d0 - 1) * d12 + min(jk, d12 - 1)]); },
+            [&](int jk, int r) {
+              const int x = min(jk, d12 - 1), j = div_by(x, inv2), k = x - j * d2, rr = min(r, R1);
+              return sel(r < R && jk < d12, W2[k * R + rr] * W1[j * R + rr]);
+            });
+      } else if (l == 1) {
+        acc = mfma_tile(tm * 16, tn * 16, d02,
+            [&](int j, int ik) {
+              const int x = min(ik, d02 - 1), i = div_by(x, inv2), k = x - i * d2;
+              return sel(j < d1 && ik < d02, S[i * d12 + min(j, d1 - 1) * d2 + k]);
+            },
+            [&](int ik, int r) {
+              const int x = min(ik, d02 - 1), i = div_by(x, inv2), k = x - i * d2, rr = min(r, R1);
+              return sel(r < R && ik < d02, W2[k * R + rr] * W0[i * R + rr]);
+            });
+      } else {
+        acc = mfma_tile(tm * 16, tn * 16, d01,
+            [&](int k, int ij) { return sel(k < d2 && ij < d01, S[min(ij, d01 - 1) * d2 + min(k, d2 - 1)]); },
+            [&](int ij, int r) {
+              const int x = min(ij, d01 - 1), i = div_by(x, inv1), j = x - i * d1, rr = min(r, R1);
+              return sel(r < R && ij < d01, W1[j * R + rr] * W0[i * R + rr]);
+            });
       }
-    } else if (l == 1) {
-      for (int ii = 0; ii < d0; ++ii) {
-        const double wi = W0[ii * R + r];
-        const double* Sij = S + ((size_t)ii * d1 + i) * d2;
-        double t = 0.0;
-        for (int k = 0; k < d2; ++k) t += Sij[k] * W2[k * R + r];
-        acc += wi * t;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = tm * 16 + 4 * v + kq, r = tn * 16 + r16;
+        if (m < dl && r < R) c.MK[offof(c, l) + m * R + r] = acc[v];
       }
     } else {
-      for (int ii = 0; ii < d0; ++ii) {
-        const double wi = W0[ii * R + r];
-        double t = 0.0;
-        for (int j = 0; j < d1; ++j) t += S[((size_t)ii * d1 + j) * d2 + i] * W1[j * R + r];
-        acc += wi * t;
+      const int tt = t - n2, tcols = tiles16(d12);
+      const int tm = tt / tcols, tn = tt - tm * tcols;
+      const dbl4 acc = mfma_tile(tm * 16, tn * 16, R,
+          [&](int i, int r) { return sel(i < d0 && r < R, W0[min(i, d0 - 1) * R + min(r, R1)]); },
+          [&](int r, int jk) {
+            const int x = min(jk, d12 - 1), j = div_by(x, inv2), k = x - j * d2, rr = min(r, R1);
+            return sel(r < R && jk < d12, W1[j * R + rr] * W2[k * R + rr]);
+          });
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = tm * 16 + 4 * v + kq, jk = tn * 16 + r16;
+        if (i < d0 && jk < d12) {
+          const double f = S[i * d12 + jk] - acc[v];
+          f2 += f * f;
+        }
       }
     }
-    c.MK[e] = acc;
   }
   return block_sum(f2, slots);
 }
@@ -347,7 +446,7 @@ __global__ __launch_bounds__(NT) void dgn_kernel(char* __restrict__ state, const
     for (int e = tid; e < c.np; e += NT) {
       int l, i, r;
       split_index(c, e, l, i, r);
-      const double* Wi = c.W + c.off[l] + i * R;
+      const double* Wi = c.W + offof(c, l) + i * R;
       const double* Pl = c.Pown + l * R * R;
       double acc = 0.0;
       for (int s = 0; s < R; ++s) acc += Wi[s] * Pl[s * R + r];

@@ -5,7 +5,8 @@
 //
 //  n <= 64 : cyclic Jacobi with the round-robin parallel ordering, the whole matrix in LDS of one
 //            workgroup (exact to rounding, no spectral-gap assumption).
-//  n  > 64 : subspace iteration on k = min(n, max(P + 8, 2P), 64) vectors with Rayleigh-Ritz
+//  n  > 64 : subspace iteration on k = min(n, P + max(8, P/4), 64) vectors (four power steps,
+//            then Rayleigh-Ritz every step)
 //            (Jacobi on the k x k projection), stopped when every wanted Ritz pair has residual
 //            ||G u - theta u|| <= 1e-13 theta_1 (at most 200 iterations).
 // Eigenvectors are signed so that each one's largest-magnitude entry is positive (ties: lowest
@@ -22,80 +23,104 @@ constexpr int JNT = 256;
 
 // Jacobi eigendecomposition of an n x n symmetric matrix (row-major, leading dim lda).
 // Outputs: lam[n] descending, V[n*n] row-major with eigenvector j in column j (ldv = n).
+// Thread map: lane = row/column index j (0..63), wave w applies the pairs i = w, w + 4, ...
 __global__ __launch_bounds__(JNT) void jacobi_kernel(const double* __restrict__ Ag, int n, int lda,
                                                      double* __restrict__ lam,
                                                      double* __restrict__ Vout) {
   __shared__ double A[JMAX][JMAX + 1];
   __shared__ double V[JMAX][JMAX + 1];
-  __shared__ double cs[JMAX / 2], sn[JMAX / 2];
-  __shared__ int pp[JMAX / 2], qq[JMAX / 2];
   __shared__ double red[2][JNT / 64];
   __shared__ int rank_of[JMAX];
-  const int tid = threadIdx.x;
+  __shared__ int rotated[2];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int NWV = JNT / 64;
   const int np = (n + 1) & ~1;   // even number of slots (one padding slot when n is odd)
-  for (int e = tid; e < JMAX * JMAX; e += JNT) {
-    const int i = e / JMAX, j = e % JMAX;
-    A[i][j] = (i < n && j < n) ? Ag[(long long)i * lda + j] : 0.0;
-    V[i][j] = (i == j) ? 1.0 : 0.0;
+  for (int i = w; i < JMAX; i += NWV) {
+    A[i][lane] = (i < n && lane < n) ? Ag[(long long)i * lda + lane] : 0.0;
+    V[i][lane] = (i == lane) ? 1.0 : 0.0;
   }
   __syncthreads();
   double fro2 = 0.0;
-  for (int e = tid; e < n * n; e += JNT) fro2 += A[e / n][e % n] * A[e / n][e % n];
+  for (int i = w; i < n; i += NWV)
+    if (lane < n) fro2 += A[i][lane] * A[i][lane];
   fro2 = block_sum(fro2, red[0]);
   const int half = np / 2;
   for (int sweep = 0; sweep < 60 && np >= 2; ++sweep) {
     double off = 0.0;
-    for (int e = tid; e < n * n; e += JNT) {
-      const int i = e / n, j = e % n;
-      if (i != j) off += A[i][j] * A[i][j];
-    }
+    for (int i = w; i < n; i += NWV)
+      if (lane < n && lane != i) off += A[i][lane] * A[i][lane];
     off = block_sum(off, red[(sweep + 1) & 1]);
     if (off <= 1e-30 * fro2 || off == 0.0) break;
+    // a sweep that rotates nothing ends the iteration (relative threshold below)
+    if (tid == 0) rotated[sweep & 1] = 0;
+    __syncthreads();
     for (int round = 0; round < np - 1; ++round) {
-      if (tid < half) {
-        // round-robin: slot 0 fixed, the others rotate
-        const int i = tid;
-        const int a = (i == 0) ? 0 : 1 + ((i - 1 + round) % (np - 1));
-        const int bslot = np - 1 - i;
-        const int b = 1 + ((bslot - 1 + round) % (np - 1));
-        const int p = min(a, b), q = max(a, b);
-        double c = 1.0, s = 0.0;
-        if (q < n) {
-          const double apq = A[p][q];
-          if (apq != 0.0) {
-            const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+      // lane u of wave w computes the rotation of pair i = w + u * NWV; the wave then broadcasts
+      // the parameters of its pairs with lane shuffles
+      constexpr int MAXP = JMAX / 2 / NWV;
+      int pl = 0, ql = 0;
+      double cl = 1.0, sl = 0.0;
+      {
+        const int i = w + lane * NWV;
+        if (lane < MAXP && i < half) {
+          // round-robin: slot 0 fixed, the others rotate
+          const int a = (i == 0) ? 0 : 1 + ((i - 1 + round) % (np - 1));
+          const int b = 1 + ((np - 2 - i + round) % (np - 1));
+          pl = min(a, b); ql = max(a, b);
+          if (ql < n) {
+            const double apq = A[pl][ql], app = A[pl][pl], aqq = A[ql][ql];
+            if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
+              rotated[sweep & 1] = 1;
+              const double tau = (aqq - app) / (2.0 * apq);
+              const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+              cl = 1.0 / sqrt(1.0 + t * t);
+              sl = t * cl;
+            }
           }
         }
-        cs[i] = c; sn[i] = s; pp[i] = p; qq[i] = q;
+      }
+      int pu[MAXP], qu[MAXP];
+      double cu[MAXP], su[MAXP];
+#pragma unroll
+      for (int u = 0; u < MAXP; ++u) {
+        pu[u] = __shfl(pl, u, 64); qu[u] = __shfl(ql, u, 64);
+        cu[u] = __shfl(cl, u, 64); su[u] = __shfl(sl, u, 64);
+      }
+      // rows: A <- J^T A (lane = column); the loads of all pairs are issued before the stores
+      {
+        double ap[MAXP], aq[MAXP];
+#pragma unroll
+        for (int u = 0; u < MAXP; ++u)
+          if (w + u * NWV < half && lane < np) { ap[u] = A[pu[u]][lane]; aq[u] = A[qu[u]][lane]; }
+#pragma unroll
+        for (int u = 0; u < MAXP; ++u)
+          if (w + u * NWV < half && lane < np) {
+            A[pu[u]][lane] = cu[u] * ap[u] - su[u] * aq[u];
+            A[qu[u]][lane] = su[u] * ap[u] + cu[u] * aq[u];
+          }
       }
       __syncthreads();
-      // rows: A <- J^T A
-      for (int e = tid; e < half * np; e += JNT) {
-        const int i = e / np, j = e % np;
-        const int p = pp[i], q = qq[i];
-        const double c = cs[i], s = sn[i];
-        const double ap = A[p][j], aq = A[q][j];
-        A[p][j] = c * ap - s * aq;
-        A[q][j] = s * ap + c * aq;
-      }
-      __syncthreads();
-      // columns: A <- A J, V <- V J
-      for (int e = tid; e < half * np; e += JNT) {
-        const int i = e / np, j = e % np;
-        const int p = pp[i], q = qq[i];
-        const double c = cs[i], s = sn[i];
-        const double ap = A[j][p], aq = A[j][q];
-        A[j][p] = c * ap - s * aq;
-        A[j][q] = s * ap + c * aq;
-        const double vp = V[j][p], vq = V[j][q];
-        V[j][p] = c * vp - s * vq;
-        V[j][q] = s * vp + c * vq;
+      // columns: A <- A J, V <- V J (lane = row)
+      {
+        double ap[MAXP], aq[MAXP], vp[MAXP], vq[MAXP];
+#pragma unroll
+        for (int u = 0; u < MAXP; ++u)
+          if (w + u * NWV < half && lane < np) {
+            ap[u] = A[lane][pu[u]]; aq[u] = A[lane][qu[u]];
+            vp[u] = V[lane][pu[u]]; vq[u] = V[lane][qu[u]];
+          }
+#pragma unroll
+        for (int u = 0; u < MAXP; ++u)
+          if (w + u * NWV < half && lane < np) {
+            A[lane][pu[u]] = cu[u] * ap[u] - su[u] * aq[u];
+            A[lane][qu[u]] = su[u] * ap[u] + cu[u] * aq[u];
+            V[lane][pu[u]] = cu[u] * vp[u] - su[u] * vq[u];
+            V[lane][qu[u]] = su[u] * vp[u] + cu[u] * vq[u];
+          }
       }
       __syncthreads();
     }
+    if (rotated[sweep & 1] == 0) break;
   }
   // rank sort, descending eigenvalue, ties by index
   if (tid < n) {
@@ -109,10 +134,8 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const double* __restrict__ 
   }
   __syncthreads();
   if (tid < n) lam[rank_of[tid]] = A[tid][tid];
-  for (int e = tid; e < n * n; e += JNT) {
-    const int i = e / n, j = e % n;   // component i of eigenvector j
-    Vout[(long long)i * n + rank_of[j]] = V[i][j];
-  }
+  for (int i = w; i < n; i += NWV)
+    if (lane < n) Vout[(long long)i * n + rank_of[lane]] = V[i][lane];   // component i of vector lane
 }
 
 // Copies the first P columns of X (n x ldx) into U (n x P) and signs each column so its
@@ -154,7 +177,14 @@ __global__ void init_block_kernel(double* Q, int n, int k, uint64_t seed) {
 // one re-orthogonalisation pass ("twice is enough").  A column whose norm collapses below 1e-12 of
 // its original norm is replaced by a fresh pseudo-random vector and orthogonalised again.
 constexpr int ONT = 512;
-__global__ __launch_bounds__(ONT) void orth_kernel(double* __restrict__ Z, int n, int k, uint64_t seed) {
+__global__ __launch_bounds__(ONT) void orth_kernel(double* __restrict__ Z, int n, int k, uint64_t seed,
+                                                   const int* __restrict__ only_if,
+                                                   const double* __restrict__ src) {
+  if (only_if != nullptr && *only_if == 0) return;
+  if (src != nullptr) {
+    for (long long e = threadIdx.x; e < (long long)n * k; e += ONT) Z[e] = src[e];
+    __syncthreads();
+  }
   __shared__ double coef[JMAX];
   __shared__ double red[2][ONT / 64];
   __shared__ double nrm0;
@@ -203,8 +233,86 @@ __global__ __launch_bounds__(ONT) void orth_kernel(double* __restrict__ Z, int n
   }
 }
 
+// Cholesky of the column-scaled Gram D C D = R^T R, D = diag(C)^{-1/2}, of a k x k SPD matrix
+// (k <= 64).  One wavefront, lane = column; right-looking, the trailing update of each column
+// runs down the column without dependences between its entries.  Writes R (upper triangular,
+// row-major k x k) and D.  A pivot below 1e-13 sets *bad = 1 (or-ed with *prev when given).
+__global__ __launch_bounds__(64) void chol_scaled_kernel(const double* __restrict__ C, int k,
+                                                         double* __restrict__ Rout, double* __restrict__ Dout,
+                                                         const int* __restrict__ prev, int* __restrict__ bad) {
+  __shared__ double A[JMAX][JMAX + 1];   // A[row][col], upper triangle used
+  __shared__ double dsc[JMAX];
+  const int c = threadIdx.x;
+  if (c < k) {
+    const double cc = C[c * k + c];
+    dsc[c] = (cc > 0.0) ? 1.0 / sqrt(cc) : 1.0;
+  }
+  __syncthreads();
+  if (c < k)
+    for (int r = 0; r <= c; ++r) A[r][c] = dsc[r] * C[r * k + c] * dsc[c];
+  __syncthreads();
+  int fail = 0;
+  for (int j = 0; j < k; ++j) {
+    const double piv = A[j][j];
+    if (!(piv > 1e-13)) fail = 1;
+    const double d = sqrt(fmax(piv, 1e-300));
+    __syncthreads();
+    // row j of R: lane c >= j scales its entry
+    if (c >= j && c < k) A[j][c] = (c == j) ? d : A[j][c] / d;
+    __syncthreads();
+    // trailing update of column c > j: A[r][c] -= R[j][r] R[j][c] for j < r <= c
+    if (c > j && c < k) {
+      const double rjc = A[j][c];
+      int r = j + 1;
+      for (; r + 3 <= c; r += 4) {
+        const double x0 = A[j][r], x1 = A[j][r + 1], x2 = A[j][r + 2], x3 = A[j][r + 3];
+        const double y0 = A[r][c], y1 = A[r + 1][c], y2 = A[r + 2][c], y3 = A[r + 3][c];
+        A[r][c] = y0 - x0 * rjc;
+        A[r + 1][c] = y1 - x1 * rjc;
+        A[r + 2][c] = y2 - x2 * rjc;
+        A[r + 3][c] = y3 - x3 * rjc;
+      }
+      for (; r <= c; ++r) A[r][c] -= A[j][r] * rjc;
+    }
+    __syncthreads();
+  }
+  if (c < k) {
+    for (int r = 0; r < k; ++r) Rout[r * k + c] = (r <= c) ? A[r][c] : 0.0;
+    Dout[c] = dsc[c];
+  }
+  if (c == 0) *bad = fail | (prev ? *prev : 0);
+}
+
+// Q[i, :] = (Y[i, :] D) R^{-1} by forward substitution along the row (thread per row, R and D
+// staged in LDS); skipped when the factorisation failed.
+__global__ __launch_bounds__(128) void rowsolve_kernel(const double* __restrict__ Y, const double* __restrict__ Rm,
+                                                       const double* __restrict__ D, int n, int k,
+                                                       const int* __restrict__ bad, double* __restrict__ Q) {
+  __shared__ double Rs[JMAX * JMAX];
+  __shared__ double Ds[JMAX];
+  if (*bad) return;
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) Rs[e] = Rm[e];
+  for (int e = threadIdx.x; e < k; e += blockDim.x) Ds[e] = D[e];
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* y = Y + (long long)i * k;
+  double* q = Q + (long long)i * k;
+  double qv[JMAX];
+#pragma unroll
+  for (int c = 0; c < JMAX; ++c) {
+    if (c < k) {
+      double v = y[c] * Ds[c];
+#pragma unroll
+      for (int t = 0; t < c; ++t) v -= qv[t] * Rs[t * k + c];
+      qv[c] = v / Rs[c * k + c];
+      q[c] = qv[c];
+    }
+  }
+}
+
 // max_j ||ZV[:,j] - theta_j U[:,j]|| / |theta_0| over the P wanted pairs (one workgroup).
-__global__ void ritz_residual_kernel(const double* __restrict__ ZV, const double* __restrict__ U,
+__global__ void ritz_residual_kernel(const double* __restrict__ ZV, int ldz, const double* __restrict__ U,
                                      const double* __restrict__ theta, int n, int P,
                                      double* __restrict__ out) {
   __shared__ double red[2][256 / 64];
@@ -213,7 +321,7 @@ __global__ void ritz_residual_kernel(const double* __restrict__ ZV, const double
   for (int j = 0; j < P; ++j) {
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const double r = ZV[(long long)i * P + j] - theta[j] * U[(long long)i * P + j];
+      const double r = ZV[(long long)i * ldz + j] - theta[j] * U[(long long)i * P + j];
       s += r * r;
     }
     s = block_sum(s, red[flip]); flip ^= 1;
@@ -226,14 +334,40 @@ __global__ void ritz_residual_kernel(const double* __restrict__ ZV, const double
 }
 
 int subspace_k(int n, int P) {
-  int k = P + 8;
-  if (2 * P > k) k = 2 * P;
+  int k = P + (P / 4 > 8 ? P / 4 : 8);
   if (k > JMAX) k = JMAX;
   if (k > n) k = n;
   return k;
 }
 
 }  // namespace
+
+// Orthonormal basis Q of the columns of Y (n x k, k <= 64) by Cholesky-QR of the column-scaled
+// Gram (one pass, or two when `twice`); if a pivot breaks down the block is orthonormalised by
+// CGS2 instead (decided on the device, no synchronisation).  Y is left unchanged.
+cpd_status chol_qr(const double* Y, int n, int k, double* Q, double* C, double* Rm, double* D, double* Qtmp,
+                   int* flags, bool twice, uint64_t seed, hipStream_t s) {
+  cpd_status st;
+  const unsigned nb = (unsigned)((n + 127) / 128);
+  if ((st = gemm_f64(k, k, n, 1.0, Y, k, 0, true, Y, CPD_F64, k, 0, false, 0.0, C, k, 0, 1, s))) return st;
+  hipLaunchKernelGGL(chol_scaled_kernel, dim3(1), dim3(64), 0, s, C, k, Rm, D, (const int*)nullptr, flags);
+  CPD_LAUNCH_CHECK();
+  double* out1 = twice ? Qtmp : Q;
+  hipLaunchKernelGGL(rowsolve_kernel, dim3(nb), dim3(128), 0, s, Y, Rm, D, n, k, flags, out1);
+  CPD_LAUNCH_CHECK();
+  int* last = flags;
+  if (twice) {
+    if ((st = gemm_f64(k, k, n, 1.0, Qtmp, k, 0, true, Qtmp, CPD_F64, k, 0, false, 0.0, C, k, 0, 1, s))) return st;
+    hipLaunchKernelGGL(chol_scaled_kernel, dim3(1), dim3(64), 0, s, C, k, Rm, D, flags, flags + 1);
+    CPD_LAUNCH_CHECK();
+    hipLaunchKernelGGL(rowsolve_kernel, dim3(nb), dim3(128), 0, s, Qtmp, Rm, D, n, k, flags + 1, Q);
+    CPD_LAUNCH_CHECK();
+    last = flags + 1;
+  }
+  hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(ONT), 0, s, Q, n, k, seed, last, Y);
+  CPD_LAUNCH_CHECK();
+  return CPD_OK;
+}
 
 size_t eig_ws_bytes(int n, int P) {
   if (n <= JMAX) {
@@ -246,12 +380,16 @@ size_t eig_ws_bytes(int n, int P) {
   Sizer z;
   z.take<double>((size_t)n * k);   // Q
   z.take<double>((size_t)n * k);   // Z
-  z.take<double>((size_t)k * k);   // B
+  z.take<double>((size_t)n * k);   // Y = Z Vb
+  z.take<double>((size_t)n * k);   // Qtmp
+  z.take<double>((size_t)k * k);   // B / C
   z.take<double>((size_t)k * k);   // Vb
+  z.take<double>((size_t)k * k);   // R
+  z.take<double>(k);               // D
   z.take<double>(k);               // theta
   z.take<double>((size_t)n * P);   // U work
-  z.take<double>((size_t)n * P);   // ZV
   z.take<double>(1);               // residual ratio
+  z.take<int>(4);                  // flags
   return z.off;
 }
 
@@ -283,37 +421,46 @@ cpd_status eig_top(const double* G, int n, int P, double* U, double* lam, void* 
   const int k = subspace_k(n, P);
   double* Q = ar.take<double>((size_t)n * k);
   double* Z = ar.take<double>((size_t)n * k);
+  double* Y = ar.take<double>((size_t)n * k);
+  double* Qt = ar.take<double>((size_t)n * k);
   double* B = ar.take<double>((size_t)k * k);
   double* Vb = ar.take<double>((size_t)k * k);
+  double* Ri = ar.take<double>((size_t)k * k);
+  double* Dv = ar.take<double>(k);
   double* theta = ar.take<double>(k);
   double* Uw = ar.take<double>((size_t)n * P);
-  double* ZV = ar.take<double>((size_t)n * P);
   double* ratio = ar.take<double>(1);
+  int* flags = ar.take<int>(4);
   const uint64_t seed = 0xC0FFEEull + (uint64_t)n * 131 + (uint64_t)P;
-  hipLaunchKernelGGL(init_block_kernel, dim3((n * k + 255) / 256), dim3(256), 0, s, Q, n, k, seed);
-  CPD_LAUNCH_CHECK();
-  hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(ONT), 0, s, Q, n, k, seed + 1);
-  CPD_LAUNCH_CHECK();
   cpd_status st;
+  hipLaunchKernelGGL(init_block_kernel, dim3((n * k + 255) / 256), dim3(256), 0, s, Y, n, k, seed);
+  CPD_LAUNCH_CHECK();
+  // a Gaussian-like start block is well conditioned: one Cholesky-QR pass
+  if ((st = chol_qr(Y, n, k, Q, B, Ri, Dv, Qt, flags, false, seed + 1, s))) return st;
+  // four plain power steps Q <- orth(G Q) before the first Rayleigh-Ritz check; the last one
+  // re-orthogonalises (two passes) since G Q is ill-conditioned
+  for (int it = 0; it < 4; ++it) {
+    if ((st = gemm_f64(n, k, n, 1.0, G, n, 0, false, Q, CPD_F64, k, 0, false, 0.0, Y, k, 0, 1, s))) return st;
+    if ((st = chol_qr(Y, n, k, Q, B, Ri, Dv, Qt, flags, it == 3, seed + 100 + it, s))) return st;
+  }
   for (int it = 0; it < 200; ++it) {
-    // Z = G Q ; B = Q^T Z ; Ritz pairs of B
+    // Z = G Q ; B = Q^T Z ; Ritz pairs (theta, Vb) of B
     if ((st = gemm_f64(n, k, n, 1.0, G, n, 0, false, Q, CPD_F64, k, 0, false, 0.0, Z, k, 0, 1, s))) return st;
     if ((st = gemm_f64(k, k, n, 1.0, Q, k, 0, true, Z, CPD_F64, k, 0, false, 0.0, B, k, 0, 1, s))) return st;
     hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(JNT), 0, s, B, k, k, theta, Vb);
     CPD_LAUNCH_CHECK();
-    // U = Q Vb[:, :P], ZV = Z Vb[:, :P]
+    // Ritz vectors U = Q Vb[:, :P]; Y = Z Vb = G (Q Vb) (its first P columns give the residuals)
     if ((st = gemm_f64(n, P, k, 1.0, Q, k, 0, false, Vb, CPD_F64, k, 0, false, 0.0, Uw, P, 0, 1, s))) return st;
-    if ((st = gemm_f64(n, P, k, 1.0, Z, k, 0, false, Vb, CPD_F64, k, 0, false, 0.0, ZV, P, 0, 1, s))) return st;
-    hipLaunchKernelGGL(ritz_residual_kernel, dim3(1), dim3(256), 0, s, ZV, Uw, theta, n, P, ratio);
+    if ((st = gemm_f64(n, k, k, 1.0, Z, k, 0, false, Vb, CPD_F64, k, 0, false, 0.0, Y, k, 0, 1, s))) return st;
+    hipLaunchKernelGGL(ritz_residual_kernel, dim3(1), dim3(256), 0, s, Y, k, Uw, theta, n, P, ratio);
     CPD_LAUNCH_CHECK();
     double r = 0.0;
     CPD_HIP_CHECK(hipMemcpyAsync(&r, ratio, sizeof(double), hipMemcpyDeviceToHost, s));
     CPD_HIP_CHECK(hipStreamSynchronize(s));
     if (r <= 1e-13) break;
-    // next block: orthonormalised Z
-    CPD_HIP_CHECK(hipMemcpyAsync(Q, Z, sizeof(double) * (size_t)n * k, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(ONT), 0, s, Q, n, k, seed + 2 + it);
-    CPD_LAUNCH_CHECK();
+    // next basis: orthonormalised G (Q Vb); its columns are nearly orthogonal (G times Ritz
+    // vectors), but a second pass keeps the Rayleigh-Ritz basis orthonormal to rounding
+    if ((st = chol_qr(Y, n, k, Q, B, Ri, Dv, Qt, flags, true, seed + 2 + it, s))) return st;
   }
   CPD_HIP_CHECK(hipMemcpyAsync(lam, theta, sizeof(double) * P, hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(sign_columns_kernel, dim3(P), dim3(256), 0, s, Uw, n, P, P, U);

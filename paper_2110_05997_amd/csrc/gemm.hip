@@ -86,6 +86,83 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, double al
   }
 }
 
+// C = A^T B for narrow operands (A: K x M, B: K x N, M, N <= 64): one workgroup per output row m,
+// lane = column n, the four waves split the K rows; partial sums combined in a fixed order.
+template <class TB>
+__global__ __launch_bounds__(256) void atb_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
+                                                  int lda, const TB* __restrict__ B, long long ldb, double beta,
+                                                  double* __restrict__ C, long long ldc) {
+  __shared__ double part[4][64];
+  const int m = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (lane < N) {
+    int k = w;
+    for (; k + 12 < K; k += 16) {
+      a0 = fma(A[(long long)k * lda + m], loadB(B + (long long)k * ldb + lane), a0);
+      a1 = fma(A[(long long)(k + 4) * lda + m], loadB(B + (long long)(k + 4) * ldb + lane), a1);
+      a2 = fma(A[(long long)(k + 8) * lda + m], loadB(B + (long long)(k + 8) * ldb + lane), a2);
+      a3 = fma(A[(long long)(k + 12) * lda + m], loadB(B + (long long)(k + 12) * ldb + lane), a3);
+    }
+    for (; k < K; k += 4) a0 = fma(A[(long long)k * lda + m], loadB(B + (long long)k * ldb + lane), a0);
+  }
+  part[w][lane] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (w == 0 && lane < N) {
+    const double v = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    double* c = C + (long long)m * ldc + lane;
+    *c = (beta == 0.0) ? alpha * v : alpha * v + beta * *c;
+  }
+}
+
+// C = A B with N <= 64 (no transposes): one wavefront per output row, lane = column.
+template <class TB>
+__global__ __launch_bounds__(256) void rowgemm_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
+                                                      int lda, const TB* __restrict__ B, long long ldb, double beta,
+                                                      double* __restrict__ C, long long ldc) {
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (m >= M || lane >= N) return;
+  const double* a = A + (long long)m * lda;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int k = 0;
+  for (; k + 3 < K; k += 4) {
+    a0 = fma(a[k], loadB(B + (long long)k * ldb + lane), a0);
+    a1 = fma(a[k + 1], loadB(B + (long long)(k + 1) * ldb + lane), a1);
+    a2 = fma(a[k + 2], loadB(B + (long long)(k + 2) * ldb + lane), a2);
+    a3 = fma(a[k + 3], loadB(B + (long long)(k + 3) * ldb + lane), a3);
+  }
+  for (; k < K; ++k) a0 = fma(a[k], loadB(B + (long long)k * ldb + lane), a0);
+  const double acc = (a0 + a1) + (a2 + a3);
+  double* c = C + (long long)m * ldc + lane;
+  *c = (beta == 0.0) ? alpha * acc : alpha * acc + beta * *c;
+}
+
+// One thread per output element, for small products where 64x64 tiles would leave the chip idle.
+template <class TB>
+__global__ void gemm_small_kernel(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
+                                  long long sA, int ta, const TB* __restrict__ B, long long ldb, long long sB,
+                                  int tb, double beta, double* __restrict__ C, long long ldc, long long sC,
+                                  int tc) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)M * N) return;
+  const int m = (int)(e / N), n = (int)(e % N);
+  const long long b = blockIdx.y;
+  A += b * sA;
+  B += b * sB;
+  C += b * sC;
+  double acc = 0.0;
+  if (!ta && !tb) {
+    for (int k = 0; k < K; ++k) acc = fma(A[(long long)m * lda + k], loadB(B + (long long)k * ldb + n), acc);
+  } else {
+    for (int k = 0; k < K; ++k) {
+      const double a = ta ? A[(long long)k * lda + m] : A[(long long)m * lda + k];
+      const double bv = tb ? loadB(B + (long long)n * ldb + k) : loadB(B + (long long)k * ldb + n);
+      acc = fma(a, bv, acc);
+    }
+  }
+  double* c = tc ? C + (long long)n * ldc + m : C + (long long)m * ldc + n;
+  *c = (beta == 0.0) ? alpha * acc : alpha * acc + beta * *c;
+}
+
 }  // namespace
 
 cpd_status gemm_f64(int M, int N, int K, double alpha, const double* A, int lda, long long sA,
@@ -96,6 +173,43 @@ cpd_status gemm_f64(int M, int N, int K, double alpha, const double* A, int lda,
   if (K < 0 || A == nullptr || B == nullptr || C == nullptr) {
     set_error("gemm_f64: bad arguments");
     return CPD_E_INVALID;
+  }
+  const long long mn = (long long)M * N;
+  if (bdtype == CPD_F64 && batch == 1 && !tc && !tb && N <= 64) {
+    if (ta && M <= 64 && K >= 128) {
+      hipLaunchKernelGGL(atb_kernel<double>, dim3(M), dim3(256), 0, s, M, N, K, alpha, A, lda, (const double*)B,
+                         ldb, beta, C, ldc);
+      CPD_LAUNCH_CHECK();
+      return CPD_OK;
+    }
+    if (!ta && K <= 4096) {
+      hipLaunchKernelGGL(rowgemm_kernel<double>, dim3((M + 3) / 4), dim3(256), 0, s, M, N, K, alpha, A, lda,
+                         (const double*)B, ldb, beta, C, ldc);
+      CPD_LAUNCH_CHECK();
+      return CPD_OK;
+    }
+  }
+  if (mn <= 65536 && K <= 4096 && batch <= 65535 && (mn < 16384 || K <= 1024)) {
+    dim3 g2((unsigned)((mn + 255) / 256), batch);
+    switch (bdtype) {
+      case CPD_F64:
+        hipLaunchKernelGGL(gemm_small_kernel<double>, g2, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, (int)ta,
+                           (const double*)B, ldb, sB, (int)tb, beta, C, ldc, sC, (int)tc);
+        break;
+      case CPD_F32:
+        hipLaunchKernelGGL(gemm_small_kernel<float>, g2, dim3(256), 0, s, M, N, K, alpha, A, lda, sA, (int)ta,
+                           (const float*)B, ldb, sB, (int)tb, beta, C, ldc, sC, (int)tc);
+        break;
+      case CPD_BF16:
+        hipLaunchKernelGGL(gemm_small_kernel<uint16_t>, g2, dim3(256), 0, s, M, N, K, alpha, A, lda, sA,
+                           (int)ta, (const uint16_t*)B, ldb, sB, (int)tb, beta, C, ldc, sC, (int)tc);
+        break;
+      default:
+        set_error("gemm_f64: bad dtype %d", bdtype);
+        return CPD_E_INVALID;
+    }
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
   }
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
   if (grid.y > 65535 || grid.z > 65535) {
