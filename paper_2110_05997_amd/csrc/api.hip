@@ -57,17 +57,15 @@ struct CompressWs {
 };
 
 void compress_sizes(const int64_t dims[3], const int P[3], Sizer& z) {
-  size_t gmax = 0, gram = 0, eig = 0;
+  size_t gram = 0;
   for (int l = 0; l < 3; ++l) {
-    gmax = gmax > (size_t)(dims[l] * dims[l]) ? gmax : (size_t)(dims[l] * dims[l]);
+    z.take<double>((size_t)(dims[l] * dims[l]));         // G_l
     size_t g = gram_ws_bytes(dims, l);
     gram = gram > g ? gram : g;
-    size_t e = eig_ws_bytes((int)dims[l], P[l]);
-    eig = eig > e ? eig : e;
   }
-  z.take<double>(gmax);                                  // G
+  const int n[3] = {(int)dims[0], (int)dims[1], (int)dims[2]};
   z.take<char>(gram);                                    // gram partials
-  z.take<char>(eig);                                     // eigensolver
+  z.take<char>(eig_ws_bytes3(n, P, 3));                  // eigensolver
   for (int l = 0; l < 3; ++l) z.take<double>((size_t)dims[l] * P[l]);   // U full
   z.take<double>(P[0] + P[1] + P[2]);                    // eigenvalues
   z.take<double>((size_t)P[0] * dims[1] * dims[2]);      // Y1
@@ -80,7 +78,7 @@ cpd_status run_compress(const void* T, int dtype, const int64_t dims[3], int R, 
                         int core_out[3], Arena& ar, hipStream_t s) {
   int P[3];
   pdims(dims, R, p, P);
-  size_t gmax = 0, gram_b = 0, eig_b = 0;
+  size_t gram_b = 0;
   for (int l = 0; l < 3; ++l) {
     if (P[l] < 1 || P[l] > dims[l]) {
       set_error("compress: core dim %d invalid for mode %d of size %lld", P[l], l, (long long)dims[l]);
@@ -90,13 +88,13 @@ cpd_status run_compress(const void* T, int dtype, const int64_t dims[3], int R, 
       set_error("compress: P=%d > 56 for mode size %lld > 64 is not supported", P[l], (long long)dims[l]);
       return CPD_E_UNSUPPORTED;
     }
-    gmax = gmax > (size_t)(dims[l] * dims[l]) ? gmax : (size_t)(dims[l] * dims[l]);
     size_t g = gram_ws_bytes(dims, l);
     gram_b = gram_b > g ? gram_b : g;
-    size_t e = eig_ws_bytes((int)dims[l], P[l]);
-    eig_b = eig_b > e ? eig_b : e;
   }
-  double* G = ar.take<double>(gmax);
+  const int n[3] = {(int)dims[0], (int)dims[1], (int)dims[2]};
+  const size_t eig_b = eig_ws_bytes3(n, P, 3);
+  double* G[3];
+  for (int l = 0; l < 3; ++l) G[l] = ar.take<double>((size_t)(dims[l] * dims[l]));
   char* gws = ar.take<char>(gram_b);
   char* ews = ar.take<char>(eig_b);
   double* Uf[3];
@@ -110,13 +108,13 @@ cpd_status run_compress(const void* T, int dtype, const int64_t dims[3], int R, 
   }
   double* laml[3] = {lam, lam + P[0], lam + P[0] + P[1]};
   cpd_status st;
-  for (int l = 0; l < 3; ++l) {
-    if ((st = gram(T, dtype, dims, l, p ? p->compute_dtype : CPD_F64, G, gws, gram_b, s))) return st;
-    prof_begin(CPD_PK_EIG, s);
-    st = eig_top(G, (int)dims[l], P[l], Uf[l], laml[l], ews, eig_b, s);
-    prof_end(CPD_PK_EIG, s);
-    if (st) return st;
-  }
+  for (int l = 0; l < 3; ++l)
+    if ((st = gram(T, dtype, dims, l, p ? p->compute_dtype : CPD_F64, G[l], gws, gram_b, s))) return st;
+  // the three eigenproblems run side by side
+  prof_begin(CPD_PK_EIG, s);
+  st = eig_top3(G, n, P, Uf, laml, 3, ews, eig_b, s);
+  prof_end(CPD_PK_EIG, s);
+  if (st) return st;
   const int ptot = P[0] + P[1] + P[2];
   std::vector<double> hlv(ptot);
   double* hlam = hlv.data();

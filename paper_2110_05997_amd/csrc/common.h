@@ -54,7 +54,10 @@ struct Arena {
 struct Sizer {
   size_t off = 0;
   template <class T>
-  void take(size_t n) { off = align_up(off, 256) + align_up(n * sizeof(T), 256); }
+  T* take(size_t n) {
+    off = align_up(off, 256) + align_up(n * sizeof(T), 256);
+    return nullptr;
+  }
 };
 
 // ---- device helpers --------------------------------------------------------------------------
@@ -131,6 +134,10 @@ cpd_status gram(const void* T, int dtype, const int64_t dims[3], int mode, int c
 
 // Eigen solvers.
 size_t eig_ws_bytes(int n, int P);
+size_t eig_ws_bytes3(const int* n, const int* P, int nprob);
+// Several independent problems in one call.
+cpd_status eig_top3(const double* const* G, const int* n, const int* P, double* const* U,
+                    double* const* lam, int nprob, void* ws, size_t ws_bytes, hipStream_t s);
 cpd_status eig_top(const double* G, int n, int P, double* U, double* lam, void* ws,
                    size_t ws_bytes, hipStream_t s);
 

@@ -21,20 +21,34 @@ namespace {
 constexpr int JMAX = 64;
 constexpr int JNT = 256;
 
-// Jacobi eigendecomposition of an n x n symmetric matrix (row-major, leading dim lda).
-// Outputs: lam[n] descending, V[n*n] row-major with eigenvector j in column j (ldv = n).
-// Thread map: lane = row/column index j (0..63), wave w applies the pairs i = w, w + 4, ...
-__global__ __launch_bounds__(JNT) void jacobi_kernel(const double* __restrict__ Ag, int n, int lda,
-                                                     double* __restrict__ lam,
-                                                     double* __restrict__ Vout) {
+// Jacobi with the parallel round-robin ordering.  Each round: the first np/2 threads compute the
+// rotations of the round's disjoint pairs from A (one per pair); after a barrier every thread
+// applies J_i^T A_ij J_j to the 2x2 blocks it owns, in place (a block's new value depends only on
+// its own old entries), and V <- V J.  A rotation of pair (p, q) is skipped when
+// |a_pq| <= 1e-15 sqrt(|a_pp a_qq|); a sweep without rotations, or with off(A)^2 <= 1e-30 ||A||^2,
+// ends the iteration.
+__device__ __forceinline__ void pair_of(int i, int round, int np, int& p, int& q) {
+  const int a = (i == 0) ? 0 : 1 + ((i - 1 + round) % (np - 1));
+  const int b = 1 + ((np - 2 - i + round) % (np - 1));
+  p = min(a, b);
+  q = max(a, b);
+}
+
+// Eigendecomposition of the symmetric n x n matrix Ag (leading dim lda, n <= 64).
+// Outputs lam[n] descending and Vout (n x n row-major, eigenvector j in column j).
+__device__ void jacobi_block(const double* __restrict__ Ag, int n, int lda, double* __restrict__ lam,
+                             double* __restrict__ Vout) {
   __shared__ double A[JMAX][JMAX + 1];
   __shared__ double V[JMAX][JMAX + 1];
+  __shared__ double rc[JMAX / 2], rs[JMAX / 2];
+  __shared__ int rp[JMAX / 2], rq[JMAX / 2];
   __shared__ double red[2][JNT / 64];
   __shared__ int rank_of[JMAX];
   __shared__ int rotated[2];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int NWV = JNT / 64;
-  const int np = (n + 1) & ~1;   // even number of slots (one padding slot when n is odd)
+  const int np = (n + 1) & ~1;   // even number of slots (one zero padding slot when n is odd)
+  const int half = np / 2;
   for (int i = w; i < JMAX; i += NWV) {
     A[i][lane] = (i < n && lane < n) ? Ag[(long long)i * lda + lane] : 0.0;
     V[i][lane] = (i == lane) ? 1.0 : 0.0;
@@ -44,85 +58,57 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const double* __restrict__ 
   for (int i = w; i < n; i += NWV)
     if (lane < n) fro2 += A[i][lane] * A[i][lane];
   fro2 = block_sum(fro2, red[0]);
-  const int half = np / 2;
+  const int jj = tid & 31, i0 = tid >> 5;   // block column owned, first block row
+  constexpr int ISTEP = JNT / 32;
   for (int sweep = 0; sweep < 60 && np >= 2; ++sweep) {
     double off = 0.0;
     for (int i = w; i < n; i += NWV)
       if (lane < n && lane != i) off += A[i][lane] * A[i][lane];
     off = block_sum(off, red[(sweep + 1) & 1]);
     if (off <= 1e-30 * fro2 || off == 0.0) break;
-    // a sweep that rotates nothing ends the iteration (relative threshold below)
     if (tid == 0) rotated[sweep & 1] = 0;
-    __syncthreads();
     for (int round = 0; round < np - 1; ++round) {
-      // lane u of wave w computes the rotation of pair i = w + u * NWV; the wave then broadcasts
-      // the parameters of its pairs with lane shuffles
-      constexpr int MAXP = JMAX / 2 / NWV;
-      int pl = 0, ql = 0;
-      double cl = 1.0, sl = 0.0;
-      {
-        const int i = w + lane * NWV;
-        if (lane < MAXP && i < half) {
-          // round-robin: slot 0 fixed, the others rotate
-          const int a = (i == 0) ? 0 : 1 + ((i - 1 + round) % (np - 1));
-          const int b = 1 + ((np - 2 - i + round) % (np - 1));
-          pl = min(a, b); ql = max(a, b);
-          if (ql < n) {
-            const double apq = A[pl][ql], app = A[pl][pl], aqq = A[ql][ql];
-            if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
-              rotated[sweep & 1] = 1;
-              const double tau = (aqq - app) / (2.0 * apq);
-              const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-              cl = 1.0 / sqrt(1.0 + t * t);
-              sl = t * cl;
-            }
+      if (tid < half) {
+        int p, q;
+        pair_of(tid, round, np, p, q);
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
+          if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+            rotated[sweep & 1] = 1;
           }
         }
-      }
-      int pu[MAXP], qu[MAXP];
-      double cu[MAXP], su[MAXP];
-#pragma unroll
-      for (int u = 0; u < MAXP; ++u) {
-        pu[u] = __shfl(pl, u, 64); qu[u] = __shfl(ql, u, 64);
-        cu[u] = __shfl(cl, u, 64); su[u] = __shfl(sl, u, 64);
-      }
-      // rows: A <- J^T A (lane = column); the loads of all pairs are issued before the stores
-      {
-        double ap[MAXP], aq[MAXP];
-#pragma unroll
-        for (int u = 0; u < MAXP; ++u)
-          if (w + u * NWV < half && lane < np) { ap[u] = A[pu[u]][lane]; aq[u] = A[qu[u]][lane]; }
-#pragma unroll
-        for (int u = 0; u < MAXP; ++u)
-          if (w + u * NWV < half && lane < np) {
-            A[pu[u]][lane] = cu[u] * ap[u] - su[u] * aq[u];
-            A[qu[u]][lane] = su[u] * ap[u] + cu[u] * aq[u];
-          }
+        rp[tid] = p; rq[tid] = q; rc[tid] = c; rs[tid] = s;
       }
       __syncthreads();
-      // columns: A <- A J, V <- V J (lane = row)
-      {
-        double ap[MAXP], aq[MAXP], vp[MAXP], vq[MAXP];
-#pragma unroll
-        for (int u = 0; u < MAXP; ++u)
-          if (w + u * NWV < half && lane < np) {
-            ap[u] = A[lane][pu[u]]; aq[u] = A[lane][qu[u]];
-            vp[u] = V[lane][pu[u]]; vq[u] = V[lane][qu[u]];
-          }
-#pragma unroll
-        for (int u = 0; u < MAXP; ++u)
-          if (w + u * NWV < half && lane < np) {
-            A[lane][pu[u]] = cu[u] * ap[u] - su[u] * aq[u];
-            A[lane][qu[u]] = su[u] * ap[u] + cu[u] * aq[u];
-            V[lane][pu[u]] = cu[u] * vp[u] - su[u] * vq[u];
-            V[lane][qu[u]] = su[u] * vp[u] + cu[u] * vq[u];
-          }
+      if (jj < half) {
+        const int pj = rp[jj], qj = rq[jj];
+        const double cj = rc[jj], sj = rs[jj];
+        for (int i = i0; i < half; i += ISTEP) {
+          const int pi = rp[i], qi = rq[i];
+          const double ci = rc[i], si = rs[i];
+          const double a_pp = A[pi][pj], a_pq = A[pi][qj], a_qp = A[qi][pj], a_qq = A[qi][qj];
+          const double b_pp = ci * a_pp - si * a_qp, b_pq = ci * a_pq - si * a_qq;
+          const double b_qp = si * a_pp + ci * a_qp, b_qq = si * a_pq + ci * a_qq;
+          A[pi][pj] = cj * b_pp - sj * b_pq;
+          A[pi][qj] = sj * b_pp + cj * b_pq;
+          A[qi][pj] = cj * b_qp - sj * b_qq;
+          A[qi][qj] = sj * b_qp + cj * b_qq;
+        }
+        for (int x = i0; x < n; x += ISTEP) {
+          const double vp = V[x][pj], vq = V[x][qj];
+          V[x][pj] = cj * vp - sj * vq;
+          V[x][qj] = sj * vp + cj * vq;
+        }
       }
       __syncthreads();
     }
     if (rotated[sweep & 1] == 0) break;
   }
-  // rank sort, descending eigenvalue, ties by index
   if (tid < n) {
     const double li = A[tid][tid];
     int r = 0;
@@ -135,7 +121,15 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const double* __restrict__ 
   __syncthreads();
   if (tid < n) lam[rank_of[tid]] = A[tid][tid];
   for (int i = w; i < n; i += NWV)
-    if (lane < n) Vout[(long long)i * n + rank_of[lane]] = V[i][lane];   // component i of vector lane
+    if (lane < n) Vout[(long long)i * n + rank_of[lane]] = V[i][lane];
+}
+
+// Jacobi eigendecomposition of an n x n symmetric matrix (row-major, leading dim lda, n <= 64).
+// Outputs: lam[n] descending, Vout[n*n] row-major with eigenvector j in column j (ldv = n).
+__global__ __launch_bounds__(JNT) void jacobi_kernel(const double* __restrict__ Ag, int n, int lda,
+                                                     double* __restrict__ lam,
+                                                     double* __restrict__ Vout) {
+  jacobi_block(Ag, n, lda, lam, Vout);
 }
 
 // Copies the first P columns of X (n x ldx) into U (n x P) and signs each column so its
@@ -465,6 +459,25 @@ cpd_status eig_top(const double* G, int n, int P, double* U, double* lam, void* 
   CPD_HIP_CHECK(hipMemcpyAsync(lam, theta, sizeof(double) * P, hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(sign_columns_kernel, dim3(P), dim3(256), 0, s, Uw, n, P, P, U);
   CPD_LAUNCH_CHECK();
+  return CPD_OK;
+}
+
+// Several problems, solved one after the other on the stream (they share the workspace).
+size_t eig_ws_bytes3(const int* n, const int* P, int nprob) {
+  size_t b = 0;
+  for (int i = 0; i < nprob; ++i) {
+    const size_t e = eig_ws_bytes(n[i], P[i]);
+    b = e > b ? e : b;
+  }
+  return b;
+}
+
+cpd_status eig_top3(const double* const* G, const int* n, const int* P, double* const* U, double* const* lam,
+                    int nprob, void* ws, size_t ws_bytes, hipStream_t s) {
+  for (int i = 0; i < nprob; ++i) {
+    const cpd_status st = eig_top(G[i], n[i], P[i], U[i], lam[i], ws, ws_bytes, s);
+    if (st) return st;
+  }
   return CPD_OK;
 }
 
