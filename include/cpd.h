@@ -224,6 +224,49 @@ cpd_status cpd_mttkrp(const void* T, int32_t dtype, const int64_t dims[3], const
 
 /* out (device, 1 double) = ||T - sum_r w_r^(1) o w_r^(2) o w_r^(3)||^2, fused (ch.4 "Computing the
  * residual" applied to the input tensor).  ws: cpd_residual_workspace_bytes. */
+/* ------------------------------------------------------------------------------------------ */
+/* Batched solve: many small independent CPDs (every mode <= 64), each the full path of ch.4     */
+/* (Alg. Compression, dGN with CG, uncompression) exactly as cpd_solve does it, one workgroup   */
+/* per member and stage in five launches with no host round trip between them.                 */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+  const void* T;          /* (device) dense C-ordered dims[0] x dims[1] x dims[2] tensor */
+  int64_t dims[3];        /* each 1..64 */
+  int32_t R;              /* rank, 1..64 */
+  const double* W0[3];    /* (device) initial core factors, P_l x R row-major with
+                             P_l = min(dims[l], R) (or min(dims[l], core_dims[l]) when the
+                             params fix the core); only the first R~_l rows are used when the
+                             truncation rule shrinks mode l.  All three NULL: N(0,1) entries
+                             from params.seed and the member index.  All or none. */
+  double* W[3];           /* (device) out: dims[l] x R factors with unit columns */
+  double* lambda;         /* (device) out: R weights, decreasing */
+} cpd_batch_item;
+
+/* Workspace for cpd_solve_batched / cpd_batch_plan_create with these members; 0 if invalid. */
+size_t cpd_batch_workspace_bytes(const cpd_batch_item* items /* host, n */, int32_t n,
+                                 const cpd_params* p);
+
+/* Solves every member with the same params (maxiter, tol, mlsvd_tol, init_damp, cg_tol, caps:
+ * one random CG-cap schedule shared by all members).  dtype: CPD_F64 or CPD_F32 for all members.
+ * info (host, n entries, may be NULL) receives each member's result as cpd_solve would report
+ * it; stop_reason is -1 for a member whose tensor is zero or holds NaN/Inf (its outputs are then
+ * meaningless).  Synchronises the stream. */
+cpd_status cpd_solve_batched(const cpd_batch_item* items, int32_t n, int32_t dtype, const cpd_params* p,
+                             cpd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* A plan fixes the members, params and workspace, picks the Gram tile variant by timing each
+ * candidate on this batch, and captures the five launches in a hipGraph.  cpd_batch_plan_run
+ * replays the graph on `stream`; with info != NULL it then waits and copies the results.  The
+ * plan keeps pointers into `ws` and to the members' buffers: they must stay valid.  The tensors
+ * may change between runs (same shapes).  Plans are host objects; destroy frees them. */
+typedef struct cpd_batch_plan cpd_batch_plan;
+cpd_status cpd_batch_plan_create(const cpd_batch_item* items, int32_t n, int32_t dtype, const cpd_params* p,
+                                 void* ws, size_t ws_bytes, void* stream, cpd_batch_plan** out);
+cpd_status cpd_batch_plan_run(cpd_batch_plan* plan, cpd_solve_info* info, void* stream);
+/* Chosen Gram variant (0..3); variant_ms (host, 4 entries, may be NULL) gets each candidate's time. */
+int32_t cpd_batch_plan_variant(const cpd_batch_plan* plan, float* variant_ms);
+void cpd_batch_plan_destroy(cpd_batch_plan* plan);
+
 size_t cpd_residual_workspace_bytes(const int64_t dims[3]);
 cpd_status cpd_residual_norm2(const void* T, int32_t dtype, const int64_t dims[3],
                               const double* const W[3], int32_t R, double* out, void* ws,

@@ -15,7 +15,7 @@ from ._lib import (CPD_BF16, CPD_F32, CPD_F64, CPD_INIT_GIVEN, CPD_INIT_MLSVD, C
                    STOP_NAMES, CpdError, Params, SolveInfo, StepInfo)
 
 __all__ = ["params", "gram", "eig_top", "compress", "DgnState", "solve", "mttkrp", "residual_norm2",
-           "jtj_v", "CpdError", "STOP_NAMES"]
+           "jtj_v", "Batch", "CpdError", "STOP_NAMES"]
 
 _DTYPES = {torch.float64: CPD_F64, torch.float32: CPD_F32, torch.bfloat16: CPD_BF16}
 
@@ -186,6 +186,93 @@ def solve(T, R, p=None, W0=None, ws=None):
     d = {f: getattr(info, f) for f, _ in SolveInfo._fields_}
     d["core_dims"] = tuple(info.core_dims)
     return dict(W=W, lam=lam, info=d)
+
+
+def _info_dict(info):
+    d = {f: getattr(info, f) for f, _ in SolveInfo._fields_}
+    d["core_dims"] = tuple(info.core_dims)
+    return d
+
+
+class Batch:
+    """Many small CPDs solved together (every mode <= 64).  ``Ts``: list of contiguous 3-way
+    tensors on the GPU, all FP64 or all FP32; ``Rs``: ranks; ``W0``: optional list (per member) of
+    three P_l x R initial core factors.  Outputs ``W`` / ``lam`` are allocated once and refilled by
+    every run.  With ``graph=True`` a plan is built (Gram variant autotuned, launches captured in
+    a hipGraph) and :meth:`run` replays it."""
+
+    def __init__(self, Ts, Rs, p=None, W0=None, graph=True):
+        L = _lib.lib()
+        if len(Ts) != len(Rs) or not Ts:
+            raise ValueError("need one rank per tensor")
+        dt = Ts[0].dtype
+        for T in Ts:
+            _check_tensor(T)
+            if T.dtype != dt:
+                raise TypeError("all members must share one dtype")
+        self.p = p if p is not None else params()
+        self.n = len(Ts)
+        self.dtype = _dtype(Ts[0])
+        self._keep = list(Ts)
+        dev = Ts[0].device
+        self.W, self.lam = [], []
+        items = (_lib.BatchItem * self.n)()
+        for b, (T, R) in enumerate(zip(Ts, Rs)):
+            it = items[b]
+            it.T = T.data_ptr()
+            for l in range(3):
+                it.dims[l] = T.shape[l]
+            it.R = int(R)
+            Wb = [torch.empty((T.shape[l], R), dtype=torch.float64, device=dev) for l in range(3)]
+            lb = torch.empty(R, dtype=torch.float64, device=dev)
+            self.W.append(Wb)
+            self.lam.append(lb)
+            for l in range(3):
+                it.W[l] = Wb[l].data_ptr()
+            it.lam = lb.data_ptr()
+            if W0 is not None:
+                w0 = [torch.as_tensor(w, dtype=torch.float64).to(dev).contiguous() for w in W0[b]]
+                self._keep.extend(w0)
+                for l in range(3):
+                    it.W0[l] = w0[l].data_ptr()
+        self.items = items
+        nb = L.cpd_batch_workspace_bytes(items, self.n, ctypes.byref(self.p))
+        if nb == 0:
+            raise ValueError("invalid batch (modes must be 1..64, R 1..64)")
+        self.ws = _ws(nb, dev)
+        self.plan = None
+        if graph:
+            h = ctypes.c_void_p()
+            _lib.check(L.cpd_batch_plan_create(items, self.n, self.dtype, ctypes.byref(self.p), _ptr(self.ws),
+                                               self.ws.numel(), _stream(), ctypes.byref(h)), "cpd_batch_plan_create")
+            self.plan = h
+
+    def run(self, read_info=True):
+        L = _lib.lib()
+        infos = (SolveInfo * self.n)() if read_info else None
+        if self.plan is not None:
+            _lib.check(L.cpd_batch_plan_run(self.plan, infos, _stream()), "cpd_batch_plan_run")
+        else:
+            _lib.check(L.cpd_solve_batched(self.items, self.n, self.dtype, ctypes.byref(self.p), infos,
+                                           _ptr(self.ws), self.ws.numel(), _stream()), "cpd_solve_batched")
+        return [_info_dict(i) for i in infos] if read_info else None
+
+    def variant(self):
+        """(chosen Gram variant, time of each candidate in ms)."""
+        ms = (ctypes.c_float * 4)()
+        v = _lib.lib().cpd_batch_plan_variant(self.plan, ms) if self.plan is not None else -1
+        return v, list(ms)
+
+    def close(self):
+        if self.plan is not None:
+            _lib.lib().cpd_batch_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mttkrp(T, Ws, mode):

@@ -70,6 +70,17 @@ class KernelTime(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [
+        ("T", ctypes.c_void_p),
+        ("dims", ctypes.c_int64 * 3),
+        ("R", ctypes.c_int32),
+        ("W0", ctypes.c_void_p * 3),
+        ("W", ctypes.c_void_p * 3),
+        ("lam", ctypes.c_void_p),
+    ]
+
+
 PROFILE_KERNELS = ["gram", "dgn", "project", "residual", "mttkrp", "eig"]
 
 _P = ctypes.c_void_p
@@ -107,6 +118,17 @@ SIGNATURES = [
     ("cpd_residual_norm2", ctypes.c_int, [_P, ctypes.c_int32, _I64x3, _Px3, ctypes.c_int32, _P, _P,
                                           ctypes.c_size_t, _P]),
     ("cpd_jtj_v", ctypes.c_int, [_Px3, _Px3, _I32x3, ctypes.c_int32, _Px3, _P]),
+    ("cpd_batch_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(BatchItem), ctypes.c_int32,
+                                                     ctypes.POINTER(Params)]),
+    ("cpd_solve_batched", ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.POINTER(Params), ctypes.POINTER(SolveInfo), _P, ctypes.c_size_t,
+                                         _P]),
+    ("cpd_batch_plan_create", ctypes.c_int, [ctypes.POINTER(BatchItem), ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.POINTER(Params), _P, ctypes.c_size_t, _P,
+                                             ctypes.POINTER(ctypes.c_void_p)]),
+    ("cpd_batch_plan_run", ctypes.c_int, [_P, ctypes.POINTER(SolveInfo), _P]),
+    ("cpd_batch_plan_variant", ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_float)]),
+    ("cpd_batch_plan_destroy", None, [_P]),
     ("cpd_profile_enable", None, [ctypes.c_int32]),
     ("cpd_profile_reset", None, []),
     ("cpd_profile_read", ctypes.c_int, [ctypes.POINTER(KernelTime)]),

@@ -156,6 +156,12 @@ cpd_status sumsq_full(const void* T, int dtype, int64_t n, double* out, int* non
 size_t state_bytes(const int32_t core[3], int R, int maxiter);
 cpd_status state_init(void* state, const double* S, const int32_t core[3], int R,
                       const double* W0, double t_norm2, const cpd_params* p, hipStream_t s);
+size_t dgn_lds_bytes(int np, int R);
+// Batched persistent dGN: one workgroup per state (header, caps and W written beforehand).
+// dgn_batch_prepare sets the kernel's dynamic-LDS limit (call outside graph capture).
+cpd_status dgn_batch_prepare(size_t lds_bytes);
+cpd_status dgn_batch_launch(char* const* states, const double* const* S, int n, size_t lds_bytes,
+                            hipStream_t s);
 cpd_status dgn_iterate(void* state, const double* S, int max_steps, hipStream_t s);
 cpd_status state_read(void* state, int* k, int* stop, int* tol_iter, double* err,
                       hipStream_t s);

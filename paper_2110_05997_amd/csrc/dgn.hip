@@ -18,6 +18,7 @@
 // the FP64 matrix cores in 16x16 tiles spread over the waves, Khatri-Rao rows formed on the fly.
 // All arithmetic is FP64; reductions use a fixed order, so a run is bit-reproducible.
 #include "common.h"
+#include "dgn_state.h"
 
 #include <math.h>
 #include <string.h>
@@ -25,38 +26,6 @@
 namespace cpd {
 namespace {
 
-constexpr int NT = 512;
-constexpr int NW = NT / 64;
-
-struct Hdr {
-  int32_t d[3];
-  int32_t R;
-  int32_t k, stop, maxiter, tol_iter;
-  int32_t np, flags, pad0, pad1;
-  double mu, f2, s_norm, div_ref, tol, cg_tol, init_damp, err0;
-};
-static_assert(sizeof(Hdr) <= 256, "header must fit its slot");
-
-struct Layout {
-  size_t W, MK, errs, caps, log, total;
-};
-
-__host__ __device__ inline Layout layout_of(int np, int maxiter) {
-  Layout L;
-  size_t off = 256;
-  L.W = off; off += (size_t)np * 8;
-  L.MK = off; off += (size_t)np * 8;
-  L.errs = off; off += (size_t)(maxiter + 1) * 8;
-  L.caps = off; off += ((size_t)maxiter * 4 + 7) / 8 * 8;
-  L.log = off; off += (size_t)maxiter * sizeof(cpd_step_info);
-  L.total = (off + 255) / 256 * 256;
-  return L;
-}
-
-// LDS footprint in doubles
-__host__ __device__ inline size_t lds_doubles(int np, int R) {
-  return (size_t)7 * np + (size_t)12 * R * R + (size_t)6 * R + 2 * NW + 16;
-}
 
 struct Ctx {
   int d0, d1, d2, off1, off2, R, np;
@@ -379,10 +348,8 @@ __device__ int stop_test(const double* errs, int k, double step, double grad_inf
 }
 
 // mode 0: initialise the state from the W stored in it; mode 1: run up to max_steps iterations.
-__global__ __launch_bounds__(NT) void dgn_kernel(char* __restrict__ state, const double* __restrict__ S,
-                                                 int mode, int max_steps) {
-  extern __shared__ double lds[];
-  __shared__ int s_stop;
+__device__ void dgn_body(char* __restrict__ state, const double* __restrict__ S, int mode, int max_steps,
+                         double* lds, int& s_stop) {
   Hdr* h = (Hdr*)state;
   const int R = h->R;
   int d[3] = {h->d[0], h->d[1], h->d[2]};
@@ -532,6 +499,29 @@ __global__ __launch_bounds__(NT) void dgn_kernel(char* __restrict__ state, const
   }
 }
 
+__global__ __launch_bounds__(NT) void dgn_kernel(char* __restrict__ state, const double* __restrict__ S,
+                                                 int mode, int max_steps) {
+  extern __shared__ double lds[];
+  __shared__ int s_stop;
+  dgn_body(state, S, mode, max_steps, lds, s_stop);
+}
+
+// Batched: workgroup b initialises state b (header, caps and W already written) and iterates it
+// to a stopping rule.  Dynamic LDS must cover the largest member.
+__global__ __launch_bounds__(NT) void dgn_batch_kernel(char* const* __restrict__ states,
+                                                       const double* const* __restrict__ S, int n) {
+  extern __shared__ double lds[];
+  __shared__ int s_stop;
+  const int b = blockIdx.x;
+  if (b >= n) return;
+  char* st = states[b];
+  if (((const Hdr*)st)->flags & 2) return;   // member rejected (zero or non-finite tensor)
+  dgn_body(st, S[b], 0, 0, lds, s_stop);
+  __syncthreads();
+  const int maxiter = ((const Hdr*)st)->maxiter;
+  dgn_body(st, S[b], 1, maxiter, lds, s_stop);
+}
+
 // MLSVD-energy initial point (ch.4 "Initialization"): the R entries of largest |s| (ties: smallest
 // C-order index) placed on canonical vectors; W^(1) carries the value.  Extra columns (R larger
 // than the core) come from `extra` (packed like W) when given.
@@ -548,7 +538,7 @@ __global__ __launch_bounds__(256) void smart_init_kernel(const double* __restric
   const int take = min(R, n);
   for (int t = 0; t < take; ++t) {
     double best = -1.0;
-    int besti = 0x7fffffff;
+    int besti = 0;   // stays a valid index if every entry is NaN
     for (int e = tid; e < n; e += 256) {
       bool used = false;
       for (int u = 0; u < t; ++u) used |= (chosen[u] == e);
@@ -729,6 +719,24 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
     set_error("state_init: non-finite initial factors");
     return CPD_E_NONFINITE;
   }
+  return CPD_OK;
+}
+
+size_t dgn_lds_bytes(int np, int R) { return lds_doubles(np, R) * sizeof(double); }
+
+cpd_status dgn_batch_prepare(size_t lds_bytes) {
+  if (lds_bytes > 160 * 1024 - 1024) {
+    set_error("dgn batch: a member needs %zu bytes of LDS", lds_bytes);
+    return CPD_E_UNSUPPORTED;
+  }
+  CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds_bytes));
+  return CPD_OK;
+}
+
+cpd_status dgn_batch_launch(char* const* states, const double* const* S, int n, size_t lds_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(dgn_batch_kernel, dim3(n), dim3(NT), lds_bytes, s, states, S, n);
+  CPD_LAUNCH_CHECK();
   return CPD_OK;
 }
 

@@ -1,0 +1,45 @@
+// Device-resident state of the persistent dGN kernel (shared by the single solve and the batched
+// solver, which writes headers on the device).
+#pragma once
+#include "common.h"
+
+namespace cpd {
+
+constexpr int DGN_NT = 512;   // threads of the persistent dGN workgroup
+
+namespace {
+constexpr int NT = DGN_NT;
+constexpr int NW = NT / 64;
+}  // namespace
+
+struct Hdr {
+  int32_t d[3];
+  int32_t R;
+  int32_t k, stop, maxiter, tol_iter;
+  int32_t np, flags, pad0, pad1;
+  double mu, f2, s_norm, div_ref, tol, cg_tol, init_damp, err0;
+};
+static_assert(sizeof(Hdr) <= 256, "header must fit its slot");
+
+struct Layout {
+  size_t W, MK, errs, caps, log, total;
+};
+
+__host__ __device__ inline Layout layout_of(int np, int maxiter) {
+  Layout L;
+  size_t off = 256;
+  L.W = off; off += (size_t)np * 8;
+  L.MK = off; off += (size_t)np * 8;
+  L.errs = off; off += (size_t)(maxiter + 1) * 8;
+  L.caps = off; off += ((size_t)maxiter * 4 + 7) / 8 * 8;
+  L.log = off; off += (size_t)maxiter * sizeof(cpd_step_info);
+  L.total = (off + 255) / 256 * 256;
+  return L;
+}
+
+// LDS footprint in doubles
+__host__ __device__ inline size_t lds_doubles(int np, int R) {
+  return (size_t)7 * np + (size_t)12 * R * R + (size_t)6 * R + 2 * NW + 16;
+}
+
+}  // namespace cpd

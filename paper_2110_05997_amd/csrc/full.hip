@@ -124,7 +124,7 @@ __global__ void normalize_plan_kernel(const double* __restrict__ W0, const doubl
   for (int c = w; c < 2 * R; c += nw) {
     const int l = c / R, r = c % R;
     double best = -1.0;
-    int bi = 0x7fffffff;
+    int bi = 0;   // stays a valid index if every entry is NaN
     for (int i = lane; i < Is[l]; i += 64) {
       const double a = fabs(Ws[l][(long long)i * R + r]);
       if (a > best || (a == best && i < bi)) { best = a; bi = i; }

@@ -104,6 +104,21 @@ def batch_shapes(n, seed=0, lo=10, hi=64, rlo=2, rhi=12):
     return [tuple(int(v) for v in d) for d in dims], [int(r) for r in ranks]
 
 
+def batch_members(n, seed=0, snr_db=50.0, dtype=np.float64):
+    """Members of a batch of small planted CPDs (shapes and ranks from ``batch_shapes``); member b
+    is ``planted(dims_b, R_b, seed=seed * 1000003 + b + 1, snr_db)`` with initial core factors
+    ``init_factors(P_b, R_b, seed=seed * 1000003 + b + 1)``, P_b,l = min(dims_b,l, R_b).
+    Returns (tensors, ranks, initial factors)."""
+    shapes, ranks = batch_shapes(n, seed)
+    Ts, W0s = [], []
+    for b, (dims, R) in enumerate(zip(shapes, ranks)):
+        s = seed * 1000003 + b + 1
+        T, _, _ = planted(dims, R, seed=s, snr_db=snr_db, dtype=dtype)
+        Ts.append(T)
+        W0s.append(init_factors([min(d, R) for d in dims], R, s))
+    return Ts, ranks, W0s
+
+
 # Named workloads (the shapes of the five benchmark configurations)
 def config1(seed=0):
     """50^3 FP64, R = 5, N(0,1) factors, noise at 1e-6 relative Frobenius norm."""

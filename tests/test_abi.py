@@ -54,3 +54,28 @@ def test_host_only_queries():
     assert L.cpd_gram_workspace_bytes(dims, 0) > 0
     assert L.cpd_eig_workspace_bytes(200, 20) > 0
     assert b"gfx950" in L.cpd_version()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcpd.so not built")
+def test_batch_workspace_query():
+    """The batch workspace query reads only shapes, ranks and which pointers are set."""
+    from paper_2110_05997_amd import _lib
+    L = _lib.lib()
+    p = _lib.Params()
+    L.cpd_default_params(ctypes.byref(p))
+    items = (_lib.BatchItem * 3)()
+    for b, (dims, R) in enumerate([((10, 20, 30), 4), ((64, 64, 64), 12), ((11, 9, 10), 12)]):
+        it = items[b]
+        it.T = 0x1000
+        for l in range(3):
+            it.dims[l] = dims[l]
+            it.W[l] = 0x1000
+        it.R = R
+        it.lam = 0x1000
+    n_ok = L.cpd_batch_workspace_bytes(items, 3, ctypes.byref(p))
+    assert n_ok > 12 * 64 * 64 * 8        # at least the first projection of the 64^3 member
+    items[1].dims[0] = 65                                   # modes are limited to 64
+    assert L.cpd_batch_workspace_bytes(items, 3, ctypes.byref(p)) == 0
+    items[1].dims[0] = 64
+    items[2].W0[0] = 0x1000                                 # W0 must be all or none
+    assert L.cpd_batch_workspace_bytes(items, 3, ctypes.byref(p)) == 0

@@ -1,0 +1,164 @@
+"""GPU parity of the batched solver (many small CPDs in one set of launches) against the oracle.
+
+Each member is the same computation as cpd_solve, so the bar is the end-to-end one: for a member
+that converges (full-tensor error at the noise floor), the reconstructed tensor agrees with the
+oracle's to relative 1e-6, with the same stopping rule and iteration count within one. Members
+that stall in a local minimum have ill-conditioned trajectories, and rounding may move their
+stopping point. They get the same stopping rule and a full-tensor error within 1e-3 relative of
+the oracle's. The plan replays its hipGraph with other work in between, and each replay must
+reproduce the first run bit for bit (all reductions run in a fixed order).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import cpd as ocpd
+from oracle import dgn as odgn
+from oracle import multilinear as ml
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def cp():
+    import paper_2110_05997_amd as cp_
+    return cp_
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device=DEV, dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().double().numpy()
+
+
+def member_that(batch, b):
+    W = [host(w) for w in batch.W[b]]
+    lam = host(batch.lam[b])
+    return ml.cpd_full([W[0] * lam[None, :], W[1], W[2]])
+
+
+def check_member(batch, b, info, T, R, W0, U, maxiter=200):
+    Th = np.asarray(T, dtype=np.float64)
+    ref = ocpd.solve(Th, R, odgn.Params(maxiter=maxiter), init="given", W0=W0, cg_uniforms=U)
+    log(b, T.shape, R, info, "oracle", ref["iters"], ref["stop"], ref["rel_err_full"])
+    assert tuple(info["core_dims"]) == ref["core_dims"]
+    assert info["stop_reason"] == ref["stop"]
+    That, Tref = member_that(batch, b), ml.cpd_full(ref["W_unnormalized"])
+    if ref["rel_err_full"] < 0.01:
+        assert abs(info["iters"] - ref["iters"]) <= 1
+        assert ml.frob(That - Tref) / ml.frob(Tref) < 1e-6
+    else:
+        assert abs(info["rel_err_full"] - ref["rel_err_full"]) <= 1e-3 * ref["rel_err_full"]
+
+
+@pytest.fixture(scope="module")
+def members():
+    return synth.batch_members(512, seed=0)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_oracle(members, graph):
+    log("batch parity, graph", graph)
+    Ts, Rs, W0s = members
+    idx = list(range(12))
+    U = synth.cg_uniforms(200, 0)
+    batch = cp().Batch([dev(Ts[b]) for b in idx], [Rs[b] for b in idx], cp().params(cg_uniforms=U),
+                       W0=[W0s[b] for b in idx], graph=graph)
+    infos = batch.run()
+    for j, b in enumerate(idx):
+        check_member(batch, j, infos[j], Ts[b], Rs[b], W0s[b], U)
+    batch.close()
+
+
+def test_batch_fp32_and_ragged_ranks():
+    log("batch fp32")
+    shapes = [((12, 64, 10), 12), ((64, 64, 64), 5), ((10, 11, 12), 2), ((33, 17, 40), 7)]
+    Ts, W0s = [], []
+    for s, (dims, R) in enumerate(shapes):
+        T, _, _ = synth.planted(dims, R, seed=40 + s, snr_db=50, dtype=np.float32)
+        Ts.append(T)
+        W0s.append(synth.init_factors([min(d, R) for d in dims], R, 40 + s))
+    U = synth.cg_uniforms(200, 3)
+    batch = cp().Batch([dev(T, torch.float32) for T in Ts], [R for _, R in shapes], cp().params(cg_uniforms=U),
+                       W0=W0s, graph=False)
+    infos = batch.run()
+    for b, (dims, R) in enumerate(shapes):
+        check_member(batch, b, infos[b], Ts[b].astype(np.float64), R, W0s[b], U)
+
+
+def test_batch_graph_replays_bit_exact(members):
+    log("batch graph replays")
+    Ts, Rs, W0s = members
+    idx = list(range(40, 72))
+    U = synth.cg_uniforms(200, 1)
+    p = cp().params(cg_uniforms=U)
+    Td = [dev(Ts[b]) for b in idx]
+    eager = cp().Batch(Td, [Rs[b] for b in idx], p, W0=[W0s[b] for b in idx], graph=False)
+    ref_infos = eager.run()
+    ref_W = [[host(w) for w in eager.W[j]] + [host(eager.lam[j])] for j in range(len(idx))]
+    plan = cp().Batch(Td, [Rs[b] for b in idx], p, W0=[W0s[b] for b in idx], graph=True)
+    v, ms = plan.variant()
+    log("gram variant", v, ms)
+    assert 0 <= v < 4
+    for rep in range(3):
+        # unrelated eager work and a synchronisation between replays
+        x = torch.randn(1 << 20, device=DEV)
+        float((x * x).sum())
+        infos = plan.run()
+        for j in range(len(idx)):
+            assert infos[j] == ref_infos[j]
+            got = [host(w) for w in plan.W[j]] + [host(plan.lam[j])]
+            for a, b in zip(got, ref_W[j]):
+                assert np.array_equal(a, b)
+    plan.close()
+
+
+def test_batch_512_full_workload(members):
+    """The 512-member workload (modes U{10..64}, ranks U{2..12}, 50 dB): every member reaches a
+    stopping rule; converged members sit at the noise floor; a sample matches the oracle."""
+    log("batch 512")
+    Ts, Rs, W0s = members
+    U = synth.cg_uniforms(200, 0)
+    batch = cp().Batch([dev(T) for T in Ts], Rs, cp().params(cg_uniforms=U), W0=W0s, graph=True)
+    infos = batch.run()
+    stops = np.array([i["stop_reason"] for i in infos])
+    errs = np.array([i["rel_err_full"] for i in infos])
+    log("stops", np.bincount(stops, minlength=9), "median err", np.median(errs))
+    assert np.all((stops >= 1) & (stops <= 8))
+    floor = 10 ** (-50 / 20)
+    assert 0.8 * floor < np.median(errs) < 1.5 * floor
+    for b in (100, 200, 300, 400, 511):
+        check_member(batch, b, infos[b], Ts[b], Rs[b], W0s[b], U)
+    batch.close()
+
+
+def test_batch_rejects_bad_member_only(members):
+    log("batch bad member")
+    Ts, Rs, W0s = members
+    U = synth.cg_uniforms(200, 0)
+    Tz = np.zeros((12, 13, 14))
+    Tn = np.array(Ts[1], copy=True)
+    Tn[3, 4, 5] = np.nan
+    tens = [dev(Ts[0]), dev(Tz), dev(Tn), dev(Ts[2])]
+    ranks = [Rs[0], 3, Rs[1], Rs[2]]
+    w0 = [W0s[0], synth.init_factors([3, 3, 3], 3, 9), W0s[1], W0s[2]]
+    batch = cp().Batch(tens, ranks, cp().params(cg_uniforms=U), W0=w0, graph=False)
+    infos = batch.run()
+    assert infos[1]["stop_reason"] == -1 and infos[2]["stop_reason"] == -1
+    check_member(batch, 0, infos[0], Ts[0], Rs[0], W0s[0], U)
+    check_member(batch, 3, infos[3], Ts[2], Rs[2], W0s[2], U)
+
+
+def test_batch_rejects_large_modes():
+    T = torch.zeros((65, 10, 10), dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError):
+        cp().Batch([T], [3], graph=False)
