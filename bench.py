@@ -180,6 +180,25 @@ def main():
         out["mttkrp_tflops"] = 2 * R * N / (ms_m / n_m / 1000.0) / 1e12
         out["gram_tflops"] = N * 201 / (ms_g / n_g / 1000.0) / 1e12
 
+        # batched solver: 512 small planted CPDs (modes U{10..64}, ranks U{2..12}, 50 dB), one graph
+        Ts4, Rs4, W04 = synth.batch_members(512, seed=0)
+        B = cp.Batch([torch.as_tensor(t).to(dev) for t in Ts4], Rs4, cp.params(cg_uniforms=synth.cg_uniforms(200, 0)),
+                     W0=W04, graph=True)
+        infos = B.run()
+        btimes = []
+        for _ in range(5):
+            a = time.perf_counter()
+            B.run(read_info=False)
+            torch.cuda.synchronize()
+            btimes.append(time.perf_counter() - a)
+        v, vms = B.variant()
+        bt = statistics.median(btimes)
+        out["batch_512"] = {"cpds_per_s": 512 / bt, "ms_per_batch": 1000.0 * bt, "gram_variant": v,
+                            "gram_variant_ms": vms,
+                            "median_rel_err_full": float(np.median([i["rel_err_full"] for i in infos])),
+                            "median_iters": float(np.median([i["iters"] for i in infos]))}
+        B.close()
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(T, R, core, U)
     print(json.dumps(out), flush=True)

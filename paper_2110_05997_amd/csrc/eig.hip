@@ -14,6 +14,8 @@
 #include "common.h"
 #include "jacobi.h"
 
+#include <string.h>
+
 #include <vector>
 
 namespace cpd {
@@ -258,120 +260,246 @@ cpd_status chol_qr(const double* Y, int n, int k, double* Q, double* C, double* 
   return CPD_OK;
 }
 
-size_t eig_ws_bytes(int n, int P) {
-  if (n <= JMAX) {
-    Sizer z;
-    z.take<double>((size_t)n * n);
-    z.take<double>(n);
-    return z.off;
+namespace {
+
+// One eigenproblem, advanced step by step so that several can share the host loop while their
+// kernels run on different streams.
+struct SubProblem {
+  const double* G;
+  int n, P, k, it;
+  bool direct, done;
+  double *U, *lam;
+  double *V, *lall;                                              // direct (n <= 64)
+  double *Q, *Z, *Y, *Qt, *B, *Vb, *Ri, *Dv, *theta, *Uw, *ratio;   // subspace iteration
+  int* flags;
+  uint64_t seed;
+  double r_host;
+};
+
+template <class Carver>
+void sp_carve(Carver& ar, SubProblem& q) {
+  if (q.direct) {
+    q.V = ar.template take<double>((size_t)q.n * q.n);
+    q.lall = ar.template take<double>(q.n);
+    return;
   }
-  const int k = subspace_k(n, P);
-  Sizer z;
-  z.take<double>((size_t)n * k);   // Q
-  z.take<double>((size_t)n * k);   // Z
-  z.take<double>((size_t)n * k);   // Y = Z Vb
-  z.take<double>((size_t)n * k);   // Qtmp
-  z.take<double>((size_t)k * k);   // B / C
-  z.take<double>((size_t)k * k);   // Vb
-  z.take<double>((size_t)k * k);   // R
-  z.take<double>(k);               // D
-  z.take<double>(k);               // theta
-  z.take<double>((size_t)n * P);   // U work
-  z.take<double>(1);               // residual ratio
-  z.take<int>(4);                  // flags
-  return z.off;
+  const size_t nk = (size_t)q.n * q.k, kk = (size_t)q.k * q.k;
+  q.Q = ar.template take<double>(nk);
+  q.Z = ar.template take<double>(nk);
+  q.Y = ar.template take<double>(nk);
+  q.Qt = ar.template take<double>(nk);
+  q.B = ar.template take<double>(kk);
+  q.Vb = ar.template take<double>(kk);
+  q.Ri = ar.template take<double>(kk);
+  q.Dv = ar.template take<double>(q.k);
+  q.theta = ar.template take<double>(q.k);
+  q.Uw = ar.template take<double>((size_t)q.n * q.P);
+  q.ratio = ar.template take<double>(1);
+  q.flags = ar.template take<int>(4);
 }
 
-cpd_status eig_top(const double* G, int n, int P, double* U, double* lam, void* ws,
-                   size_t ws_bytes, hipStream_t s) {
+void sp_describe(SubProblem& q, const double* G, int n, int P, double* U, double* lam) {
+  memset(&q, 0, sizeof(q));
+  q.G = G; q.n = n; q.P = P; q.U = U; q.lam = lam;
+  q.direct = n <= JMAX;
+  q.k = q.direct ? n : subspace_k(n, P);
+  q.seed = 0xC0FFEEull + (uint64_t)n * 131 + (uint64_t)P;
+}
+
+cpd_status sp_check(int n, int P, const double* G, const double* U, const double* lam) {
   if (n < 1 || P < 1 || P > n || G == nullptr || U == nullptr || lam == nullptr) {
     set_error("eig_top: bad arguments n=%d P=%d", n, P);
     return CPD_E_INVALID;
   }
+  if (n > JMAX && P > JMAX - 8) {
+    set_error("eig_top: P=%d exceeds %d for n=%d > %d", P, JMAX - 8, n, JMAX);
+    return CPD_E_UNSUPPORTED;
+  }
+  return CPD_OK;
+}
+
+cpd_status sp_finish(SubProblem& q, hipStream_t s) {
+  const double* X = q.direct ? q.V : q.Uw;
+  const int ldx = q.direct ? q.n : q.P;
+  CPD_HIP_CHECK(hipMemcpyAsync(q.lam, q.direct ? q.lall : q.theta, sizeof(double) * q.P, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(sign_columns_kernel, dim3(q.P), dim3(256), 0, s, X, q.n, ldx, q.P, q.U);
+  CPD_LAUNCH_CHECK();
+  q.done = true;
+  return CPD_OK;
+}
+
+// One Rayleigh-Ritz step; the Ritz residual ratio is copied to q.r_host (valid after the stream
+// has been synchronised).
+cpd_status sp_rr(SubProblem& q, hipStream_t s) {
+  const int n = q.n, k = q.k, P = q.P;
+  cpd_status st;
+  // Z = G Q ; B = Q^T Z ; Ritz pairs (theta, Vb) of B
+  if ((st = gemm_f64(n, k, n, 1.0, q.G, n, 0, false, q.Q, CPD_F64, k, 0, false, 0.0, q.Z, k, 0, 1, s))) return st;
+  if ((st = gemm_f64(k, k, n, 1.0, q.Q, k, 0, true, q.Z, CPD_F64, k, 0, false, 0.0, q.B, k, 0, 1, s))) return st;
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(JNT), 0, s, q.B, k, k, q.theta, q.Vb);
+  CPD_LAUNCH_CHECK();
+  // Ritz vectors U = Q Vb[:, :P]; Y = Z Vb = G (Q Vb) (its first P columns give the residuals)
+  if ((st = gemm_f64(n, P, k, 1.0, q.Q, k, 0, false, q.Vb, CPD_F64, k, 0, false, 0.0, q.Uw, P, 0, 1, s))) return st;
+  if ((st = gemm_f64(n, k, k, 1.0, q.Z, k, 0, false, q.Vb, CPD_F64, k, 0, false, 0.0, q.Y, k, 0, 1, s))) return st;
+  hipLaunchKernelGGL(ritz_residual_kernel, dim3(1), dim3(256), 0, s, q.Y, k, q.Uw, q.theta, n, P, q.ratio);
+  CPD_LAUNCH_CHECK();
+  CPD_HIP_CHECK(hipMemcpyAsync(&q.r_host, q.ratio, sizeof(double), hipMemcpyDeviceToHost, s));
+  return CPD_OK;
+}
+
+// Enqueues phase `ph` (0..5) of the first part of the problem: 0 the whole direct solve, or the
+// start block; 1..4 the power steps; 5 the first Rayleigh-Ritz step.  Problems that share the host
+// loop are enqueued phase by phase so that every stream has work early.
+constexpr int START_PHASES = 6;
+cpd_status sp_start_phase(SubProblem& q, int ph, hipStream_t s) {
+  if (q.direct) {
+    if (ph != 0) return CPD_OK;
+    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(JNT), 0, s, q.G, q.n, q.n, q.lall, q.V);
+    CPD_LAUNCH_CHECK();
+    return sp_finish(q, s);
+  }
+  const int n = q.n, k = q.k;
+  if (ph == 0) {
+    hipLaunchKernelGGL(init_block_kernel, dim3((n * k + 255) / 256), dim3(256), 0, s, q.Y, n, k, q.seed);
+    CPD_LAUNCH_CHECK();
+    // a Gaussian-like start block is well conditioned: one Cholesky-QR pass
+    return chol_qr(q.Y, n, k, q.Q, q.B, q.Ri, q.Dv, q.Qt, q.flags, false, q.seed + 1, s);
+  }
+  if (ph <= 4) {
+    // plain power steps Q <- orth(G Q) before the first Rayleigh-Ritz check; the last one
+    // re-orthogonalises (two passes) since G Q is ill-conditioned
+    const int it = ph - 1;
+    cpd_status st;
+    if ((st = gemm_f64(n, k, n, 1.0, q.G, n, 0, false, q.Q, CPD_F64, k, 0, false, 0.0, q.Y, k, 0, 1, s))) return st;
+    return chol_qr(q.Y, n, k, q.Q, q.B, q.Ri, q.Dv, q.Qt, q.flags, it == 3, q.seed + 100 + it, s);
+  }
+  return sp_rr(q, s);
+}
+
+cpd_status sp_start(SubProblem& q, hipStream_t s) {
+  cpd_status st;
+  for (int ph = 0; ph < START_PHASES; ++ph)
+    if ((st = sp_start_phase(q, ph, s))) return st;
+  return CPD_OK;
+}
+
+// After the stream has been synchronised: finish, or enqueue the next basis and Ritz step.
+cpd_status sp_continue(SubProblem& q, hipStream_t s) {
+  if (q.r_host <= 1e-13 || q.it >= 199) return sp_finish(q, s);
+  // next basis: orthonormalised G (Q Vb); its columns are nearly orthogonal (G times Ritz
+  // vectors), but a second pass keeps the Rayleigh-Ritz basis orthonormal to rounding
+  cpd_status st;
+  if ((st = chol_qr(q.Y, q.n, q.k, q.Q, q.B, q.Ri, q.Dv, q.Qt, q.flags, true, q.seed + 2 + q.it, s))) return st;
+  ++q.it;
+  return sp_rr(q, s);
+}
+
+// Streams (default priority) and events for running up to three problems side by side; created
+// once per host thread.
+constexpr int NSIDE = 3;
+struct SideStreams {
+  hipStream_t st[NSIDE];
+  hipEvent_t fork, join[NSIDE];
+  bool ok;
+};
+
+SideStreams* side_streams() {
+  static thread_local SideStreams ss = {};
+  static thread_local bool tried = false;
+  if (!tried) {
+    tried = true;
+    ss.ok = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < NSIDE && ss.ok; ++i)
+      ss.ok = hipStreamCreateWithFlags(&ss.st[i], hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&ss.join[i], hipEventDisableTiming) == hipSuccess;
+  }
+  return ss.ok ? &ss : nullptr;
+}
+
+}  // namespace
+
+cpd_status eig_top(const double* G, int n, int P, double* U, double* lam, void* ws,
+                   size_t ws_bytes, hipStream_t s) {
+  cpd_status st;
+  if ((st = sp_check(n, P, G, U, lam))) return st;
   if (ws == nullptr || ws_bytes < eig_ws_bytes(n, P)) {
     set_error("eig_top: workspace too small");
     return CPD_E_WORKSPACE;
   }
+  SubProblem q;
+  sp_describe(q, G, n, P, U, lam);
   Arena ar(ws, ws_bytes);
-  if (n <= JMAX) {
-    double* V = ar.take<double>((size_t)n * n);
-    double* lall = ar.take<double>(n);
-    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(JNT), 0, s, G, n, n, lall, V);
-    CPD_LAUNCH_CHECK();
-    CPD_HIP_CHECK(hipMemcpyAsync(lam, lall, sizeof(double) * P, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(sign_columns_kernel, dim3(P), dim3(256), 0, s, V, n, n, P, U);
-    CPD_LAUNCH_CHECK();
-    return CPD_OK;
-  }
-  if (P > JMAX - 8) {
-    set_error("eig_top: P=%d exceeds %d for n=%d > %d", P, JMAX - 8, n, JMAX);
-    return CPD_E_UNSUPPORTED;
-  }
-  const int k = subspace_k(n, P);
-  double* Q = ar.take<double>((size_t)n * k);
-  double* Z = ar.take<double>((size_t)n * k);
-  double* Y = ar.take<double>((size_t)n * k);
-  double* Qt = ar.take<double>((size_t)n * k);
-  double* B = ar.take<double>((size_t)k * k);
-  double* Vb = ar.take<double>((size_t)k * k);
-  double* Ri = ar.take<double>((size_t)k * k);
-  double* Dv = ar.take<double>(k);
-  double* theta = ar.take<double>(k);
-  double* Uw = ar.take<double>((size_t)n * P);
-  double* ratio = ar.take<double>(1);
-  int* flags = ar.take<int>(4);
-  const uint64_t seed = 0xC0FFEEull + (uint64_t)n * 131 + (uint64_t)P;
-  cpd_status st;
-  hipLaunchKernelGGL(init_block_kernel, dim3((n * k + 255) / 256), dim3(256), 0, s, Y, n, k, seed);
-  CPD_LAUNCH_CHECK();
-  // a Gaussian-like start block is well conditioned: one Cholesky-QR pass
-  if ((st = chol_qr(Y, n, k, Q, B, Ri, Dv, Qt, flags, false, seed + 1, s))) return st;
-  // four plain power steps Q <- orth(G Q) before the first Rayleigh-Ritz check; the last one
-  // re-orthogonalises (two passes) since G Q is ill-conditioned
-  for (int it = 0; it < 4; ++it) {
-    if ((st = gemm_f64(n, k, n, 1.0, G, n, 0, false, Q, CPD_F64, k, 0, false, 0.0, Y, k, 0, 1, s))) return st;
-    if ((st = chol_qr(Y, n, k, Q, B, Ri, Dv, Qt, flags, it == 3, seed + 100 + it, s))) return st;
-  }
-  for (int it = 0; it < 200; ++it) {
-    // Z = G Q ; B = Q^T Z ; Ritz pairs (theta, Vb) of B
-    if ((st = gemm_f64(n, k, n, 1.0, G, n, 0, false, Q, CPD_F64, k, 0, false, 0.0, Z, k, 0, 1, s))) return st;
-    if ((st = gemm_f64(k, k, n, 1.0, Q, k, 0, true, Z, CPD_F64, k, 0, false, 0.0, B, k, 0, 1, s))) return st;
-    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(JNT), 0, s, B, k, k, theta, Vb);
-    CPD_LAUNCH_CHECK();
-    // Ritz vectors U = Q Vb[:, :P]; Y = Z Vb = G (Q Vb) (its first P columns give the residuals)
-    if ((st = gemm_f64(n, P, k, 1.0, Q, k, 0, false, Vb, CPD_F64, k, 0, false, 0.0, Uw, P, 0, 1, s))) return st;
-    if ((st = gemm_f64(n, k, k, 1.0, Z, k, 0, false, Vb, CPD_F64, k, 0, false, 0.0, Y, k, 0, 1, s))) return st;
-    hipLaunchKernelGGL(ritz_residual_kernel, dim3(1), dim3(256), 0, s, Y, k, Uw, theta, n, P, ratio);
-    CPD_LAUNCH_CHECK();
-    double r = 0.0;
-    CPD_HIP_CHECK(hipMemcpyAsync(&r, ratio, sizeof(double), hipMemcpyDeviceToHost, s));
+  sp_carve(ar, q);
+  if ((st = sp_start(q, s))) return st;
+  while (!q.done) {
     CPD_HIP_CHECK(hipStreamSynchronize(s));
-    if (r <= 1e-13) break;
-    // next basis: orthonormalised G (Q Vb); its columns are nearly orthogonal (G times Ritz
-    // vectors), but a second pass keeps the Rayleigh-Ritz basis orthonormal to rounding
-    if ((st = chol_qr(Y, n, k, Q, B, Ri, Dv, Qt, flags, true, seed + 2 + it, s))) return st;
+    if ((st = sp_continue(q, s))) return st;
   }
-  CPD_HIP_CHECK(hipMemcpyAsync(lam, theta, sizeof(double) * P, hipMemcpyDeviceToDevice, s));
-  hipLaunchKernelGGL(sign_columns_kernel, dim3(P), dim3(256), 0, s, Uw, n, P, P, U);
-  CPD_LAUNCH_CHECK();
   return CPD_OK;
 }
 
-// Several problems, solved one after the other on the stream (they share the workspace).
+size_t eig_ws_bytes(int n, int P) {
+  SubProblem q;
+  sp_describe(q, nullptr, n, P, nullptr, nullptr);
+  Sizer z;
+  sp_carve(z, q);
+  return z.off;
+}
+
+// Up to three problems: each runs on its own stream (forked from and joined back to s), so their
+// single-workgroup kernels execute concurrently; one host loop advances them all.
 size_t eig_ws_bytes3(const int* n, const int* P, int nprob) {
-  size_t b = 0;
+  Sizer z;
   for (int i = 0; i < nprob; ++i) {
-    const size_t e = eig_ws_bytes(n[i], P[i]);
-    b = e > b ? e : b;
+    SubProblem q;
+    sp_describe(q, nullptr, n[i], P[i], nullptr, nullptr);
+    sp_carve(z, q);
   }
-  return b;
+  return z.off;
 }
 
 cpd_status eig_top3(const double* const* G, const int* n, const int* P, double* const* U, double* const* lam,
                     int nprob, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (nprob < 1 || nprob > NSIDE) {
+    set_error("eig_top: 1..%d problems per call", NSIDE);
+    return CPD_E_INVALID;
+  }
+  cpd_status st;
+  for (int i = 0; i < nprob; ++i)
+    if ((st = sp_check(n[i], P[i], G[i], U[i], lam[i]))) return st;
+  if (ws == nullptr || ws_bytes < eig_ws_bytes3(n, P, nprob)) {
+    set_error("eig_top: workspace too small");
+    return CPD_E_WORKSPACE;
+  }
+  SubProblem q[NSIDE];
+  Arena ar(ws, ws_bytes);
   for (int i = 0; i < nprob; ++i) {
-    const cpd_status st = eig_top(G[i], n[i], P[i], U[i], lam[i], ws, ws_bytes, s);
-    if (st) return st;
+    sp_describe(q[i], G[i], n[i], P[i], U[i], lam[i]);
+    sp_carve(ar, q[i]);
+  }
+  SideStreams* ss = side_streams();
+  if (ss == nullptr) {
+    set_error("eig_top: could not create side streams");
+    return CPD_E_HIP;
+  }
+  CPD_HIP_CHECK(hipEventRecord(ss->fork, s));
+  for (int i = 0; i < nprob; ++i) CPD_HIP_CHECK(hipStreamWaitEvent(ss->st[i], ss->fork, 0));
+  for (int ph = 0; ph < START_PHASES; ++ph)
+    for (int i = 0; i < nprob; ++i)
+      if ((st = sp_start_phase(q[i], ph, ss->st[i]))) return st;
+  for (;;) {
+    bool all = true;
+    for (int i = 0; i < nprob; ++i) {
+      if (q[i].done) continue;
+      CPD_HIP_CHECK(hipStreamSynchronize(ss->st[i]));
+      if ((st = sp_continue(q[i], ss->st[i]))) return st;
+      all = all && q[i].done;
+    }
+    if (all) break;
+  }
+  for (int i = 0; i < nprob; ++i) {
+    CPD_HIP_CHECK(hipEventRecord(ss->join[i], ss->st[i]));
+    CPD_HIP_CHECK(hipStreamWaitEvent(s, ss->join[i], 0));
   }
   return CPD_OK;
 }

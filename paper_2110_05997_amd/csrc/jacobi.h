@@ -16,10 +16,27 @@ constexpr int JNT = 256;
 // |a_pq| <= 1e-15 sqrt(|a_pp a_qq|); a sweep without rotations, or with off(A)^2 <= 1e-30 ||A||^2,
 // ends the iteration.
 __device__ __forceinline__ void pair_of(int i, int round, int np, int& p, int& q) {
-  const int a = (i == 0) ? 0 : 1 + ((i - 1 + round) % (np - 1));
-  const int b = 1 + ((np - 2 - i + round) % (np - 1));
+  // round-robin ordering: slot 0 fixed, the others rotate; (x mod (np - 1)) for 0 <= x < 2(np - 1)
+  const int m = np - 1;
+  int x = i - 1 + round;
+  x = (x >= m) ? x - m : x;
+  int y = np - 2 - i + round;
+  y = (y >= m) ? y - m : y;
+  const int a = (i == 0) ? 0 : 1 + x;
+  const int b = 1 + y;
   p = min(a, b);
   q = max(a, b);
+}
+
+// Rotation annihilating a_pq: with d = a_qq - a_pp and h = 2 a_pq, t = tan(theta) is
+// sign(d) h / (|d| + sqrt(d^2 + h^2)) (the smaller root of t^2 + 2 (d/h) t - 1 = 0), c = 1/sqrt(1+t^2),
+// s = t c.
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double& c, double& s) {
+  const double d = aqq - app, h = 2.0 * apq;
+  const double r = sqrt(d * d + h * h);
+  const double t = (d >= 0.0 ? h : -h) / (fabs(d) + r);
+  c = rsqrt(1.0 + t * t);
+  s = t * c;
 }
 
 // Eigendecomposition of the symmetric n x n matrix Ag (leading dim lda, n <= 64).
@@ -46,8 +63,11 @@ __device__ void jacobi_block(const double* __restrict__ Ag, int n, int lda, doub
   for (int i = w; i < n; i += NWV)
     if (lane < n) fro2 += A[i][lane] * A[i][lane];
   fro2 = block_sum(fro2, red[0]);
-  const int jj = tid & 31, i0 = tid >> 5;   // block column owned, first block row
+  // thread map of the update phase: block column jj (pair), block rows i0, i0 + ISTEP, ...
+  const int jj = tid & 31, i0 = tid >> 5;
   constexpr int ISTEP = JNT / 32;
+  constexpr int NBI = (JMAX / 2 + ISTEP - 1) / ISTEP;   // block rows per thread
+  constexpr int NVX = (JMAX + ISTEP - 1) / ISTEP;       // rows of V per thread
   for (int sweep = 0; sweep < 60 && np >= 2; ++sweep) {
     double off = 0.0;
     for (int i = w; i < n; i += NWV)
@@ -63,10 +83,7 @@ __device__ void jacobi_block(const double* __restrict__ Ag, int n, int lda, doub
         if (q < n) {
           const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
           if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+            jacobi_rotation(app, aqq, apq, c, s);
             rotated[sweep & 1] = 1;
           }
         }
@@ -74,23 +91,50 @@ __device__ void jacobi_block(const double* __restrict__ Ag, int n, int lda, doub
       }
       __syncthreads();
       if (jj < half) {
+        // gather every entry this thread owns, then rotate, then scatter (one LDS round trip
+        // each way; the 2x2 blocks and V entries of different threads are disjoint)
         const int pj = rp[jj], qj = rq[jj];
         const double cj = rc[jj], sj = rs[jj];
-        for (int i = i0; i < half; i += ISTEP) {
-          const int pi = rp[i], qi = rq[i];
-          const double ci = rc[i], si = rs[i];
-          const double a_pp = A[pi][pj], a_pq = A[pi][qj], a_qp = A[qi][pj], a_qq = A[qi][qj];
-          const double b_pp = ci * a_pp - si * a_qp, b_pq = ci * a_pq - si * a_qq;
-          const double b_qp = si * a_pp + ci * a_qp, b_qq = si * a_pq + ci * a_qq;
-          A[pi][pj] = cj * b_pp - sj * b_pq;
-          A[pi][qj] = sj * b_pp + cj * b_pq;
-          A[qi][pj] = cj * b_qp - sj * b_qq;
-          A[qi][qj] = sj * b_qp + cj * b_qq;
+        int pi[NBI], qi[NBI];
+        double ci[NBI], si[NBI], a_pp[NBI], a_pq[NBI], a_qp[NBI], a_qq[NBI];
+#pragma unroll
+        for (int u = 0; u < NBI; ++u) {
+          if (i0 + u * ISTEP < half) {
+            const int i = i0 + u * ISTEP;
+            pi[u] = rp[i]; qi[u] = rq[i]; ci[u] = rc[i]; si[u] = rs[i];
+          }
         }
-        for (int x = i0; x < n; x += ISTEP) {
-          const double vp = V[x][pj], vq = V[x][qj];
-          V[x][pj] = cj * vp - sj * vq;
-          V[x][qj] = sj * vp + cj * vq;
+#pragma unroll
+        for (int u = 0; u < NBI; ++u) {
+          if (i0 + u * ISTEP < half) {
+            a_pp[u] = A[pi[u]][pj]; a_pq[u] = A[pi[u]][qj];
+            a_qp[u] = A[qi[u]][pj]; a_qq[u] = A[qi[u]][qj];
+          }
+        }
+        double vp[NVX], vq[NVX];
+#pragma unroll
+        for (int u = 0; u < NVX; ++u) {
+          const int x = i0 + u * ISTEP;
+          if (x < n) { vp[u] = V[x][pj]; vq[u] = V[x][qj]; }
+        }
+#pragma unroll
+        for (int u = 0; u < NBI; ++u) {
+          if (i0 + u * ISTEP < half) {
+            const double b_pp = ci[u] * a_pp[u] - si[u] * a_qp[u], b_pq = ci[u] * a_pq[u] - si[u] * a_qq[u];
+            const double b_qp = si[u] * a_pp[u] + ci[u] * a_qp[u], b_qq = si[u] * a_pq[u] + ci[u] * a_qq[u];
+            A[pi[u]][pj] = cj * b_pp - sj * b_pq;
+            A[pi[u]][qj] = sj * b_pp + cj * b_pq;
+            A[qi[u]][pj] = cj * b_qp - sj * b_qq;
+            A[qi[u]][qj] = sj * b_qp + cj * b_qq;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < NVX; ++u) {
+          const int x = i0 + u * ISTEP;
+          if (x < n) {
+            V[x][pj] = cj * vp[u] - sj * vq[u];
+            V[x][qj] = sj * vp[u] + cj * vq[u];
+          }
         }
       }
       __syncthreads();
