@@ -1,7 +1,6 @@
 // Kernels on the full (uncompressed) tensor and the output stage.
 //  * residual_full: ||T - sum_r w_r^(1) o w_r^(2) o w_r^(3)||^2 fused with its reduction (the
 //    residual of ch.4 "Computing the residual" evaluated on T instead of the core);
-//  * mttkrp_full: T_(l) (KR of the other factors), the MTTKRP of the gradient theorem of ch.4;
 //  * sumsq_full: ||T||^2 with detection of NaN/Inf;
 //  * normalize_output: unit columns and lambda (ch.4 flow chart output).
 // Reductions go through per-block partials summed in a fixed order (bit-reproducible).
@@ -76,28 +75,6 @@ __global__ void final_sum_kernel(const double* __restrict__ part, int n, double*
   for (int i = threadIdx.x; i < n; i += RNT) acc += part[i];
   const double s = block_sum(acc, slots);
   if (threadIdx.x == 0) *out = s;
-}
-
-// KR rows of the two factors other than `mode`, in the index order of the matching view of T.
-__global__ void kr_kernel(const double* __restrict__ A, const double* __restrict__ B, int nA, int nB,
-                          int R, double* __restrict__ KR) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)nA * nB * R) return;
-  const int r = (int)(e % R);
-  const long long ab = e / R;
-  const int ia = (int)(ab / nB), ib = (int)(ab % nB);
-  KR[e] = A[(long long)ia * R + r] * B[(long long)ib * R + r];
-}
-
-// mode 2: M[j][r] = sum_i Y[i][j][r] W0[i][r]
-__global__ void reduce_mode1_kernel(const double* __restrict__ Y, const double* __restrict__ W0, int I1,
-                                    int I2, int R, double* __restrict__ M) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= I2 * R) return;
-  const int j = e / R, r = e % R;
-  double acc = 0.0;
-  for (int i = 0; i < I1; ++i) acc += Y[((long long)i * I2 + j) * R + r] * W0[(long long)i * R + r];
-  M[e] = acc;
 }
 
 // Column norms, lambda, signs and order of the uncompressed factors (one workgroup).
@@ -241,53 +218,6 @@ cpd_status sumsq_full(const void* T, int dtype, int64_t n, double* out, int* non
     CPD_LAUNCH_CHECK();
   }
   return CPD_OK;
-}
-
-size_t mttkrp_ws_bytes(const int64_t dims[3], int R, int mode) {
-  const size_t I1 = dims[0], I2 = dims[1], I3 = dims[2];
-  if (mode == 0) return align_up(I2 * I3 * R * sizeof(double), 256);
-  if (mode == 1) return align_up(I1 * I2 * R * sizeof(double), 256);
-  return align_up(I1 * I2 * R * sizeof(double), 256);
-}
-
-cpd_status mttkrp_full(const void* T, int dtype, const int64_t dims[3], const double* const W[3],
-                       int R, int mode, double* M, void* ws, size_t ws_bytes, hipStream_t s) {
-  if (R < 1 || mode < 0 || mode > 2 || !T || !M) {
-    set_error("mttkrp_full: bad arguments");
-    return CPD_E_INVALID;
-  }
-  if (!ws || ws_bytes < mttkrp_ws_bytes(dims, R, mode)) {
-    set_error("mttkrp_full: workspace too small");
-    return CPD_E_WORKSPACE;
-  }
-  const int I1 = (int)dims[0], I2 = (int)dims[1], I3 = (int)dims[2];
-  double* buf = (double*)ws;
-  cpd_status st;
-  prof_begin(CPD_PK_MTTKRP, s);
-  if (mode == 0) {
-    // KR[(j,k)][r] = W1[j][r] W2[k][r]; M^T (R x I1) = KR^T (R x I2I3) . T_mat^T, stored transposed
-    const long long n = (long long)I2 * I3 * R;
-    hipLaunchKernelGGL(kr_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W[1], W[2], I2, I3, R, buf);
-    CPD_LAUNCH_CHECK();
-    st = gemm_f64(R, I1, I2 * I3, 1.0, buf, R, 0, true, T, dtype, (long long)I2 * I3, 0, true, 0.0, M, R, 0,
-                  1, s, true);
-  } else if (mode == 1) {
-    // Y[i] = T[i] (I2 x I3) . W2 (I3 x R) -> T is the B operand: Y[i]^T = W2^T T[i]^T
-    st = gemm_f64(R, I2, I3, 1.0, W[2], R, 0, true, T, dtype, I3, (long long)I2 * I3, true, 0.0, buf, R,
-                  (long long)I2 * R, I1, s, true);
-    if (st) return st;
-    hipLaunchKernelGGL(reduce_mode1_kernel, dim3((I2 * R + 255) / 256), dim3(256), 0, s, buf, W[0], I1, I2,
-                       R, M);
-    CPD_LAUNCH_CHECK();
-  } else {
-    // KR[(i,j)][r] = W0[i][r] W1[j][r]; M^T (R x I3) = KR^T . T_mat (I1I2 x I3)
-    const long long n = (long long)I1 * I2 * R;
-    hipLaunchKernelGGL(kr_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W[0], W[1], I1, I2, R, buf);
-    CPD_LAUNCH_CHECK();
-    st = gemm_f64(R, I3, I1 * I2, 1.0, buf, R, 0, true, T, dtype, I3, 0, false, 0.0, M, R, 0, 1, s, true);
-  }
-  prof_end(CPD_PK_MTTKRP, s);
-  return st;
 }
 
 size_t normalize_ws_bytes(int R) {

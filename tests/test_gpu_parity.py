@@ -126,7 +126,8 @@ def test_jtj_v_matches_oracle(dims, R):
 
 
 @pytest.mark.parametrize("dims,R,dtype", [((30, 20, 25), 4, torch.float64), ((64, 70, 33), 9, torch.float32),
-                                          ((3, 130, 2), 2, torch.float64)])
+                                          ((3, 130, 2), 2, torch.float64), ((33, 70, 41), 64, torch.float64),
+                                          ((130, 67, 1), 17, torch.bfloat16), ((200, 200, 200), 20, torch.float32)])
 def test_mttkrp_and_residual_match_oracle(dims, R, dtype):
     log("mttkrp", dims, R, dtype)
     rng = np.random.default_rng(7)
