@@ -221,7 +221,7 @@ __global__ __launch_bounds__(PROJ_NT) void batch_project_kernel(const BItem* __r
   }
   // dGN state: header, caps, initial point (first c_l rows of W0, or N(0,1))
   const int np = (c1 + c2 + c3) * R;
-  const Layout Lo = layout_of(np, a.maxiter);
+  const Layout Lo = layout_of(np, R, a.maxiter);
   char* st = it.state;
   int* caps = (int*)(st + Lo.caps);
   for (int k = tid; k < a.maxiter; k += PROJ_NT) caps[k] = a.caps[k];
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(FIN_NT) void batch_finish_kernel(const BItem* __res
   const int R = it.R;
   const int cs[3] = {h->d[0], h->d[1], h->d[2]};
   const int np = (cs[0] + cs[1] + cs[2]) * R;
-  const Layout Lo = layout_of(np, maxiter);
+  const Layout Lo = layout_of(np, R, maxiter);
   const double* Wc = (const double*)(it.state + Lo.W);
   const double* errs = (const double*)(it.state + Lo.errs);
   const bool skipped = (h->flags & 2) != 0;

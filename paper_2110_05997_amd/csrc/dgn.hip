@@ -348,7 +348,7 @@ __device__ int stop_test(const double* errs, int k, double step, double grad_inf
 }
 
 // mode 0: initialise the state from the W stored in it; mode 1: run up to max_steps iterations.
-__device__ void dgn_body(char* __restrict__ state, const double* __restrict__ S, int mode, int max_steps,
+__device__ __forceinline__ void dgn_body(char* __restrict__ state, const double* __restrict__ S, int mode, int max_steps,
                          double* lds, int& s_stop) {
   Hdr* h = (Hdr*)state;
   const int R = h->R;
@@ -356,7 +356,7 @@ __device__ void dgn_body(char* __restrict__ state, const double* __restrict__ S,
   const int maxiter = h->maxiter;
   Ctx c;
   setup_ctx(c, lds, d, R, S);
-  const Layout Lo = layout_of(c.np, maxiter);
+  const Layout Lo = layout_of(c.np, R, maxiter);
   double* gW = (double*)(state + Lo.W);
   double* gMK = (double*)(state + Lo.MK);
   double* errs = (double*)(state + Lo.errs);
@@ -506,6 +506,16 @@ __global__ __launch_bounds__(NT) void dgn_kernel(char* __restrict__ state, const
   dgn_body(state, S, mode, max_steps, lds, s_stop);
 }
 
+// Same iteration for states too large for LDS: the working set lives in the state's own work
+// region (global memory; one workgroup, so its accesses stay coherent through the CU's cache).
+__global__ __launch_bounds__(NT) void dgn_kernel_g(char* __restrict__ state, const double* __restrict__ S,
+                                                   int mode, int max_steps) {
+  __shared__ int s_stop;
+  const Hdr* h = (const Hdr*)state;
+  const Layout Lo = layout_of(h->np, h->R, h->maxiter);
+  dgn_body(state, S, mode, max_steps, (double*)(state + Lo.work), s_stop);
+}
+
 // Batched: workgroup b initialises state b (header, caps and W already written) and iterates it
 // to a stopping rule.  Dynamic LDS must cover the largest member.
 __global__ __launch_bounds__(NT) void dgn_batch_kernel(char* const* __restrict__ states,
@@ -640,9 +650,25 @@ int cg_cap_for(int k, double u) {
   return (int)(lo + off);
 }
 
+namespace {
+// The persistent dGN kernel with its working set in LDS when it fits, else in the state's work
+// region.
+cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int np, int R, hipStream_t s) {
+  size_t lb;
+  if (lds_fits(np, R, &lb)) {
+    CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
+    hipLaunchKernelGGL(dgn_kernel, dim3(1), dim3(NT), lb, s, state, S, mode, max_steps);
+  } else {
+    hipLaunchKernelGGL(dgn_kernel_g, dim3(1), dim3(NT), 0, s, state, S, mode, max_steps);
+  }
+  CPD_LAUNCH_CHECK();
+  return CPD_OK;
+}
+}  // namespace
+
 size_t state_bytes(const int32_t core[3], int R, int maxiter) {
   const int np = (core[0] + core[1] + core[2]) * R;
-  return layout_of(np, maxiter).total;
+  return layout_of(np, R, maxiter).total;
 }
 
 cpd_status state_init(void* state, const double* S, const int32_t core[3], int R,
@@ -657,13 +683,7 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
       return CPD_E_INVALID;
     }
   const int np = (core[0] + core[1] + core[2]) * R;
-  size_t lb;
-  if (!lds_fits(np, R, &lb)) {
-    set_error("state_init: core %dx%dx%d with R=%d needs %zu bytes of LDS", core[0], core[1],
-              core[2], R, lb);
-    return CPD_E_UNSUPPORTED;
-  }
-  const Layout Lo = layout_of(np, p->maxiter);
+  const Layout Lo = layout_of(np, R, p->maxiter);
   char* st = (char*)state;
   // header + caps on the host, then one copy
   Hdr h;
@@ -709,9 +729,8 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
     set_error("state_init: CPD_INIT_GIVEN needs W0");
     return CPD_E_INVALID;
   }
-  CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
-  hipLaunchKernelGGL(dgn_kernel, dim3(1), dim3(NT), lb, s, st, S, 0, 0);
-  CPD_LAUNCH_CHECK();
+  cpd_status lst;
+  if ((lst = launch_dgn(st, S, 0, 0, np, R, s))) return lst;
   int flags = 0;
   CPD_HIP_CHECK(hipMemcpyAsync(&flags, st + offsetof(Hdr, flags), sizeof(int), hipMemcpyDeviceToHost, s));
   CPD_HIP_CHECK(hipStreamSynchronize(s));
@@ -748,17 +767,10 @@ cpd_status dgn_iterate(void* state, const double* S, int max_steps, hipStream_t 
     set_error("dgn_iterate: state not initialised");
     return CPD_E_INVALID;
   }
-  size_t lb;
-  if (!lds_fits(h.np, h.R, &lb)) {
-    set_error("dgn_iterate: state too large for LDS");
-    return CPD_E_UNSUPPORTED;
-  }
-  CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
   prof_begin(CPD_PK_DGN, s);
-  hipLaunchKernelGGL(dgn_kernel, dim3(1), dim3(NT), lb, s, (char*)state, S, 1, max_steps);
+  const cpd_status st = launch_dgn((char*)state, S, 1, max_steps, h.np, h.R, s);
   prof_end(CPD_PK_DGN, s);
-  CPD_LAUNCH_CHECK();
-  return CPD_OK;
+  return st;
 }
 
 cpd_status state_read(void* state, int* k, int* stop, int* tol_iter, double* err, hipStream_t s) {
@@ -769,7 +781,7 @@ cpd_status state_read(void* state, int* k, int* stop, int* tol_iter, double* err
   if (stop) *stop = h.stop;
   if (tol_iter) *tol_iter = h.tol_iter;
   if (err) {
-    const Layout Lo = layout_of(h.np, h.maxiter);
+    const Layout Lo = layout_of(h.np, h.R, h.maxiter);
     CPD_HIP_CHECK(hipMemcpyAsync(err, (char*)state + Lo.errs + sizeof(double) * h.k, sizeof(double),
                                  hipMemcpyDeviceToHost, s));
     CPD_HIP_CHECK(hipStreamSynchronize(s));
@@ -785,7 +797,7 @@ cpd_status state_log(void* state, int first, int count, cpd_step_info* out, hipS
     set_error("state_log: range out of bounds");
     return CPD_E_INVALID;
   }
-  const Layout Lo = layout_of(h.np, h.maxiter);
+  const Layout Lo = layout_of(h.np, h.R, h.maxiter);
   if (count > 0) {
     CPD_HIP_CHECK(hipMemcpyAsync(out, (char*)state + Lo.log + sizeof(cpd_step_info) * first,
                                  sizeof(cpd_step_info) * count, hipMemcpyDeviceToHost, s));
@@ -798,7 +810,7 @@ cpd_status state_factors(void* state, double* W, int set, hipStream_t s) {
   Hdr h;
   CPD_HIP_CHECK(hipMemcpyAsync(&h, state, sizeof(h), hipMemcpyDeviceToHost, s));
   CPD_HIP_CHECK(hipStreamSynchronize(s));
-  const Layout Lo = layout_of(h.np, h.maxiter);
+  const Layout Lo = layout_of(h.np, h.R, h.maxiter);
   char* gW = (char*)state + Lo.W;
   if (set)
     CPD_HIP_CHECK(hipMemcpyAsync(gW, W, sizeof(double) * h.np, hipMemcpyDeviceToDevice, s));

@@ -22,10 +22,13 @@ struct Hdr {
 static_assert(sizeof(Hdr) <= 256, "header must fit its slot");
 
 struct Layout {
-  size_t W, MK, errs, caps, log, total;
+  size_t W, MK, errs, caps, log, work, total;
 };
 
-__host__ __device__ inline Layout layout_of(int np, int maxiter) {
+__host__ __device__ inline size_t lds_doubles(int np, int R);
+
+// Regions of a state (the work region holds the working set when it does not fit in LDS)
+__host__ __device__ inline Layout layout_of(int np, int R, int maxiter) {
   Layout L;
   size_t off = 256;
   L.W = off; off += (size_t)np * 8;
@@ -33,6 +36,8 @@ __host__ __device__ inline Layout layout_of(int np, int maxiter) {
   L.errs = off; off += (size_t)(maxiter + 1) * 8;
   L.caps = off; off += ((size_t)maxiter * 4 + 7) / 8 * 8;
   L.log = off; off += (size_t)maxiter * sizeof(cpd_step_info);
+  off = (off + 255) / 256 * 256;
+  L.work = off; off += lds_doubles(np, R) * 8;
   L.total = (off + 255) / 256 * 256;
   return L;
 }

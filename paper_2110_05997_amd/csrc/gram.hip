@@ -17,29 +17,32 @@ namespace cpd {
 namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int TILE = 64;   // G tile edge
-constexpr int BK = 32;     // contraction chunk staged in LDS
 constexpr int NT = 256;    // 4 waves, each a 32x32 quarter of the tile
-constexpr int LDP = BK + 1;
 
 struct GramGeom {
   int variant;        // 0: rows (modes 1, 2), 1: columns (mode 3)
   int M;              // Gram size
-  long long Ktot;     // total contraction length (B*K for variant 0)
-  long long K;        // inner contraction length of one slab (variant 0)
-  long long sb, sm;   // variant 0: slab stride, row stride
-  long long sk;       // variant 1: row stride of the (I1 I2) x I3 view
+  int Ktot;           // total contraction length (slabs x K for variant 0)
+  int K;              // inner contraction length of one slab (variant 0)
+  long long sb;       // variant 0: slab stride
+  int sm;             // variant 0: row stride
+  int sk;             // variant 1: row stride of the (I1 I2) x I3 view
   int ntile;          // tiles per edge
   int nupper;         // number of upper-triangle tiles
   int nsplit;         // split-K factor (multiple of 8)
-  long long kchunk;   // contraction length per split (multiple of BK)
+  int kchunk;         // contraction length per split (multiple of the k-tile)
 };
 
-template <class T>
-__device__ __forceinline__ double ld(const T* p, long long i) { return (double)p[i]; }
+// Staged value of a tensor element: FP64 for the FP64 path (BF16 bits decoded), raw bits for the
+// BF16 path.
+template <class V, class T>
+__device__ __forceinline__ V conv(T x) { return (V)x; }
 template <>
-__device__ __forceinline__ double ld<uint16_t>(const uint16_t* p, long long i) { return bf16_bits_to_f64(p[i]); }
+__device__ __forceinline__ double conv<double, uint16_t>(uint16_t x) { return bf16_bits_to_f64(x); }
 
 __device__ __forceinline__ void tile_of(int t, int ntile, int& tm, int& tn) {
   int row = 0, start = 0;
@@ -48,37 +51,55 @@ __device__ __forceinline__ void tile_of(int t, int ntile, int& tm, int& tn) {
   tn = row + (t - start);
 }
 
+// Pointer to element (row gm, contraction index kp) of the unfolding; both already clamped into
+// range.  Variant 0 splits kp = b K + k by a double-precision reciprocal (exact for kp < 2^26).
 template <class T>
-__device__ __forceinline__ void stage(double (*X)[LDP], const T* __restrict__ src, const GramGeom& g,
-                                      int row0, long long k0, long long kend) {
-  const int tid = threadIdx.x;
+__device__ __forceinline__ const T* elem(const T* src, const GramGeom g, int gm, int kp, double invK) {
   if (g.variant == 0) {
+    const int b = (int)(((double)kp + 0.5) * invK);
+    const int k = kp - b * g.K;
+    return src + (long long)b * g.sb + (long long)gm * g.sm + k;
+  }
+  return src + (long long)kp * g.sk + gm;
+}
+
+// Staging of one k-tile of the two 64-row operands: every thread owns the same (row, k) slots in
+// every tile; loads are unconditional (indices clamped, values zeroed afterwards) so they issue
+// back to back, and they are made for tile t + 1 while tile t is multiplied.
+template <class T, class V, int BKT>
+struct Stager {
+  static constexpr int PER = TILE * BKT / NT;   // elements per thread and operand
+  int m[PER], kk[PER];
+  V rm[PER], rn[PER];
+  __device__ __forceinline__ void init(const GramGeom g) {
 #pragma unroll
-    for (int t = 0; t < (TILE * BK) / NT; ++t) {
-      const int e = tid + t * NT;
-      const int kk = e % BK, m = e / BK;
-      const long long kp = k0 + kk;
-      const int gm = row0 + m;
-      double v = 0.0;
-      if (gm < g.M && kp < kend) {
-        const long long b = kp / g.K, k = kp - b * g.K;
-        v = ld(src, b * g.sb + (long long)gm * g.sm + k);
-      }
-      X[m][kk] = v;
-    }
-  } else {
-#pragma unroll
-    for (int t = 0; t < (TILE * BK) / NT; ++t) {
-      const int e = tid + t * NT;
-      const int m = e % TILE, kk = e / TILE;
-      const long long kp = k0 + kk;
-      const int gm = row0 + m;
-      double v = 0.0;
-      if (gm < g.M && kp < kend) v = ld(src, kp * g.sk + gm);
-      X[m][kk] = v;
+    for (int t = 0; t < PER; ++t) {
+      const int e = threadIdx.x + t * NT;
+      if (g.variant == 0) { kk[t] = e % BKT; m[t] = e / BKT; }   // contraction index contiguous
+      else { m[t] = e % TILE; kk[t] = e / TILE; }                // row index contiguous
     }
   }
-}
+  __device__ __forceinline__ void fetch(const T* src, const GramGeom g, double invK, int rowm, int rown, bool diag, int k0, int kend) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int kp = k0 + kk[t];
+      const bool okk = kp < kend;
+      const int kc = okk ? kp : 0;
+      const int gm = rowm + m[t], gn = rown + m[t];
+      const bool okm = okk && gm < g.M, okn = okk && gn < g.M;
+      const T vm = *elem(src, g, okm ? gm : 0, kc, invK);
+      rm[t] = okm ? conv<V, T>(vm) : (V)0;
+      if (!diag) {
+        const T vn = *elem(src, g, okn ? gn : 0, kc, invK);
+        rn[t] = okn ? conv<V, T>(vn) : (V)0;
+      }
+    }
+  }
+};
+
+// FP64 path (FP64 / FP32 input promoted exactly): v_mfma_f64_16x16x4f64, 32-wide k-tiles.
+constexpr int BK = 32;
+constexpr int LDP = BK + 1;
 
 template <class T>
 __global__ __launch_bounds__(NT) void gram_partial_kernel(const T* __restrict__ src, GramGeom g,
@@ -95,9 +116,9 @@ __global__ __launch_bounds__(NT) void gram_partial_kernel(const T* __restrict__ 
   int tm, tn;
   tile_of(tile, g.ntile, tm, tn);
   const bool diag = (tm == tn);
-  const long long kbeg = (long long)split * g.kchunk;
-  const long long kend = min(g.Ktot, kbeg + g.kchunk);
-
+  const int kbeg = split * g.kchunk;
+  const int kend = min(g.Ktot, kbeg + g.kchunk);
+  const double invK = 1.0 / (double)(g.variant == 0 ? g.K : 1);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
   dbl4 acc[2][2];
@@ -105,12 +126,18 @@ __global__ __launch_bounds__(NT) void gram_partial_kernel(const T* __restrict__ 
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-
+  Stager<T, double, BK> st;
+  st.init(g);
   double (*Bn)[LDP] = diag ? Xm : Xn;
-  for (long long k0 = kbeg; k0 < kend; k0 += BK) {
-    stage(Xm, src, g, tm * TILE, k0, kend);
-    if (!diag) stage(Xn, src, g, tn * TILE, k0, kend);
+  if (kbeg < kend) st.fetch(src, g, invK, tm * TILE, tn * TILE, diag, kbeg, kend);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int t = 0; t < st.PER; ++t) {
+      Xm[st.m[t]][st.kk[t]] = st.rm[t];
+      if (!diag) Xn[st.m[t]][st.kk[t]] = st.rn[t];
+    }
     __syncthreads();
+    if (k0 + BK < kend) st.fetch(src, g, invK, tm * TILE, tn * TILE, diag, k0 + BK, kend);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       // A fragment: lane holds A[lane%16][lane/16] (16x4); B fragment: B[lane/16][lane%16] (4x16)
@@ -141,6 +168,76 @@ __global__ __launch_bounds__(NT) void gram_partial_kernel(const T* __restrict__ 
       }
 }
 
+// BF16 path: v_mfma_f32_16x16x16bf16_1k with FP32 accumulation inside a split (the split sums
+// are added in FP64), 64-wide k-tiles.  Fragment layout (checked on the device): A[i][k] is
+// element k % 4 of lane i + 16 (k / 4), B[k][j] element k % 4 of lane j + 16 (k / 4), and
+// D[4 (l / 16) + v][l % 16] is acc[v] of lane l.
+constexpr int BKH = 64;
+constexpr int LDH = BKH + 4;   // row pitch in bf16 elements (keeps 8-byte fragment reads aligned)
+
+__global__ __launch_bounds__(NT) void gram_partial_bf16_kernel(const uint16_t* __restrict__ src, GramGeom g,
+                                                               double* __restrict__ part) {
+  __shared__ __align__(16) uint16_t Hm[TILE][LDH];
+  __shared__ __align__(16) uint16_t Hn[TILE][LDH];
+  const int L = blockIdx.x;
+  const int xcd = L & 7, idx = L >> 3;
+  const int tile = idx % g.nupper;
+  const int split = (idx / g.nupper) * 8 + xcd;
+  if (split >= g.nsplit) return;
+  int tm, tn;
+  tile_of(tile, g.ntile, tm, tn);
+  const bool diag = (tm == tn);
+  const int kbeg = split * g.kchunk;
+  const int kend = min(g.Ktot, kbeg + g.kchunk);
+  const double invK = 1.0 / (double)(g.variant == 0 ? g.K : 1);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  flt4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+  Stager<uint16_t, uint16_t, BKH> st;
+  st.init(g);
+  uint16_t (*Bn)[LDH] = diag ? Hm : Hn;
+  if (kbeg < kend) st.fetch(src, g, invK, tm * TILE, tn * TILE, diag, kbeg, kend);
+  for (int k0 = kbeg; k0 < kend; k0 += BKH) {
+#pragma unroll
+    for (int t = 0; t < st.PER; ++t) {
+      Hm[st.m[t]][st.kk[t]] = st.rm[t];
+      if (!diag) Hn[st.m[t]][st.kk[t]] = st.rn[t];
+    }
+    __syncthreads();
+    if (k0 + BKH < kend) st.fetch(src, g, invK, tm * TILE, tn * TILE, diag, k0 + BKH, kend);
+#pragma unroll
+    for (int kk = 0; kk < BKH; kk += 16) {
+      bf16x4 a[2], b[2];
+      const int kq = kk + 4 * (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = *(const bf16x4*)&Hm[wm + 16 * i + (lane & 15)][kq];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = *(const bf16x4*)&Bn[wn + 16 * j + (lane & 15)][kq];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* out = part + ((long long)tile * g.nsplit + split) * (TILE * TILE);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wm + 16 * i + 4 * (lane >> 4) + v;   // bf16 result layout differs from f64's
+        const int c = wn + 16 * j + (lane & 15);
+        out[r * TILE + c] = (double)acc[i][j][v];
+      }
+}
+
 __global__ void gram_reduce_kernel(const double* __restrict__ part, GramGeom g, double* __restrict__ G) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)g.nupper * TILE * TILE) return;
@@ -159,48 +256,51 @@ __global__ void gram_reduce_kernel(const double* __restrict__ part, GramGeom g, 
   G[(long long)n * g.M + m] = s;
 }
 
-GramGeom make_geom(const int64_t dims[3], int mode) {
+GramGeom make_geom(const int64_t dims[3], int mode, int bk) {
   GramGeom g{};
   const long long I1 = dims[0], I2 = dims[1], I3 = dims[2];
   if (mode == 0) {
-    g.variant = 0; g.M = (int)I1; g.K = I2 * I3; g.Ktot = g.K; g.sb = 0; g.sm = I2 * I3;
+    g.variant = 0; g.M = (int)I1; g.K = (int)(I2 * I3); g.Ktot = g.K; g.sb = 0; g.sm = (int)(I2 * I3);
   } else if (mode == 1) {
-    g.variant = 0; g.M = (int)I2; g.K = I3; g.Ktot = I1 * I3; g.sb = I2 * I3; g.sm = I3;
+    g.variant = 0; g.M = (int)I2; g.K = (int)I3; g.Ktot = (int)(I1 * I3); g.sb = I2 * I3; g.sm = (int)I3;
   } else {
-    g.variant = 1; g.M = (int)I3; g.Ktot = I1 * I2; g.sk = I3;
+    g.variant = 1; g.M = (int)I3; g.Ktot = (int)(I1 * I2); g.sk = (int)I3;
   }
   g.ntile = (g.M + TILE - 1) / TILE;
   g.nupper = g.ntile * (g.ntile + 1) / 2;
-  // aim for ~1024 workgroups (4 per CU) without chunks shorter than 4*BK
+  // aim for ~1024 workgroups (4 per CU) without chunks shorter than 4 k-tiles
   long long want = (1024 + g.nupper - 1) / g.nupper;
-  long long maxsplit = (g.Ktot + 4 * BK - 1) / (4 * BK);
+  long long maxsplit = (g.Ktot + 4 * bk - 1) / (4 * bk);
   long long ns = want < maxsplit ? want : maxsplit;
   if (ns < 1) ns = 1;
   ns = (ns + 7) / 8 * 8;
   long long chunk = (g.Ktot + ns - 1) / ns;
-  chunk = (chunk + BK - 1) / BK * BK;
+  chunk = (chunk + bk - 1) / bk * bk;
   ns = (g.Ktot + chunk - 1) / chunk;
   ns = (ns + 7) / 8 * 8;
   g.nsplit = (int)ns;
-  g.kchunk = chunk;
+  g.kchunk = (int)chunk;
   return g;
 }
+
+bool use_bf16(int dtype, int compute_dtype) { return dtype == CPD_BF16 && compute_dtype == CPD_BF16; }
 
 }  // namespace
 
 size_t gram_ws_bytes(const int64_t dims[3], int mode) {
-  GramGeom g = make_geom(dims, mode);
-  return align_up((size_t)g.nupper * g.nsplit * TILE * TILE * sizeof(double), 256);
+  const GramGeom g = make_geom(dims, mode, BK), h = make_geom(dims, mode, BKH);
+  const int ns = g.nsplit > h.nsplit ? g.nsplit : h.nsplit;
+  return align_up((size_t)g.nupper * ns * TILE * TILE * sizeof(double), 256);
 }
 
 cpd_status gram(const void* T, int dtype, const int64_t dims[3], int mode, int compute_dtype,
                 double* G, void* ws, size_t ws_bytes, hipStream_t s) {
-  (void)compute_dtype;
   if (mode < 0 || mode > 2 || T == nullptr || G == nullptr) {
     set_error("gram: bad arguments");
     return CPD_E_INVALID;
   }
-  GramGeom g = make_geom(dims, mode);
+  const bool bf = use_bf16(dtype, compute_dtype);
+  GramGeom g = make_geom(dims, mode, bf ? BKH : BK);
   const size_t need = gram_ws_bytes(dims, mode);
   if (ws == nullptr || ws_bytes < need) {
     set_error("gram: workspace %zu < %zu", ws_bytes, need);
@@ -219,8 +319,10 @@ cpd_status gram(const void* T, int dtype, const int64_t dims[3], int mode, int c
                          (const float*)T, g, part);
       break;
     case CPD_BF16:
-      hipLaunchKernelGGL(gram_partial_kernel<uint16_t>, dim3(nblocks), dim3(NT), 0, s,
-                         (const uint16_t*)T, g, part);
+      if (bf)
+        hipLaunchKernelGGL(gram_partial_bf16_kernel, dim3(nblocks), dim3(NT), 0, s, (const uint16_t*)T, g, part);
+      else
+        hipLaunchKernelGGL(gram_partial_kernel<uint16_t>, dim3(nblocks), dim3(NT), 0, s, (const uint16_t*)T, g, part);
       break;
     default:
       set_error("gram: bad dtype %d", dtype);

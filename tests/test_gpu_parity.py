@@ -67,6 +67,25 @@ def test_gram_matches_unfolding_gram(dims, dtype):
         assert np.array_equal(G, G.T)
 
 
+@pytest.mark.parametrize("dims", [(70, 45, 130), (64, 64, 64), (17, 200, 33)])
+def test_gram_bf16_matrix_cores(dims):
+    """BF16 tensor: the FP64 path is exact on the BF16 values; the BF16 MFMA path (FP32 accumulation
+    within a split-K chunk of at most a few thousand products, FP64 across chunks) stays within
+    2^-24 * chunk length of the largest entry."""
+    log("gram bf16", dims)
+    rng = np.random.default_rng(sum(dims) + 1)
+    Td = dev(rng.standard_normal(dims), torch.bfloat16)
+    Th = host(Td)
+    for mode in range(3):
+        A = ml.unfold(Th, mode)
+        ref = A @ A.T
+        G64 = host(cp().gram(Td, mode))
+        assert relmax(G64, ref) < 1e-12
+        Gbf = host(cp().gram(Td, mode, compute_dtype=cp().CPD_BF16))
+        assert relmax(Gbf, ref) < 1e-5, (mode, relmax(Gbf, ref))
+        assert np.array_equal(Gbf, Gbf.T)
+
+
 @pytest.mark.parametrize("n,P", [(6, 3), (50, 5), (64, 20), (150, 20), (200, 20), (600, 50)])
 def test_eig_top_matches_eigh(n, P):
     log("eig", n, P)
@@ -155,7 +174,8 @@ def oracle_steps(S, W0, params, uniforms, nsteps):
     return st, infos
 
 
-@pytest.mark.parametrize("dims,R,seed", [((5, 5, 5), 5, 0), ((12, 9, 10), 6, 1), ((20, 20, 20), 20, 2)])
+@pytest.mark.parametrize("dims,R,seed", [((5, 5, 5), 5, 0), ((12, 9, 10), 6, 1), ((20, 20, 20), 20, 2),
+                                         ((30, 30, 30), 30, 3), ((50, 50, 50), 50, 4)])
 def test_dgn_steps_match_oracle(dims, R, seed):
     log("dgn_step", dims, R)
     rng = np.random.default_rng(seed)
