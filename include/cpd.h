@@ -267,6 +267,17 @@ cpd_status cpd_batch_plan_run(cpd_batch_plan* plan, cpd_solve_info* info, void* 
 int32_t cpd_batch_plan_variant(const cpd_batch_plan* plan, float* variant_ms);
 void cpd_batch_plan_destroy(cpd_batch_plan* plan);
 
+/* Precision variant of cpd_solve for large tensors: the three compression Grams (ch.4 Alg.
+ * Compression, eigenvector route of the App. B lemma) are formed from T_lo, a BF16 copy of T
+ * (device, same shape, lo_dtype = CPD_BF16), on the BF16 matrix cores with FP32 accumulation
+ * (FP64 across split-K chunks).  Everything else reads T (FP32 or FP64): the core projection, the
+ * dGN on the core (FP64 throughout, so every CG inner product, the damping update and the final
+ * iterations are FP64) and the final error.  Arguments, workspace (cpd_workspace_bytes of T's
+ * shape) and results as cpd_solve. */
+cpd_status cpd_solve_mixed(const void* T_lo, int32_t lo_dtype, const void* T, int32_t dtype, const int64_t dims[3],
+                           int32_t R, const cpd_params* p, const double* W0, double* W_out[3], double* lambda_out,
+                           cpd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
 size_t cpd_residual_workspace_bytes(const int64_t dims[3]);
 cpd_status cpd_residual_norm2(const void* T, int32_t dtype, const int64_t dims[3],
                               const double* const W[3], int32_t R, double* out, void* ws,

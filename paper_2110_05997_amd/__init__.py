@@ -15,7 +15,7 @@ from ._lib import (CPD_BF16, CPD_F32, CPD_F64, CPD_INIT_GIVEN, CPD_INIT_MLSVD, C
                    STOP_NAMES, CpdError, Params, SolveInfo, StepInfo)
 
 __all__ = ["params", "gram", "eig_top", "compress", "DgnState", "solve", "mttkrp", "residual_norm2",
-           "jtj_v", "Batch", "CpdError", "STOP_NAMES"]
+           "jtj_v", "Batch", "solve_mixed", "CpdError", "STOP_NAMES"]
 
 _DTYPES = {torch.float64: CPD_F64, torch.float32: CPD_F32, torch.bfloat16: CPD_BF16}
 
@@ -273,6 +273,31 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def solve_mixed(T_lo, T, R, p=None, W0=None, ws=None):
+    """cpd_solve with the compression Grams from the BF16 copy T_lo on the BF16 matrix cores and
+    everything else from T.  Returns dict(W, lam, info) like :func:`solve`."""
+    _check_tensor(T)
+    _check_tensor(T_lo)
+    if T_lo.dtype != torch.bfloat16 or tuple(T_lo.shape) != tuple(T.shape):
+        raise ValueError("T_lo must be a BF16 copy of T")
+    L = _lib.lib()
+    if p is None:
+        p = params()
+    dims = _dims(T)
+    if ws is None:
+        ws = _ws(L.cpd_workspace_bytes(dims, R, ctypes.byref(p)), T.device)
+    W = [torch.empty((T.shape[l], R), dtype=torch.float64, device=T.device) for l in range(3)]
+    lam = torch.empty(R, dtype=torch.float64, device=T.device)
+    w0 = None
+    if W0 is not None:
+        w0 = torch.cat([w.reshape(-1) for w in W0]).to(device=T.device, dtype=torch.float64).contiguous()
+    info = SolveInfo()
+    _lib.check(L.cpd_solve_mixed(_ptr(T_lo), CPD_BF16, _ptr(T), _dtype(T), dims, R, ctypes.byref(p), _ptr(w0),
+                                 (ctypes.c_void_p * 3)(*[w.data_ptr() for w in W]), _ptr(lam), ctypes.byref(info),
+                                 _ptr(ws), ws.numel(), _stream()), "cpd_solve_mixed")
+    return dict(W=W, lam=lam, info=_info_dict(info))
 
 
 def mttkrp(T, Ws, mode):

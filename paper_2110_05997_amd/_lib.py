@@ -106,6 +106,9 @@ SIGNATURES = [
     ("cpd_state_factors", ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
     ("cpd_solve", ctypes.c_int, [_P, ctypes.c_int32, _I64x3, ctypes.c_int32, ctypes.POINTER(Params), _P,
                                  _Px3, _P, ctypes.POINTER(SolveInfo), _P, ctypes.c_size_t, _P]),
+    ("cpd_solve_mixed", ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, _I64x3, ctypes.c_int32,
+                                       ctypes.POINTER(Params), _P, _Px3, _P, ctypes.POINTER(SolveInfo), _P,
+                                       ctypes.c_size_t, _P]),
     ("cpd_gram_workspace_bytes", ctypes.c_size_t, [_I64x3, ctypes.c_int32]),
     ("cpd_gram", ctypes.c_int, [_P, ctypes.c_int32, _I64x3, ctypes.c_int32, ctypes.c_int32, _P, _P,
                                 ctypes.c_size_t, _P]),

@@ -73,7 +73,10 @@ void compress_sizes(const int64_t dims[3], const int P[3], Sizer& z) {
 }
 
 // Runs compression with carved workspace; outputs U (compact I_l x R~_l), sigma, S.
-cpd_status run_compress(const void* T, int dtype, const int64_t dims[3], int R, const cpd_params* p,
+// T_gram / gram_dtype / gram_compute: the tensor copy and precision the Grams are formed from
+// (normally T itself); the projection always reads T.
+cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_dtype, int gram_compute,
+                        const int64_t dims[3], int R, const cpd_params* p,
                         double* const U_out[3], double* const sigma_out[3], double* S_out,
                         int core_out[3], Arena& ar, hipStream_t s) {
   int P[3];
@@ -109,7 +112,7 @@ cpd_status run_compress(const void* T, int dtype, const int64_t dims[3], int R, 
   double* laml[3] = {lam, lam + P[0], lam + P[0] + P[1]};
   cpd_status st;
   for (int l = 0; l < 3; ++l)
-    if ((st = gram(T, dtype, dims, l, p ? p->compute_dtype : CPD_F64, G[l], gws, gram_b, s))) return st;
+    if ((st = gram(T_gram, gram_dtype, dims, l, gram_compute, G[l], gws, gram_b, s))) return st;
   // the three eigenproblems run side by side
   prof_begin(CPD_PK_EIG, s);
   st = eig_top3(G, n, P, Uf, laml, 3, ews, eig_b, s);
@@ -225,7 +228,8 @@ cpd_status cpd_compress(const void* T, int32_t dtype, const int64_t dims[3], int
   if (!p) { cpd_default_params(&def); p = &def; }
   Arena ar(ws, ws_bytes);
   int core[3];
-  cpd_status st = run_compress(T, dtype, dims, R, p, U_out, sigma_out, S_out, core, ar, (hipStream_t)stream);
+  cpd_status st = run_compress(T, dtype, T, dtype, p->compute_dtype, dims, R, p, U_out, sigma_out, S_out, core, ar,
+                               (hipStream_t)stream);
   if (st) return st;
   CPD_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
   for (int l = 0; l < 3; ++l) core_dims_out[l] = core[l];
@@ -285,13 +289,12 @@ cpd_status cpd_state_factors(void* state, double* W, int32_t set, void* stream) 
   return state_factors(state, W, set, (hipStream_t)stream);
 }
 
-cpd_status cpd_solve(const void* T, int32_t dtype, const int64_t dims[3], int32_t R,
-                     const cpd_params* p, const double* W0, double* W_out[3], double* lambda_out,
-                     cpd_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
+namespace {
+cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, const void* T, int32_t dtype,
+                      const int64_t dims[3], int32_t R, const cpd_params* p, const double* W0, double* W_out[3],
+                      double* lambda_out, cpd_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
   CPD_REQUIRE(T && W_out && W_out[0] && W_out[1] && W_out[2] && lambda_out && info, "cpd_solve: null argument");
   CPD_REQUIRE(dims_ok(dims) && dtype_ok(dtype) && R >= 1 && R <= 64, "cpd_solve: bad dims/dtype/R");
-  cpd_params def;
-  if (!p) { cpd_default_params(&def); p = &def; }
   CPD_REQUIRE(p->maxiter >= 1 && p->tol >= 0.0, "cpd_solve: bad parameters");
   hipStream_t s = (hipStream_t)stream;
   const size_t need = solve_ws(dims, R, p);
@@ -327,7 +330,8 @@ cpd_status cpd_solve(const void* T, int32_t dtype, const int64_t dims[3], int32_
   if (h_bad) { set_error("cpd_solve: non-finite entries in T"); return CPD_E_NONFINITE; }
   if (!(h_tn2 > 0.0)) { set_error("cpd_solve: ||T|| = 0"); return CPD_E_ZERO_TENSOR; }
   int core[3];
-  if ((st = run_compress(T, dtype, dims, R, p, U, nullptr, S, core, ar, s))) return st;
+  if ((st = run_compress(T, dtype, T_gram, gram_dtype, gram_compute, dims, R, p, U, nullptr, S, core, ar, s)))
+    return st;
   if ((st = state_init(state, S, core, R, W0, h_tn2, p, s))) return st;
   if ((st = dgn_iterate(state, S, p->maxiter, s))) return st;
   int k = 0, stop = 0, ti = -1;
@@ -356,6 +360,25 @@ cpd_status cpd_solve(const void* T, int32_t dtype, const int64_t dims[3], int32_
   info->t_norm = sqrt(h_tn2);
   info->rel_err_full = sqrt(h_res > 0.0 ? h_res : 0.0) / sqrt(h_tn2);
   return CPD_OK;
+}
+}  // namespace
+
+cpd_status cpd_solve(const void* T, int32_t dtype, const int64_t dims[3], int32_t R,
+                     const cpd_params* p, const double* W0, double* W_out[3], double* lambda_out,
+                     cpd_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
+  cpd_params def;
+  if (!p) { cpd_default_params(&def); p = &def; }
+  return solve_impl(T, dtype, p->compute_dtype, T, dtype, dims, R, p, W0, W_out, lambda_out, info, ws, ws_bytes,
+                    stream);
+}
+
+cpd_status cpd_solve_mixed(const void* T_lo, int32_t lo_dtype, const void* T, int32_t dtype, const int64_t dims[3],
+                           int32_t R, const cpd_params* p, const double* W0, double* W_out[3], double* lambda_out,
+                           cpd_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
+  CPD_REQUIRE(T_lo && lo_dtype == CPD_BF16, "cpd_solve_mixed: T_lo must be a BF16 tensor");
+  cpd_params def;
+  if (!p) { cpd_default_params(&def); p = &def; }
+  return solve_impl(T_lo, lo_dtype, CPD_BF16, T, dtype, dims, R, p, W0, W_out, lambda_out, info, ws, ws_bytes, stream);
 }
 
 size_t cpd_gram_workspace_bytes(const int64_t dims[3], int32_t mode) {

