@@ -289,6 +289,50 @@ cpd_status cpd_jtj_v(const double* const W[3], const double* const V[3], const i
                      int32_t R, double* const out[3], void* stream);
 
 /* ------------------------------------------------------------------------------------------ */
+/* Learned initialisation (an extension; the thesis has no learned part): a multilayer          */
+/* perceptron y = W3^T relu(W2^T relu(W1^T x + b1) + b2) + b3 mapping a normalised compressed     */
+/* core (n_in = prod(core dims)) to initial core factors (n_out = R * sum(core dims)), trained   */
+/* with the mean squared error and Adam.  All arrays FP32, device, row-major: W[l] is             */
+/* dims[l] x dims[l+1] with dims = {n_in, n_h1, n_h2, n_out}; a batch is B x n_in (inputs) or    */
+/* B x n_out (outputs).  The GEMMs run on the FP32 matrix cores with FP32 accumulation.          */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n_in, n_h1, n_h2, n_out;
+  float* W[3];
+  float* b[3];
+} cpd_mlp;
+
+typedef struct {
+  float* dW[3];   /* same shapes as the weights */
+  float* db[3];
+} cpd_mlp_grads;
+
+typedef struct {
+  float lr, beta1, beta2, eps;   /* Adam hyper-parameters (Kingma & Ba 2015) */
+  int32_t step;                  /* updates done so far; cpd_mlp_adam_step increments it */
+  float* mW[3];                  /* first and second moments, same shapes as the weights, zeroed */
+  float* mb[3];                  /* by the caller before the first step */
+  float* vW[3];
+  float* vb[3];
+} cpd_adam;
+
+/* Workspace of cpd_mlp_forward / cpd_mlp_backward for batch size B (the hidden activations of the
+ * last forward pass live in it: backward must follow a forward of the same x with the same ws). */
+size_t cpd_mlp_workspace_bytes(const cpd_mlp* net, int32_t B);
+cpd_status cpd_mlp_forward(const cpd_mlp* net, const float* x, float* y, int32_t B, void* ws, size_t ws_bytes,
+                           void* stream);
+/* Mean over n entries of (y - t)^2 into *loss (device float) and its gradient dy = 2 (y - t) / n.
+ * ws: at least 8 KiB (device). */
+cpd_status cpd_mlp_mse(const float* y, const float* t, int64_t n, float* dy, float* loss, void* ws, size_t ws_bytes,
+                       void* stream);
+/* Gradients of a loss with output gradient dy (B x n_out) into g, using the activations left in ws by
+ * cpd_mlp_forward(net, x, ...). */
+cpd_status cpd_mlp_backward(const cpd_mlp* net, const float* x, const float* dy, cpd_mlp_grads* g, int32_t B,
+                            void* ws, size_t ws_bytes, void* stream);
+/* One Adam update of every weight and bias (host struct a: step is incremented on the host). */
+cpd_status cpd_mlp_adam_step(cpd_mlp* net, const cpd_mlp_grads* g, cpd_adam* a, void* stream);
+
+/* ------------------------------------------------------------------------------------------ */
 /* Kernel timing: when enabled, HIP events are recorded on the launch stream around the main   */
 /* kernels of the path; cpd_profile_read waits for them and accumulates durations.  Intended   */
 /* for single-threaded measurement runs.                                                        */

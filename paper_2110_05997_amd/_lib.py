@@ -81,6 +81,21 @@ class BatchItem(ctypes.Structure):
     ]
 
 
+class Mlp(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("n_h1", ctypes.c_int32), ("n_h2", ctypes.c_int32),
+                ("n_out", ctypes.c_int32), ("W", ctypes.c_void_p * 3), ("b", ctypes.c_void_p * 3)]
+
+
+class MlpGrads(ctypes.Structure):
+    _fields_ = [("dW", ctypes.c_void_p * 3), ("db", ctypes.c_void_p * 3)]
+
+
+class Adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("step", ctypes.c_int32), ("mW", ctypes.c_void_p * 3),
+                ("mb", ctypes.c_void_p * 3), ("vW", ctypes.c_void_p * 3), ("vb", ctypes.c_void_p * 3)]
+
+
 PROFILE_KERNELS = ["gram", "dgn", "project", "residual", "mttkrp", "eig"]
 
 _P = ctypes.c_void_p
@@ -132,6 +147,12 @@ SIGNATURES = [
     ("cpd_batch_plan_run", ctypes.c_int, [_P, ctypes.POINTER(SolveInfo), _P]),
     ("cpd_batch_plan_variant", ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_float)]),
     ("cpd_batch_plan_destroy", None, [_P]),
+    ("cpd_mlp_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(Mlp), ctypes.c_int32]),
+    ("cpd_mlp_forward", ctypes.c_int, [ctypes.POINTER(Mlp), _P, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P]),
+    ("cpd_mlp_mse", ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P, _P, ctypes.c_size_t, _P]),
+    ("cpd_mlp_backward", ctypes.c_int, [ctypes.POINTER(Mlp), _P, _P, ctypes.POINTER(MlpGrads), ctypes.c_int32, _P,
+                                        ctypes.c_size_t, _P]),
+    ("cpd_mlp_adam_step", ctypes.c_int, [ctypes.POINTER(Mlp), ctypes.POINTER(MlpGrads), ctypes.POINTER(Adam), _P]),
     ("cpd_profile_enable", None, [ctypes.c_int32]),
     ("cpd_profile_reset", None, []),
     ("cpd_profile_read", ctypes.c_int, [ctypes.POINTER(KernelTime)]),
