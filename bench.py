@@ -36,7 +36,45 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-solve", action="store_true", help="skip the kernel-level extras")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 512 MiB three times (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+# HBM bytes per launch of a kernel, measured with two rocprofv3 --pmc passes (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch) over `bench.py --only-solve` and scaled by the same counters' reading
+# for a plain copy of known size (`bench.py --copy-calibration`).  A figure is reported only while
+# the kernel's sources hash to the digest it was taken with.
+TRAFFIC = {}
+
+
+def source_digest(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2110_05997_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_of(kernel):
+    t = TRAFFIC.get(kernel)
+    if t is None or source_digest(t["sources"]) != t["digest"]:
+        return None
+    return t["bytes"]
+
+
+def copy_calibration():
+    import torch
+    n = 64 << 20                       # 64 Mi doubles = 512 MiB each way
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.neg(a, out=b)            # one elementwise kernel: reads 512 MiB, writes 512 MiB
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_kib_each_way": n * 8 / 1024, "launches": 3}), flush=True)
 
 
 def dgn_flops(core, R, log):
@@ -56,6 +94,10 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(see DESIGN.md for how the work would shard)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import numpy as np
     import torch
@@ -119,7 +161,7 @@ def main():
         achieved, unit = units / avg_s / 1e12, "TFLOP/s"
     peak = PEAK[peak_key]
     roofline = {"kernel": dominant, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": None,
+                "frac": achieved / peak, "traffic": traffic_of(dominant),
                 "algorithmic_per_launch": units}
 
     out = {
@@ -204,6 +246,7 @@ def main():
         B.close()
 
         out["c3_600cube"] = bench_600cube(cp, synth, torch, dev)
+        out["c5_learned_init"] = bench_learned(torch)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(T, R, core, U)
@@ -248,6 +291,28 @@ def bench_600cube(cp, synth, torch, dev):
             "iters_bf16_grams": res["bf16_grams"]["info"]["iters"],
             "iters_fp64_grams": res["fp64_grams"]["info"]["iters"],
             "reconstruction_diff_bf16_vs_fp64": cpd_diff(res["bf16_grams"], res["fp64_grams"], torch)}
+
+
+def bench_learned(torch, n_train=8192, epochs=20, n_test=100):
+    """Learned vs MLSVD-energy vs N(0,1) starting points on new planted 100^3 rank-8 tensors compressed
+    to a 16^3 core: the network (4096 -> 1024 -> 1024 -> 384) is trained here on n_train solver-
+    generated pairs (the full 100k-pair run is the module's own driver: python -m
+    paper_2110_05997_amd.learned)."""
+    from paper_2110_05997_amd import learned as lr
+    t0 = time.perf_counter()
+    X, T, kept = lr.make_dataset(n_train, seed=0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    net, hist = lr.train(X, T, epochs=epochs, batch=256)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    summ = lr.summarize(lr.evaluate(net, n_test, seed=1))
+    steps = epochs * (kept // 256)
+    flops_per_step = 6 * 256 * sum(a * b for a, b in zip(net.sizes[:-1], net.sizes[1:]))
+    return {"workload": "planted 100^3 rank 8 (noiseless) -> fixed 16^3 core; MLP 4096-1024-1024-384",
+            "n_train_requested": n_train, "n_train_kept": kept, "data_s": t1 - t0, "train_s": t2 - t1,
+            "train_tflops": steps * flops_per_step / (t2 - t1) / 1e12, "loss_first_last": [hist[0], hist[-1]],
+            "n_test": n_test, "eval": summ}
 
 
 def cpu_baseline(T, R, core, U):

@@ -71,6 +71,10 @@ __device__ __forceinline__ double bf16_bits_to_f64(uint16_t b) {
 
 // Sum over a 64-wide wavefront; every lane gets the result.  Fixed butterfly order keeps the
 // result identical run to run.
+// Index of the calling wave within its workgroup, as a wave-uniform (scalar) value, so that
+// tile indices derived from it stay in scalar registers and branches on them are uniform.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -108,7 +108,7 @@ __device__ void setup_ctx(Ctx& c, double* lds, const int d[3], int R, const doub
 // pi^(l) = W^(l)T W^(l) on the matrix cores, then Pi^(l); ends with a barrier.
 __device__ void grams(Ctx& c) {
   const int R = c.R, RR = R * R, tr = tiles16(R);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r16 = lane & 15, kq = lane >> 4;
+  const int lane = threadIdx.x & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
   for (int t = w; t < 3 * tr * tr; t += NW) {
     const int l = t / (tr * tr), tt = t - l * tr * tr, tm = tt / tr, tn = tt - tm * tr;
     const double* Wl = c.W + offof(c, l);
@@ -162,7 +162,7 @@ __device__ void precond(Ctx& c, double mu) {
 // without a barrier after phase 2.
 __device__ double hv(Ctx& c, const double* V, double* out, double mu, bool scale) {
   const int R = c.R, RR = R * R, tr = tiles16(R);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r16 = lane & 15, kq = lane >> 4;
+  const int lane = threadIdx.x & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
   for (int t = w; t < 3 * tr * tr; t += NW) {
     const int b = t / (tr * tr), tt = t - b * tr * tr, tm = tt / tr, tn = tt - tm * tr;
     const double* Vb = V + offof(c, b);
@@ -261,7 +261,7 @@ __device__ double residual_mttkrp(Ctx& c, double* slots) {
   const double* W1 = c.W + c.off1;
   const double* W2 = c.W + c.off2;
   const double* S = c.S;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r16 = lane & 15, kq = lane >> 4;
+  const int lane = threadIdx.x & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
   const int n0 = tiles16(d0) * tr, n1 = n0 + tiles16(d1) * tr, n2 = n1 + tiles16(d2) * tr;
   const int nres = tiles16(d0) * tiles16(d12);
   const int R1 = R - 1;

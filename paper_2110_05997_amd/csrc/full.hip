@@ -17,33 +17,71 @@ __device__ __forceinline__ double ldv(const T* p, long long i) { return (double)
 template <>
 __device__ __forceinline__ double ldv<uint16_t>(const uint16_t* p, long long i) { return bf16_bits_to_f64(p[i]); }
 
-// One fibre (i, j) at a time: a_r = W0[i][r] W1[j][r] staged in LDS, threads over k.
-template <class T>
+// Tiles of RJB fibres (i, j0..j0+RJB-1) with threads over k: the R values W2[k][.] of a thread's k
+// stay in registers (R <= 8 RC), a_jr = W0[i][r] W1[j][r] of the tile is staged in LDS and read
+// by broadcast, and the RJB model values of a thread are independent FMA chains.  Each model
+// value is sum_r a_jr W2[k][r] in increasing r.  Fixed grid, fixed order: bit-reproducible.
+constexpr int RJB = 8;
+
+template <class T, int RC>
 __global__ __launch_bounds__(RNT) void residual_kernel(const T* __restrict__ X, int I1, int I2, int I3,
                                                        const double* __restrict__ W0,
                                                        const double* __restrict__ W1,
                                                        const double* __restrict__ W2, int R,
                                                        double* __restrict__ part) {
-  __shared__ double a[64];
+  constexpr int RM = 8 * RC;
+  __shared__ double a[RJB][RM];
   __shared__ double slots[RNT / 64];
-  const long long nf = (long long)I1 * I2;
+  const int njb = (I2 + RJB - 1) / RJB;
+  const int ntiles = I1 * njb;
+  const int R1 = R - 1;
   double acc = 0.0;
-  for (long long f = blockIdx.x; f < nf; f += gridDim.x) {
-    const int i = (int)(f / I2), j = (int)(f % I2);
-    __syncthreads();
-    if (threadIdx.x < R) a[threadIdx.x] = W0[(long long)i * R + threadIdx.x] * W1[(long long)j * R + threadIdx.x];
-    __syncthreads();
-    const long long base = f * I3;
-    for (int k = threadIdx.x; k < I3; k += RNT) {
-      const double* w2 = W2 + (long long)k * R;
-      double model = 0.0;
-      for (int r = 0; r < R; ++r) model += a[r] * w2[r];
-      const double d = ldv(X, base + k) - model;
-      acc += d * d;
+  for (int k0 = 0; k0 < I3; k0 += RNT) {
+    const int k = k0 + (int)threadIdx.x;
+    const bool kin = k < I3;
+    const int kc = kin ? k : I3 - 1;
+    double w[RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) w[r] = (r < R) ? W2[(size_t)kc * R + min(r, R1)] : 0.0;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+      const int i = t / njb, j0 = (t - i * njb) * RJB;
+      __syncthreads();
+      for (int e = threadIdx.x; e < RJB * RM; e += RNT) {
+        const int jj = e / RM, r = e - jj * RM;
+        const int j = j0 + jj;
+        a[jj][r] = (j < I2 && r < R) ? W0[(size_t)i * R + min(r, R1)] * W1[(size_t)min(j, I2 - 1) * R + min(r, R1)] : 0.0;
+      }
+      __syncthreads();
+      const int nj = min(RJB, I2 - j0);
+      const T* x = X + ((size_t)i * I2 + j0) * I3 + kc;
+#pragma unroll
+      for (int jj = 0; jj < RJB; ++jj) {
+        double model = 0.0;
+#pragma unroll
+        for (int r = 0; r < RM; ++r) model += a[jj][r] * w[r];
+        const double d = ldv(x, (long long)min(jj, nj - 1) * I3) - model;
+        acc += (kin && jj < nj) ? d * d : 0.0;
+      }
     }
   }
   const double s = block_sum(acc, slots);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <class T>
+void launch_residual(const T* X, int I1, int I2, int I3, const double* const W[3], int R, double* part,
+                     hipStream_t s) {
+  switch ((R + 7) / 8) {
+#define CPD_RES_CASE(rc)                                                                               \
+  case rc:                                                                                             \
+    hipLaunchKernelGGL((residual_kernel<T, rc>), dim3(RB), dim3(RNT), 0, s, X, I1, I2, I3, W[0], W[1], \
+                       W[2], R, part);                                                                 \
+    break;
+    CPD_RES_CASE(1) CPD_RES_CASE(2) CPD_RES_CASE(3) CPD_RES_CASE(4)
+    CPD_RES_CASE(5) CPD_RES_CASE(6) CPD_RES_CASE(7) CPD_RES_CASE(8)
+#undef CPD_RES_CASE
+    default: break;
+  }
 }
 
 template <class T>
@@ -166,16 +204,13 @@ cpd_status residual_full(const void* T, int dtype, const int64_t dims[3], const 
   prof_begin(CPD_PK_RESIDUAL, s);
   switch (dtype) {
     case CPD_F64:
-      hipLaunchKernelGGL(residual_kernel<double>, dim3(RB), dim3(RNT), 0, s, (const double*)T, I1, I2, I3,
-                         W[0], W[1], W[2], R, part);
+      launch_residual((const double*)T, I1, I2, I3, W, R, part, s);
       break;
     case CPD_F32:
-      hipLaunchKernelGGL(residual_kernel<float>, dim3(RB), dim3(RNT), 0, s, (const float*)T, I1, I2, I3,
-                         W[0], W[1], W[2], R, part);
+      launch_residual((const float*)T, I1, I2, I3, W, R, part, s);
       break;
     case CPD_BF16:
-      hipLaunchKernelGGL(residual_kernel<uint16_t>, dim3(RB), dim3(RNT), 0, s, (const uint16_t*)T, I1, I2,
-                         I3, W[0], W[1], W[2], R, part);
+      launch_residual((const uint16_t*)T, I1, I2, I3, W, R, part, s);
       break;
     default:
       set_error("residual_full: bad dtype");
