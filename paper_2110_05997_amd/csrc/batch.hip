@@ -126,7 +126,8 @@ __global__ __launch_bounds__(JNT) void batch_eig_kernel(const BItem* __restrict_
   const BItem& it = items[b];
   const int I = it.d[mode], P = it.P[mode];
   double* V = it.V[mode];
-  jacobi_block(it.G[mode], I, I, it.ev[mode], V);
+  __shared__ JacobiLds L;
+  jacobi_block<JNT>(L, it.G[mode], I, I, it.ev[mode], V);
   __syncthreads();
   // first P eigenvectors, each signed so that its largest-|.| entry is positive (ties: lowest
   // index); one wave per column

@@ -19,6 +19,7 @@
 // All arithmetic is FP64; reductions use a fixed order, so a run is bit-reproducible.
 #include "common.h"
 #include "dgn_state.h"
+#include "mfma_f64.h"
 
 #include <math.h>
 #include <string.h>
@@ -48,49 +49,20 @@ __device__ __forceinline__ void split_index(const Ctx& c, int e, int& l, int& i,
   r = loc - i * c.R;
 }
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
-// One 16x16 output tile C[m0.., n0..] = sum_k A(m, k) B(k, n) on v_mfma_f64_16x16x4f64.
-// Lane layout: A fragment A[lane%16][lane/16], B fragment B[lane/16][lane%16], result
-// D[4v + lane/16][lane%16] in acc[v].  fa / fb return 0 outside the operands.
-template <class FA, class FB>
-__device__ __forceinline__ dbl4 mfma_tile(int m0, int n0, int K, FA fa, FB fb) {
-  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
-  dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-  // fragments of four k-steps are loaded before their MFMAs, which alternate between two
-  // accumulators, so LDS latency and the MFMA dependency chain overlap
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    double a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = k0 + 4 * u + kq;
-      a[u] = fa(m0 + r16, k);
-      b[u] = fb(k, n0 + r16);
-    }
-    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], acc1, 0, 0, 0);
-    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], b[2], acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], b[3], acc1, 0, 0, 0);
-  }
-  return acc0 + acc1;
-}
-
-__device__ __forceinline__ int tiles16(int n) { return (n + 15) >> 4; }
-
 // q = floor(x / d) for 0 <= x < 2^26 through a double reciprocal (exact: the error of
 // (x + 0.5) * inv is far below the distance 0.5 / d to an integer).
 __device__ __forceinline__ int div_by(int x, double inv) { return (int)(((double)x + 0.5) * inv); }
 
 __device__ __forceinline__ double sel(bool ok, double v) { return ok ? v : 0.0; }
 
-__device__ void setup_ctx(Ctx& c, double* lds, const int d[3], int R, const double* S) {
+__device__ void setup_ctx(Ctx& c, double* lds, const int d[3], int R, const double* S, double* MK, double* G) {
   c.d0 = d[0]; c.d1 = d[1]; c.d2 = d[2]; c.R = R;
   c.off1 = d[0] * R; c.off2 = (d[0] + d[1]) * R;
   c.np = (d[0] + d[1] + d[2]) * R;
   double* p = lds;
   c.W = p; p += c.np;
-  c.MK = p; p += c.np;
-  c.G = p; p += c.np;
+  c.MK = MK;
+  c.G = G;
   c.X = p; p += c.np;
   c.Rv = p; p += c.np;
   c.P = p; p += c.np;
@@ -348,17 +320,27 @@ __device__ int stop_test(const double* errs, int k, double step, double grad_inf
 }
 
 // mode 0: initialise the state from the W stored in it; mode 1: run up to max_steps iterations.
+// SL: the core S is copied into LDS after the working set (the caller sized the LDS for it).
+template <bool SL>
 __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double* __restrict__ S, int mode, int max_steps,
                          double* lds, int& s_stop) {
   Hdr* h = (Hdr*)state;
   const int R = h->R;
   int d[3] = {h->d[0], h->d[1], h->d[2]};
   const int maxiter = h->maxiter;
-  Ctx c;
-  setup_ctx(c, lds, d, R, S);
-  const Layout Lo = layout_of(c.np, R, maxiter);
+  const int np = (d[0] + d[1] + d[2]) * R;
+  const Layout Lo = layout_of(np, R, maxiter);
   double* gW = (double*)(state + Lo.W);
   double* gMK = (double*)(state + Lo.MK);
+  Ctx c;
+  if (SL) {
+    double* Sl = lds + lds_doubles(np, R);
+    const int n3 = d[0] * d[1] * d[2];
+    for (int e = threadIdx.x; e < n3; e += NT) Sl[e] = S[e];
+    setup_ctx(c, lds, d, R, Sl, gMK, (double*)(state + Lo.G));
+  } else {
+    setup_ctx(c, lds, d, R, S, gMK, (double*)(state + Lo.G));
+  }
   double* errs = (double*)(state + Lo.errs);
   const int* caps = (const int*)(state + Lo.caps);
   cpd_step_info* logp = (cpd_step_info*)(state + Lo.log);
@@ -381,7 +363,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     s2 = block_sum(s2, slotB);
     sa = block_sum(sa, slotA);
     const double f2 = residual_mttkrp(c, slotB);
-    for (int e = tid; e < c.np; e += NT) { gW[e] = c.W[e]; gMK[e] = c.MK[e]; }
+    for (int e = tid; e < c.np; e += NT) gW[e] = c.W[e];
     if (tid == 0) {
       const double s_norm = sqrt(s2);
       h->s_norm = s_norm;
@@ -398,7 +380,6 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     return;
   }
 
-  for (int e = tid; e < c.np; e += NT) c.MK[e] = gMK[e];
   double mu = h->mu, f2 = h->f2;
   const double s_norm = h->s_norm, div_ref = h->div_ref, tol = h->tol, cg_tol = h->cg_tol;
   int k = h->k, stop = h->stop, tol_iter = h->tol_iter;
@@ -493,17 +474,18 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     mu = mu_new;
     f2 = f2_new;
   }
-  for (int e = tid; e < c.np; e += NT) { gW[e] = c.W[e]; gMK[e] = c.MK[e]; }
+  for (int e = tid; e < c.np; e += NT) gW[e] = c.W[e];
   if (tid == 0) {
     h->mu = mu; h->f2 = f2; h->k = k; h->stop = stop; h->tol_iter = tol_iter;
   }
 }
 
+template <bool SL>
 __global__ __launch_bounds__(NT) void dgn_kernel(char* __restrict__ state, const double* __restrict__ S,
                                                  int mode, int max_steps) {
   extern __shared__ double lds[];
   __shared__ int s_stop;
-  dgn_body(state, S, mode, max_steps, lds, s_stop);
+  dgn_body<SL>(state, S, mode, max_steps, lds, s_stop);
 }
 
 // Same iteration for states too large for LDS: the working set lives in the state's own work
@@ -513,7 +495,7 @@ __global__ __launch_bounds__(NT) void dgn_kernel_g(char* __restrict__ state, con
   __shared__ int s_stop;
   const Hdr* h = (const Hdr*)state;
   const Layout Lo = layout_of(h->np, h->R, h->maxiter);
-  dgn_body(state, S, mode, max_steps, (double*)(state + Lo.work), s_stop);
+  dgn_body<false>(state, S, mode, max_steps, (double*)(state + Lo.work), s_stop);
 }
 
 // Batched: workgroup b initialises state b (header, caps and W already written) and iterates it
@@ -526,10 +508,10 @@ __global__ __launch_bounds__(NT) void dgn_batch_kernel(char* const* __restrict__
   if (b >= n) return;
   char* st = states[b];
   if (((const Hdr*)st)->flags & 2) return;   // member rejected (zero or non-finite tensor)
-  dgn_body(st, S[b], 0, 0, lds, s_stop);
+  dgn_body<false>(st, S[b], 0, 0, lds, s_stop);
   __syncthreads();
   const int maxiter = ((const Hdr*)st)->maxiter;
-  dgn_body(st, S[b], 1, maxiter, lds, s_stop);
+  dgn_body<false>(st, S[b], 1, maxiter, lds, s_stop);
 }
 
 // MLSVD-energy initial point (ch.4 "Initialization"): the R entries of largest |s| (ties: smallest
@@ -599,7 +581,7 @@ __global__ __launch_bounds__(NT) void jtjv_kernel(const double* W0, const double
   extern __shared__ double lds[];
   Ctx c;
   int d[3] = {d0, d1, d2};
-  setup_ctx(c, lds, d, R, nullptr);
+  setup_ctx(c, lds, d, R, nullptr, nullptr, nullptr);
   const double* Ws[3] = {W0, W1, W2};
   const double* Vs[3] = {V0, V1, V2};
   double* Os[3] = {O0, O1, O2};
@@ -620,10 +602,12 @@ __global__ __launch_bounds__(NT) void jtjv_kernel(const double* W0, const double
   }
 }
 
+constexpr size_t LDS_LIMIT = 160 * 1024 - 1024;   // dynamic LDS available next to the static slots
+
 bool lds_fits(int np, int R, size_t* bytes) {
   const size_t b = lds_doubles(np, R) * sizeof(double);
   if (bytes) *bytes = b;
-  return b <= 160 * 1024 - 1024;
+  return b <= LDS_LIMIT;
 }
 
 }  // namespace
@@ -653,11 +637,18 @@ int cg_cap_for(int k, double u) {
 namespace {
 // The persistent dGN kernel with its working set in LDS when it fits, else in the state's work
 // region.
-cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int np, int R, hipStream_t s) {
+cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int np, int R, int n3,
+                      hipStream_t s) {
   size_t lb;
-  if (lds_fits(np, R, &lb)) {
-    CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
-    hipLaunchKernelGGL(dgn_kernel, dim3(1), dim3(NT), lb, s, state, S, mode, max_steps);
+  if (lds_fits(np, R, &lb) && lb + (size_t)n3 * sizeof(double) <= LDS_LIMIT) {
+    lb += (size_t)n3 * sizeof(double);
+    CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lb));
+    hipLaunchKernelGGL(dgn_kernel<true>, dim3(1), dim3(NT), lb, s, state, S, mode, max_steps);
+  } else if (lds_fits(np, R, &lb)) {
+    CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lb));
+    hipLaunchKernelGGL(dgn_kernel<false>, dim3(1), dim3(NT), lb, s, state, S, mode, max_steps);
   } else {
     hipLaunchKernelGGL(dgn_kernel_g, dim3(1), dim3(NT), 0, s, state, S, mode, max_steps);
   }
@@ -730,7 +721,7 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
     return CPD_E_INVALID;
   }
   cpd_status lst;
-  if ((lst = launch_dgn(st, S, 0, 0, np, R, s))) return lst;
+  if ((lst = launch_dgn(st, S, 0, 0, np, R, core[0] * core[1] * core[2], s))) return lst;
   int flags = 0;
   CPD_HIP_CHECK(hipMemcpyAsync(&flags, st + offsetof(Hdr, flags), sizeof(int), hipMemcpyDeviceToHost, s));
   CPD_HIP_CHECK(hipStreamSynchronize(s));
@@ -744,7 +735,7 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
 size_t dgn_lds_bytes(int np, int R) { return lds_doubles(np, R) * sizeof(double); }
 
 cpd_status dgn_batch_prepare(size_t lds_bytes) {
-  if (lds_bytes > 160 * 1024 - 1024) {
+  if (lds_bytes > LDS_LIMIT) {
     set_error("dgn batch: a member needs %zu bytes of LDS", lds_bytes);
     return CPD_E_UNSUPPORTED;
   }
@@ -768,7 +759,7 @@ cpd_status dgn_iterate(void* state, const double* S, int max_steps, hipStream_t 
     return CPD_E_INVALID;
   }
   prof_begin(CPD_PK_DGN, s);
-  const cpd_status st = launch_dgn((char*)state, S, 1, max_steps, h.np, h.R, s);
+  const cpd_status st = launch_dgn((char*)state, S, 1, max_steps, h.np, h.R, h.d[0] * h.d[1] * h.d[2], s);
   prof_end(CPD_PK_DGN, s);
   return st;
 }

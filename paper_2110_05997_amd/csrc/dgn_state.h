@@ -22,7 +22,7 @@ struct Hdr {
 static_assert(sizeof(Hdr) <= 256, "header must fit its slot");
 
 struct Layout {
-  size_t W, MK, errs, caps, log, work, total;
+  size_t W, MK, G, errs, caps, log, work, total;
 };
 
 __host__ __device__ inline size_t lds_doubles(int np, int R);
@@ -33,6 +33,7 @@ __host__ __device__ inline Layout layout_of(int np, int R, int maxiter) {
   size_t off = 256;
   L.W = off; off += (size_t)np * 8;
   L.MK = off; off += (size_t)np * 8;
+  L.G = off; off += (size_t)np * 8;
   L.errs = off; off += (size_t)(maxiter + 1) * 8;
   L.caps = off; off += ((size_t)maxiter * 4 + 7) / 8 * 8;
   L.log = off; off += (size_t)maxiter * sizeof(cpd_step_info);
@@ -42,9 +43,12 @@ __host__ __device__ inline Layout layout_of(int np, int R, int maxiter) {
   return L;
 }
 
-// LDS footprint in doubles
+// LDS footprint in doubles of the working set (W and the CG vectors X, r, p, z; the R x R
+// Grams and products; preconditioner and regularisation scalars; reduction slots).  The MTTKRP and
+// the gradient stay in the state (each is written and read once per iteration); the core S is
+// staged after the working set when it fits.
 __host__ __device__ inline size_t lds_doubles(int np, int R) {
-  return (size_t)7 * np + (size_t)12 * R * R + (size_t)6 * R + 2 * NW + 16;
+  return (size_t)5 * np + (size_t)12 * R * R + (size_t)6 * R + 2 * NW + 16;
 }
 
 }  // namespace cpd

@@ -13,6 +13,7 @@
 // index), the convention the oracle applies to its singular vectors.
 #include "common.h"
 #include "jacobi.h"
+#include "mfma_f64.h"
 
 #include <string.h>
 
@@ -26,7 +27,8 @@ namespace {
 __global__ __launch_bounds__(JNT) void jacobi_kernel(const double* __restrict__ Ag, int n, int lda,
                                                      double* __restrict__ lam,
                                                      double* __restrict__ Vout) {
-  jacobi_block(Ag, n, lda, lam, Vout);
+  __shared__ JacobiLds L;
+  jacobi_block<JNT>(L, Ag, n, lda, lam, Vout);
 }
 
 // Copies the first P columns of X (n x ldx) into U (n x P) and signs each column so its
@@ -224,6 +226,287 @@ __global__ void ritz_residual_kernel(const double* __restrict__ ZV, int ldz, con
   }
 }
 
+// ---- whole subspace iteration in one workgroup -------------------------------------------------
+// For moderate n the iteration above is a chain of small dependent launches.  The kernel below
+// runs the same algorithm (start block, Cholesky-QR, four power steps, Rayleigh-Ritz until the
+// Ritz residual test passes, signs) inside one workgroup per problem: the n x k blocks live in
+// the workspace (L2-resident), the k x k matrices in LDS, products on the FP64 matrix cores.
+constexpr int FNT = 1024;           // threads of the fused solver
+constexpr int FNW = FNT / 64;
+constexpr int FUSED_NMAX = 320;      // largest order handled by one workgroup
+
+struct FusedLds {
+  union {
+    JacobiLds jac;
+    struct {
+      double C[JMAX][JMAX + 1];      // Gram of the block, then its Cholesky factor R (upper)
+      double M[JMAX][JMAX + 1];      // D R^{-1}
+      double dsc[JMAX];
+    } qr;
+  } u;
+  double coef[JMAX];
+  double red[2][FNW];
+  double colmax[FNW];
+  int bad;
+};
+
+// Orders the LDS accesses of the lanes of one wave (no other wave takes part).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// out(m, c) = sum_t A(m, t) B(t, c) over 16 x 16 tiles spread over the waves; fa / fb return 0
+// outside the operands (clamped indices), st stores an in-range entry.
+template <class FA, class FB, class FS>
+__device__ __forceinline__ void wg_gemm(int M, int N, int K, FA fa, FB fb, FS st) {
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int tm = tiles16(M), tn = tiles16(N);
+  for (int t = w; t < tm * tn; t += FNW) {
+    const int bm = t / tn, bn = t - bm * tn;
+    const dbl4 acc = mfma_tile(bm * 16, bn * 16, K, fa, fb);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = bm * 16 + 4 * v + (lane >> 4), c = bn * 16 + (lane & 15);
+      if (r < M && c < N) st(r, c, acc[v]);
+    }
+  }
+}
+
+// One Cholesky-QR pass Out = X D R^{-1}, D C D = R^T R, C = X^T X, D = diag(C)^{-1/2} (n x k, row
+// major).  Returns (uniformly) whether a pivot fell below 1e-13; Out is then not written.
+__device__ bool cholqr_pass(FusedLds& S, const double* X, int n, int k, double* Out) {
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int n1 = n - 1, k1 = k - 1;
+  wg_gemm(k, k, n,
+      [&](int r, int i) { return (r < k && i < n) ? X[min(i, n1) * k + min(r, k1)] : 0.0; },
+      [&](int i, int c) { return (c < k && i < n) ? X[min(i, n1) * k + min(c, k1)] : 0.0; },
+      [&](int r, int c, double v) { S.u.qr.C[r][c] = v; });
+  __syncthreads();
+  if (w == 0) {
+    // lane c owns column c: scaling, right-looking factorisation, then column c of R^{-1}
+    const int c = lane;
+    double (*A)[JMAX + 1] = S.u.qr.C;
+    double (*Mi)[JMAX + 1] = S.u.qr.M;
+    if (c < k) {
+      const double cc = A[c][c];
+      S.u.qr.dsc[c] = (cc > 0.0) ? 1.0 / sqrt(cc) : 1.0;
+    }
+    wave_sync();
+    if (c < k)
+      for (int r = 0; r <= c; ++r) A[r][c] = S.u.qr.dsc[r] * A[r][c] * S.u.qr.dsc[c];
+    wave_sync();
+    int fail = 0;
+    for (int j = 0; j < k; ++j) {
+      const double piv = A[j][j];
+      if (!(piv > 1e-13)) fail = 1;
+      const double d = sqrt(fmax(piv, 1e-300));
+      wave_sync();
+      if (c >= j && c < k) A[j][c] = (c == j) ? d : A[j][c] / d;
+      wave_sync();
+      if (c > j && c < k) {
+        const double rjc = A[j][c];
+        int r = j + 1;
+        for (; r + 3 <= c; r += 4) {
+          const double x0 = A[j][r], x1 = A[j][r + 1], x2 = A[j][r + 2], x3 = A[j][r + 3];
+          const double y0 = A[r][c], y1 = A[r + 1][c], y2 = A[r + 2][c], y3 = A[r + 3][c];
+          A[r][c] = y0 - x0 * rjc;
+          A[r + 1][c] = y1 - x1 * rjc;
+          A[r + 2][c] = y2 - x2 * rjc;
+          A[r + 3][c] = y3 - x3 * rjc;
+        }
+        for (; r <= c; ++r) A[r][c] -= A[j][r] * rjc;
+      }
+      wave_sync();
+    }
+    if (c < k) {
+      // R x = e_c by back substitution; Mi[i][c] = dsc[i] x[i]
+      Mi[c][c] = 1.0 / A[c][c];
+      for (int i = c - 1; i >= 0; --i) {
+        double acc = 0.0;
+        for (int t = i + 1; t <= c; ++t) acc += A[i][t] * Mi[t][c];
+        Mi[i][c] = -acc / A[i][i];
+      }
+      for (int i = 0; i <= c; ++i) Mi[i][c] *= S.u.qr.dsc[i];
+      for (int i = c + 1; i < k; ++i) Mi[i][c] = 0.0;
+    }
+    if (lane == 0) S.bad = fail;
+  }
+  __syncthreads();
+  const bool bad = S.bad != 0;
+  if (!bad) {
+    wg_gemm(n, k, k,
+        [&](int i, int t) { return (i < n && t < k) ? X[min(i, n1) * k + min(t, k1)] : 0.0; },
+        [&](int t, int c) { return (t < k && c < k) ? S.u.qr.M[min(t, k1)][min(c, k1)] : 0.0; },
+        [&](int i, int c, double v) { Out[i * k + c] = v; });
+  }
+  __syncthreads();
+  return bad;
+}
+
+// Classical Gram-Schmidt with one re-orthogonalisation pass on the k columns of Z (n x k) in
+// place; a column whose norm collapses below 1e-12 of its original norm restarts from a
+// pseudo-random vector (the breakdown fallback of the Cholesky-QR).
+__device__ void cgs2(FusedLds& S, double* Z, int n, int k, uint64_t seed) {
+  const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
+  int flip = 0;
+  for (int j = 0; j < k; ++j) {
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      double s = 0.0;
+      for (int i = tid; i < n; i += FNT) s += Z[i * k + j] * Z[i * k + j];
+      const double nrm0 = sqrt(block_sum(s, S.red[flip])); flip ^= 1;
+      for (int pass = 0; pass < 2 && j > 0; ++pass) {
+        for (int c = w; c < j; c += FNW) {
+          double d = 0.0;
+          for (int i = lane; i < n; i += 64) d += Z[i * k + c] * Z[i * k + j];
+          d = wave_sum(d);
+          if (lane == 0) S.coef[c] = d;
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += FNT) {
+          double v = Z[i * k + j];
+          for (int c = 0; c < j; ++c) v -= S.coef[c] * Z[i * k + c];
+          Z[i * k + j] = v;
+        }
+        __syncthreads();
+      }
+      s = 0.0;
+      for (int i = tid; i < n; i += FNT) s += Z[i * k + j] * Z[i * k + j];
+      const double nrm = sqrt(block_sum(s, S.red[flip])); flip ^= 1;
+      if (nrm > 1e-12 * nrm0 && nrm > 1e-300) {
+        const double inv = 1.0 / nrm;
+        for (int i = tid; i < n; i += FNT) Z[i * k + j] *= inv;
+        __syncthreads();
+        break;
+      }
+      for (int i = tid; i < n; i += FNT)
+        Z[i * k + j] = 2.0 * u01_from_bits(splitmix64(seed + 0x9E37ull * (uint64_t)(j + 1) +
+                                                      0x1000193ull * (uint64_t)(attempt + 1) +
+                                                      (uint64_t)i * 0x85EBCA6Bull)) - 1.0;
+      __syncthreads();
+    }
+  }
+}
+
+// Orthonormal basis Q of the columns of Y: one or two Cholesky-QR passes, CGS2 on Y's copy when a
+// pass breaks down.  Y is left unchanged.
+__device__ void cholqr(FusedLds& S, const double* Y, int n, int k, double* Q, double* Qt, bool twice,
+                       uint64_t seed) {
+  bool bad = cholqr_pass(S, Y, n, k, twice ? Qt : Q);
+  if (twice && !bad) bad = cholqr_pass(S, Qt, n, k, Q);
+  if (bad) {
+    for (int e = threadIdx.x; e < n * k; e += FNT) Q[e] = Y[e];
+    __syncthreads();
+    cgs2(S, Q, n, k, seed);
+  }
+}
+
+struct FusedBufs {
+  double *Q, *Y, *Z, *Qt, *B, *Vb, *theta, *Uw;
+};
+
+// Rayleigh-Ritz on span(Q): Z = G Q, B = Q^T Z, (theta, Vb) = eig(B), Uw = Q Vb[:, :P],
+// Y = Z Vb; returns max_j<P ||Y[:, j] - theta_j Uw[:, j]|| / |theta_0|.
+__device__ double rayleigh_ritz(FusedLds& S, const double* G, int n, int P, int k, const FusedBufs& b) {
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int n1 = n - 1, k1 = k - 1;
+  const double* Q = b.Q;
+  double* Z = b.Z;
+  wg_gemm(n, k, n,
+      [&](int i, int t) { return (i < n && t < n) ? G[min(i, n1) * n + min(t, n1)] : 0.0; },
+      [&](int t, int c) { return (t < n && c < k) ? Q[min(t, n1) * k + min(c, k1)] : 0.0; },
+      [&](int i, int c, double v) { Z[i * k + c] = v; });
+  __syncthreads();
+  double* B = b.B;
+  wg_gemm(k, k, n,
+      [&](int r, int i) { return (r < k && i < n) ? Q[min(i, n1) * k + min(r, k1)] : 0.0; },
+      [&](int i, int c) { return (c < k && i < n) ? Z[min(i, n1) * k + min(c, k1)] : 0.0; },
+      [&](int r, int c, double v) { B[r * k + c] = v; });
+  __syncthreads();
+  jacobi_block<FNT>(S.u.jac, B, k, k, b.theta, b.Vb);
+  __syncthreads();
+  const double* Vb = b.Vb;
+  double* Uw = b.Uw;
+  double* Y = b.Y;
+  const int P1 = P - 1;
+  wg_gemm(n, P, k,
+      [&](int i, int t) { return (i < n && t < k) ? Q[min(i, n1) * k + min(t, k1)] : 0.0; },
+      [&](int t, int c) { return (t < k && c < P) ? Vb[min(t, k1) * k + min(c, P1)] : 0.0; },
+      [&](int i, int c, double v) { Uw[i * P + c] = v; });
+  wg_gemm(n, k, k,
+      [&](int i, int t) { return (i < n && t < k) ? Z[min(i, n1) * k + min(t, k1)] : 0.0; },
+      [&](int t, int c) { return (t < k && c < k) ? Vb[min(t, k1) * k + min(c, k1)] : 0.0; },
+      [&](int i, int c, double v) { Y[i * k + c] = v; });
+  __syncthreads();
+  // one wave per wanted column
+  double worst = 0.0;
+  for (int j = w; j < P; j += FNW) {
+    const double th = b.theta[j];
+    double s = 0.0;
+    for (int i = lane; i < n; i += 64) {
+      const double r = Y[i * k + j] - th * Uw[i * P + j];
+      s += r * r;
+    }
+    worst = fmax(worst, sqrt(wave_sum(s)));
+  }
+  if (lane == 0) S.colmax[w] = worst;
+  __syncthreads();
+  double m = 0.0;
+  for (int i = 0; i < FNW; ++i) m = fmax(m, S.colmax[i]);
+  const double t0 = fabs(b.theta[0]);
+  __syncthreads();
+  return (t0 > 0.0) ? m / t0 : 0.0;
+}
+
+__global__ __launch_bounds__(FNT) void subspace_kernel(const double* __restrict__ G, int n, int P, int k,
+                                                       double* Q, double* Y, double* Z, double* Qt, double* B,
+                                                       double* Vb, double* theta, double* Uw, uint64_t seed,
+                                                       double* __restrict__ U, double* __restrict__ lam) {
+  __shared__ FusedLds S;
+  const FusedBufs b = {Q, Y, Z, Qt, B, Vb, theta, Uw};
+  const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
+  // start block and one Cholesky-QR pass
+  for (int e = tid; e < n * k; e += FNT)
+    b.Y[e] = 2.0 * u01_from_bits(splitmix64(seed ^ (0x51ED2701ull * (uint64_t)(e + 1)))) - 1.0;
+  __syncthreads();
+  cholqr(S, b.Y, n, k, b.Q, b.Qt, false, seed + 1);
+  // four power steps, the last with two passes
+  const int n1 = n - 1, k1 = k - 1;
+  for (int it = 0; it < 4; ++it) {
+    const double* Q = b.Q;
+    double* Y = b.Y;
+    wg_gemm(n, k, n,
+        [&](int i, int t) { return (i < n && t < n) ? G[min(i, n1) * n + min(t, n1)] : 0.0; },
+        [&](int t, int c) { return (t < n && c < k) ? Q[min(t, n1) * k + min(c, k1)] : 0.0; },
+        [&](int i, int c, double v) { Y[i * k + c] = v; });
+    __syncthreads();
+    cholqr(S, b.Y, n, k, b.Q, b.Qt, it == 3, seed + 100 + it);
+  }
+  double ratio = rayleigh_ritz(S, G, n, P, k, b);
+  for (int it = 0; ratio > 1e-13 && it < 199; ++it) {
+    cholqr(S, b.Y, n, k, b.Q, b.Qt, true, seed + 2 + it);
+    ratio = rayleigh_ritz(S, G, n, P, k, b);
+  }
+  // eigenvalues and signed eigenvectors (largest-|.| entry positive, ties: lowest index)
+  for (int j = tid; j < P; j += FNT) lam[j] = b.theta[j];
+  for (int j = w; j < P; j += FNW) {
+    double best = -1.0;
+    int bi = 0;
+    for (int i = lane; i < n; i += 64) {
+      const double a = fabs(b.Uw[i * P + j]);
+      if (a > best || (a == best && i < bi)) { best = a; bi = i; }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const double sgn = (b.Uw[bi * P + j] < 0.0) ? -1.0 : 1.0;
+    for (int i = lane; i < n; i += 64) U[i * P + j] = sgn * b.Uw[i * P + j];
+  }
+}
+
 int subspace_k(int n, int P) {
   int k = P + (P / 4 > 8 ? P / 4 : 8);
   if (k > JMAX) k = JMAX;
@@ -359,6 +642,14 @@ cpd_status sp_start_phase(SubProblem& q, int ph, hipStream_t s) {
     return sp_finish(q, s);
   }
   const int n = q.n, k = q.k;
+  if (n <= FUSED_NMAX) {
+    if (ph != 0) return CPD_OK;
+    hipLaunchKernelGGL(subspace_kernel, dim3(1), dim3(FNT), 0, s, q.G, n, q.P, k, q.Q, q.Y, q.Z, q.Qt, q.B,
+                       q.Vb, q.theta, q.Uw, q.seed, q.U, q.lam);
+    CPD_LAUNCH_CHECK();
+    q.done = true;
+    return CPD_OK;
+  }
   if (ph == 0) {
     hipLaunchKernelGGL(init_block_kernel, dim3((n * k + 255) / 256), dim3(256), 0, s, q.Y, n, k, q.seed);
     CPD_LAUNCH_CHECK();

@@ -86,13 +86,18 @@ def test_gram_bf16_matrix_cores(dims):
         assert np.array_equal(Gbf, Gbf.T)
 
 
-@pytest.mark.parametrize("n,P", [(6, 3), (50, 5), (64, 20), (150, 20), (200, 20), (600, 50)])
-def test_eig_top_matches_eigh(n, P):
-    log("eig", n, P)
+@pytest.mark.parametrize("n,P,tail", [(6, 3, 1e-4), (50, 5, 1e-4), (64, 20, 1e-4), (65, 56, 1e-4), (150, 20, 1e-4),
+                                      (150, 20, 0.5), (200, 20, 1e-4), (320, 30, 1e-4), (321, 30, 1e-4),
+                                      (600, 50, 1e-4)])
+def test_eig_top_matches_eigh(n, P, tail):
+    """Orders 65..320 run the whole subspace iteration in one workgroup, larger ones as a chain of
+    launches; tail = 0.5 puts the unwanted eigenvalues at half the smallest wanted one, so the
+    iteration needs many Rayleigh-Ritz steps."""
+    log("eig", n, P, tail)
     rng = np.random.default_rng(n)
-    # planted spectrum: P dominant eigenvalues with relative gaps >= 1e-3, a noise floor below
+    # planted spectrum: P dominant eigenvalues with relative gaps >= 1e-3, the rest below tail
     Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
-    lam = np.concatenate([np.linspace(10.0, 1.0, P), 1e-4 * rng.uniform(0, 1, n - P)])
+    lam = np.concatenate([np.linspace(10.0, 1.0, P), tail * rng.uniform(0, 1, n - P)])
     G = (Q * lam) @ Q.T
     G = 0.5 * (G + G.T)
     U, l = cp().eig_top(dev(G), P)
