@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-solve", action="store_true", help="skip the kernel-level extras")
+    ap.add_argument("--legs", default="50cube,kernels,batch,600cube,learned",
+                    help="comma list of the extra legs to run after the timed solves")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -185,7 +187,8 @@ def main():
         "roofline": roofline,
     }
 
-    if not args.only_solve:
+    legs = set() if args.only_solve else set(args.legs.split(","))
+    if "50cube" in legs:
         # 50^3 workload: time to rel. err 1e-6 (the solve stops at the first iteration below 1e-6)
         T1, _, _ = synth.config1()
         T1d = torch.as_tensor(T1).to(dev)
@@ -206,6 +209,7 @@ def main():
         out["solve_50cube"] = {"iters": r1["info"]["iters"], "stop": cp.STOP_NAMES[r1["info"]["stop_reason"]],
                                "rel_err_core": r1["info"]["rel_err_core"]}
 
+    if "kernels" in legs:
         # full-tensor MTTKRP and Gram throughput on the 200^3 tensor
         Wf = [torch.randn(200, R, dtype=torch.float64, device=dev) for _ in range(3)]
         for mode in range(3):   # untimed: first launches load the kernels
@@ -226,6 +230,7 @@ def main():
         out["mttkrp_tflops"] = 2 * R * N / (ms_m / n_m / 1000.0) / 1e12
         out["gram_tflops"] = N * 201 / (ms_g / n_g / 1000.0) / 1e12
 
+    if "batch" in legs:
         # batched solver: 512 small planted CPDs (modes U{10..64}, ranks U{2..12}, 50 dB), one graph
         Ts4, Rs4, W04 = synth.batch_members(512, seed=0)
         B = cp.Batch([torch.as_tensor(t).to(dev) for t in Ts4], Rs4, cp.params(cg_uniforms=synth.cg_uniforms(200, 0)),
@@ -244,8 +249,9 @@ def main():
                             "median_rel_err_full": float(np.median([i["rel_err_full"] for i in infos])),
                             "median_iters": float(np.median([i["iters"] for i in infos]))}
         B.close()
-
+    if "600cube" in legs:
         out["c3_600cube"] = bench_600cube(cp, synth, torch, dev)
+    if "learned" in legs:
         out["c5_learned_init"] = bench_learned(torch)
 
     if not args.no_cpu_baseline:
@@ -284,7 +290,26 @@ def bench_600cube(cp, synth, torch, dev):
             times.append(time.perf_counter() - a)
         res[name] = r
         res[name + "_s"] = statistics.median(times[1:])
+    # full-tensor MTTKRP (2 R N flop per mode) and Gram (N (I+1) per mode) on the FP32 tensor and
+    # its BF16 copy
+    Wf = [torch.randn(600, 50, dtype=torch.float64, device=dev) for _ in range(3)]
+    N = 600 ** 3
+    rates = {}
+    for tag, X in (("fp32", Td), ("bf16", Tlo)):
+        for mode in range(3):
+            cp.mttkrp(X, Wf, mode)
+        torch.cuda.synchronize()
+        cp.profile_reset()
+        cp.profile_enable(True)
+        for _ in range(2):
+            for mode in range(3):
+                cp.mttkrp(X, Wf, mode)
+        torch.cuda.synchronize()
+        cp.profile_enable(False)
+        n_m, ms_m = cp.profile_read()["mttkrp"]
+        rates["mttkrp_tflops_" + tag] = 2 * 50 * N / (ms_m / n_m / 1000.0) / 1e12
     return {"workload": "dense 600^3 FP32 (+ BF16 copy), planted R=50, SNR 60 dB",
+            **rates,
             "s_per_solve_bf16_grams": res["bf16_grams_s"], "s_per_solve_fp64_grams": res["fp64_grams_s"],
             "rel_err_full_bf16_grams": res["bf16_grams"]["info"]["rel_err_full"],
             "rel_err_full_fp64_grams": res["fp64_grams"]["info"]["rel_err_full"],

@@ -120,20 +120,23 @@ __global__ __launch_bounds__(NWAVE * 64) void batch_gram_kernel(const BItem* __r
 }
 
 // ---- 2. eigenpairs ------------------------------------------------------------------------------
-__global__ __launch_bounds__(JNT) void batch_eig_kernel(const BItem* __restrict__ items, int n) {
+// 256 threads per member: many members share each CU, so throughput (fewer redundant rotation
+// evaluations per round) matters more than the latency of one member.
+constexpr int BJNT = 256;
+__global__ __launch_bounds__(BJNT) void batch_eig_kernel(const BItem* __restrict__ items, int n) {
   const int b = blockIdx.x / 3, mode = blockIdx.x - 3 * (blockIdx.x / 3);
   if (b >= n) return;
   const BItem& it = items[b];
   const int I = it.d[mode], P = it.P[mode];
   double* V = it.V[mode];
   __shared__ JacobiLds L;
-  jacobi_block<JNT>(L, it.G[mode], I, I, it.ev[mode], V);
+  jacobi_block<BJNT, true>(L, it.G[mode], I, I, it.ev[mode], V);
   __syncthreads();
   // first P eigenvectors, each signed so that its largest-|.| entry is positive (ties: lowest
   // index); one wave per column
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double* U = it.U[mode];
-  for (int j = w; j < P; j += JNT / 64) {
+  for (int j = w; j < P; j += BJNT / 64) {
     double best = -1.0;
     int bi = 0;
     for (int i = lane; i < I; i += 64) {
@@ -500,7 +503,7 @@ cpd_status launch_gram(const Launch& L, hipStream_t s) {
 cpd_status launch_all(const Launch& L, hipStream_t s) {
   cpd_status st;
   if ((st = launch_gram(L, s))) return st;
-  hipLaunchKernelGGL(batch_eig_kernel, dim3(3 * L.n), dim3(JNT), 0, s, L.items, L.n);
+  hipLaunchKernelGGL(batch_eig_kernel, dim3(3 * L.n), dim3(BJNT), 0, s, L.items, L.n);
   CPD_LAUNCH_CHECK();
   if (L.dtype == CPD_F64)
     hipLaunchKernelGGL(batch_project_kernel<double>, dim3(L.n), dim3(PROJ_NT), 0, s, L.items, L.n, L.setup);

@@ -30,6 +30,7 @@ namespace {
 
 struct Ctx {
   int d0, d1, d2, off1, off2, R, np;
+  int sp1, sp2;            // strides of S[i][j][k] (padded when S is staged in LDS)
   double *W, *MK, *G, *X, *Rv, *P, *Z;
   double *pi, *Pown, *Y, *Qb;   // 3 R^2 each
   double *msq, *gam;       // 3 R each
@@ -59,6 +60,8 @@ __device__ void setup_ctx(Ctx& c, double* lds, const int d[3], int R, const doub
   c.d0 = d[0]; c.d1 = d[1]; c.d2 = d[2]; c.R = R;
   c.off1 = d[0] * R; c.off2 = (d[0] + d[1]) * R;
   c.np = (d[0] + d[1] + d[2]) * R;
+  c.sp1 = d[1] * d[2];
+  c.sp2 = d[2];
   double* p = lds;
   c.W = p; p += c.np;
   c.MK = MK;
@@ -233,6 +236,7 @@ __device__ double residual_mttkrp(Ctx& c, double* slots) {
   const double* W1 = c.W + c.off1;
   const double* W2 = c.W + c.off2;
   const double* S = c.S;
+  const int sp1 = c.sp1, sp2 = c.sp2;
   const int lane = threadIdx.x & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
   const int n0 = tiles16(d0) * tr, n1 = n0 + tiles16(d1) * tr, n2 = n1 + tiles16(d2) * tr;
   const int nres = tiles16(d0) * tiles16(d12);
@@ -247,7 +251,10 @@ __device__ double residual_mttkrp(Ctx& c, double* slots) {
       dbl4 acc;
       if (l == 0) {
         acc = mfma_tile(tm * 16, tn * 16, d12,
-            [&](int i, int jk) { return sel(i < d0 && jk < d12, S[min(i, d0 - 1) * d12 + min(jk, d12 - 1)]); },
+            [&](int i, int jk) {
+              const int x = min(jk, d12 - 1), j = div_by(x, inv2), k = x - j * d2;
+              return sel(i < d0 && jk < d12, S[min(i, d0 - 1) * sp1 + j * sp2 + k]);
+            },
             [&](int jk, int r) {
               const int x = min(jk, d12 - 1), j = div_by(x, inv2), k = x - j * d2, rr = min(r, R1);
               return sel(r < R && jk < d12, W2[k * R + rr] * W1[j * R + rr]);
@@ -256,7 +263,7 @@ __device__ double residual_mttkrp(Ctx& c, double* slots) {
         acc = mfma_tile(tm * 16, tn * 16, d02,
             [&](int j, int ik) {
               const int x = min(ik, d02 - 1), i = div_by(x, inv2), k = x - i * d2;
-              return sel(j < d1 && ik < d02, S[i * d12 + min(j, d1 - 1) * d2 + k]);
+              return sel(j < d1 && ik < d02, S[i * sp1 + min(j, d1 - 1) * sp2 + k]);
             },
             [&](int ik, int r) {
               const int x = min(ik, d02 - 1), i = div_by(x, inv2), k = x - i * d2, rr = min(r, R1);
@@ -264,7 +271,10 @@ __device__ double residual_mttkrp(Ctx& c, double* slots) {
             });
       } else {
         acc = mfma_tile(tm * 16, tn * 16, d01,
-            [&](int k, int ij) { return sel(k < d2 && ij < d01, S[min(ij, d01 - 1) * d2 + min(k, d2 - 1)]); },
+            [&](int k, int ij) {
+              const int x = min(ij, d01 - 1), i = div_by(x, inv1), j = x - i * d1;
+              return sel(k < d2 && ij < d01, S[i * sp1 + j * sp2 + min(k, d2 - 1)]);
+            },
             [&](int ij, int r) {
               const int x = min(ij, d01 - 1), i = div_by(x, inv1), j = x - i * d1, rr = min(r, R1);
               return sel(r < R && ij < d01, W1[j * R + rr] * W0[i * R + rr]);
@@ -288,7 +298,8 @@ __device__ double residual_mttkrp(Ctx& c, double* slots) {
       for (int v = 0; v < 4; ++v) {
         const int i = tm * 16 + 4 * v + kq, jk = tn * 16 + r16;
         if (i < d0 && jk < d12) {
-          const double f = S[i * d12 + jk] - acc[v];
+          const int j = div_by(jk, inv2), k = jk - j * d2;
+          const double f = S[i * sp1 + j * sp2 + k] - acc[v];
           f2 += f * f;
         }
       }
@@ -334,10 +345,18 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
   double* gMK = (double*)(state + Lo.MK);
   Ctx c;
   if (SL) {
+    // rows of S padded to odd strides (in doubles): the sixteen rows a matrix-core fragment reads
+    // then fall into distinct LDS banks
     double* Sl = lds + lds_doubles(np, R);
-    const int n3 = d[0] * d[1] * d[2];
-    for (int e = threadIdx.x; e < n3; e += NT) Sl[e] = S[e];
+    const int p2 = d[2] | 1, p1 = (d[1] * p2) | 1;
+    const int n3 = d[0] * d[1] * d[2], d12 = d[1] * d[2];
+    for (int e = threadIdx.x; e < n3; e += NT) {
+      const int i = e / d12, jk = e - i * d12, j = jk / d[2], k = jk - j * d[2];
+      Sl[i * p1 + j * p2 + k] = S[e];
+    }
     setup_ctx(c, lds, d, R, Sl, gMK, (double*)(state + Lo.G));
+    c.sp1 = p1;
+    c.sp2 = p2;
   } else {
     setup_ctx(c, lds, d, R, S, gMK, (double*)(state + Lo.G));
   }
@@ -480,22 +499,32 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
   }
 }
 
+// Initialisation (mode 0) and iterations (mode 1) are separate kernels, so that traces and
+// counters attribute them separately.
 template <bool SL>
-__global__ __launch_bounds__(NT) void dgn_kernel(char* __restrict__ state, const double* __restrict__ S,
-                                                 int mode, int max_steps) {
+__global__ __launch_bounds__(NT) void dgn_init_kernel(char* __restrict__ state, const double* __restrict__ S) {
   extern __shared__ double lds[];
   __shared__ int s_stop;
-  dgn_body<SL>(state, S, mode, max_steps, lds, s_stop);
+  dgn_body<SL>(state, S, 0, 0, lds, s_stop);
+}
+
+template <bool SL>
+__global__ __launch_bounds__(NT) void dgn_kernel(char* __restrict__ state, const double* __restrict__ S,
+                                                 int max_steps) {
+  extern __shared__ double lds[];
+  __shared__ int s_stop;
+  dgn_body<SL>(state, S, 1, max_steps, lds, s_stop);
 }
 
 // Same iteration for states too large for LDS: the working set lives in the state's own work
 // region (global memory; one workgroup, so its accesses stay coherent through the CU's cache).
+template <int MODE>
 __global__ __launch_bounds__(NT) void dgn_kernel_g(char* __restrict__ state, const double* __restrict__ S,
-                                                   int mode, int max_steps) {
+                                                   int max_steps) {
   __shared__ int s_stop;
   const Hdr* h = (const Hdr*)state;
   const Layout Lo = layout_of(h->np, h->R, h->maxiter);
-  dgn_body<false>(state, S, mode, max_steps, (double*)(state + Lo.work), s_stop);
+  dgn_body<false>(state, S, MODE, max_steps, (double*)(state + Lo.work), s_stop);
 }
 
 // Batched: workgroup b initialises state b (header, caps and W already written) and iterates it
@@ -637,20 +666,36 @@ int cg_cap_for(int k, double u) {
 namespace {
 // The persistent dGN kernel with its working set in LDS when it fits, else in the state's work
 // region.
-cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int np, int R, int n3,
+cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int np, int R, const int d[3],
                       hipStream_t s) {
+  const int p2 = d[2] | 1, p1 = (d[1] * p2) | 1;
+  const size_t s_lds = (size_t)(d[0] - 1) * p1 + (size_t)(d[1] - 1) * p2 + d[2];   // padded core in LDS
   size_t lb;
-  if (lds_fits(np, R, &lb) && lb + (size_t)n3 * sizeof(double) <= LDS_LIMIT) {
-    lb += (size_t)n3 * sizeof(double);
-    CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)lb));
-    hipLaunchKernelGGL(dgn_kernel<true>, dim3(1), dim3(NT), lb, s, state, S, mode, max_steps);
+  if (lds_fits(np, R, &lb) && lb + (size_t)s_lds * sizeof(double) <= LDS_LIMIT) {
+    lb += (size_t)s_lds * sizeof(double);
+    if (mode == 0) {
+      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_init_kernel<true>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
+      hipLaunchKernelGGL(dgn_init_kernel<true>, dim3(1), dim3(NT), lb, s, state, S);
+    } else {
+      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lb));
+      hipLaunchKernelGGL(dgn_kernel<true>, dim3(1), dim3(NT), lb, s, state, S, max_steps);
+    }
   } else if (lds_fits(np, R, &lb)) {
-    CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)lb));
-    hipLaunchKernelGGL(dgn_kernel<false>, dim3(1), dim3(NT), lb, s, state, S, mode, max_steps);
+    if (mode == 0) {
+      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_init_kernel<false>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
+      hipLaunchKernelGGL(dgn_init_kernel<false>, dim3(1), dim3(NT), lb, s, state, S);
+    } else {
+      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lb));
+      hipLaunchKernelGGL(dgn_kernel<false>, dim3(1), dim3(NT), lb, s, state, S, max_steps);
+    }
+  } else if (mode == 0) {
+    hipLaunchKernelGGL(dgn_kernel_g<0>, dim3(1), dim3(NT), 0, s, state, S, max_steps);
   } else {
-    hipLaunchKernelGGL(dgn_kernel_g, dim3(1), dim3(NT), 0, s, state, S, mode, max_steps);
+    hipLaunchKernelGGL(dgn_kernel_g<1>, dim3(1), dim3(NT), 0, s, state, S, max_steps);
   }
   CPD_LAUNCH_CHECK();
   return CPD_OK;
@@ -721,7 +766,8 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
     return CPD_E_INVALID;
   }
   cpd_status lst;
-  if ((lst = launch_dgn(st, S, 0, 0, np, R, core[0] * core[1] * core[2], s))) return lst;
+  const int dc[3] = {core[0], core[1], core[2]};
+  if ((lst = launch_dgn(st, S, 0, 0, np, R, dc, s))) return lst;
   int flags = 0;
   CPD_HIP_CHECK(hipMemcpyAsync(&flags, st + offsetof(Hdr, flags), sizeof(int), hipMemcpyDeviceToHost, s));
   CPD_HIP_CHECK(hipStreamSynchronize(s));
@@ -759,7 +805,8 @@ cpd_status dgn_iterate(void* state, const double* S, int max_steps, hipStream_t 
     return CPD_E_INVALID;
   }
   prof_begin(CPD_PK_DGN, s);
-  const cpd_status st = launch_dgn((char*)state, S, 1, max_steps, h.np, h.R, h.d[0] * h.d[1] * h.d[2], s);
+  const int dc[3] = {h.d[0], h.d[1], h.d[2]};
+  const cpd_status st = launch_dgn((char*)state, S, 1, max_steps, h.np, h.R, dc, s);
   prof_end(CPD_PK_DGN, s);
   return st;
 }

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const double* __restrict__ 
                                                      double* __restrict__ lam,
                                                      double* __restrict__ Vout) {
   __shared__ JacobiLds L;
-  jacobi_block<JNT>(L, Ag, n, lda, lam, Vout);
+  jacobi_block<JNT, true>(L, Ag, n, lda, lam, Vout);
 }
 
 // Copies the first P columns of X (n x ldx) into U (n x P) and signs each column so its
@@ -274,6 +274,17 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, FA fa, FB fb, FS st
   }
 }
 
+// Out = G Q (n x k) for symmetric G, formed as (Q^T G)^T: the tiles of Q^T G read rows of Q and
+// rows of G, sixteen consecutive doubles per fragment row, where G Q would read sixteen rows of G
+// per fragment.
+__device__ __forceinline__ void gq_product(const double* G, const double* Q, int n, int k, double* Out) {
+  const int n1 = n - 1, k1 = k - 1;
+  wg_gemm(k, n, n,
+      [&](int c, int t) { return (c < k && t < n) ? Q[min(t, n1) * k + min(c, k1)] : 0.0; },
+      [&](int t, int i) { return (t < n && i < n) ? G[min(t, n1) * n + min(i, n1)] : 0.0; },
+      [&](int c, int i, double v) { Out[i * k + c] = v; });
+}
+
 // One Cholesky-QR pass Out = X D R^{-1}, D C D = R^T R, C = X^T X, D = diag(C)^{-1/2} (n x k, row
 // major).  Returns (uniformly) whether a pivot fell below 1e-13; Out is then not written.
 __device__ bool cholqr_pass(FusedLds& S, const double* X, int n, int k, double* Out) {
@@ -413,10 +424,7 @@ __device__ double rayleigh_ritz(FusedLds& S, const double* G, int n, int P, int 
   const int n1 = n - 1, k1 = k - 1;
   const double* Q = b.Q;
   double* Z = b.Z;
-  wg_gemm(n, k, n,
-      [&](int i, int t) { return (i < n && t < n) ? G[min(i, n1) * n + min(t, n1)] : 0.0; },
-      [&](int t, int c) { return (t < n && c < k) ? Q[min(t, n1) * k + min(c, k1)] : 0.0; },
-      [&](int i, int c, double v) { Z[i * k + c] = v; });
+  gq_product(G, Q, n, k, Z);
   __syncthreads();
   double* B = b.B;
   wg_gemm(k, k, n,
@@ -424,7 +432,7 @@ __device__ double rayleigh_ritz(FusedLds& S, const double* G, int n, int P, int 
       [&](int i, int c) { return (c < k && i < n) ? Z[min(i, n1) * k + min(c, k1)] : 0.0; },
       [&](int r, int c, double v) { B[r * k + c] = v; });
   __syncthreads();
-  jacobi_block<FNT>(S.u.jac, B, k, k, b.theta, b.Vb);
+  jacobi_block<FNT, true>(S.u.jac, B, k, k, b.theta, b.Vb);
   __syncthreads();
   const double* Vb = b.Vb;
   double* Uw = b.Uw;
@@ -472,14 +480,10 @@ __global__ __launch_bounds__(FNT) void subspace_kernel(const double* __restrict_
   __syncthreads();
   cholqr(S, b.Y, n, k, b.Q, b.Qt, false, seed + 1);
   // four power steps, the last with two passes
-  const int n1 = n - 1, k1 = k - 1;
   for (int it = 0; it < 4; ++it) {
     const double* Q = b.Q;
     double* Y = b.Y;
-    wg_gemm(n, k, n,
-        [&](int i, int t) { return (i < n && t < n) ? G[min(i, n1) * n + min(t, n1)] : 0.0; },
-        [&](int t, int c) { return (t < n && c < k) ? Q[min(t, n1) * k + min(c, k1)] : 0.0; },
-        [&](int i, int c, double v) { Y[i * k + c] = v; });
+    gq_product(G, Q, n, k, Y);
     __syncthreads();
     cholqr(S, b.Y, n, k, b.Q, b.Qt, it == 3, seed + 100 + it);
   }

@@ -17,6 +17,7 @@ struct JacobiLds {
   double V[JMAX][JMAX + 1];
   double dg[2][JMAX];    // A[x][x] for the round that reads this buffer
   double od[2][JMAX];    // A[p][q] of the pair (p < q) that contains p, indexed by p
+  double rc[JMAX / 2], rs[JMAX / 2];   // rotations of the round (shared-rotation mode)
   double red[2][32];
   int rank_of[JMAX];
   int rotated[2];
@@ -79,11 +80,14 @@ __device__ __forceinline__ bool pair_rotation(const double* dg, const double* od
 
 // Eigendecomposition of the symmetric n x n matrix Ag (leading dim lda, n <= 64) by NTH threads.
 // Outputs lam[n] descending and Vout (n x n row-major, eigenvector j in column j).
-// Each round applies the rotations of its disjoint pairs as A <- J^T A J, V <- V J: the thread of
-// block (bi, bj) forms both rotations it needs and updates its 2x2 block in place (a block's new
-// value depends only on its own old entries); V's column pairs are split the same way.  A sweep
+// Each round applies the rotations of its disjoint pairs as A <- J^T A J, V <- V J; the thread of
+// block (bi, bj) updates its 2x2 block in place (a block's new value depends only on its own old
+// entries); V's column pairs are split the same way.  Rotations: with SHARED, one thread per pair
+// forms it into LDS and a barrier publishes it (two barriers per round, least arithmetic: for many
+// workgroups per CU); otherwise every thread forms the two rotations it needs from the side
+// buffers (one barrier per round, shortest round: for a single latency-bound solve).  A sweep
 // without rotations, or with off(A)^2 <= 1e-30 ||A||^2, ends the iteration (at most 60 sweeps).
-template <int NTH>
+template <int NTH, bool SHARED>
 __device__ __forceinline__ void jacobi_block(JacobiLds& L, const double* __restrict__ Ag, int n, int lda,
                                              double* __restrict__ lam, double* __restrict__ Vout) {
   static_assert(NTH % 64 == 0 && NTH >= 64 && NTH <= 1024, "thread count");
@@ -129,11 +133,33 @@ __device__ __forceinline__ void jacobi_block(JacobiLds& L, const double* __restr
       const double* od = L.od[par];
       double* dgn = L.dg[par ^ 1];
       double* odn = L.od[par ^ 1];
+      if (SHARED) {
+        if (tid < half) {
+          int p, q;
+          pair_of(tid, round, np, p, q);
+          double c = 1.0, sn = 0.0;
+          if (q < n) {
+            const double apq = L.A[p][q], app = L.A[p][p], aqq = L.A[q][q];
+            if (apq * apq > 1e-30 * fabs(app * aqq) && fabs(apq) > 1e-300) {
+              jacobi_rotation(app, aqq, apq, c, sn);
+              L.rotated[sweep & 1] = 1;
+            }
+          }
+          L.rc[tid] = c;
+          L.rs[tid] = sn;
+        }
+        __syncthreads();
+      }
       if (bj < half) {
         int pj, qj;
         pair_of(bj, round, np, pj, qj);
         double cj, sj;
-        if (pair_rotation(dg, od, pj, qj, n, cj, sj)) L.rotated[sweep & 1] = 1;
+        if (SHARED) {
+          cj = L.rc[bj];
+          sj = L.rs[bj];
+        } else if (pair_rotation(dg, od, pj, qj, n, cj, sj)) {
+          L.rotated[sweep & 1] = 1;
+        }
 #pragma unroll
         for (int u = 0; u < NBI; ++u) {
           const int bi = bi0 + u * ISTEP;
@@ -141,7 +167,12 @@ __device__ __forceinline__ void jacobi_block(JacobiLds& L, const double* __restr
             int pi, qi;
             pair_of(bi, round, np, pi, qi);
             double ci, si;
-            pair_rotation(dg, od, pi, qi, n, ci, si);
+            if (SHARED) {
+              ci = L.rc[bi];
+              si = L.rs[bi];
+            } else {
+              pair_rotation(dg, od, pi, qi, n, ci, si);
+            }
             const double a_pp = L.A[pi][pj], a_pq = L.A[pi][qj], a_qp = L.A[qi][pj], a_qq = L.A[qi][qj];
             const double b_pp = ci * a_pp - si * a_qp, b_pq = ci * a_pq - si * a_qq;
             const double b_qp = si * a_pp + ci * a_qp, b_qq = si * a_pq + ci * a_qq;
@@ -151,13 +182,15 @@ __device__ __forceinline__ void jacobi_block(JacobiLds& L, const double* __restr
             L.A[pi][qj] = n_pq;
             L.A[qi][pj] = n_qp;
             L.A[qi][qj] = n_qq;
-            // inputs of the next round produced by this block
-            if (bi == bj) { dgn[pi] = n_pp; dgn[qi] = n_qq; }
-            const int ppi = partner_of(pi, nround, np), pqi = partner_of(qi, nround, np);
-            if (pi < pj && ppi == pj) odn[pi] = n_pp;
-            if (pi < qj && ppi == qj) odn[pi] = n_pq;
-            if (qi < pj && pqi == pj) odn[qi] = n_qp;
-            if (qi < qj && pqi == qj) odn[qi] = n_qq;
+            if (!SHARED) {
+              // inputs of the next round produced by this block
+              if (bi == bj) { dgn[pi] = n_pp; dgn[qi] = n_qq; }
+              const int ppi = partner_of(pi, nround, np), pqi = partner_of(qi, nround, np);
+              if (pi < pj && ppi == pj) odn[pi] = n_pp;
+              if (pi < qj && ppi == qj) odn[pi] = n_pq;
+              if (qi < pj && pqi == pj) odn[qi] = n_qp;
+              if (qi < qj && pqi == qj) odn[qi] = n_qq;
+            }
           }
         }
 #pragma unroll

@@ -106,10 +106,10 @@ def planted_device(dims, R, gen, device="cuda"):
     return (F[0] @ KR.T).reshape(dims).contiguous()
 
 
-def make_dataset(n, seed, dims=(100, 100, 100), R=8, core=(16, 16, 16), chunk=512, device="cuda"):
+def make_dataset(n, seed, dims=(100, 100, 100), R=8, core=(16, 16, 16), chunk=512, device="cuda", progress=None):
     """n training pairs (x, t) from planted tensors: core of cpd_compress with fixed core dims, target
     the batched solver's CPD of that core (pairs whose solve did not reach rel. err 1e-6 are dropped).
-    Returns (X, T, kept)."""
+    progress(done, n) is called after each chunk.  Returns (X, T, kept)."""
     gen = torch.Generator(device="cpu").manual_seed(int(seed))
     pc = params(core_dims=core)
     X, Tt = [], []
@@ -129,14 +129,17 @@ def make_dataset(n, seed, dims=(100, 100, 100), R=8, core=(16, 16, 16), chunk=51
             Tt.append(factor_target(b.W[j], b.lam[j], scales[j]) if infos[j]["rel_err_full"] < 1e-6 else None)
         b.close()
         done += m
+        if progress is not None:
+            progress(done, n)
     keep = [i for i, t in enumerate(Tt) if t is not None]
     X = torch.stack([X[i] for i in keep])
     T = torch.stack([Tt[i] for i in keep])
     return X, T, len(keep)
 
 
-def train(X, T, sizes=None, epochs=10, batch=512, lr=1e-3, seed=0):
-    """Adam on the squared error over the shuffled training set; returns (network, loss history)."""
+def train(X, T, sizes=None, epochs=10, batch=512, lr=1e-3, seed=0, progress=None):
+    """Adam on the squared error over the shuffled training set; returns (network, loss history).
+    progress(epoch, loss) is called after each epoch."""
     sizes = sizes or [X.shape[1], 1024, 1024, T.shape[1]]
     net = MLP(sizes, seed=seed, device=X.device)
     g = torch.Generator(device="cpu").manual_seed(int(seed) + 1)
@@ -152,10 +155,12 @@ def train(X, T, sizes=None, epochs=10, batch=512, lr=1e-3, seed=0):
             tot += float(loss.item()) if (i // batch) % 16 == 0 else 0.0
             nb += 1 if (i // batch) % 16 == 0 else 0
         hist.append(tot / max(nb, 1))
+        if progress is not None:
+            progress(ep, hist[-1])
     return net, hist
 
 
-def evaluate(net, n_test, seed, dims=(100, 100, 100), R=8, core=(16, 16, 16), maxiter=200):
+def evaluate(net, n_test, seed, dims=(100, 100, 100), R=8, core=(16, 16, 16), maxiter=200, progress=None):
     """Solves n_test new planted tensors from the starting points
       learned  - the network's prediction for the compressed core,
       fallback - the prediction unless the MLSVD-energy point has a smaller core residual
@@ -189,6 +194,8 @@ def evaluate(net, n_test, seed, dims=(100, 100, 100), R=8, core=(16, 16, 16), ma
             dt = time.perf_counter() - t0
             inf = r["info"]
             out[name].append((max(inf["tol_iter"], 0), inf["iters"], dt, inf["rel_err_core"], e0))
+        if progress is not None and (i + 1) % 100 == 0:
+            progress(i + 1, n_test)
     return out
 
 
@@ -214,13 +221,18 @@ if __name__ == "__main__":
     ap.add_argument("--n-train", type=int, default=100000)
     ap.add_argument("--n-test", type=int, default=1000)
     ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=256)
     a = ap.parse_args()
+
+    def say(*args):
+        print(*args, flush=True)
+
     t0 = time.perf_counter()
-    X, T, kept = make_dataset(a.n_train, seed=0)
+    X, T, kept = make_dataset(a.n_train, seed=0, progress=lambda d, n: say(f"data {d}/{n}"))
     t1 = time.perf_counter()
-    net, hist = train(X, T, epochs=a.epochs)
+    net, hist = train(X, T, epochs=a.epochs, batch=a.batch, progress=lambda e, l: say(f"epoch {e} loss {l:.5f}"))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    res = evaluate(net, a.n_test, seed=1)
+    res = evaluate(net, a.n_test, seed=1, progress=lambda d, n: say(f"eval {d}/{n}"))
     print(json.dumps({"n_train": a.n_train, "kept": kept, "data_s": t1 - t0, "train_s": t2 - t1,
                       "loss": hist, "eval": summarize(res)}), flush=True)
