@@ -48,7 +48,11 @@ def parse():
 # WRITE_SIZE, KiB per dispatch) over `bench.py --only-solve` and scaled by the same counters' reading
 # for a plain copy of known size (`bench.py --copy-calibration`).  A figure is reported only while
 # the kernel's sources hash to the digest it was taken with.
-TRAFFIC = {}
+TRAFFIC = {
+    # dgn_kernel on the 200^3 R = 20 workload (20^3 core, 19 iterations): FETCH_SIZE 71.8 KiB x 2.0,
+    # WRITE_SIZE 29.6 KiB x 1.0 (profiles/dgn_kernel_200cube_traffic.md)
+    "dgn": {"bytes": 147046 + 30310, "sources": ['dgn.hip', 'dgn_state.h', 'mfma_f64.h', 'common.h'], "digest": '4b3c03f0a6ef4a01'},
+}
 
 
 def source_digest(files):
