@@ -1,6 +1,7 @@
 // C ABI of libcpd: argument checking, workspace carving and the host-side sequencing of the
 // Tensor Fox pipeline (ch.4 flow chart: Compress -> Initialize -> dGN -> Uncompress).
 #include "common.h"
+#include "dgn_state.h"
 
 #include <math.h>
 #include <stdarg.h>
@@ -332,12 +333,23 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   int core[3];
   if ((st = run_compress(T, dtype, T_gram, gram_dtype, gram_compute, dims, R, p, U, nullptr, S, core, ar, s)))
     return st;
-  if ((st = state_init(state, S, core, R, W0, h_tn2, p, s))) return st;
-  if ((st = dgn_iterate(state, S, p->maxiter, s))) return st;
-  int k = 0, stop = 0, ti = -1;
-  double err = 0.0;
-  if ((st = state_read(state, &k, &stop, &ti, &err, s))) return st;
-  if ((st = state_factors(state, Wc, 0, s))) return st;
+  if ((st = state_init(state, S, core, R, W0, h_tn2, p, s, false))) return st;
+  if ((st = dgn_iterate_known(state, S, core, R, p->maxiter, s))) return st;
+  // one read-back after the dGN: the header (flags, iterations, stop, final core error)
+  Hdr h;
+  CPD_HIP_CHECK(hipMemcpyAsync(&h, state, sizeof(Hdr), hipMemcpyDeviceToHost, s));
+  CPD_HIP_CHECK(hipStreamSynchronize(s));
+  if (h.flags & 1) {
+    set_error("state_init: non-finite initial factors");
+    return CPD_E_NONFINITE;
+  }
+  const int k = h.k, stop = h.stop, ti = h.tol_iter;
+  const double err = (h.s_norm > 0.0) ? sqrt(h.f2) / h.s_norm : 0.0;   // = the logged error of step k
+  {
+    const int np = (core[0] + core[1] + core[2]) * R;
+    const Layout Lo = layout_of(np, R, p->maxiter);
+    CPD_HIP_CHECK(hipMemcpyAsync(Wc, state + Lo.W, sizeof(double) * np, hipMemcpyDeviceToDevice, s));
+  }
   // uncompress W~ = U W
   size_t o = 0;
   for (int l = 0; l < 3; ++l) {

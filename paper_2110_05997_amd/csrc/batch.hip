@@ -179,6 +179,7 @@ __global__ __launch_bounds__(PROJ_NT) void batch_project_kernel(const BItem* __r
                                                                 SetupArgs a) {
   __shared__ int core[3];
   __shared__ double red[2][PROJ_NT / 64];
+  __shared__ double U1s[BMAX_DIM * BMAX_DIM];
   const int b = blockIdx.x;
   if (b >= n) return;
   const BItem& it = items[b];
@@ -199,13 +200,28 @@ __global__ __launch_bounds__(PROJ_NT) void batch_project_kernel(const BItem* __r
   s2 = block_sum(s2, red[0]);
   bad = block_sum(bad, red[1]);
   const int c1 = core[0], c2 = core[1], c3 = core[2];
-  // Y1[a][j k] = sum_i U1[i][a] T[i][j][k]
-  for (int aa = 0; aa < c1; ++aa)
+  // Y1[a][j k] = sum_i U1[i][a] T[i][j][k]: U1 staged in LDS, up to 16 outputs per thread from one
+  // read of T[:, j, k] (each output accumulated over i in increasing order)
+  for (int e = tid; e < I1 * P1; e += PROJ_NT) U1s[e] = it.U[0][e];
+  __syncthreads();
+  for (int a0 = 0; a0 < c1; a0 += 16) {
+    const int na = min(16, c1 - a0);
     for (int jk = tid; jk < K1; jk += PROJ_NT) {
-      double acc = 0.0;
-      for (int i = 0; i < I1; ++i) acc = fma(it.U[0][i * P1 + aa], ld_elem(T + (long long)i * K1 + jk), acc);
-      it.Y1[(long long)aa * K1 + jk] = acc;
+      double acc[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+      for (int i = 0; i < I1; ++i) {
+        const double t = ld_elem(T + (long long)i * K1 + jk);
+        const double* u = U1s + i * P1 + a0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (q < na) acc[q] = fma(u[q], t, acc[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (q < na) it.Y1[(long long)(a0 + q) * K1 + jk] = acc[q];
     }
+  }
   __syncthreads();
   // Y2[a][b][k] = sum_j U2[j][b] Y1[a][j][k]
   for (int e = tid; e < c1 * c2 * I3; e += PROJ_NT) {
@@ -271,6 +287,7 @@ __global__ __launch_bounds__(FIN_NT) void batch_finish_kernel(const BItem* __res
   __shared__ double lamv[64];
   __shared__ double scale[3][64];
   __shared__ int dest[64];
+  __shared__ double W1s[BMAX_DIM * 64], W2s[BMAX_DIM * 64];   // modes <= 64, R <= 64
   const int b = blockIdx.x;
   if (b >= n) return;
   const BItem& it = items[b];
@@ -297,16 +314,19 @@ __global__ __launch_bounds__(FIN_NT) void batch_finish_kernel(const BItem* __res
     off += cs[l] * R;
   }
   __syncthreads();
-  // ||T - [[W~]]||^2
+  // ||T - [[W~]]||^2, with the mode-2 and mode-3 factors staged in LDS
   const int I1 = it.d[0], I2 = it.d[1], I3 = it.d[2], K1 = I2 * I3;
+  for (int e = tid; e < I2 * R; e += FIN_NT) W1s[e] = it.Wt[1][e];
+  for (int e = tid; e < I3 * R; e += FIN_NT) W2s[e] = it.Wt[2][e];
+  __syncthreads();
   const double inv3 = 1.0 / (double)I3;
   double res = 0.0;
   for (int i = 0; i < I1; ++i) {
     const double* A = it.Wt[0] + i * R;
     for (int jk = tid; jk < K1; jk += FIN_NT) {
       const int j = (int)(((double)jk + 0.5) * inv3), k = jk - j * I3;
-      const double* B = it.Wt[1] + j * R;
-      const double* C = it.Wt[2] + k * R;
+      const double* B = W1s + j * R;
+      const double* C = W2s + k * R;
       double m = 0.0;
       for (int r = 0; r < R; ++r) m = fma(A[r] * B[r], C[r], m);
       const double d = ld_elem(T + (long long)i * K1 + jk) - m;

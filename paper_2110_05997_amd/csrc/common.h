@@ -158,8 +158,13 @@ cpd_status sumsq_full(const void* T, int dtype, int64_t n, double* out, int* non
 
 // dGN.
 size_t state_bytes(const int32_t core[3], int R, int maxiter);
+// check_flags = false leaves the non-finite-start flag in the header for the caller to read.
 cpd_status state_init(void* state, const double* S, const int32_t core[3], int R,
-                      const double* W0, double t_norm2, const cpd_params* p, hipStream_t s);
+                      const double* W0, double t_norm2, const cpd_params* p, hipStream_t s,
+                      bool check_flags = true);
+// dgn_iterate for a state whose sizes the caller knows (no header read-back).
+cpd_status dgn_iterate_known(void* state, const double* S, const int32_t core[3], int R, int max_steps,
+                             hipStream_t s);
 size_t dgn_lds_bytes(int np, int R);
 // Batched persistent dGN: one workgroup per state (header, caps and W written beforehand).
 // dgn_batch_prepare sets the kernel's dynamic-LDS limit (call outside graph capture).

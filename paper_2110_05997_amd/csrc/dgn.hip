@@ -32,7 +32,7 @@ struct Ctx {
   int d0, d1, d2, off1, off2, R, np;
   int sp1, sp2;            // strides of S[i][j][k] (padded when S is staged in LDS)
   double *W, *MK, *G, *X, *Rv, *P, *Z;
-  double *pi, *Pown, *Y, *Qb;   // 3 R^2 each
+  double *pi, *Pown, *Qb;   // 3 R^2 each
   double *msq, *gam;       // 3 R each
   double *red;             // 2 x NW
   const double* S;
@@ -72,7 +72,6 @@ __device__ void setup_ctx(Ctx& c, double* lds, const int d[3], int R, const doub
   c.Z = p; p += c.np;
   c.pi = p; p += 3 * R * R;
   c.Pown = p; p += 3 * R * R;
-  c.Y = p; p += 3 * R * R;
   c.Qb = p; p += 3 * R * R;
   c.msq = p; p += 3 * R;
   c.gam = p; p += 3 * R;
@@ -133,7 +132,8 @@ __device__ void precond(Ctx& c, double mu) {
 // msq * (J^T J v + mu D v) (the preconditioned CG operator); with scale = false it is J^T J V.
 // Phase 1: Q_b = v_b^T W_b (R x R) for the three modes.  Phase 2, block a:
 //   out_a = [v_a | W_a] [Pi^(a) ; Y_a],  Y_a = pi^(b2) * Q_b1 + pi^(b1) * Q_b2 ({b1, b2} = other modes),
-// with Y formed inside the B-fragment loads.  Returns this thread's partial of <V, out>; ends
+// with Y formed inside the B-fragment loads (no barrier between the phases beyond the one that
+// publishes Q).  Returns this thread's partial of <V, out>; ends
 // without a barrier after phase 2.
 __device__ double hv(Ctx& c, const double* V, double* out, double mu, bool scale) {
   const int R = c.R, RR = R * R, tr = tiles16(R);
@@ -153,14 +153,6 @@ __device__ double hv(Ctx& c, const double* V, double* out, double mu, bool scale
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < RR; e += NT) {
-    const double q0 = c.Qb[e], q1 = c.Qb[RR + e], q2 = c.Qb[2 * RR + e];
-    const double p0 = c.pi[e], p1 = c.pi[RR + e], p2 = c.pi[2 * RR + e];
-    c.Y[e] = p2 * q1 + p1 * q2;
-    c.Y[RR + e] = p2 * q0 + p0 * q2;
-    c.Y[2 * RR + e] = p1 * q0 + p0 * q1;
-  }
-  __syncthreads();
   double dotp = 0.0;
   const int t0 = tiles16(c.d0) * tr, t1 = t0 + tiles16(c.d1) * tr, t2 = t1 + tiles16(c.d2) * tr;
   for (int t = w; t < t2; t += NW) {
@@ -171,8 +163,13 @@ __device__ double hv(Ctx& c, const double* V, double* out, double mu, bool scale
     const double* Va = V + offof(c, a);
     const double* Wa = c.W + offof(c, a);
     const double* Pa = c.Pown + a * RR;
-    const double* Ya = c.Y + a * RR;
     const double* ma = c.msq + a * R;
+    // Y_a = pi^(b2) * Q_b1 + pi^(b1) * Q_b2 over the other two modes b1 < b2, formed in the loads
+    const int b1 = (a == 0) ? 1 : 0, b2 = (a == 2) ? 1 : 2;
+    const double* pb1 = c.pi + b1 * RR;
+    const double* pb2 = c.pi + b2 * RR;
+    const double* qb1 = c.Qb + b1 * RR;
+    const double* qb2 = c.Qb + b2 * RR;
     // v_a Pi^(a) then W_a Y_a, accumulated into one tile
     const dbl4 acc1 = mfma_tile(tm * 16, tn * 16, R,
         [&](int i, int k) {
@@ -183,7 +180,10 @@ __device__ double hv(Ctx& c, const double* V, double* out, double mu, bool scale
         [&](int k, int r) { return sel(r < R && k < R, Pa[min(k, R - 1) * R + min(r, R - 1)]); });
     const dbl4 acc2 = mfma_tile(tm * 16, tn * 16, R,
         [&](int i, int k) { return sel(i < da && k < R, Wa[min(i, da - 1) * R + min(k, R - 1)]); },
-        [&](int k, int r) { return sel(r < R && k < R, Ya[min(k, R - 1) * R + min(r, R - 1)]); });
+        [&](int k, int r) {
+          const int q = min(k, R - 1) * R + min(r, R - 1);
+          return sel(r < R && k < R, pb2[q] * qb1[q] + pb1[q] * qb2[q]);
+        });
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = tm * 16 + 4 * v + kq, r = tn * 16 + r16;
@@ -708,7 +708,7 @@ size_t state_bytes(const int32_t core[3], int R, int maxiter) {
 }
 
 cpd_status state_init(void* state, const double* S, const int32_t core[3], int R,
-                      const double* W0, double t_norm2, const cpd_params* p, hipStream_t s) {
+                      const double* W0, double t_norm2, const cpd_params* p, hipStream_t s, bool check_flags) {
   if (state == nullptr || S == nullptr || p == nullptr || R < 1 || R > 64 || p->maxiter < 1) {
     set_error("state_init: bad arguments (R=%d)", R);
     return CPD_E_INVALID;
@@ -768,6 +768,7 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
   cpd_status lst;
   const int dc[3] = {core[0], core[1], core[2]};
   if ((lst = launch_dgn(st, S, 0, 0, np, R, dc, s))) return lst;
+  if (!check_flags) return CPD_OK;
   int flags = 0;
   CPD_HIP_CHECK(hipMemcpyAsync(&flags, st + offsetof(Hdr, flags), sizeof(int), hipMemcpyDeviceToHost, s));
   CPD_HIP_CHECK(hipStreamSynchronize(s));
@@ -807,6 +808,16 @@ cpd_status dgn_iterate(void* state, const double* S, int max_steps, hipStream_t 
   prof_begin(CPD_PK_DGN, s);
   const int dc[3] = {h.d[0], h.d[1], h.d[2]};
   const cpd_status st = launch_dgn((char*)state, S, 1, max_steps, h.np, h.R, dc, s);
+  prof_end(CPD_PK_DGN, s);
+  return st;
+}
+
+cpd_status dgn_iterate_known(void* state, const double* S, const int32_t core[3], int R, int max_steps,
+                             hipStream_t s) {
+  const int np = (core[0] + core[1] + core[2]) * R;
+  const int dc[3] = {core[0], core[1], core[2]};
+  prof_begin(CPD_PK_DGN, s);
+  const cpd_status st = launch_dgn((char*)state, S, 1, max_steps, np, R, dc, s);
   prof_end(CPD_PK_DGN, s);
   return st;
 }

@@ -48,7 +48,7 @@ __host__ __device__ inline Layout layout_of(int np, int R, int maxiter) {
 // the gradient stay in the state (each is written and read once per iteration); the core S is
 // staged after the working set when it fits.
 __host__ __device__ inline size_t lds_doubles(int np, int R) {
-  return (size_t)5 * np + (size_t)12 * R * R + (size_t)6 * R + 2 * NW + 16;
+  return (size_t)5 * np + (size_t)9 * R * R + (size_t)6 * R + 2 * NW + 16;
 }
 
 }  // namespace cpd

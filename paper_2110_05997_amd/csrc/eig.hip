@@ -239,9 +239,10 @@ struct FusedLds {
   union {
     JacobiLds jac;
     struct {
-      double C[JMAX][JMAX + 1];      // Gram of the block, then its Cholesky factor R (upper)
+      double C[JMAX][JMAX + 1];      // Gram of the block, then the working matrix of the factorisation
+      double R[JMAX][JMAX + 1];      // Cholesky factor (upper)
       double M[JMAX][JMAX + 1];      // D R^{-1}
-      double dsc[JMAX];
+      double dsc[JMAX];              // D = diag(C)^{-1/2}
     } qr;
   } u;
   double coef[JMAX];
@@ -249,13 +250,6 @@ struct FusedLds {
   double colmax[FNW];
   int bad;
 };
-
-// Orders the LDS accesses of the lanes of one wave (no other wave takes part).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // out(m, c) = sum_t A(m, t) B(t, c) over 16 x 16 tiles spread over the waves; fa / fb return 0
 // outside the operands (clamped indices), st stores an in-range entry.
@@ -274,6 +268,36 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, FA fa, FB fb, FS st
   }
 }
 
+// Small product with a long contraction (k x k outputs, K = n): the output tiles times K slices
+// are spread over all waves, each slice's tile goes to LDS scratch (ns x tiles x 256 doubles) and
+// the slices are summed in a fixed order.
+template <class FA, class FB, class FS>
+__device__ __forceinline__ void wg_gemm_ksplit(int M, int N, int K, FA fa, FB fb, FS st, double* scratch) {
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int tm = tiles16(M), tn = tiles16(N), nt = tm * tn;
+  const int ns = max(1, FNW / nt);
+  const int ks = (((K + ns - 1) / ns) + 15) & ~15;
+  for (int job = w; job < nt * ns; job += FNW) {
+    const int t = job % nt, sl = job / nt;
+    const int bm = t / tn, bn = t - bm * tn;
+    const int k0 = sl * ks, kn = max(0, min(K, k0 + ks) - k0);
+    const dbl4 acc = mfma_tile(bm * 16, bn * 16, kn,
+        [&](int m, int kk) { return (kk < kn) ? fa(m, k0 + kk) : 0.0; },
+        [&](int kk, int c) { return (kk < kn) ? fb(k0 + kk, c) : 0.0; });
+#pragma unroll
+    for (int v = 0; v < 4; ++v) scratch[(sl * nt + t) * 256 + v * 64 + lane] = acc[v];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nt * 256; e += FNT) {
+    const int t = e >> 8, q = e & 255, v = q >> 6, ln = q & 63;
+    const int bm = t / tn, bn = t - bm * tn;
+    const int r = bm * 16 + 4 * v + (ln >> 4), c = bn * 16 + (ln & 15);
+    double sum = 0.0;
+    for (int sl = 0; sl < ns; ++sl) sum += scratch[(sl * nt + t) * 256 + q];
+    if (r < M && c < N) st(r, c, sum);
+  }
+}
+
 // Out = G Q (n x k) for symmetric G, formed as (Q^T G)^T: the tiles of Q^T G read rows of Q and
 // rows of G, sixteen consecutive doubles per fragment row, where G Q would read sixteen rows of G
 // per fragment.
@@ -288,56 +312,51 @@ __device__ __forceinline__ void gq_product(const double* G, const double* Q, int
 // One Cholesky-QR pass Out = X D R^{-1}, D C D = R^T R, C = X^T X, D = diag(C)^{-1/2} (n x k, row
 // major).  Returns (uniformly) whether a pivot fell below 1e-13; Out is then not written.
 __device__ bool cholqr_pass(FusedLds& S, const double* X, int n, int k, double* Out) {
-  const int lane = threadIdx.x & 63, w = wave_id();
+  const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
   const int n1 = n - 1, k1 = k - 1;
-  wg_gemm(k, k, n,
+  wg_gemm_ksplit(k, k, n,
       [&](int r, int i) { return (r < k && i < n) ? X[min(i, n1) * k + min(r, k1)] : 0.0; },
       [&](int i, int c) { return (c < k && i < n) ? X[min(i, n1) * k + min(c, k1)] : 0.0; },
-      [&](int r, int c, double v) { S.u.qr.C[r][c] = v; });
+      [&](int r, int c, double v) { S.u.qr.C[r][c] = v; }, &S.u.qr.M[0][0]);
   __syncthreads();
+  double (*A)[JMAX + 1] = S.u.qr.C;
+  double (*Rf)[JMAX + 1] = S.u.qr.R;
+  double (*Mi)[JMAX + 1] = S.u.qr.M;
+  if (tid < k) {
+    const double cc = A[tid][tid];
+    S.u.qr.dsc[tid] = (cc > 0.0) ? 1.0 / sqrt(cc) : 1.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += FNT) {
+    const int r = e / k, c = e - r * k;
+    if (r <= c) A[r][c] = S.u.qr.dsc[r] * A[r][c] * S.u.qr.dsc[c];
+  }
+  __syncthreads();
+  // D C D = R^T R by the whole workgroup, one barrier per column: row j of R (row j of the working
+  // matrix over sqrt(a_jj)) goes to Rf while the trailing part is updated from the unchanged row j,
+  // so the two never touch the same entries.
+  int fail = 0;
+  for (int j = 0; j < k; ++j) {
+    const double piv = A[j][j];
+    if (!(piv > 1e-13)) fail = 1;
+    const double d = sqrt(fmax(piv, 1e-300));
+    for (int c = j + tid; c < k; c += FNT) Rf[j][c] = (c == j) ? d : A[j][c] / d;
+    const int m = k - 1 - j;
+    for (int e = tid; e < m * m; e += FNT) {
+      const int r = j + 1 + e / m, c = j + 1 + (e - (e / m) * m);
+      if (r <= c) A[r][c] -= (A[j][r] / d) * (A[j][c] / d);
+    }
+    __syncthreads();
+  }
   if (w == 0) {
-    // lane c owns column c: scaling, right-looking factorisation, then column c of R^{-1}
+    // lane c: column c of R^{-1} by back substitution, scaled by D
     const int c = lane;
-    double (*A)[JMAX + 1] = S.u.qr.C;
-    double (*Mi)[JMAX + 1] = S.u.qr.M;
     if (c < k) {
-      const double cc = A[c][c];
-      S.u.qr.dsc[c] = (cc > 0.0) ? 1.0 / sqrt(cc) : 1.0;
-    }
-    wave_sync();
-    if (c < k)
-      for (int r = 0; r <= c; ++r) A[r][c] = S.u.qr.dsc[r] * A[r][c] * S.u.qr.dsc[c];
-    wave_sync();
-    int fail = 0;
-    for (int j = 0; j < k; ++j) {
-      const double piv = A[j][j];
-      if (!(piv > 1e-13)) fail = 1;
-      const double d = sqrt(fmax(piv, 1e-300));
-      wave_sync();
-      if (c >= j && c < k) A[j][c] = (c == j) ? d : A[j][c] / d;
-      wave_sync();
-      if (c > j && c < k) {
-        const double rjc = A[j][c];
-        int r = j + 1;
-        for (; r + 3 <= c; r += 4) {
-          const double x0 = A[j][r], x1 = A[j][r + 1], x2 = A[j][r + 2], x3 = A[j][r + 3];
-          const double y0 = A[r][c], y1 = A[r + 1][c], y2 = A[r + 2][c], y3 = A[r + 3][c];
-          A[r][c] = y0 - x0 * rjc;
-          A[r + 1][c] = y1 - x1 * rjc;
-          A[r + 2][c] = y2 - x2 * rjc;
-          A[r + 3][c] = y3 - x3 * rjc;
-        }
-        for (; r <= c; ++r) A[r][c] -= A[j][r] * rjc;
-      }
-      wave_sync();
-    }
-    if (c < k) {
-      // R x = e_c by back substitution; Mi[i][c] = dsc[i] x[i]
-      Mi[c][c] = 1.0 / A[c][c];
+      Mi[c][c] = 1.0 / Rf[c][c];
       for (int i = c - 1; i >= 0; --i) {
         double acc = 0.0;
-        for (int t = i + 1; t <= c; ++t) acc += A[i][t] * Mi[t][c];
-        Mi[i][c] = -acc / A[i][i];
+        for (int t = i + 1; t <= c; ++t) acc += Rf[i][t] * Mi[t][c];
+        Mi[i][c] = -acc / Rf[i][i];
       }
       for (int i = 0; i <= c; ++i) Mi[i][c] *= S.u.qr.dsc[i];
       for (int i = c + 1; i < k; ++i) Mi[i][c] = 0.0;
@@ -427,10 +446,10 @@ __device__ double rayleigh_ritz(FusedLds& S, const double* G, int n, int P, int 
   gq_product(G, Q, n, k, Z);
   __syncthreads();
   double* B = b.B;
-  wg_gemm(k, k, n,
+  wg_gemm_ksplit(k, k, n,
       [&](int r, int i) { return (r < k && i < n) ? Q[min(i, n1) * k + min(r, k1)] : 0.0; },
       [&](int i, int c) { return (c < k && i < n) ? Z[min(i, n1) * k + min(c, k1)] : 0.0; },
-      [&](int r, int c, double v) { B[r * k + c] = v; });
+      [&](int r, int c, double v) { B[r * k + c] = v; }, &S.u.qr.M[0][0]);
   __syncthreads();
   jacobi_block<FNT, true>(S.u.jac, B, k, k, b.theta, b.Vb);
   __syncthreads();

@@ -223,5 +223,7 @@ __device__ __forceinline__ void jacobi_block(JacobiLds& L, const double* __restr
     if (lane < n) Vout[(long long)i * n + L.rank_of[lane]] = L.V[i][lane];
 }
 
+
+
 }  // namespace
 }  // namespace cpd

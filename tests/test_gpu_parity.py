@@ -346,6 +346,9 @@ def test_solve_edge_cases():
     bad = [torch.full((d, 3), float("nan"), dtype=torch.float64, device=DEV) for d in core]
     with pytest.raises(lib.CpdError, match="status -4"):
         lib.DgnState(S, 3, lib.params(), W0=bad)
+    # the same start through the whole solve: reported after the dGN, before the output stage
+    with pytest.raises(lib.CpdError, match="status -4"):
+        lib.solve(Tg, 3, lib.params(init="given"), W0=bad)
 
 
 def test_solve_is_deterministic():
