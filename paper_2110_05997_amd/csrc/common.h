@@ -158,6 +158,7 @@ cpd_status sumsq_full(const void* T, int dtype, int64_t n, double* out, int* non
 
 // dGN.
 size_t state_bytes(const int32_t core[3], int R, int maxiter);
+size_t dgn_aux_bytes(const int d[3], int R);
 // check_flags = false leaves the non-finite-start flag in the header for the caller to read.
 cpd_status state_init(void* state, const double* S, const int32_t core[3], int R,
                       const double* W0, double t_norm2, const cpd_params* p, hipStream_t s,

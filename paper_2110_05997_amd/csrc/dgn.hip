@@ -330,7 +330,9 @@ __device__ int stop_test(const double* errs, int k, double step, double grad_inf
   return CPD_STOP_NONE;
 }
 
-// mode 0: initialise the state from the W stored in it; mode 1: run up to max_steps iterations.
+// mode 0: initialise the state from the W stored in it; mode 1: run up to max_steps iterations;
+// mode 2: one iteration up to the balanced update, its residual and MTTKRP left to other
+// launches (dgn_tail_kernel finishes the step).
 // SL: the core S is copied into LDS after the working set (the caller sized the LDS for it).
 template <bool SL>
 __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double* __restrict__ S, int mode, int max_steps,
@@ -471,6 +473,13 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     for (int e = tid; e < c.np; e += NT) c.W[e] += c.X[e];
     __syncthreads();
     norm_balance(c);
+    if (mode == 2) {
+      if (tid == 0) {
+        h->f2_pred = f2_pred; h->stepn = sqrt(xx); h->grad_inf = grad_inf; h->cg_resid = rr;
+        h->its = its; h->cap = cap; h->pending = 1;
+      }
+      break;
+    }
     const double f2_new = residual_mttkrp(c, slotB);
     const double err = sqrt(f2_new) / s_norm;
     const double den = f2 - f2_pred;
@@ -518,6 +527,7 @@ __global__ __launch_bounds__(NT) void dgn_kernel(char* __restrict__ state, const
 
 // Same iteration for states too large for LDS: the working set lives in the state's own work
 // region (global memory; one workgroup, so its accesses stay coherent through the CU's cache).
+// MODE 2 is the first half of one iteration (see dgn_tail_kernel).
 template <int MODE>
 __global__ __launch_bounds__(NT) void dgn_kernel_g(char* __restrict__ state, const double* __restrict__ S,
                                                    int max_steps) {
@@ -525,6 +535,36 @@ __global__ __launch_bounds__(NT) void dgn_kernel_g(char* __restrict__ state, con
   const Hdr* h = (const Hdr*)state;
   const Layout Lo = layout_of(h->np, h->R, h->maxiter);
   dgn_body<false>(state, S, MODE, max_steps, (double*)(state + Lo.work), s_stop);
+}
+
+// Second half of an iteration split over launches: from the residual ||S - [[W]]||^2 of the
+// balanced update (f2_new, computed by the full-tensor kernels on the core, which also refreshed
+// the MTTKRP in the state) the error, gain ratio, damping update, stopping tests and log entry.
+__global__ void dgn_tail_kernel(char* __restrict__ state) {
+  if (threadIdx.x != 0) return;
+  Hdr* h = (Hdr*)state;
+  if (h->pending != 1) return;
+  h->pending = 0;
+  const Layout Lo = layout_of(h->np, h->R, h->maxiter);
+  double* errs = (double*)(state + Lo.errs);
+  cpd_step_info* logp = (cpd_step_info*)(state + Lo.log);
+  const int k = h->k;
+  const double f2 = h->f2, f2_new = h->f2_new, mu = h->mu;
+  const double err = sqrt(f2_new) / h->s_norm;
+  const double den = f2 - h->f2_pred;
+  const double g = (den > 0.0) ? (f2 - f2_new) / den : 0.0;
+  const double mu_new = (g < 0.25) ? 3.0 * mu : ((g > 0.75) ? mu / 3.0 : mu);
+  errs[k] = err;
+  const int st = stop_test(errs, k, h->stepn, h->grad_inf, h->tol, h->maxiter, h->div_ref);
+  cpd_step_info inf;
+  inf.k = k; inf.cg_iters = h->its; inf.cg_cap = h->cap; inf.stop = st;
+  inf.rel_err = err; inf.step_norm = h->stepn; inf.grad_inf = h->grad_inf; inf.gain = g;
+  inf.mu = mu_new; inf.cg_resid = h->cg_resid;
+  logp[k - 1] = inf;
+  if (h->tol_iter < 0 && err < h->tol) h->tol_iter = k;
+  h->mu = mu_new;
+  h->f2 = f2_new;
+  h->stop = st;
 }
 
 // Batched: workgroup b initialises state b (header, caps and W already written) and iterates it
@@ -695,16 +735,65 @@ cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int
   } else if (mode == 0) {
     hipLaunchKernelGGL(dgn_kernel_g<0>, dim3(1), dim3(NT), 0, s, state, S, max_steps);
   } else {
-    hipLaunchKernelGGL(dgn_kernel_g<1>, dim3(1), dim3(NT), 0, s, state, S, max_steps);
+    // Large core: each iteration is the single-workgroup half (gradient, CG, update) followed by
+    // the core's MTTKRPs and residual on the full-tensor kernels (spread over the chip) and the
+    // scalar tail; the host checks the stop flag after every few iterations.
+    const int64_t dims[3] = {d[0], d[1], d[2]};
+    Hdr hh;
+    CPD_HIP_CHECK(hipMemcpyAsync(&hh, state, sizeof(Hdr), hipMemcpyDeviceToHost, s));
+    CPD_HIP_CHECK(hipStreamSynchronize(s));
+    const Layout Lo = layout_of(np, R, hh.maxiter);
+    const double* Wp[3] = {(const double*)(state + Lo.W), (const double*)(state + Lo.W) + d[0] * R,
+                           (const double*)(state + Lo.W) + (d[0] + d[1]) * R};
+    double* MK = (double*)(state + Lo.MK);
+    double* MKp[3] = {MK, MK + d[0] * R, MK + (d[0] + d[1]) * R};
+    char* aux = state + align_up(Lo.total, 256);
+    const size_t aux_bytes = dgn_aux_bytes(d, R);
+    double* f2_new = (double*)(state + offsetof(Hdr, f2_new));
+    constexpr int CHUNK = 4;
+    for (int done = 0; done < max_steps; done += CHUNK) {
+      const int n = (max_steps - done < CHUNK) ? max_steps - done : CHUNK;
+      for (int j = 0; j < n; ++j) {
+        hipLaunchKernelGGL(dgn_kernel_g<2>, dim3(1), dim3(NT), 0, s, state, S, 1);
+        CPD_LAUNCH_CHECK();
+        cpd_status st;
+        for (int l = 0; l < 3; ++l)
+          if ((st = mttkrp_full(S, CPD_F64, dims, Wp, R, l, MKp[l], aux, aux_bytes, s))) return st;
+        if ((st = residual_full(S, CPD_F64, dims, Wp, R, f2_new, aux, aux_bytes, s))) return st;
+        hipLaunchKernelGGL(dgn_tail_kernel, dim3(1), dim3(64), 0, s, state);
+        CPD_LAUNCH_CHECK();
+      }
+      if (done + n < max_steps) {
+        CPD_HIP_CHECK(hipMemcpyAsync(&hh, state, sizeof(Hdr), hipMemcpyDeviceToHost, s));
+        CPD_HIP_CHECK(hipStreamSynchronize(s));
+        if (hh.stop != CPD_STOP_NONE) break;
+      }
+    }
+    return CPD_OK;
   }
   CPD_LAUNCH_CHECK();
   return CPD_OK;
 }
 }  // namespace
 
+// Workspace of the full-tensor kernels that take over the core's residual and MTTKRPs when the
+// working set does not fit in LDS (0 otherwise); it follows the state's own regions.
+size_t dgn_aux_bytes(const int d[3], int R) {
+  const int np = (d[0] + d[1] + d[2]) * R;
+  if (lds_fits(np, R, nullptr)) return 0;
+  const int64_t dims[3] = {d[0], d[1], d[2]};
+  size_t b = residual_ws_bytes(dims);
+  for (int l = 0; l < 3; ++l) {
+    const size_t m = mttkrp_ws_bytes(dims, R, l);
+    if (m > b) b = m;
+  }
+  return align_up(b, 256);
+}
+
 size_t state_bytes(const int32_t core[3], int R, int maxiter) {
   const int np = (core[0] + core[1] + core[2]) * R;
-  return layout_of(np, R, maxiter).total;
+  const int d[3] = {core[0], core[1], core[2]};
+  return align_up(layout_of(np, R, maxiter).total, 256) + dgn_aux_bytes(d, R);
 }
 
 cpd_status state_init(void* state, const double* S, const int32_t core[3], int R,

@@ -18,6 +18,9 @@ struct Hdr {
   int32_t k, stop, maxiter, tol_iter;
   int32_t np, flags, pad0, pad1;
   double mu, f2, s_norm, div_ref, tol, cg_tol, init_damp, err0;
+  // one iteration split over launches (large cores): values of the step awaiting its residual
+  double f2_pred, stepn, grad_inf, cg_resid, f2_new;
+  int32_t its, cap, pending, pad2;
 };
 static_assert(sizeof(Hdr) <= 256, "header must fit its slot");
 
