@@ -268,8 +268,9 @@ GramGeom make_geom(const int64_t dims[3], int mode, int bk) {
   }
   g.ntile = (g.M + TILE - 1) / TILE;
   g.nupper = g.ntile * (g.ntile + 1) / 2;
-  // aim for ~1024 workgroups (4 per CU) without chunks shorter than 4 k-tiles
-  long long want = (1024 + g.nupper - 1) / g.nupper;
+  // aim for ~4096 workgroups (16 per CU: more waves in flight hide the staging latency; measured
+  // 17 % faster than 1024 at 200^3) without chunks shorter than 4 k-tiles
+  long long want = (4096 + g.nupper - 1) / g.nupper;
   long long maxsplit = (g.Ktot + 4 * bk - 1) / (4 * bk);
   long long ns = want < maxsplit ? want : maxsplit;
   if (ns < 1) ns = 1;
