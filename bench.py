@@ -217,22 +217,20 @@ def main():
         # full-tensor MTTKRP and Gram throughput on the 200^3 tensor
         Wf = [torch.randn(200, R, dtype=torch.float64, device=dev) for _ in range(3)]
         for mode in range(3):   # untimed: first launches load the kernels
-            cp.mttkrp(Td, Wf, mode)
             cp.gram(Td, mode)
         torch.cuda.synchronize()
         cp.profile_reset()
         cp.profile_enable(True)
         for _ in range(3):
             for mode in range(3):
-                cp.mttkrp(Td, Wf, mode)
                 cp.gram(Td, mode)
         torch.cuda.synchronize()
         cp.profile_enable(False)
-        kp = cp.profile_read()
-        n_m, ms_m = kp["mttkrp"]
-        n_g, ms_g = kp["gram"]
-        out["mttkrp_tflops"] = 2 * R * N / (ms_m / n_m / 1000.0) / 1e12
+        n_g, ms_g = cp.profile_read()["gram"]
         out["gram_tflops"] = N * 201 / (ms_g / n_g / 1000.0) / 1e12
+        mt = mttkrp_rates(cp, torch, Td, Wf, R, [("fp32_in_f64_mfma", cp.CPD_F64), ("fp32_in_f32_mfma", cp.CPD_F32)])
+        out["mttkrp_tflops"] = mt["fp32_in_f64_mfma"]["tflops"]
+        out["mttkrp_200cube"] = mt
 
     if "batch" in legs:
         # batched solver: 512 small planted CPDs (modes U{10..64}, ranks U{2..12}, 50 dB), one graph
@@ -297,21 +295,12 @@ def bench_600cube(cp, synth, torch, dev):
     # full-tensor MTTKRP (2 R N flop per mode) and Gram (N (I+1) per mode) on the FP32 tensor and
     # its BF16 copy
     Wf = [torch.randn(600, 50, dtype=torch.float64, device=dev) for _ in range(3)]
-    N = 600 ** 3
-    rates = {}
-    for tag, X in (("fp32", Td), ("bf16", Tlo)):
-        for mode in range(3):
-            cp.mttkrp(X, Wf, mode)
-        torch.cuda.synchronize()
-        cp.profile_reset()
-        cp.profile_enable(True)
-        for _ in range(2):
-            for mode in range(3):
-                cp.mttkrp(X, Wf, mode)
-        torch.cuda.synchronize()
-        cp.profile_enable(False)
-        n_m, ms_m = cp.profile_read()["mttkrp"]
-        rates["mttkrp_tflops_" + tag] = 2 * 50 * N / (ms_m / n_m / 1000.0) / 1e12
+    m32 = mttkrp_rates(cp, torch, Td, Wf, 50, [("fp32_in_f64_mfma", cp.CPD_F64), ("fp32_in_f32_mfma", cp.CPD_F32)])
+    m16 = mttkrp_rates(cp, torch, Tlo, Wf, 50, [("bf16_in_f64_mfma", cp.CPD_F64), ("bf16_in_f32_mfma", cp.CPD_F32),
+                                                ("bf16_in_bf16_mfma", cp.CPD_BF16)])
+    rates = {"mttkrp_tflops_fp32": m32["fp32_in_f64_mfma"]["tflops"],
+             "mttkrp_tflops_bf16": m16["bf16_in_f64_mfma"]["tflops"],
+             "mttkrp": {**m32, **m16}}
     return {"workload": "dense 600^3 FP32 (+ BF16 copy), planted R=50, SNR 60 dB",
             **rates,
             "s_per_solve_bf16_grams": res["bf16_grams_s"], "s_per_solve_fp64_grams": res["fp64_grams_s"],
@@ -320,6 +309,37 @@ def bench_600cube(cp, synth, torch, dev):
             "iters_bf16_grams": res["bf16_grams"]["info"]["iters"],
             "iters_fp64_grams": res["fp64_grams"]["info"]["iters"],
             "reconstruction_diff_bf16_vs_fp64": cpd_diff(res["bf16_grams"], res["fp64_grams"], torch)}
+
+
+def mttkrp_rates(cp, torch, X, Wf, R, variants, reps=2):
+    """Per compute dtype: TFLOP/s (2 R N flop per mode), tensor bytes streamed per second, the
+    fraction of the matrix-core peak of that dtype and of HBM, and the largest error against the
+    FP64-MFMA result relative to its largest entry (that path is the one checked against the oracle
+    to 1e-12).  Times are HIP events around the whole call (factor rounding, main and reduce kernels),
+    averaged over reps x 3 modes."""
+    N = X.numel()
+    ebytes = X.element_size()
+    peak = {cp.CPD_F64: 78.6, cp.CPD_F32: 157.3, cp.CPD_BF16: 2500.0}
+    ref = [cp.mttkrp(X, Wf, mode, compute_dtype=cp.CPD_F64) for mode in range(3)]
+    res = {}
+    for tag, cd in variants:
+        outs = [cp.mttkrp(X, Wf, mode, compute_dtype=cd) for mode in range(3)]   # untimed first launches
+        torch.cuda.synchronize()
+        err = max(float((o - r).abs().max() / r.abs().max()) for o, r in zip(outs, ref))
+        cp.profile_reset()
+        cp.profile_enable(True)
+        for _ in range(reps):
+            for mode in range(3):
+                cp.mttkrp(X, Wf, mode, compute_dtype=cd)
+        torch.cuda.synchronize()
+        cp.profile_enable(False)
+        n_m, ms_m = cp.profile_read()["mttkrp"]
+        s = ms_m / n_m / 1000.0
+        tf = 2 * R * N / s / 1e12
+        gbs = N * ebytes / s / 1e9
+        res[tag] = {"us": s * 1e6, "tflops": tf, "frac_mfma_peak": tf / peak[cd], "tensor_GBps": gbs,
+                    "frac_hbm": gbs / 8000.0, "max_rel_err_vs_f64": err}
+    return res
 
 
 def bench_learned(torch, n_train=8192, epochs=20, n_test=100):

@@ -215,12 +215,21 @@ size_t cpd_eig_workspace_bytes(int32_t n, int32_t P);
 cpd_status cpd_eig_top(const double* G, int32_t n, int32_t P, double* U, double* lam, void* ws,
                        size_t ws_bytes, void* stream);
 
-/* M (device, dims[mode] x R) = T_(mode) (W^(L) (.) ... (.) W^(1) without W^(mode)), the MTTKRP of
- * the gradient theorem (ch.4 "Computing the gradient").  W[l] (device) dims[l] x R.
- * ws: cpd_mttkrp_workspace_bytes. */
+/* M (device, dims[mode] x R, FP64) = T_(mode) (W^(L) (.) ... (.) W^(1) without W^(mode)), the
+ * MTTKRP of the gradient theorem (ch.4 "Computing the gradient").  W[l] (device) dims[l] x R FP64,
+ * R <= 64.  compute_dtype selects the matrix cores:
+ *   CPD_F64  -- any input dtype, promoted exactly; FP64 products and sums (order-only rounding);
+ *   CPD_F32  -- FP32 or BF16 input: FP32 MFMA; the inner factor (W^(3), or W^(2) for mode 3) is
+ *               rounded to FP32, the outer one is applied in FP32, inner sums accumulate in FP32,
+ *               the partial sums of different workgroups are added in FP64;
+ *   CPD_BF16 -- BF16 input only: BF16 MFMA with FP32 accumulation; the inner factor is rounded
+ *               (to nearest even) to BF16, the rest as for CPD_F32.
+ * Any other pairing returns CPD_E_INVALID.  ws: cpd_mttkrp_workspace_bytes (covers every
+ * compute_dtype). */
 size_t cpd_mttkrp_workspace_bytes(const int64_t dims[3], int32_t R, int32_t mode);
 cpd_status cpd_mttkrp(const void* T, int32_t dtype, const int64_t dims[3], const double* const W[3],
-                      int32_t R, int32_t mode, double* M, void* ws, size_t ws_bytes, void* stream);
+                      int32_t R, int32_t mode, int32_t compute_dtype, double* M, void* ws, size_t ws_bytes,
+                      void* stream);
 
 /* out (device, 1 double) = ||T - sum_r w_r^(1) o w_r^(2) o w_r^(3)||^2, fused (ch.4 "Computing the
  * residual" applied to the input tensor).  ws: cpd_residual_workspace_bytes. */

@@ -300,7 +300,9 @@ def solve_mixed(T_lo, T, R, p=None, W0=None, ws=None):
     return dict(W=W, lam=lam, info=_info_dict(info))
 
 
-def mttkrp(T, Ws, mode):
+def mttkrp(T, Ws, mode, compute_dtype=CPD_F64):
+    """M = T_(mode) (Khatri-Rao of the other two factors), FP64 result; compute_dtype picks the
+    FP64, FP32 or BF16 matrix-core path (see cpd_mttkrp in cpd.h)."""
     _check_tensor(T)
     L = _lib.lib()
     R = Ws[0].shape[1]
@@ -309,7 +311,7 @@ def mttkrp(T, Ws, mode):
     M = torch.empty((T.shape[mode], R), dtype=torch.float64, device=T.device)
     Wc = [w.contiguous().to(torch.float64) for w in Ws]
     _lib.check(L.cpd_mttkrp(_ptr(T), _dtype(T), dims, (ctypes.c_void_p * 3)(*[w.data_ptr() for w in Wc]), R, mode,
-                            _ptr(M), _ptr(ws), ws.numel(), _stream()), "cpd_mttkrp")
+                            compute_dtype, _ptr(M), _ptr(ws), ws.numel(), _stream()), "cpd_mttkrp")
     return M
 
 

@@ -130,8 +130,8 @@ SIGNATURES = [
     ("cpd_eig_workspace_bytes", ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     ("cpd_eig_top", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P]),
     ("cpd_mttkrp_workspace_bytes", ctypes.c_size_t, [_I64x3, ctypes.c_int32, ctypes.c_int32]),
-    ("cpd_mttkrp", ctypes.c_int, [_P, ctypes.c_int32, _I64x3, _Px3, ctypes.c_int32, ctypes.c_int32, _P, _P,
-                                  ctypes.c_size_t, _P]),
+    ("cpd_mttkrp", ctypes.c_int, [_P, ctypes.c_int32, _I64x3, _Px3, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, _P, _P, ctypes.c_size_t, _P]),
     ("cpd_residual_workspace_bytes", ctypes.c_size_t, [_I64x3]),
     ("cpd_residual_norm2", ctypes.c_int, [_P, ctypes.c_int32, _I64x3, _Px3, ctypes.c_int32, _P, _P,
                                           ctypes.c_size_t, _P]),

@@ -421,10 +421,12 @@ size_t cpd_mttkrp_workspace_bytes(const int64_t dims[3], int32_t R, int32_t mode
 }
 
 cpd_status cpd_mttkrp(const void* T, int32_t dtype, const int64_t dims[3], const double* const W[3],
-                      int32_t R, int32_t mode, double* M, void* ws, size_t ws_bytes, void* stream) {
-  CPD_REQUIRE(T && W && W[0] && W[1] && W[2] && M && dims_ok(dims) && dtype_ok(dtype) && R >= 1 && R <= 64,
+                      int32_t R, int32_t mode, int32_t compute_dtype, double* M, void* ws, size_t ws_bytes,
+                      void* stream) {
+  CPD_REQUIRE(T && W && W[0] && W[1] && W[2] && M && dims_ok(dims) && dtype_ok(dtype) && dtype_ok(compute_dtype) &&
+                  R >= 1 && R <= 64,
               "cpd_mttkrp: bad arguments");
-  return mttkrp_full(T, dtype, dims, W, R, mode, M, ws, ws_bytes, (hipStream_t)stream);
+  return mttkrp_full(T, dtype, dims, W, R, mode, compute_dtype, M, ws, ws_bytes, (hipStream_t)stream);
 }
 
 size_t cpd_residual_workspace_bytes(const int64_t dims[3]) {

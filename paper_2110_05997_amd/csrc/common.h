@@ -147,7 +147,7 @@ cpd_status eig_top(const double* G, int n, int P, double* U, double* lam, void* 
 
 // Full-tensor kernels.
 cpd_status mttkrp_full(const void* T, int dtype, const int64_t dims[3], const double* const W[3],
-                       int R, int mode, double* M, void* ws, size_t ws_bytes, hipStream_t s);
+                       int R, int mode, int compute_dtype, double* M, void* ws, size_t ws_bytes, hipStream_t s);
 size_t residual_ws_bytes(const int64_t dims[3]);
 size_t sumsq_ws_bytes();
 cpd_status residual_full(const void* T, int dtype, const int64_t dims[3],

@@ -758,7 +758,7 @@ cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int
         CPD_LAUNCH_CHECK();
         cpd_status st;
         for (int l = 0; l < 3; ++l)
-          if ((st = mttkrp_full(S, CPD_F64, dims, Wp, R, l, MKp[l], aux, aux_bytes, s))) return st;
+          if ((st = mttkrp_full(S, CPD_F64, dims, Wp, R, l, CPD_F64, MKp[l], aux, aux_bytes, s))) return st;
         if ((st = residual_full(S, CPD_F64, dims, Wp, R, f2_new, aux, aux_bytes, s))) return st;
         hipLaunchKernelGGL(dgn_tail_kernel, dim3(1), dim3(64), 0, s, state);
         CPD_LAUNCH_CHECK();

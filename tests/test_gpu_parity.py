@@ -167,6 +167,53 @@ def test_mttkrp_and_residual_match_oracle(dims, R, dtype):
     assert abs(r2 - ref) <= 1e-12 * ref
 
 
+# FP32 / BF16 matrix-core MTTKRP.  Every rounding is bounded by a standard dot-product argument:
+# the inner factor is rounded once (unit roundoff u_w: 2^-24 for FP32, 2^-8 for BF16 to nearest
+# even), the outer factor once to FP32, and the inner (<= Y terms) and outer (<= X terms) FP32 sums
+# plus the fold and the cross-wave adds take at most Y + X + 16 roundings of 2^-24; the FP64 sums
+# of the partials are far below that.  Hence, elementwise,
+#   |M - M_exact| <= ((1 + u_w)(1 + 2^-24)^(Y + X + 16) - 1) * (|T|_(mode) (|W| (.) |W|))
+# with M_exact the FP64 oracle on the same (FP32 / BF16) tensor values.
+LP_CASES = [((70, 45, 130), 5, torch.float32), ((33, 97, 64), 17, torch.float32), ((64, 70, 48), 40, torch.bfloat16),
+            ((50, 41, 100), 64, torch.bfloat16), ((3, 130, 2), 2, torch.float32), ((129, 1, 65), 9, torch.bfloat16),
+            ((200, 200, 200), 20, torch.float32), ((200, 200, 200), 20, torch.bfloat16),
+            # inner length 1700 at R = 64: the inner factor exceeds LDS, so modes 1 and 2 read it from L2
+            ((9, 20, 1700), 64, torch.bfloat16)]
+
+
+@pytest.mark.parametrize("dims,R,dtype", LP_CASES)
+def test_mttkrp_fp32_bf16_matrix_cores_within_rounding_bound(dims, R, dtype):
+    log("mttkrp lp", dims, R, dtype)
+    rng = np.random.default_rng(11)
+    T = rng.standard_normal(dims)
+    Ws = [rng.standard_normal((d, R)) for d in dims]
+    Td = dev(T, dtype)
+    Th = host(Td)
+    computes = [cp().CPD_F32] + ([cp().CPD_BF16] if dtype == torch.bfloat16 else [])
+    for mode in range(3):
+        ref = odgn.mttkrp(Th, Ws, mode)
+        mag = odgn.mttkrp(np.abs(Th), [np.abs(w) for w in Ws], mode)
+        X = dims[1] if mode == 0 else dims[0]
+        Y = dims[1] if mode == 2 else dims[2]
+        for cd in computes:
+            uw = 2.0 ** -24 if cd == cp().CPD_F32 else 2.0 ** -8
+            gam = (1 + uw) * (1 + 2.0 ** -24) ** (Y + X + 16) - 1
+            M = host(cp().mttkrp(Td, [dev(w) for w in Ws], mode, compute_dtype=cd))
+            err = np.abs(M - ref)
+            assert np.all(err <= gam * mag), (mode, cd, float(np.max(err / (gam * mag + 1e-300))))
+            # and the result is not trivially inside a loose bound: it tracks the FP64 product
+            assert relmax(M, ref) < (1e-5 if cd == cp().CPD_F32 else 3e-2), (mode, cd, relmax(M, ref))
+
+
+def test_mttkrp_rejects_unsupported_compute_pairing():
+    T = dev(np.ones((4, 5, 6)), torch.float32)
+    Ws = [dev(np.ones((d, 3))) for d in (4, 5, 6)]
+    with pytest.raises(RuntimeError):
+        cp().mttkrp(T, Ws, 0, compute_dtype=cp().CPD_BF16)
+    with pytest.raises(RuntimeError):
+        cp().mttkrp(dev(np.ones((4, 5, 6))), Ws, 0, compute_dtype=cp().CPD_F32)
+
+
 def oracle_steps(S, W0, params, uniforms, nsteps):
     st = odgn.init_state(S, W0, params)
     infos = []
