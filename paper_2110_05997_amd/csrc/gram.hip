@@ -256,7 +256,8 @@ __global__ void gram_reduce_kernel(const double* __restrict__ part, GramGeom g, 
   G[(long long)n * g.M + m] = s;
 }
 
-GramGeom make_geom(const int64_t dims[3], int mode, int bk) {
+// Unfolding view of mode `mode` (variant, sizes and strides; no tiling).
+GramGeom make_geom_base(const int64_t dims[3], int mode) {
   GramGeom g{};
   const long long I1 = dims[0], I2 = dims[1], I3 = dims[2];
   if (mode == 0) {
@@ -266,6 +267,157 @@ GramGeom make_geom(const int64_t dims[3], int mode, int bk) {
   } else {
     g.variant = 1; g.M = (int)I3; g.Ktot = (int)(I1 * I2); g.sk = (int)I3;
   }
+  return g;
+}
+
+// Small Grams (M <= 208), FP64 path: one workgroup per split-K chunk computes every upper-triangle
+// 16x16 tile of G from its chunk, which it holds for all M rows in LDS.  Each tensor element is
+// read once, and the partials are one triangle per chunk (at M = 200: 91 tiles, 47 MB for 250
+// chunks) instead of one 64x64 tile per (tile, chunk) pair (105 MB), with 64x64 tiles that are
+// 22 % padding at M = 200.  Eight waves take the tiles round robin.
+constexpr int GT_NW = 8;
+constexpr int GT_NT = 64 * GT_NW;
+constexpr int GT_KC = 32;            // contraction indices per stage
+constexpr int GT_LD = GT_KC + 1;     // LDS row pitch (doubles)
+constexpr int GT_MAXM = 208;   // up to 91 tiles, 12 per wave: accumulators stay in registers
+constexpr int GT_PER = GT_MAXM * GT_KC / GT_NT;   // staged elements per thread and stage
+
+template <class T, int NTW>
+__global__ __launch_bounds__(GT_NT) void gram_tri_kernel(const T* __restrict__ src, GramGeom g, int mp,
+                                                         double* __restrict__ part) {
+  extern __shared__ double xs[];   // [mp][GT_LD]
+  const int nt = mp / 16, ntri = nt * (nt + 1) / 2;
+  const int split = blockIdx.x;
+  const int kbeg = split * g.kchunk, kend = min(g.Ktot, kbeg + g.kchunk);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r = lane & 15, q = lane >> 4;
+  const double invK = 1.0 / (double)(g.variant == 0 ? g.K : 1);
+  int ti[NTW], tj[NTW];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) {
+    // (row, column) of upper-triangle tile t, rows enumerated in order; a fixed-trip search so the
+    // surrounding loop unrolls and ti / tj stay in registers
+    const int t = w + GT_NW * j < ntri ? w + GT_NW * j : 0;
+    int row = 0, start = 0;
+#pragma unroll
+    for (int rr = 0; rr < GT_MAXM / 16; ++rr) {
+      const bool next = rr == row && rr < nt && t >= start + (nt - rr);
+      start += next ? nt - rr : 0;
+      row += next ? 1 : 0;
+    }
+    ti[j] = row;
+    tj[j] = row + (t - start);
+  }
+  dbl4 acc[NTW];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) acc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  // staging slot s of this thread: element e = tid + s GT_NT of the mp x GT_KC stage, along the
+  // index that is contiguous in memory (k for variant 0, the row for variant 1)
+  const int nel = mp * GT_KC;
+  double rv[GT_PER];
+  const bool rowk = g.variant == 0;
+  auto slot = [=](int s) {   // (row, k) of slot s, returned by value
+    const int e = tid + s * GT_NT;
+    const int m0 = e / GT_KC, k0 = e & (GT_KC - 1), k1 = e / mp, m1 = e - k1 * mp;
+    return rowk ? int2{m0, k0} : int2{m1, k1};
+  };
+  // element (m, kp) of the unfolding, from scalar strides (variant 0 splits kp = b K + k by a
+  // double-precision reciprocal, exact for kp < 2^26)
+  const bool v0 = g.variant == 0;
+  const int gM = g.M, gK = g.K, sm = g.sm, sk = g.sk;
+  const long long sb = g.sb;
+  auto addr = [=](int m, int kp) -> long long {
+    if (v0) {
+      const int b = (int)(((double)kp + 0.5) * invK);
+      return (long long)b * sb + (long long)m * sm + (kp - b * gK);
+    }
+    return (long long)kp * sk + m;
+  };
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int s = 0; s < GT_PER; ++s) {
+      const int2 mk = slot(s);
+      const int m = mk.x, kk = mk.y;
+      const int kp = k0 + kk;
+      const bool ok = tid + s * GT_NT < nel && m < gM && kp < kend;
+      const T v = src[addr(ok ? m : 0, ok ? kp : 0)];
+      rv[s] = ok ? conv<double, T>(v) : 0.0;
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += GT_KC) {
+#pragma unroll
+    for (int s = 0; s < GT_PER; ++s) {
+      const int2 mk = slot(s);
+      if (tid + s * GT_NT < nel) xs[mk.x * GT_LD + mk.y] = rv[s];
+    }
+    __syncthreads();
+    if (k0 + GT_KC < kend) fetch(k0 + GT_KC);
+#pragma unroll
+    for (int kk = 0; kk < GT_KC; kk += 4) {
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) {
+        if (w + GT_NW * j < ntri) {
+          // A fragment: lane holds A[lane%16][lane/16]; B fragment: B[lane/16][lane%16]
+          const double a = xs[(16 * ti[j] + r) * GT_LD + kk + q];
+          const double b = xs[(16 * tj[j] + r) * GT_LD + kk + q];
+          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // D[4 v + lane/16][lane%16] is acc[v] (result layout of v_mfma_f64_16x16x4f64)
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) {
+    const int t = w + GT_NW * j;
+    if (t < ntri) {
+      double* out = part + ((long long)split * ntri + t) * 256;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(4 * v + q) * 16 + r] = acc[j][v];
+    }
+  }
+}
+
+// G[m][n] = G[n][m] = sum over chunks (in order) of the partial triangles
+__global__ void gram_tri_reduce_kernel(const double* __restrict__ part, int M, int mp, int nsplit,
+                                       double* __restrict__ G) {
+  const int nt = mp / 16, ntri = nt * (nt + 1) / 2;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)ntri * 256) return;
+  const int t = (int)(e >> 8), rc = (int)(e & 255), rr = rc >> 4, cc = rc & 15;
+  int tm, tn;
+  tile_of(t, nt, tm, tn);
+  if (tm == tn && rr > cc) return;
+  const int m = tm * 16 + rr, n = tn * 16 + cc;
+  if (m >= M || n >= M) return;
+  const double* p = part + e;
+  const long long stride = (long long)ntri * 256;
+  double s0 = 0.0, s1 = 0.0;
+  int k = 0;
+  for (; k + 1 < nsplit; k += 2) {
+    s0 += p[(long long)k * stride];
+    s1 += p[(long long)(k + 1) * stride];
+  }
+  if (k < nsplit) s0 += p[(long long)k * stride];
+  const double s = s0 + s1;
+  G[(long long)m * M + n] = s;
+  G[(long long)n * M + m] = s;
+}
+
+// Split of the contraction for gram_tri_kernel: about 256 chunks (one workgroup per CU), each a
+// multiple of the stage length.
+GramGeom make_tri_geom(const int64_t dims[3], int mode, int* mp) {
+  GramGeom g = make_geom_base(dims, mode);
+  *mp = (g.M + 15) / 16 * 16;
+  long long chunk = (g.Ktot + 255) / 256;
+  chunk = (chunk + GT_KC - 1) / GT_KC * GT_KC;
+  g.kchunk = (int)chunk;
+  g.nsplit = (int)((g.Ktot + chunk - 1) / chunk);
+  return g;
+}
+
+GramGeom make_geom(const int64_t dims[3], int mode, int bk) {
+  GramGeom g = make_geom_base(dims, mode);
   g.ntile = (g.M + TILE - 1) / TILE;
   g.nupper = g.ntile * (g.ntile + 1) / 2;
   // aim for ~4096 workgroups (16 per CU: more waves in flight hide the staging latency; measured
@@ -286,12 +438,32 @@ GramGeom make_geom(const int64_t dims[3], int mode, int bk) {
 
 bool use_bf16(int dtype, int compute_dtype) { return dtype == CPD_BF16 && compute_dtype == CPD_BF16; }
 
+template <class T>
+cpd_status launch_tri(const void* src, const GramGeom& g, int mp, int ntw, size_t lds, double* part, hipStream_t s) {
+  const dim3 grid(g.nsplit), block(GT_NT);
+  const T* p = (const T*)src;
+  auto k = ntw <= 2 ? gram_tri_kernel<T, 2> : ntw <= 5 ? gram_tri_kernel<T, 5>
+         : ntw <= 10 ? gram_tri_kernel<T, 10> : gram_tri_kernel<T, 12>;
+  if (lds > 64 * 1024)
+    CPD_HIP_CHECK(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k, grid, block, lds, s, p, g, mp, part);
+  return CPD_OK;
+}
+
 }  // namespace
 
 size_t gram_ws_bytes(const int64_t dims[3], int mode) {
   const GramGeom g = make_geom(dims, mode, BK), h = make_geom(dims, mode, BKH);
   const int ns = g.nsplit > h.nsplit ? g.nsplit : h.nsplit;
-  return align_up((size_t)g.nupper * ns * TILE * TILE * sizeof(double), 256);
+  size_t b = align_up((size_t)g.nupper * ns * TILE * TILE * sizeof(double), 256);
+  if (g.M <= GT_MAXM) {
+    int mp;
+    const GramGeom t = make_tri_geom(dims, mode, &mp);
+    const size_t nt = mp / 16;
+    const size_t bt = align_up((size_t)t.nsplit * (nt * (nt + 1) / 2) * 256 * sizeof(double), 256);
+    b = b > bt ? b : bt;
+  }
+  return b;
 }
 
 cpd_status gram(const void* T, int dtype, const int64_t dims[3], int mode, int compute_dtype,
@@ -308,6 +480,28 @@ cpd_status gram(const void* T, int dtype, const int64_t dims[3], int mode, int c
     return CPD_E_WORKSPACE;
   }
   double* part = (double*)ws;
+  if (!bf && g.M <= GT_MAXM) {
+    int mp;
+    const GramGeom t = make_tri_geom(dims, mode, &mp);
+    const int nt = mp / 16, ntri = nt * (nt + 1) / 2;
+    const int ntw = (ntri + GT_NW - 1) / GT_NW;
+    const size_t lds = (size_t)mp * GT_LD * sizeof(double);
+    prof_begin(CPD_PK_GRAM, s);
+    cpd_status st = CPD_OK;
+    switch (dtype) {
+      case CPD_F64: st = launch_tri<double>(T, t, mp, ntw, lds, part, s); break;
+      case CPD_F32: st = launch_tri<float>(T, t, mp, ntw, lds, part, s); break;
+      case CPD_BF16: st = launch_tri<uint16_t>(T, t, mp, ntw, lds, part, s); break;
+      default: set_error("gram: bad dtype %d", dtype); return CPD_E_INVALID;
+    }
+    if (st) return st;
+    const long long nel = (long long)ntri * 256;
+    hipLaunchKernelGGL(gram_tri_reduce_kernel, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, s, part, t.M, mp,
+                       t.nsplit, G);
+    prof_end(CPD_PK_GRAM, s);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+  }
   const int nblocks = g.nupper * g.nsplit;
   prof_begin(CPD_PK_GRAM, s);
   switch (dtype) {
@@ -329,11 +523,11 @@ cpd_status gram(const void* T, int dtype, const int64_t dims[3], int mode, int c
       set_error("gram: bad dtype %d", dtype);
       return CPD_E_INVALID;
   }
-  prof_end(CPD_PK_GRAM, s);
   CPD_LAUNCH_CHECK();
   const long long nel = (long long)g.nupper * TILE * TILE;
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, s,
                      part, g, G);
+  prof_end(CPD_PK_GRAM, s);
   CPD_LAUNCH_CHECK();
   return CPD_OK;
 }

@@ -51,8 +51,12 @@ def log(*a):
 
 
 # ---------------------------------------------------------------------------------------------
+# Gram sizes <= 208 take the whole-triangle kernel, larger ones the 64x64-tile kernel (230, 209);
+# bf16 input is promoted exactly on the FP64 path
 @pytest.mark.parametrize("dims,dtype", [((70, 45, 130), torch.float64), ((33, 97, 20), torch.float32),
-                                        ((5, 4, 3), torch.float64), ((130, 1, 65), torch.float64)])
+                                        ((5, 4, 3), torch.float64), ((130, 1, 65), torch.float64),
+                                        ((230, 20, 9), torch.float32), ((7, 209, 208), torch.bfloat16),
+                                        ((200, 200, 200), torch.float32)])
 def test_gram_matches_unfolding_gram(dims, dtype):
     log("gram", dims, dtype)
     rng = np.random.default_rng(sum(dims))
