@@ -274,13 +274,13 @@ GramGeom make_geom_base(const int64_t dims[3], int mode) {
 // 16x16 tile of G from its chunk, which it holds for all M rows in LDS.  Each tensor element is
 // read once, and the partials are one triangle per chunk (at M = 200: 91 tiles, 47 MB for 250
 // chunks) instead of one 64x64 tile per (tile, chunk) pair (105 MB), with 64x64 tiles that are
-// 22 % padding at M = 200.  Eight waves take the tiles round robin.
-constexpr int GT_NW = 8;
+// 22 % padding at M = 200.  Twelve waves take the tiles round robin.
+constexpr int GT_NW = 12;
 constexpr int GT_NT = 64 * GT_NW;
 constexpr int GT_KC = 32;            // contraction indices per stage
 constexpr int GT_LD = GT_KC + 1;     // LDS row pitch (doubles)
-constexpr int GT_MAXM = 208;   // up to 91 tiles, 12 per wave: accumulators stay in registers
-constexpr int GT_PER = GT_MAXM * GT_KC / GT_NT;   // staged elements per thread and stage
+constexpr int GT_MAXM = 208;   // up to 91 tiles, 8 per wave: accumulators stay in registers
+constexpr int GT_PER = (GT_MAXM * GT_KC + GT_NT - 1) / GT_NT;   // staged elements per thread and stage
 
 template <class T, int NTW>
 __global__ __launch_bounds__(GT_NT) void gram_tri_kernel(const T* __restrict__ src, GramGeom g, int mp,
@@ -313,7 +313,8 @@ __global__ __launch_bounds__(GT_NT) void gram_tri_kernel(const T* __restrict__ s
   // staging slot s of this thread: element e = tid + s GT_NT of the mp x GT_KC stage, along the
   // index that is contiguous in memory (k for variant 0, the row for variant 1)
   const int nel = mp * GT_KC;
-  double rv[GT_PER];
+  T rv[GT_PER];   // raw staged values: masked and converted only when written to LDS, so the
+                  // loads stay in flight through the previous stage's MFMAs
   const bool rowk = g.variant == 0;
   auto slot = [=](int s) {   // (row, k) of slot s, returned by value
     const int e = tid + s * GT_NT;
@@ -339,8 +340,7 @@ __global__ __launch_bounds__(GT_NT) void gram_tri_kernel(const T* __restrict__ s
       const int m = mk.x, kk = mk.y;
       const int kp = k0 + kk;
       const bool ok = tid + s * GT_NT < nel && m < gM && kp < kend;
-      const T v = src[addr(ok ? m : 0, ok ? kp : 0)];
-      rv[s] = ok ? conv<double, T>(v) : 0.0;
+      rv[s] = src[addr(ok ? m : 0, ok ? kp : 0)];
     }
   };
   if (kbeg < kend) fetch(kbeg);
@@ -348,21 +348,27 @@ __global__ __launch_bounds__(GT_NT) void gram_tri_kernel(const T* __restrict__ s
 #pragma unroll
     for (int s = 0; s < GT_PER; ++s) {
       const int2 mk = slot(s);
-      if (tid + s * GT_NT < nel) xs[mk.x * GT_LD + mk.y] = rv[s];
+      const bool ok = mk.x < gM && k0 + mk.y < kend;
+      if (tid + s * GT_NT < nel) xs[mk.x * GT_LD + mk.y] = ok ? conv<double, T>(rv[s]) : 0.0;
     }
     __syncthreads();
     if (k0 + GT_KC < kend) fetch(k0 + GT_KC);
 #pragma unroll
     for (int kk = 0; kk < GT_KC; kk += 4) {
+      // every slot runs (a slot past the last tile repeats tile 0 and is not written): no branch,
+      // so the LDS reads of a k-step are issued together ahead of its MFMAs.
+      // A fragment: lane holds A[lane%16][lane/16]; B fragment: B[lane/16][lane%16]
+      double a[NTW], b[NTW];
 #pragma unroll
       for (int j = 0; j < NTW; ++j) {
-        if (w + GT_NW * j < ntri) {
-          // A fragment: lane holds A[lane%16][lane/16]; B fragment: B[lane/16][lane%16]
-          const double a = xs[(16 * ti[j] + r) * GT_LD + kk + q];
-          const double b = xs[(16 * tj[j] + r) * GT_LD + kk + q];
-          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
-        }
+        a[j] = xs[(16 * ti[j] + r) * GT_LD + kk + q];
+        b[j] = xs[(16 * tj[j] + r) * GT_LD + kk + q];
       }
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b[j], acc[j], 0, 0, 0);
+      // keep the next k-step's reads below this point: hoisted further they would need more
+      // registers than the accumulators leave
+      __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
   }
@@ -378,30 +384,41 @@ __global__ __launch_bounds__(GT_NT) void gram_tri_kernel(const T* __restrict__ s
   }
 }
 
-// G[m][n] = G[n][m] = sum over chunks (in order) of the partial triangles
-__global__ void gram_tri_reduce_kernel(const double* __restrict__ part, int M, int mp, int nsplit,
-                                       double* __restrict__ G) {
+// G[m][n] = G[n][m] = sum over chunks of the partial triangles: 32 entries per 256-thread block,
+// eight threads per entry each adding every eighth chunk (four interleaved sums, so loads stay in
+// flight), the eight results combined in a fixed order (bit-reproducible).
+__global__ __launch_bounds__(256) void gram_tri_reduce_kernel(const double* __restrict__ part, int M, int mp,
+                                                              int nsplit, double* __restrict__ G) {
+  __shared__ double red[8][33];
   const int nt = mp / 16, ntri = nt * (nt + 1) / 2;
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)ntri * 256) return;
-  const int t = (int)(e >> 8), rc = (int)(e & 255), rr = rc >> 4, cc = rc & 15;
-  int tm, tn;
-  tile_of(t, nt, tm, tn);
-  if (tm == tn && rr > cc) return;
-  const int m = tm * 16 + rr, n = tn * 16 + cc;
-  if (m >= M || n >= M) return;
-  const double* p = part + e;
-  const long long stride = (long long)ntri * 256;
-  double s0 = 0.0, s1 = 0.0;
-  int k = 0;
-  for (; k + 1 < nsplit; k += 2) {
-    s0 += p[(long long)k * stride];
-    s1 += p[(long long)(k + 1) * stride];
+  const int o = threadIdx.x & 31, qq = threadIdx.x >> 5;
+  const long long n = (long long)ntri * 256;
+  const long long e = (long long)blockIdx.x * 32 + o;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (e < n) {
+    int sp = qq;
+    for (; sp + 24 < nsplit; sp += 32) {
+      s0 += part[(long long)sp * n + e];
+      s1 += part[(long long)(sp + 8) * n + e];
+      s2 += part[(long long)(sp + 16) * n + e];
+      s3 += part[(long long)(sp + 24) * n + e];
+    }
+    for (; sp < nsplit; sp += 8) s0 += part[(long long)sp * n + e];
   }
-  if (k < nsplit) s0 += p[(long long)k * stride];
-  const double s = s0 + s1;
-  G[(long long)m * M + n] = s;
-  G[(long long)n * M + m] = s;
+  red[qq][o] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (qq == 0 && e < n) {
+    const int t = (int)(e >> 8), rc = (int)(e & 255), rr = rc >> 4, cc = rc & 15;
+    int tm, tn;
+    tile_of(t, nt, tm, tn);
+    const int m = tm * 16 + rr, c = tn * 16 + cc;
+    if ((tm != tn || rr <= cc) && m < M && c < M) {
+      const double v = ((red[0][o] + red[1][o]) + (red[2][o] + red[3][o])) +
+                       ((red[4][o] + red[5][o]) + (red[6][o] + red[7][o]));
+      G[(long long)m * M + c] = v;
+      G[(long long)c * M + m] = v;
+    }
+  }
 }
 
 // Split of the contraction for gram_tri_kernel: about 256 chunks (one workgroup per CU), each a
@@ -442,8 +459,7 @@ template <class T>
 cpd_status launch_tri(const void* src, const GramGeom& g, int mp, int ntw, size_t lds, double* part, hipStream_t s) {
   const dim3 grid(g.nsplit), block(GT_NT);
   const T* p = (const T*)src;
-  auto k = ntw <= 2 ? gram_tri_kernel<T, 2> : ntw <= 5 ? gram_tri_kernel<T, 5>
-         : ntw <= 10 ? gram_tri_kernel<T, 10> : gram_tri_kernel<T, 12>;
+  auto k = ntw <= 1 ? gram_tri_kernel<T, 1> : ntw <= 3 ? gram_tri_kernel<T, 3> : gram_tri_kernel<T, 8>;
   if (lds > 64 * 1024)
     CPD_HIP_CHECK(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k, grid, block, lds, s, p, g, mp, part);
@@ -496,7 +512,7 @@ cpd_status gram(const void* T, int dtype, const int64_t dims[3], int mode, int c
     }
     if (st) return st;
     const long long nel = (long long)ntri * 256;
-    hipLaunchKernelGGL(gram_tri_reduce_kernel, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, s, part, t.M, mp,
+    hipLaunchKernelGGL(gram_tri_reduce_kernel, dim3((unsigned)((nel + 31) / 32)), dim3(256), 0, s, part, t.M, mp,
                        t.nsplit, G);
     prof_end(CPD_PK_GRAM, s);
     CPD_LAUNCH_CHECK();
