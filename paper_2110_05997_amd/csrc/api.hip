@@ -152,14 +152,21 @@ cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_d
   // S = T x1 U1^T x2 U2^T x3 U3^T
   const int I1 = (int)dims[0], I2 = (int)dims[1], I3 = (int)dims[2];
   const int r1 = rk[0], r2 = rk[1], r3 = rk[2];
+  // Y1[a][i2 i3] = sum_i1 U1[i1][a] T[i1][i2 i3]; Y2[a][b][i3] = sum_i2 U2[i2][b] Y1[a][i2][i3]
   prof_begin(CPD_PK_PROJECT, s);
-  st = gemm_f64(r1, I2 * I3, I1, 1.0, U_out[0], r1, 0, true, T, dtype, (long long)I2 * I3, 0, false, 0.0, Y1,
-                (long long)I2 * I3, 0, 1, s);
+  if (mode_product_mid_fits(I1, r1))
+    st = mode_product_mid(T, dtype, 1, I1, (long long)I2 * I3, U_out[0], r1, Y1, s);
+  else
+    st = gemm_f64(r1, I2 * I3, I1, 1.0, U_out[0], r1, 0, true, T, dtype, (long long)I2 * I3, 0, false, 0.0, Y1,
+                  (long long)I2 * I3, 0, 1, s);
   prof_end(CPD_PK_PROJECT, s);
   if (st) return st;
-  if ((st = gemm_f64(r2, I3, I2, 1.0, U_out[1], r2, 0, true, Y1, CPD_F64, I3, (long long)I2 * I3, false,
-                     0.0, Y2, I3, (long long)r2 * I3, r1, s)))
-    return st;
+  if (mode_product_mid_fits(I2, r2))
+    st = mode_product_mid(Y1, CPD_F64, r1, I2, I3, U_out[1], r2, Y2, s);
+  else
+    st = gemm_f64(r2, I3, I2, 1.0, U_out[1], r2, 0, true, Y1, CPD_F64, I3, (long long)I2 * I3, false, 0.0, Y2, I3,
+                  (long long)r2 * I3, r1, s);
+  if (st) return st;
   if ((st = gemm_f64(r1 * r2, r3, I3, 1.0, Y2, I3, 0, false, U_out[2], CPD_F64, r3, 0, false, 0.0, S_out,
                      r3, 0, 1, s)))
     return st;

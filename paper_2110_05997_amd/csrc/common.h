@@ -126,6 +126,10 @@ __host__ __device__ __forceinline__ double u01_from_bits(uint64_t x) {
 //   op(A)(m,k) = ta ? A[k*lda + m] : A[m*lda + k];  op(B)(k,n) = tb ? B[n*ldb + k] : B[k*ldb + n]
 //   C(m,n) = tc ? C[n*ldc + m] : C[m*ldc + n]
 //   bdtype: element type of B (CPD_F64, CPD_F32 or CPD_BF16); A and C are FP64.
+// Y[a][b][k] = sum_j U[j][b] X[a][j][k] (U is J x nb row-major, X and Y dense, k contiguous).
+cpd_status mode_product_mid(const void* X, int xdtype, int A, int J, long long K, const double* U, int nb,
+                            double* Y, hipStream_t s);
+bool mode_product_mid_fits(int J, int nb);   // whether mode_product_mid supports J rows of U
 cpd_status gemm_f64(int M, int N, int K, double alpha, const double* A, int lda, long long sA,
                     bool ta, const void* B, int bdtype, long long ldb, long long sB, bool tb,
                     double beta, double* C, long long ldc, long long sC, int batch,

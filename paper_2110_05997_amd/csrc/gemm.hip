@@ -163,6 +163,79 @@ __global__ void gemm_small_kernel(int M, int N, int K, double alpha, const doubl
   *c = (beta == 0.0) ? alpha * acc : alpha * acc + beta * *c;
 }
 
+// Mode product along a middle index: Y[a][b][k] = sum_j U[j][b] X[a][j][k] for a < A, b < nb,
+// k < K (k contiguous).  The first two factor products of the core projection S = T x1 U1^T x2 U2^T
+// x3 U3^T are of this form (a = 1, j = i1, k = (i2, i3); then a = row of the first product, j = i2,
+// k = i3).  Lane = k, so every load of X is coalesced and X is read once; U is the same for the
+// whole wave and is staged once in LDS (each read a broadcast, off the X loads' wait counter); NB
+// accumulators per lane; the four waves split j and are added in a fixed order through LDS.
+constexpr int MP_NB = 20;                  // outputs per pass
+constexpr size_t MP_LDS = 64 * 1024;       // LDS for the staged rows of U
+
+template <class TX, int NB>
+__global__ __launch_bounds__(256) void mprod_kernel(const TX* __restrict__ X, int J, long long K,
+                                                    const double* __restrict__ U, int ldu, int b0, int nb,
+                                                    double* __restrict__ Y, long long ldy) {
+  __shared__ double red[3][NB][64];
+  extern __shared__ double us[];   // [J][NB]: columns b0 .. b0 + NB - 1 of U, zero past nb
+  for (int e = threadIdx.x; e < J * NB; e += 256) {
+    const int jj = e / NB, b = e - jj * NB;
+    us[e] = b0 + b < nb ? U[(long long)jj * ldu + b0 + b] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long long k = (long long)blockIdx.x * 64 + lane;
+  const long long a = blockIdx.y;
+  const TX* x = X + a * (long long)J * K + (k < K ? k : 0);
+  const int jb = (int)((long long)J * w / 4), je = (int)((long long)J * (w + 1) / 4);
+  double acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = 0.0;
+  // X values of the next four j in flight (ring, refilled in range: a load past je reloads je - 1)
+  double xr[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) xr[u] = loadB(x + (long long)min(jb + u, je - 1 < jb ? jb : je - 1) * K);
+  // branch-free steps (a step past je adds 0 times row je - 1): a branch per step would make the
+  // wait-count bookkeeping drain the ring at every join
+  for (int j = jb; j < je; j += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool ok = j + u < je;
+      const double xv = ok ? xr[u] : 0.0;
+      xr[u] = loadB(x + (long long)min(j + u + 4, je - 1) * K);
+      const double* ur = us + min(j + u, je - 1) * NB;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[b] = fma(ur[b], xv, acc[b]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  if (w > 0) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) red[w - 1][b][lane] = acc[b];
+  }
+  __syncthreads();
+  if (w == 0 && k < K) {
+    double* y = Y + a * (long long)nb * ldy + k;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      if (b0 + b < nb) y[(long long)(b0 + b) * ldy] = ((acc[b] + red[0][b][lane]) + red[1][b][lane]) + red[2][b][lane];
+  }
+}
+
+template <class TX>
+void mprod_launch(const TX* X, int A, int J, long long K, const double* U, int nb, double* Y, hipStream_t s) {
+  const dim3 grid((unsigned)((K + 63) / 64), (unsigned)A);
+  for (int b0 = 0; b0 < nb; b0 += MP_NB) {
+    const int left = nb - b0;
+    const int w = left <= 8 ? 8 : left <= 12 ? 12 : left <= 16 ? 16 : 20;
+    const size_t lds = (size_t)J * w * sizeof(double);
+    if (w == 8) hipLaunchKernelGGL((mprod_kernel<TX, 8>), grid, dim3(256), lds, s, X, J, K, U, nb, b0, nb, Y, K);
+    else if (w == 12) hipLaunchKernelGGL((mprod_kernel<TX, 12>), grid, dim3(256), lds, s, X, J, K, U, nb, b0, nb, Y, K);
+    else if (w == 16) hipLaunchKernelGGL((mprod_kernel<TX, 16>), grid, dim3(256), lds, s, X, J, K, U, nb, b0, nb, Y, K);
+    else hipLaunchKernelGGL((mprod_kernel<TX, 20>), grid, dim3(256), lds, s, X, J, K, U, nb, b0, nb, Y, K);
+  }
+}
+
 }  // namespace
 
 cpd_status gemm_f64(int M, int N, int K, double alpha, const double* A, int lda, long long sA,
@@ -232,6 +305,37 @@ cpd_status gemm_f64(int M, int N, int K, double alpha, const double* A, int lda,
     default:
       set_error("gemm_f64: bad dtype %d", bdtype);
       return CPD_E_INVALID;
+  }
+  CPD_LAUNCH_CHECK();
+  return CPD_OK;
+}
+
+}  // namespace cpd
+
+namespace cpd {
+
+// U rows staged in LDS (plus the 15 KB reduction buffer) must fit the 64 KB default
+bool mode_product_mid_fits(int J, int nb) {
+  const int w = nb <= 8 ? 8 : nb <= 12 ? 12 : nb <= 16 ? 16 : MP_NB;
+  return J >= 1 && (size_t)J * w * sizeof(double) + 3 * MP_NB * 64 * sizeof(double) <= MP_LDS;
+}
+
+cpd_status mode_product_mid(const void* X, int xdtype, int A, int J, long long K, const double* U, int nb,
+                            double* Y, hipStream_t s) {
+  if (A <= 0 || nb <= 0 || K <= 0) return CPD_OK;
+  if (!mode_product_mid_fits(J, nb)) {
+    set_error("mode_product_mid: %d rows of U exceed the staging buffer", J);
+    return CPD_E_UNSUPPORTED;
+  }
+  if (X == nullptr || U == nullptr || Y == nullptr || J < 1 || A > 65535 || (K + 63) / 64 > 0x7fffffffLL) {
+    set_error("mode_product_mid: bad arguments");
+    return CPD_E_INVALID;
+  }
+  switch (xdtype) {
+    case CPD_F64: mprod_launch<double>((const double*)X, A, J, K, U, nb, Y, s); break;
+    case CPD_F32: mprod_launch<float>((const float*)X, A, J, K, U, nb, Y, s); break;
+    case CPD_BF16: mprod_launch<uint16_t>((const uint16_t*)X, A, J, K, U, nb, Y, s); break;
+    default: set_error("mode_product_mid: bad dtype %d", xdtype); return CPD_E_INVALID;
   }
   CPD_LAUNCH_CHECK();
   return CPD_OK;
