@@ -51,7 +51,7 @@ def parse():
 TRAFFIC = {
     # dgn_kernel on the 200^3 R = 20 workload (20^3 core, 19 iterations): FETCH_SIZE 71.8 KiB x 2.0,
     # WRITE_SIZE 29.6 KiB x 1.0 (profiles/dgn_kernel_200cube_traffic.md)
-    "dgn": {"bytes": 147046 + 30310, "sources": ['dgn.hip', 'dgn_state.h', 'mfma_f64.h', 'common.h'], "digest": '4b3c03f0a6ef4a01'},
+    "dgn": {"bytes": 147046 + 30310, "sources": ['dgn.hip', 'dgn_state.h', 'mfma_f64.h', 'common.h'], "digest": '5f8ebce0d17f5c49'},
 }
 
 

@@ -70,7 +70,8 @@ template <class T, class V, int BKT>
 struct Stager {
   static constexpr int PER = TILE * BKT / NT;   // elements per thread and operand
   int m[PER], kk[PER];
-  V rm[PER], rn[PER];
+  T rm[PER], rn[PER];   // raw loaded values: masked and converted by put(), after the MFMAs, so
+                        // a select right after a load does not make each load wait for the last
   __device__ __forceinline__ void init(const GramGeom g) {
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
@@ -87,13 +88,16 @@ struct Stager {
       const int kc = okk ? kp : 0;
       const int gm = rowm + m[t], gn = rown + m[t];
       const bool okm = okk && gm < g.M, okn = okk && gn < g.M;
-      const T vm = *elem(src, g, okm ? gm : 0, kc, invK);
-      rm[t] = okm ? conv<V, T>(vm) : (V)0;
-      if (!diag) {
-        const T vn = *elem(src, g, okn ? gn : 0, kc, invK);
-        rn[t] = okn ? conv<V, T>(vn) : (V)0;
-      }
+      rm[t] = *elem(src, g, okm ? gm : 0, kc, invK);
+      if (!diag) rn[t] = *elem(src, g, okn ? gn : 0, kc, invK);
     }
+  }
+  // staged value of slot t for the rows (rowm, rown) and contraction start k0, zero when out of range
+  __device__ __forceinline__ V valm(const GramGeom g, int t, int rowm, int k0, int kend) const {
+    return (rowm + m[t] < g.M && k0 + kk[t] < kend) ? conv<V, T>(rm[t]) : (V)0;
+  }
+  __device__ __forceinline__ V valn(const GramGeom g, int t, int rown, int k0, int kend) const {
+    return (rown + m[t] < g.M && k0 + kk[t] < kend) ? conv<V, T>(rn[t]) : (V)0;
   }
 };
 
@@ -133,8 +137,8 @@ __global__ __launch_bounds__(NT) void gram_partial_kernel(const T* __restrict__ 
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
     for (int t = 0; t < st.PER; ++t) {
-      Xm[st.m[t]][st.kk[t]] = st.rm[t];
-      if (!diag) Xn[st.m[t]][st.kk[t]] = st.rn[t];
+      Xm[st.m[t]][st.kk[t]] = st.valm(g, t, tm * TILE, k0, kend);
+      if (!diag) Xn[st.m[t]][st.kk[t]] = st.valn(g, t, tn * TILE, k0, kend);
     }
     __syncthreads();
     if (k0 + BK < kend) st.fetch(src, g, invK, tm * TILE, tn * TILE, diag, k0 + BK, kend);
@@ -204,8 +208,8 @@ __global__ __launch_bounds__(NT) void gram_partial_bf16_kernel(const uint16_t* _
   for (int k0 = kbeg; k0 < kend; k0 += BKH) {
 #pragma unroll
     for (int t = 0; t < st.PER; ++t) {
-      Hm[st.m[t]][st.kk[t]] = st.rm[t];
-      if (!diag) Hn[st.m[t]][st.kk[t]] = st.rn[t];
+      Hm[st.m[t]][st.kk[t]] = st.valm(g, t, tm * TILE, k0, kend);
+      if (!diag) Hn[st.m[t]][st.kk[t]] = st.valn(g, t, tn * TILE, k0, kend);
     }
     __syncthreads();
     if (k0 + BKH < kend) st.fetch(src, g, invK, tm * TILE, tn * TILE, diag, k0 + BKH, kend);
