@@ -242,22 +242,134 @@ __global__ __launch_bounds__(NT) void gram_partial_bf16_kernel(const uint16_t* _
       }
 }
 
+template <int TE>
 __global__ void gram_reduce_kernel(const double* __restrict__ part, GramGeom g, double* __restrict__ G) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)g.nupper * TILE * TILE) return;
-  const int tile = (int)(e / (TILE * TILE));
-  const int rc = (int)(e % (TILE * TILE));
-  const int r = rc / TILE, c = rc % TILE;
+  if (e >= (long long)g.nupper * TE * TE) return;
+  const int tile = (int)(e / (TE * TE));
+  const int rc = (int)(e % (TE * TE));
+  const int r = rc / TE, c = rc % TE;
   int tm, tn;
   tile_of(tile, g.ntile, tm, tn);
   if (tm == tn && r > c) return;
-  const int m = tm * TILE + r, n = tn * TILE + c;
+  const int m = tm * TE + r, n = tn * TE + c;
   if (m >= g.M || n >= g.M) return;
-  const double* p = part + (long long)tile * g.nsplit * (TILE * TILE) + rc;
+  const double* p = part + (long long)tile * g.nsplit * (TE * TE) + rc;
   double s = 0.0;
-  for (int k = 0; k < g.nsplit; ++k) s += p[(long long)k * TILE * TILE];
+  for (int k = 0; k < g.nsplit; ++k) s += p[(long long)k * TE * TE];
   G[(long long)m * g.M + n] = s;
   G[(long long)n * g.M + m] = s;
+}
+
+// BF16 Gram for large modes (BF16 MFMA v_mfma_f32_16x16x32_bf16, FP32 accumulation within a
+// contraction chunk of at most 8192 indices, FP64 across chunks).  128x128 tiles of G, each of the
+// four waves owning a 64x64 quarter (sixteen 16x16 accumulators), 64 contraction indices per
+// stage.  Staging moves 16-byte vectors: along the contraction index for modes 1 and 2 (written to
+// LDS as they are), along the row index for mode 3 (written transposed, eight 2-byte stores); the
+// loaded vectors stay raw in registers through the previous stage's MFMAs and are masked only at
+// the LDS store.  Fragment layout: lane (i, q) holds elements 8q .. 8q + 7 of row i of a 16-row
+// block (both operands the same way, so each instruction pairs matching contraction indices).
+constexpr int GB_T = 128;
+constexpr int GB_NT = 256;
+constexpr int GB_KC = 64;
+constexpr int GB_LD = GB_KC + 8;                        // LDS row pitch in bf16 elements
+constexpr int GB_VPT = GB_T * GB_KC / 8 / GB_NT;        // 16-byte vectors per thread and operand
+constexpr int GB_MAXCHUNK = 8192;
+
+typedef unsigned int gb_u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 gb_bf16x8 __attribute__((ext_vector_type(8)));
+
+__global__ __launch_bounds__(GB_NT) void gram_bf16_big_kernel(const uint16_t* __restrict__ src, GramGeom g,
+                                                              double* __restrict__ part) {
+  __shared__ __align__(16) uint16_t Xm[GB_T][GB_LD];
+  __shared__ __align__(16) uint16_t Xn[GB_T][GB_LD];
+  const int L = blockIdx.x;
+  const int xcd = L & 7, idx = L >> 3;
+  const int tile = idx % g.nupper;
+  const int split = (idx / g.nupper) * 8 + xcd;
+  if (split >= g.nsplit) return;
+  int tm, tn;
+  tile_of(tile, g.ntile, tm, tn);
+  const bool diag = (tm == tn);
+  const int kbeg = split * g.kchunk, kend = min(g.Ktot, kbeg + g.kchunk);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, i = lane & 15, q = lane >> 4;
+  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+  const bool v0 = g.variant == 0;
+  const int gM = g.M, gK = g.K, sm = g.sm, sk = g.sk;
+  const long long sb = g.sb;
+  const double invK = 1.0 / (double)(v0 ? gK : 1);
+  // vector v of this thread: variant 0 -> (row, 8 contraction indices), variant 1 -> (8 rows, index)
+  auto vrow = [=](int v) { const int e = tid + v * GB_NT; return v0 ? (e >> 3) : ((e & 15) * 8); };
+  auto vk = [=](int v) { const int e = tid + v * GB_NT; return v0 ? ((e & 7) * 8) : (e >> 4); };
+  auto addr = [=](int m, int kp) -> long long {
+    if (v0) {
+      const int b = (int)(((double)kp + 0.5) * invK);
+      return (long long)b * sb + (long long)m * sm + (kp - b * gK);
+    }
+    return (long long)kp * sk + m;
+  };
+  gb_u32x4 rm[GB_VPT], rn[GB_VPT];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int v = 0; v < GB_VPT; ++v) {
+      const int r = vrow(v), kp = k0 + vk(v);
+      const bool okk = kp < kend;
+      const int gm = tm * GB_T + r, gn = tn * GB_T + r;
+      rm[v] = *(const gb_u32x4*)(src + addr(gm < gM && okk ? gm : 0, okk ? kp : 0));
+      if (!diag) rn[v] = *(const gb_u32x4*)(src + addr(gn < gM && okk ? gn : 0, okk ? kp : 0));
+    }
+  };
+  auto put = [&](uint16_t (*X)[GB_LD], const gb_u32x4* raw, int row0, int k0) {
+#pragma unroll
+    for (int v = 0; v < GB_VPT; ++v) {
+      const int r = vrow(v), kk = vk(v);
+      const bool ok = row0 + r < gM && k0 + kk < kend;   // whole vectors are in or out of range
+      const gb_u32x4 val = ok ? raw[v] : gb_u32x4{0u, 0u, 0u, 0u};
+      if (v0) {
+        *(gb_u32x4*)&X[r][kk] = val;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) X[r + e][kk] = (uint16_t)(val[e >> 1] >> (16 * (e & 1)));
+      }
+    }
+  };
+  flt4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = flt4{0.f, 0.f, 0.f, 0.f};
+  uint16_t (*Bn)[GB_LD] = diag ? Xm : Xn;
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += GB_KC) {
+    put(Xm, rm, tm * GB_T, k0);
+    if (!diag) put(Xn, rn, tn * GB_T, k0);
+    __syncthreads();
+    if (k0 + GB_KC < kend) fetch(k0 + GB_KC);
+#pragma unroll
+    for (int ks = 0; ks < GB_KC; ks += 32) {
+      gb_u32x4 fa[4], fb[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) fa[a] = *(const gb_u32x4*)&Xm[wm + 16 * a + i][ks + 8 * q];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) fb[b] = *(const gb_u32x4*)&Bn[wn + 16 * b + i][ks + 8 * q];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(gb_bf16x8, fa[a]),
+                                                              __builtin_bit_cast(gb_bf16x8, fb[b]), acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D[4 q + v][i] of a 16x16 block is element v of lane i + 16 q
+  double* out = part + ((long long)tile * g.nsplit + split) * (GB_T * GB_T);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        out[(wm + 16 * a + 4 * q + v) * GB_T + wn + 16 * b + i] = (double)acc[a][b][v];
 }
 
 // Unfolding view of mode `mode` (variant, sizes and strides; no tiling).
@@ -459,6 +571,32 @@ GramGeom make_geom(const int64_t dims[3], int mode, int bk) {
 
 bool use_bf16(int dtype, int compute_dtype) { return dtype == CPD_BF16 && compute_dtype == CPD_BF16; }
 
+// 128x128 tiles for the large BF16 Gram: chunks of at most GB_MAXCHUNK indices (a multiple of the
+// stage), split count a multiple of 8 (XCD order) and at least ~512 workgroups.
+GramGeom make_big_geom(const int64_t dims[3], int mode) {
+  GramGeom g = make_geom_base(dims, mode);
+  g.ntile = (g.M + GB_T - 1) / GB_T;
+  g.nupper = g.ntile * (g.ntile + 1) / 2;
+  long long ns = (512 + g.nupper - 1) / g.nupper;
+  const long long minsplit = (g.Ktot + GB_MAXCHUNK - 1) / GB_MAXCHUNK;
+  if (ns < minsplit) ns = minsplit;
+  ns = (ns + 7) / 8 * 8;
+  long long chunk = (g.Ktot + ns - 1) / ns;
+  chunk = (chunk + GB_KC - 1) / GB_KC * GB_KC;
+  ns = (g.Ktot + chunk - 1) / chunk;
+  ns = (ns + 7) / 8 * 8;
+  g.nsplit = (int)ns;
+  g.kchunk = (int)chunk;
+  return g;
+}
+
+// The large BF16 kernel moves whole 16-byte vectors: every vector must be in one slab and aligned.
+bool big_bf16_ok(const GramGeom& g, const void* T) {
+  if (g.M <= GT_MAXM || ((uintptr_t)T & 15)) return false;
+  if (g.variant == 0) return g.K % 8 == 0 && g.sm % 8 == 0 && g.sb % 8 == 0;
+  return g.sk % 8 == 0 && g.M % 8 == 0;
+}
+
 template <class T>
 cpd_status launch_tri(const void* src, const GramGeom& g, int mp, int ntw, size_t lds, double* part, hipStream_t s) {
   const dim3 grid(g.nsplit), block(GT_NT);
@@ -476,6 +614,11 @@ size_t gram_ws_bytes(const int64_t dims[3], int mode) {
   const GramGeom g = make_geom(dims, mode, BK), h = make_geom(dims, mode, BKH);
   const int ns = g.nsplit > h.nsplit ? g.nsplit : h.nsplit;
   size_t b = align_up((size_t)g.nupper * ns * TILE * TILE * sizeof(double), 256);
+  if (g.M > GT_MAXM) {
+    const GramGeom gb = make_big_geom(dims, mode);
+    const size_t bb = align_up((size_t)gb.nupper * gb.nsplit * GB_T * GB_T * sizeof(double), 256);
+    b = b > bb ? b : bb;
+  }
   if (g.M <= GT_MAXM) {
     int mp;
     const GramGeom t = make_tri_geom(dims, mode, &mp);
@@ -522,6 +665,18 @@ cpd_status gram(const void* T, int dtype, const int64_t dims[3], int mode, int c
     CPD_LAUNCH_CHECK();
     return CPD_OK;
   }
+  if (bf && big_bf16_ok(make_geom_base(dims, mode), T)) {
+    const GramGeom gb = make_big_geom(dims, mode);
+    prof_begin(CPD_PK_GRAM, s);
+    hipLaunchKernelGGL(gram_bf16_big_kernel, dim3(gb.nupper * gb.nsplit), dim3(GB_NT), 0, s, (const uint16_t*)T, gb,
+                       part);
+    CPD_LAUNCH_CHECK();
+    const long long nelb = (long long)gb.nupper * GB_T * GB_T;
+    hipLaunchKernelGGL(gram_reduce_kernel<GB_T>, dim3((unsigned)((nelb + 255) / 256)), dim3(256), 0, s, part, gb, G);
+    prof_end(CPD_PK_GRAM, s);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+  }
   const int nblocks = g.nupper * g.nsplit;
   prof_begin(CPD_PK_GRAM, s);
   switch (dtype) {
@@ -545,7 +700,7 @@ cpd_status gram(const void* T, int dtype, const int64_t dims[3], int mode, int c
   }
   CPD_LAUNCH_CHECK();
   const long long nel = (long long)g.nupper * TILE * TILE;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL(gram_reduce_kernel<TILE>, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, s,
                      part, g, G);
   prof_end(CPD_PK_GRAM, s);
   CPD_LAUNCH_CHECK();

@@ -71,7 +71,9 @@ def test_gram_matches_unfolding_gram(dims, dtype):
         assert np.array_equal(G, G.T)
 
 
-@pytest.mark.parametrize("dims", [(70, 45, 130), (64, 64, 64), (17, 200, 33)])
+# mode sizes > 208 with 16-byte-aligned rows take the 128x128-tile BF16 kernel: (216, 40, 232) modes 1
+# and 3 (contraction-contiguous and row-contiguous staging), (8, 264, 16) mode 2 (slabs of 16)
+@pytest.mark.parametrize("dims", [(70, 45, 130), (64, 64, 64), (17, 200, 33), (216, 40, 232), (8, 264, 16)])
 def test_gram_bf16_matrix_cores(dims):
     """BF16 tensor: the FP64 path is exact on the BF16 values; the BF16 MFMA path (FP32 accumulation
     within a split-K chunk of at most a few thousand products, FP64 across chunks) stays within
