@@ -298,9 +298,18 @@ __global__ __launch_bounds__(GB_NT) void gram_bf16_big_kernel(const uint16_t* __
   const int gM = g.M, gK = g.K, sm = g.sm, sk = g.sk;
   const long long sb = g.sb;
   const double invK = 1.0 / (double)(v0 ? gK : 1);
-  // vector v of this thread: variant 0 -> (row, 8 contraction indices), variant 1 -> (8 rows, index)
-  auto vrow = [=](int v) { const int e = tid + v * GB_NT; return v0 ? (e >> 3) : ((e & 15) * 8); };
-  auto vk = [=](int v) { const int e = tid + v * GB_NT; return v0 ? ((e & 7) * 8) : (e >> 4); };
+  // vector v of this thread: variant 0 -> (row, 8 contraction indices); variant 1 -> (8 rows, one
+  // index), the thread's GB_VPT vectors at consecutive indices of the same 8 rows so that they are
+  // written to LDS as one 8-byte word per row
+  static_assert(GB_VPT == 4 && GB_KC == 4 * (GB_NT / (GB_T / 8)), "variant-1 staging covers the stage");
+  auto vrow = [=](int v) {
+    const int e = tid + v * GB_NT;
+    return v0 ? e / (GB_KC / 8) : (tid % (GB_T / 8)) * 8;
+  };
+  auto vk = [=](int v) {
+    const int e = tid + v * GB_NT;
+    return v0 ? (e % (GB_KC / 8)) * 8 : GB_VPT * (tid / (GB_T / 8)) + v;
+  };
   auto addr = [=](int m, int kp) -> long long {
     if (v0) {
       const int b = (int)(((double)kp + 0.5) * invK);
@@ -320,16 +329,29 @@ __global__ __launch_bounds__(GB_NT) void gram_bf16_big_kernel(const uint16_t* __
     }
   };
   auto put = [&](uint16_t (*X)[GB_LD], const gb_u32x4* raw, int row0, int k0) {
+    if (v0) {
 #pragma unroll
-    for (int v = 0; v < GB_VPT; ++v) {
-      const int r = vrow(v), kk = vk(v);
-      const bool ok = row0 + r < gM && k0 + kk < kend;   // whole vectors are in or out of range
-      const gb_u32x4 val = ok ? raw[v] : gb_u32x4{0u, 0u, 0u, 0u};
-      if (v0) {
-        *(gb_u32x4*)&X[r][kk] = val;
-      } else {
+      for (int v = 0; v < GB_VPT; ++v) {
+        const int r = vrow(v), kk = vk(v);
+        const bool ok = row0 + r < gM && k0 + kk < kend;   // whole vectors are in or out of range
+        *(gb_u32x4*)&X[r][kk] = ok ? raw[v] : gb_u32x4{0u, 0u, 0u, 0u};
+      }
+    } else {
+      // four vectors = rows r .. r+7 at indices kk .. kk+3: row r + e gets the 8-byte word
+      // (element e of vectors 0..3)
+      const int r = vrow(0), kk = vk(0);
+      gb_u32x4 val[GB_VPT];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) X[r + e][kk] = (uint16_t)(val[e >> 1] >> (16 * (e & 1)));
+      for (int v = 0; v < GB_VPT; ++v) {
+        const bool ok = row0 + r < gM && k0 + kk + v < kend;
+        val[v] = ok ? raw[v] : gb_u32x4{0u, 0u, 0u, 0u};
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int sh = 16 * (e & 1);
+        const uint32_t h0 = (val[0][e >> 1] >> sh) & 0xFFFFu, h1 = (val[1][e >> 1] >> sh) & 0xFFFFu;
+        const uint32_t h2 = (val[2][e >> 1] >> sh) & 0xFFFFu, h3 = (val[3][e >> 1] >> sh) & 0xFFFFu;
+        *(uint2*)&X[r + e][kk] = uint2{h0 | (h1 << 16), h2 | (h3 << 16)};
       }
     }
   };
