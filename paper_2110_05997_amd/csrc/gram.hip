@@ -271,7 +271,7 @@ __global__ void gram_reduce_kernel(const double* __restrict__ part, GramGeom g, 
 // block (both operands the same way, so each instruction pairs matching contraction indices).
 constexpr int GB_T = 128;
 constexpr int GB_NT = 256;
-constexpr int GB_KC = 64;
+constexpr int GB_KC = 128;                       // a stage's MFMAs cover the next stage's loads
 constexpr int GB_LD = GB_KC + 8;                        // LDS row pitch in bf16 elements
 constexpr int GB_VPT = GB_T * GB_KC / 8 / GB_NT;        // 16-byte vectors per thread and operand
 constexpr int GB_MAXCHUNK = 8192;
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(GB_NT) void gram_bf16_big_kernel(const uint16_t* __
   // vector v of this thread: variant 0 -> (row, 8 contraction indices); variant 1 -> (8 rows, one
   // index), the thread's GB_VPT vectors at consecutive indices of the same 8 rows so that they are
   // written to LDS as one 8-byte word per row
-  static_assert(GB_VPT == 4 && GB_KC == 4 * (GB_NT / (GB_T / 8)), "variant-1 staging covers the stage");
+  static_assert(GB_VPT == 8 && GB_KC == GB_VPT * (GB_NT / (GB_T / 8)), "variant-1 staging covers the stage");
   auto vrow = [=](int v) {
     const int e = tid + v * GB_NT;
     return v0 ? e / (GB_KC / 8) : (tid % (GB_T / 8)) * 8;
@@ -337,8 +337,8 @@ __global__ __launch_bounds__(GB_NT) void gram_bf16_big_kernel(const uint16_t* __
         *(gb_u32x4*)&X[r][kk] = ok ? raw[v] : gb_u32x4{0u, 0u, 0u, 0u};
       }
     } else {
-      // four vectors = rows r .. r+7 at indices kk .. kk+3: row r + e gets the 8-byte word
-      // (element e of vectors 0..3)
+      // eight vectors = rows r .. r+7 at indices kk .. kk+7: row r + e gets the 16-byte word
+      // (element e of vectors 0..7)
       const int r = vrow(0), kk = vk(0);
       gb_u32x4 val[GB_VPT];
 #pragma unroll
@@ -349,9 +349,11 @@ __global__ __launch_bounds__(GB_NT) void gram_bf16_big_kernel(const uint16_t* __
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int sh = 16 * (e & 1);
-        const uint32_t h0 = (val[0][e >> 1] >> sh) & 0xFFFFu, h1 = (val[1][e >> 1] >> sh) & 0xFFFFu;
-        const uint32_t h2 = (val[2][e >> 1] >> sh) & 0xFFFFu, h3 = (val[3][e >> 1] >> sh) & 0xFFFFu;
-        *(uint2*)&X[r + e][kk] = uint2{h0 | (h1 << 16), h2 | (h3 << 16)};
+        uint32_t h[GB_VPT];
+#pragma unroll
+        for (int v = 0; v < GB_VPT; ++v) h[v] = (val[v][e >> 1] >> sh) & 0xFFFFu;
+        *(gb_u32x4*)&X[r + e][kk] = gb_u32x4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                                            h[6] | (h[7] << 16)};
       }
     }
   };
