@@ -300,7 +300,9 @@ def bench_600cube(cp, synth, torch, dev):
                                                 ("bf16_in_bf16_mfma", cp.CPD_BF16)])
     rates = {"mttkrp_tflops_fp32": m32["fp32_in_f64_mfma"]["tflops"],
              "mttkrp_tflops_bf16": m16["bf16_in_f64_mfma"]["tflops"],
-             "mttkrp": {**m32, **m16}}
+             "mttkrp": {**m32, **m16},
+             "gram": {**gram_rates(cp, torch, Td, [("fp32_in_f64_mfma", cp.CPD_F64)]),
+                      **gram_rates(cp, torch, Tlo, [("bf16_in_bf16_mfma", cp.CPD_BF16)])}}
     return {"workload": "dense 600^3 FP32 (+ BF16 copy), planted R=50, SNR 60 dB",
             **rates,
             "s_per_solve_bf16_grams": res["bf16_grams_s"], "s_per_solve_fp64_grams": res["fp64_grams_s"],
@@ -309,6 +311,32 @@ def bench_600cube(cp, synth, torch, dev):
             "iters_bf16_grams": res["bf16_grams"]["info"]["iters"],
             "iters_fp64_grams": res["fp64_grams"]["info"]["iters"],
             "reconstruction_diff_bf16_vs_fp64": cpd_diff(res["bf16_grams"], res["fp64_grams"], torch)}
+
+
+def gram_rates(cp, torch, X, variants, reps=2):
+    """Per compute dtype: mode-l Gram time (HIP events around the partial and reduction kernels),
+    TFLOP/s on N (I_l + 1) flop (the upper half of the SYRK), the fraction of that dtype's matrix
+    peak, and the largest error against the FP64 Gram relative to its largest entry."""
+    N = X.numel()
+    peak = {cp.CPD_F64: 78.6, cp.CPD_BF16: 2500.0}
+    ref = [cp.gram(X, mode) for mode in range(3)]
+    res = {}
+    for tag, cd in variants:
+        outs = [cp.gram(X, mode, cd) for mode in range(3)]
+        torch.cuda.synchronize()
+        err = max(float((o - r).abs().max() / r.abs().max()) for o, r in zip(outs, ref))
+        cp.profile_reset()
+        cp.profile_enable(True)
+        for _ in range(reps):
+            for mode in range(3):
+                cp.gram(X, mode, cd)
+        torch.cuda.synchronize()
+        cp.profile_enable(False)
+        n_g, ms_g = cp.profile_read()["gram"]
+        s = ms_g / n_g / 1000.0
+        tf = N * (X.shape[0] + 1) / s / 1e12
+        res[tag] = {"us": s * 1e6, "tflops": tf, "frac_mfma_peak": tf / peak[cd], "max_rel_err_vs_f64": err}
+    return res
 
 
 def mttkrp_rates(cp, torch, X, Wf, R, variants, reps=2):
