@@ -199,6 +199,79 @@ __device__ double hv(Ctx& c, const double* V, double* out, double mu, bool scale
   return dotp;
 }
 
+// The same product for a working set in global memory (cores too large for LDS): each mode's
+// operands are staged in LDS first with coalesced loads (phase 1: W_b and V_b; phase 2: W_a, the
+// scaled V_a, Pi^(a) and the Hadamard combination Y_a), so the MFMA operands come from LDS instead
+// of one L2 round trip per k-group.  Same tile products in the same order as hv, bit-identical
+// results.  sh holds 2 dmax R + 2 R^2 doubles (hv_stage_doubles).
+__device__ double hv_staged(Ctx& c, const double* V, double* out, double mu, bool scale, double* sh) {
+  const int R = c.R, RR = R * R, tr = tiles16(R);
+  const int tid = threadIdx.x, lane = tid & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
+  const int dmax = max(c.d0, max(c.d1, c.d2));
+  double* sW = sh;
+  double* sV = sh + dmax * R;
+  double* sP = sV + dmax * R;
+  double* sY = sP + RR;
+  for (int b = 0; b < 3; ++b) {
+    const int db = dimof(c, b), ob = offof(c, b);
+    for (int e = tid; e < db * R; e += NT) {
+      sW[e] = c.W[ob + e];
+      sV[e] = V[ob + e];
+    }
+    __syncthreads();
+    for (int t = w; t < tr * tr; t += NW) {
+      const int tm = t / tr, tn = t - tm * tr;
+      const dbl4 acc = mfma_tile(tm * 16, tn * 16, db,
+          [&](int sidx, int i) { return sel(sidx < R && i < db, sV[min(i, db - 1) * R + min(sidx, R - 1)]); },
+          [&](int i, int r) { return sel(r < R && i < db, sW[min(i, db - 1) * R + min(r, R - 1)]); });
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int sidx = tm * 16 + 4 * v + kq, r = tn * 16 + r16;
+        if (sidx < R && r < R) c.Qb[b * RR + sidx * R + r] = scale ? c.msq[b * R + sidx] * acc[v] : acc[v];
+      }
+    }
+    __syncthreads();
+  }
+  double dotp = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const int da = dimof(c, a), oa = offof(c, a);
+    const int b1 = (a == 0) ? 1 : 0, b2 = (a == 2) ? 1 : 2;
+    const double* ma = c.msq + a * R;
+    for (int e = tid; e < da * R; e += NT) {
+      sW[e] = c.W[oa + e];
+      const double v = V[oa + e];
+      sV[e] = scale ? ma[e % R] * v : v;
+    }
+    for (int e = tid; e < RR; e += NT) {
+      sP[e] = c.Pown[a * RR + e];
+      sY[e] = c.pi[b2 * RR + e] * c.Qb[b1 * RR + e] + c.pi[b1 * RR + e] * c.Qb[b2 * RR + e];
+    }
+    __syncthreads();
+    for (int t = w; t < tiles16(da) * tr; t += NW) {
+      const int tm = t / tr, tn = t - tm * tr;
+      const dbl4 acc1 = mfma_tile(tm * 16, tn * 16, R,
+          [&](int i, int k) { return sel(i < da && k < R, sV[min(i, da - 1) * R + min(k, R - 1)]); },
+          [&](int k, int r) { return sel(r < R && k < R, sP[min(k, R - 1) * R + min(r, R - 1)]); });
+      const dbl4 acc2 = mfma_tile(tm * 16, tn * 16, R,
+          [&](int i, int k) { return sel(i < da && k < R, sW[min(i, da - 1) * R + min(k, R - 1)]); },
+          [&](int k, int r) { return sel(r < R && k < R, sY[min(k, R - 1) * R + min(r, R - 1)]); });
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = tm * 16 + 4 * v + kq, r = tn * 16 + r16;
+        if (i < da && r < R) {
+          const int e = oa + i * R + r;
+          double tv = acc1[v] + acc2[v];
+          if (scale) tv = ma[r] * (tv + mu * c.gam[a * R + r] * (ma[r] * V[e]));
+          out[e] = tv;
+          dotp += V[e] * tv;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return dotp;
+}
+
 // Norm balancing (ch.4 "Updates"): every rank-one term gets equal column norms.  Uses msq as
 // scratch for the column norms.  Ends with a barrier.
 __device__ void norm_balance(Ctx& c) {
@@ -334,9 +407,10 @@ __device__ int stop_test(const double* errs, int k, double step, double grad_inf
 // mode 2: one iteration up to the balanced update, its residual and MTTKRP left to other
 // launches (dgn_tail_kernel finishes the step).
 // SL: the core S is copied into LDS after the working set (the caller sized the LDS for it).
-template <bool SL>
+// GW: working set in global memory with hv_staged's LDS buffer at `stage`.
+template <bool SL, bool GW = false>
 __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double* __restrict__ S, int mode, int max_steps,
-                         double* lds, int& s_stop) {
+                         double* lds, int& s_stop, double* stage = nullptr) {
   Hdr* h = (Hdr*)state;
   const int R = h->R;
   int d[3] = {h->d[0], h->d[1], h->d[2]};
@@ -434,7 +508,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     int its = 0;
     while (its < cap) {
       if (rr == 0.0) break;
-      const double pz = block_sum(hv(c, c.P, c.Z, mu, true), slotA);
+      const double pz = block_sum(GW ? hv_staged(c, c.P, c.Z, mu, true, stage) : hv(c, c.P, c.Z, mu, true), slotA);
       if (!(pz > 0.0)) break;
       const double alpha = rr / pz;
       double eps = 0.0;
@@ -460,7 +534,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     }
     __syncthreads();
     // J^T J x for the predicted residual, into Z
-    const double xjx = block_sum(hv(c, c.X, c.Z, 0.0, false), slotA);
+    const double xjx = block_sum(GW ? hv_staged(c, c.X, c.Z, 0.0, false, stage) : hv(c, c.X, c.Z, 0.0, false), slotA);
     double gx = 0.0, xx = 0.0;
     for (int e = tid; e < c.np; e += NT) {
       gx += c.G[e] * c.X[e];
@@ -528,13 +602,15 @@ __global__ __launch_bounds__(NT) void dgn_kernel(char* __restrict__ state, const
 // Same iteration for states too large for LDS: the working set lives in the state's own work
 // region (global memory; one workgroup, so its accesses stay coherent through the CU's cache).
 // MODE 2 is the first half of one iteration (see dgn_tail_kernel).
-template <int MODE>
+// STG: J^T J v through hv_staged with its operands in dynamic LDS (hv_stage_doubles).
+template <int MODE, bool STG>
 __global__ __launch_bounds__(NT) void dgn_kernel_g(char* __restrict__ state, const double* __restrict__ S,
                                                    int max_steps) {
+  extern __shared__ double g_stage[];
   __shared__ int s_stop;
   const Hdr* h = (const Hdr*)state;
   const Layout Lo = layout_of(h->np, h->R, h->maxiter);
-  dgn_body<false>(state, S, MODE, max_steps, (double*)(state + Lo.work), s_stop);
+  dgn_body<false, STG>(state, S, MODE, max_steps, (double*)(state + Lo.work), s_stop, g_stage);
 }
 
 // Second half of an iteration split over launches: from the residual ||S - [[W]]||^2 of the
@@ -704,6 +780,11 @@ int cg_cap_for(int k, double u) {
 }
 
 namespace {
+size_t hv_stage_doubles(const int d[3], int R) {
+  const int dmax = d[0] > d[1] ? (d[0] > d[2] ? d[0] : d[2]) : (d[1] > d[2] ? d[1] : d[2]);
+  return 2 * (size_t)dmax * R + 2 * (size_t)R * R;
+}
+
 // The persistent dGN kernel with its working set in LDS when it fits, else in the state's work
 // region.
 cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int np, int R, const int d[3],
@@ -733,7 +814,7 @@ cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int
       hipLaunchKernelGGL(dgn_kernel<false>, dim3(1), dim3(NT), lb, s, state, S, max_steps);
     }
   } else if (mode == 0) {
-    hipLaunchKernelGGL(dgn_kernel_g<0>, dim3(1), dim3(NT), 0, s, state, S, max_steps);
+    hipLaunchKernelGGL((dgn_kernel_g<0, false>), dim3(1), dim3(NT), 0, s, state, S, max_steps);
   } else {
     // Large core: each iteration is the single-workgroup half (gradient, CG, update) followed by
     // the core's MTTKRPs and residual on the full-tensor kernels (spread over the chip) and the
@@ -750,11 +831,17 @@ cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int
     char* aux = state + align_up(Lo.total, 256);
     const size_t aux_bytes = dgn_aux_bytes(d, R);
     double* f2_new = (double*)(state + offsetof(Hdr, f2_new));
+    const size_t stage_b = hv_stage_doubles(d, R) * sizeof(double);
+    const bool stg = stage_b <= LDS_LIMIT;
+    if (stg && stage_b > 64 * 1024)
+      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel_g<2, true>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)stage_b));
     constexpr int CHUNK = 4;
     for (int done = 0; done < max_steps; done += CHUNK) {
       const int n = (max_steps - done < CHUNK) ? max_steps - done : CHUNK;
       for (int j = 0; j < n; ++j) {
-        hipLaunchKernelGGL(dgn_kernel_g<2>, dim3(1), dim3(NT), 0, s, state, S, 1);
+        if (stg) hipLaunchKernelGGL((dgn_kernel_g<2, true>), dim3(1), dim3(NT), stage_b, s, state, S, 1);
+        else hipLaunchKernelGGL((dgn_kernel_g<2, false>), dim3(1), dim3(NT), 0, s, state, S, 1);
         CPD_LAUNCH_CHECK();
         cpd_status st;
         for (int l = 0; l < 3; ++l)
