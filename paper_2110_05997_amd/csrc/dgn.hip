@@ -484,13 +484,23 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     ++k;
     grams(c);
     precond(c, mu);
-    // gradient, CG start r = p = M^{-1/2}(-grad), x = 0
+    // gradient, CG start r = p = M^{-1/2}(-grad), x = 0.  With the working set in global memory, W
+    // and the Pi^(l) are staged in LDS first (same values, same order of operations)
+    const double* gWs = c.W;
+    const double* gPs = c.Pown;
+    if constexpr (GW) {
+      for (int e = tid; e < c.np; e += NT) stage[e] = c.W[e];
+      for (int e = tid; e < 3 * R * R; e += NT) stage[c.np + e] = c.Pown[e];
+      __syncthreads();
+      gWs = stage;
+      gPs = stage + c.np;
+    }
     double rr = 0.0, gi = 0.0;
     for (int e = tid; e < c.np; e += NT) {
       int l, i, r;
       split_index(c, e, l, i, r);
-      const double* Wi = c.W + offof(c, l) + i * R;
-      const double* Pl = c.Pown + l * R * R;
+      const double* Wi = gWs + offof(c, l) + i * R;
+      const double* Pl = gPs + l * R * R;
       double acc = 0.0;
       for (int s = 0; s < R; ++s) acc += Wi[s] * Pl[s * R + r];
       const double g = acc - c.MK[e];
@@ -602,7 +612,7 @@ __global__ __launch_bounds__(NT) void dgn_kernel(char* __restrict__ state, const
 // Same iteration for states too large for LDS: the working set lives in the state's own work
 // region (global memory; one workgroup, so its accesses stay coherent through the CU's cache).
 // MODE 2 is the first half of one iteration (see dgn_tail_kernel).
-// STG: J^T J v through hv_staged with its operands in dynamic LDS (hv_stage_doubles).
+// STG: the gradient and J^T J v read their operands from dynamic LDS (hv_stage_doubles).
 template <int MODE, bool STG>
 __global__ __launch_bounds__(NT) void dgn_kernel_g(char* __restrict__ state, const double* __restrict__ S,
                                                    int max_steps) {
@@ -780,9 +790,13 @@ int cg_cap_for(int k, double u) {
 }
 
 namespace {
+// LDS of the staged large-core kernel: hv_staged's operands, or W and the three Pi^(l) for the
+// gradient, whichever is larger
 size_t hv_stage_doubles(const int d[3], int R) {
   const int dmax = d[0] > d[1] ? (d[0] > d[2] ? d[0] : d[2]) : (d[1] > d[2] ? d[1] : d[2]);
-  return 2 * (size_t)dmax * R + 2 * (size_t)R * R;
+  const size_t hvs = 2 * (size_t)dmax * R + 2 * (size_t)R * R;
+  const size_t grs = (size_t)(d[0] + d[1] + d[2]) * R + 3 * (size_t)R * R;
+  return hvs > grs ? hvs : grs;
 }
 
 // The persistent dGN kernel with its working set in LDS when it fits, else in the state's work
