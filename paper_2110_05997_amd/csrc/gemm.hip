@@ -170,7 +170,9 @@ __global__ void gemm_small_kernel(int M, int N, int K, double alpha, const doubl
 // whole wave and is staged once in LDS (each read a broadcast, off the X loads' wait counter); NB
 // accumulators per lane; the four waves split j and are added in a fixed order through LDS.
 constexpr int MP_NB = 20;                  // outputs per pass
-constexpr size_t MP_LDS = 64 * 1024;       // LDS for the staged rows of U
+constexpr size_t MP_LDS = 64 * 1024;   // LDS for the staged rows of U and the reduction: beyond it (J > 217 at
+                                       // 20 outputs) one 4-wave workgroup per CU is too little to hide the
+                                       // serial j loop; measured slower than the tiled GEMM at J = 600
 
 template <class TX, int NB>
 __global__ __launch_bounds__(256) void mprod_kernel(const TX* __restrict__ X, int J, long long K,
@@ -184,10 +186,13 @@ __global__ __launch_bounds__(256) void mprod_kernel(const TX* __restrict__ X, in
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const long long k = (long long)blockIdx.x * 64 + lane;
   const long long a = blockIdx.y;
-  const TX* x = X + a * (long long)J * K + (k < K ? k : 0);
   const int jb = (int)((long long)J * w / 4), je = (int)((long long)J * (w + 1) / 4);
+  // 64-column blocks, grid-stride, so one staging of U serves several blocks
+  const long long nkb = (K + 63) / 64;
+  for (long long kb = blockIdx.x; kb < nkb; kb += gridDim.x) {
+  const long long k = kb * 64 + lane;
+  const TX* x = X + a * (long long)J * K + (k < K ? k : 0);
   double acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = 0.0;
@@ -220,19 +225,23 @@ __global__ __launch_bounds__(256) void mprod_kernel(const TX* __restrict__ X, in
     for (int b = 0; b < NB; ++b)
       if (b0 + b < nb) y[(long long)(b0 + b) * ldy] = ((acc[b] + red[0][b][lane]) + red[1][b][lane]) + red[2][b][lane];
   }
+  __syncthreads();   // red is rewritten by the next block
+  }
 }
 
 template <class TX>
 void mprod_launch(const TX* X, int A, int J, long long K, const double* U, int nb, double* Y, hipStream_t s) {
-  const dim3 grid((unsigned)((K + 63) / 64), (unsigned)A);
+  const long long nkb = (K + 63) / 64;
+  const dim3 grid((unsigned)(nkb < 1024 ? nkb : 1024), (unsigned)A);
   for (int b0 = 0; b0 < nb; b0 += MP_NB) {
     const int left = nb - b0;
     const int w = left <= 8 ? 8 : left <= 12 ? 12 : left <= 16 ? 16 : 20;
     const size_t lds = (size_t)J * w * sizeof(double);
-    if (w == 8) hipLaunchKernelGGL((mprod_kernel<TX, 8>), grid, dim3(256), lds, s, X, J, K, U, nb, b0, nb, Y, K);
-    else if (w == 12) hipLaunchKernelGGL((mprod_kernel<TX, 12>), grid, dim3(256), lds, s, X, J, K, U, nb, b0, nb, Y, K);
-    else if (w == 16) hipLaunchKernelGGL((mprod_kernel<TX, 16>), grid, dim3(256), lds, s, X, J, K, U, nb, b0, nb, Y, K);
-    else hipLaunchKernelGGL((mprod_kernel<TX, 20>), grid, dim3(256), lds, s, X, J, K, U, nb, b0, nb, Y, K);
+    auto k = w == 8 ? mprod_kernel<TX, 8> : w == 12 ? mprod_kernel<TX, 12> : w == 16 ? mprod_kernel<TX, 16>
+                                                                                     : mprod_kernel<TX, 20>;
+    if (lds + 3 * MP_NB * 64 * sizeof(double) > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, dim3(256), lds, s, X, J, K, U, nb, b0, nb, Y, K);
   }
 }
 
@@ -314,7 +323,7 @@ cpd_status gemm_f64(int M, int N, int K, double alpha, const double* A, int lda,
 
 namespace cpd {
 
-// U rows staged in LDS (plus the 15 KB reduction buffer) must fit the 64 KB default
+// U rows staged in LDS (plus the reduction buffer of up to 30 KB) must fit MP_LDS
 bool mode_product_mid_fits(int J, int nb) {
   const int w = nb <= 8 ? 8 : nb <= 12 ? 12 : nb <= 16 ? 16 : MP_NB;
   return J >= 1 && (size_t)J * w * sizeof(double) + 3 * MP_NB * 64 * sizeof(double) <= MP_LDS;
