@@ -446,7 +446,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
   for (int e = tid; e < c.np; e += NT) c.W[e] = gW[e];
   __syncthreads();
 
-  if (mode == 0) {
+  if (mode == 0 || mode == 3) {   // mode 3: the residual and MTTKRP are left to other launches
     // non-finite initial point?
     int bad = 0;
     for (int e = tid; e < c.np; e += NT) bad |= !isfinite(c.W[e]);
@@ -457,7 +457,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     for (int e = tid; e < n; e += NT) { s2 += S[e] * S[e]; sa += fabs(S[e]); }
     s2 = block_sum(s2, slotB);
     sa = block_sum(sa, slotA);
-    const double f2 = residual_mttkrp(c, slotB);
+    const double f2 = (mode == 3) ? 0.0 : residual_mttkrp(c, slotB);
     for (int e = tid; e < c.np; e += NT) gW[e] = c.W[e];
     if (tid == 0) {
       const double s_norm = sqrt(s2);
@@ -653,6 +653,18 @@ __global__ void dgn_tail_kernel(char* __restrict__ state) {
   h->stop = st;
 }
 
+// Finishes an initialisation whose residual ||S - [[W]]||^2 (into f2_new) and MTTKRP (into the
+// state's MK) were computed by the full-tensor kernels on the core.
+__global__ void dgn_init_tail_kernel(char* __restrict__ state) {
+  if (threadIdx.x != 0) return;
+  Hdr* h = (Hdr*)state;
+  const Layout Lo = layout_of(h->np, h->R, h->maxiter);
+  double* errs = (double*)(state + Lo.errs);
+  h->f2 = h->f2_new;
+  h->err0 = (h->s_norm > 0.0) ? sqrt(h->f2_new) / h->s_norm : 0.0;
+  errs[0] = h->err0;
+}
+
 // Batched: workgroup b initialises state b (header, caps and W already written) and iterates it
 // to a stopping rule.  Dynamic LDS must cover the largest member.
 __global__ __launch_bounds__(NT) void dgn_batch_kernel(char* const* __restrict__ states,
@@ -827,12 +839,11 @@ cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int
                                         (int)lb));
       hipLaunchKernelGGL(dgn_kernel<false>, dim3(1), dim3(NT), lb, s, state, S, max_steps);
     }
-  } else if (mode == 0) {
-    hipLaunchKernelGGL((dgn_kernel_g<0, false>), dim3(1), dim3(NT), 0, s, state, S, max_steps);
   } else {
-    // Large core: each iteration is the single-workgroup half (gradient, CG, update) followed by
-    // the core's MTTKRPs and residual on the full-tensor kernels (spread over the chip) and the
-    // scalar tail; the host checks the stop flag after every few iterations.
+    // Large core: the core's MTTKRPs and residual run on the full-tensor kernels (spread over the
+    // chip). Initialisation: the single-workgroup part (balancing, norms, header), those kernels,
+    // and a one-thread tail. Each iteration: the single-workgroup half (gradient, CG, update),
+    // those kernels and the scalar tail; the host checks the stop flag after every few iterations.
     const int64_t dims[3] = {d[0], d[1], d[2]};
     Hdr hh;
     CPD_HIP_CHECK(hipMemcpyAsync(&hh, state, sizeof(Hdr), hipMemcpyDeviceToHost, s));
@@ -845,6 +856,17 @@ cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int
     char* aux = state + align_up(Lo.total, 256);
     const size_t aux_bytes = dgn_aux_bytes(d, R);
     double* f2_new = (double*)(state + offsetof(Hdr, f2_new));
+    if (mode == 0) {
+      hipLaunchKernelGGL((dgn_kernel_g<3, false>), dim3(1), dim3(NT), 0, s, state, S, max_steps);
+      CPD_LAUNCH_CHECK();
+      cpd_status st;
+      for (int l = 0; l < 3; ++l)
+        if ((st = mttkrp_full(S, CPD_F64, dims, Wp, R, l, CPD_F64, MKp[l], aux, aux_bytes, s))) return st;
+      if ((st = residual_full(S, CPD_F64, dims, Wp, R, f2_new, aux, aux_bytes, s))) return st;
+      hipLaunchKernelGGL(dgn_init_tail_kernel, dim3(1), dim3(64), 0, s, state);
+      CPD_LAUNCH_CHECK();
+      return CPD_OK;
+    }
     const size_t stage_b = hv_stage_doubles(d, R) * sizeof(double);
     const bool stg = stage_b <= LDS_LIMIT;
     if (stg && stage_b > 64 * 1024)
