@@ -5,7 +5,7 @@
 //
 //  n <= 64 : cyclic Jacobi with the round-robin parallel ordering, the whole matrix in LDS of one
 //            workgroup (exact to rounding, no spectral-gap assumption).
-//  n  > 64 : subspace iteration on k = min(n, P + max(8, P/4), 64) vectors (four power steps,
+//  n  > 64 : subspace iteration on k = min(n, P + max(4, P/8), 64) vectors (four power steps,
 //            then Rayleigh-Ritz every step)
 //            (Jacobi on the k x k projection), stopped when every wanted Ritz pair has residual
 //            ||G u - theta u|| <= 1e-13 theta_1 (at most 200 iterations).
@@ -531,7 +531,7 @@ __global__ __launch_bounds__(FNT) void subspace_kernel(const double* __restrict_
 }
 
 int subspace_k(int n, int P) {
-  int k = P + (P / 4 > 8 ? P / 4 : 8);
+  int k = P + (P / 8 > 4 ? P / 8 : 4);
   if (k > JMAX) k = JMAX;
   if (k > n) k = n;
   return k;
