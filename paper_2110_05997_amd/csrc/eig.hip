@@ -354,9 +354,17 @@ __device__ bool cholqr_pass(FusedLds& S, const double* X, int n, int k, double* 
     if (c < k) {
       Mi[c][c] = 1.0 / Rf[c][c];
       for (int i = c - 1; i >= 0; --i) {
-        double acc = 0.0;
-        for (int t = i + 1; t <= c; ++t) acc += Rf[i][t] * Mi[t][c];
-        Mi[i][c] = -acc / Rf[i][i];
+        // four interleaved partial sums, so four LDS reads are in flight instead of one
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int t = i + 1;
+        for (; t + 3 <= c; t += 4) {
+          a0 += Rf[i][t] * Mi[t][c];
+          a1 += Rf[i][t + 1] * Mi[t + 1][c];
+          a2 += Rf[i][t + 2] * Mi[t + 2][c];
+          a3 += Rf[i][t + 3] * Mi[t + 3][c];
+        }
+        for (; t <= c; ++t) a0 += Rf[i][t] * Mi[t][c];
+        Mi[i][c] = -((a0 + a1) + (a2 + a3)) / Rf[i][i];
       }
       for (int i = 0; i <= c; ++i) Mi[i][c] *= S.u.qr.dsc[i];
       for (int i = c + 1; i < k; ++i) Mi[i][c] = 0.0;
