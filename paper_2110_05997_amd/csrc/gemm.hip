@@ -186,13 +186,10 @@ __global__ __launch_bounds__(256) void mprod_kernel(const TX* __restrict__ X, in
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long long k = (long long)blockIdx.x * 64 + lane;
   const long long a = blockIdx.y;
-  const int jb = (int)((long long)J * w / 4), je = (int)((long long)J * (w + 1) / 4);
-  // 64-column blocks, grid-stride, so one staging of U serves several blocks
-  const long long nkb = (K + 63) / 64;
-  for (long long kb = blockIdx.x; kb < nkb; kb += gridDim.x) {
-  const long long k = kb * 64 + lane;
   const TX* x = X + a * (long long)J * K + (k < K ? k : 0);
+  const int jb = (int)((long long)J * w / 4), je = (int)((long long)J * (w + 1) / 4);
   double acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = 0.0;
@@ -225,23 +222,19 @@ __global__ __launch_bounds__(256) void mprod_kernel(const TX* __restrict__ X, in
     for (int b = 0; b < NB; ++b)
       if (b0 + b < nb) y[(long long)(b0 + b) * ldy] = ((acc[b] + red[0][b][lane]) + red[1][b][lane]) + red[2][b][lane];
   }
-  __syncthreads();   // red is rewritten by the next block
-  }
 }
 
 template <class TX>
 void mprod_launch(const TX* X, int A, int J, long long K, const double* U, int nb, double* Y, hipStream_t s) {
-  const long long nkb = (K + 63) / 64;
-  const dim3 grid((unsigned)(nkb < 1024 ? nkb : 1024), (unsigned)A);
+  const dim3 grid((unsigned)((K + 63) / 64), (unsigned)A);
   for (int b0 = 0; b0 < nb; b0 += MP_NB) {
     const int left = nb - b0;
     const int w = left <= 8 ? 8 : left <= 12 ? 12 : left <= 16 ? 16 : 20;
     const size_t lds = (size_t)J * w * sizeof(double);
-    auto k = w == 8 ? mprod_kernel<TX, 8> : w == 12 ? mprod_kernel<TX, 12> : w == 16 ? mprod_kernel<TX, 16>
-                                                                                     : mprod_kernel<TX, 20>;
-    if (lds + 3 * MP_NB * 64 * sizeof(double) > 64 * 1024)
-      (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, grid, dim3(256), lds, s, X, J, K, U, nb, b0, nb, Y, K);
+    if (w == 8) hipLaunchKernelGGL((mprod_kernel<TX, 8>), grid, dim3(256), lds, s, X, J, K, U, nb, b0, nb, Y, K);
+    else if (w == 12) hipLaunchKernelGGL((mprod_kernel<TX, 12>), grid, dim3(256), lds, s, X, J, K, U, nb, b0, nb, Y, K);
+    else if (w == 16) hipLaunchKernelGGL((mprod_kernel<TX, 16>), grid, dim3(256), lds, s, X, J, K, U, nb, b0, nb, Y, K);
+    else hipLaunchKernelGGL((mprod_kernel<TX, 20>), grid, dim3(256), lds, s, X, J, K, U, nb, b0, nb, Y, K);
   }
 }
 
