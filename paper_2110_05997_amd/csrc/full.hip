@@ -115,57 +115,69 @@ __global__ void final_sum_kernel(const double* __restrict__ part, int n, double*
   if (threadIdx.x == 0) *out = s;
 }
 
-// Column norms, lambda, signs and order of the uncompressed factors (one workgroup).
-__global__ void normalize_plan_kernel(const double* __restrict__ W0, const double* __restrict__ W1,
-                                      const double* __restrict__ W2, int I1, int I2, int I3, int R,
-                                      double* __restrict__ scale, int* __restrict__ dest,
-                                      double* __restrict__ lambda) {
+// Column norms, lambda, signs and order of the uncompressed factors (one workgroup).  Lane =
+// column (loads along a row are coalesced), 16 row groups of 1024 threads, partial results
+// combined in a fixed order; the sign comes from the largest-|.| entry of modes 1 and 2 (ties:
+// lowest index).
+constexpr int NP_NT = 1024;
+constexpr int NP_G = NP_NT / 64;
+
+__global__ __launch_bounds__(NP_NT) void normalize_plan_kernel(const double* __restrict__ W0, const double* __restrict__ W1,
+                                                              const double* __restrict__ W2, int I1, int I2, int I3, int R,
+                                                              double* __restrict__ scale, int* __restrict__ dest,
+                                                              double* __restrict__ lambda) {
+  __shared__ double ps[NP_G][64];
+  __shared__ double pb[NP_G][64];
+  __shared__ int px[NP_G][64];
   __shared__ double nrm[3][64];
   __shared__ double lam[64];
   __shared__ double sgn[2][64];
-  const double* Ws[3] = {W0, W1, W2};
-  const int Is[3] = {I1, I2, I3};
-  const int tid = threadIdx.x;
-  // norms: one wave per (mode, column)
-  const int lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
-  for (int c = w; c < 3 * R; c += nw) {
-    const int l = c / R, r = c % R;
-    double s = 0.0;
-    for (int i = lane; i < Is[l]; i += 64) s += Ws[l][(long long)i * R + r] * Ws[l][(long long)i * R + r];
-    s = wave_sum(s);
-    if (lane == 0) nrm[l][r] = sqrt(s);
-  }
-  // sign of the largest-|.| entry of modes 1 and 2 (ties: lowest index)
-  for (int c = w; c < 2 * R; c += nw) {
-    const int l = c / R, r = c % R;
-    double best = -1.0;
+  const int tid = threadIdx.x, r = tid & 63, q = tid >> 6;
+  for (int l = 0; l < 3; ++l) {
+    const double* W = (l == 0) ? W0 : (l == 1 ? W1 : W2);
+    const int I = (l == 0) ? I1 : (l == 1 ? I2 : I3);
+    double s = 0.0, best = -1.0;
     int bi = 0;   // stays a valid index if every entry is NaN
-    for (int i = lane; i < Is[l]; i += 64) {
-      const double a = fabs(Ws[l][(long long)i * R + r]);
-      if (a > best || (a == best && i < bi)) { best = a; bi = i; }
+    if (r < R) {
+      for (int i = q; i < I; i += NP_G) {
+        const double v = W[(long long)i * R + r];
+        s += v * v;
+        const double a = fabs(v);
+        if (a > best) { best = a; bi = i; }   // rows ascend: the first maximum is kept
+      }
     }
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    ps[q][r] = s;
+    pb[q][r] = best;
+    px[q][r] = bi;
+    __syncthreads();
+    if (q == 0 && r < R) {
+      double t = 0.0;
+      for (int g = 0; g < NP_G; ++g) t += ps[g][r];
+      nrm[l][r] = sqrt(t);
+      if (l < 2) {
+        double b = pb[0][r];
+        int ix = px[0][r];
+        for (int g = 1; g < NP_G; ++g)
+          if (pb[g][r] > b || (pb[g][r] == b && px[g][r] < ix)) { b = pb[g][r]; ix = px[g][r]; }
+        sgn[l][r] = (W[(long long)ix * R + r] < 0.0) ? -1.0 : 1.0;
+      }
     }
-    if (lane == 0) sgn[l][r] = (Ws[l][(long long)bi * R + r] < 0.0) ? -1.0 : 1.0;
+    __syncthreads();
   }
-  __syncthreads();
   if (tid < R) lam[tid] = (nrm[0][tid] * nrm[1][tid]) * nrm[2][tid];
   __syncthreads();
   if (tid < R) {
-    const int r = tid;
+    const int rr = tid;
     int rank = 0;
-    for (int s = 0; s < R; ++s)
-      if (lam[s] > lam[r] || (lam[s] == lam[r] && s < r)) ++rank;
-    dest[r] = rank;
-    lambda[rank] = lam[r];
+    for (int s2 = 0; s2 < R; ++s2)
+      if (lam[s2] > lam[rr] || (lam[s2] == lam[rr] && s2 < rr)) ++rank;
+    dest[rr] = rank;
+    lambda[rank] = lam[rr];
     for (int l = 0; l < 3; ++l) {
-      double sc = (nrm[l][r] > 0.0) ? 1.0 / nrm[l][r] : 1.0;
-      if (l < 2) sc *= sgn[l][r];
-      else sc *= sgn[0][r] * sgn[1][r];
-      scale[l * 64 + r] = sc;
+      double sc = (nrm[l][rr] > 0.0) ? 1.0 / nrm[l][rr] : 1.0;
+      if (l < 2) sc *= sgn[l][rr];
+      else sc *= sgn[0][rr] * sgn[1][rr];
+      scale[l * 64 + rr] = sc;
     }
   }
 }
@@ -273,7 +285,7 @@ cpd_status normalize_output(const double* const Wt[3], const int64_t dims[3], in
   }
   double* scale = (double*)ws;
   int* dest = (int*)((char*)ws + align_up(3 * 64 * sizeof(double), 256));
-  hipLaunchKernelGGL(normalize_plan_kernel, dim3(1), dim3(256), 0, s, Wt[0], Wt[1], Wt[2], (int)dims[0],
+  hipLaunchKernelGGL(normalize_plan_kernel, dim3(1), dim3(NP_NT), 0, s, Wt[0], Wt[1], Wt[2], (int)dims[0],
                      (int)dims[1], (int)dims[2], R, scale, dest, lambda);
   CPD_LAUNCH_CHECK();
   for (int l = 0; l < 3; ++l) {
