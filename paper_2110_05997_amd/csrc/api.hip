@@ -76,10 +76,15 @@ void compress_sizes(const int64_t dims[3], const int P[3], Sizer& z) {
 // Runs compression with carved workspace; outputs U (compact I_l x R~_l), sigma, S.
 // T_gram / gram_dtype / gram_compute: the tensor copy and precision the Grams are formed from
 // (normally T itself); the projection always reads T.
+// chk (optional, device): the input tensor's ||T||^2 and non-finite flag from sumsq_full, read back
+// with the eigenvalues (one host round trip for both) and checked before any host decision;
+// h_tn2 receives ||T||^2.  A zero or non-finite tensor only runs the Gram and eigen kernels on
+// workspace (their loops are bounded) before the error is returned.
 cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_dtype, int gram_compute,
                         const int64_t dims[3], int R, const cpd_params* p,
                         double* const U_out[3], double* const sigma_out[3], double* S_out,
-                        int core_out[3], Arena& ar, hipStream_t s) {
+                        int core_out[3], Arena& ar, hipStream_t s, const double* chk_tn2 = nullptr,
+                        const int* chk_bad = nullptr, double* h_tn2 = nullptr) {
   int P[3];
   pdims(dims, R, p, P);
   size_t gram_b = 0;
@@ -123,7 +128,18 @@ cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_d
   std::vector<double> hlv(ptot);
   double* hlam = hlv.data();
   CPD_HIP_CHECK(hipMemcpyAsync(hlam, lam, sizeof(double) * ptot, hipMemcpyDeviceToHost, s));
+  double c_tn2 = 1.0;
+  int c_bad = 0;
+  if (chk_tn2) {
+    CPD_HIP_CHECK(hipMemcpyAsync(&c_tn2, chk_tn2, sizeof(double), hipMemcpyDeviceToHost, s));
+    CPD_HIP_CHECK(hipMemcpyAsync(&c_bad, chk_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  }
   CPD_HIP_CHECK(hipStreamSynchronize(s));
+  if (chk_tn2) {
+    if (c_bad) { set_error("cpd_solve: non-finite entries in T"); return CPD_E_NONFINITE; }
+    if (!(c_tn2 > 0.0)) { set_error("cpd_solve: ||T|| = 0"); return CPD_E_ZERO_TENSOR; }
+    if (h_tn2) *h_tn2 = c_tn2;
+  }
   const bool fixed = p && p->core_dims[0] > 0 && p->core_dims[1] > 0 && p->core_dims[2] > 0;
   int rk[3];
   int o = 0;
@@ -330,21 +346,35 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   cpd_status st;
   const int64_t n = dims[0] * dims[1] * dims[2];
   if ((st = sumsq_full(T, dtype, n, tn2, bad, sws, sumsq_ws_bytes(), s))) return st;
+  // ||T||^2 and the non-finite flag come back with the eigenvalues (one host round trip)
   double h_tn2 = 0.0;
-  int h_bad = 0;
-  CPD_HIP_CHECK(hipMemcpyAsync(&h_tn2, tn2, sizeof(double), hipMemcpyDeviceToHost, s));
-  CPD_HIP_CHECK(hipMemcpyAsync(&h_bad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
-  CPD_HIP_CHECK(hipStreamSynchronize(s));
-  if (h_bad) { set_error("cpd_solve: non-finite entries in T"); return CPD_E_NONFINITE; }
-  if (!(h_tn2 > 0.0)) { set_error("cpd_solve: ||T|| = 0"); return CPD_E_ZERO_TENSOR; }
   int core[3];
-  if ((st = run_compress(T, dtype, T_gram, gram_dtype, gram_compute, dims, R, p, U, nullptr, S, core, ar, s)))
+  if ((st = run_compress(T, dtype, T_gram, gram_dtype, gram_compute, dims, R, p, U, nullptr, S, core, ar, s, tn2,
+                         bad, &h_tn2)))
     return st;
   if ((st = state_init(state, S, core, R, W0, h_tn2, p, s, false))) return st;
   if ((st = dgn_iterate_known(state, S, core, R, p->maxiter, s))) return st;
-  // one read-back after the dGN: the header (flags, iterations, stop, final core error)
+  // no read-back here: the header is read with the final residual; the output writes check its
+  // non-finite flag on the device, so a rejected initial point leaves the outputs untouched
+  (void)Wc;
+  const int npc = (core[0] + core[1] + core[2]) * R;
+  const double* Wst = (const double*)(state + layout_of(npc, R, p->maxiter).W);
+  const int* flags_dev = (const int*)(state + offsetof(Hdr, flags));
+  // uncompress W~ = U W
+  size_t o = 0;
+  for (int l = 0; l < 3; ++l) {
+    if ((st = gemm_f64((int)dims[l], R, core[l], 1.0, U[l], core[l], 0, false, Wst + o, CPD_F64, R, 0, false,
+                       0.0, Wt[l], R, 0, 1, s)))
+      return st;
+    o += (size_t)core[l] * R;
+  }
+  const double* Wtc[3] = {Wt[0], Wt[1], Wt[2]};
+  if ((st = residual_full(T, dtype, dims, Wtc, R, res, rws, residual_ws_bytes(dims), s))) return st;
+  if ((st = normalize_output(Wtc, dims, R, W_out, lambda_out, nws, normalize_ws_bytes(R), s, flags_dev))) return st;
+  double h_res = 0.0;
   Hdr h;
   CPD_HIP_CHECK(hipMemcpyAsync(&h, state, sizeof(Hdr), hipMemcpyDeviceToHost, s));
+  CPD_HIP_CHECK(hipMemcpyAsync(&h_res, res, sizeof(double), hipMemcpyDeviceToHost, s));
   CPD_HIP_CHECK(hipStreamSynchronize(s));
   if (h.flags & 1) {
     set_error("state_init: non-finite initial factors");
@@ -352,25 +382,6 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   }
   const int k = h.k, stop = h.stop, ti = h.tol_iter;
   const double err = (h.s_norm > 0.0) ? sqrt(h.f2) / h.s_norm : 0.0;   // = the logged error of step k
-  {
-    const int np = (core[0] + core[1] + core[2]) * R;
-    const Layout Lo = layout_of(np, R, p->maxiter);
-    CPD_HIP_CHECK(hipMemcpyAsync(Wc, state + Lo.W, sizeof(double) * np, hipMemcpyDeviceToDevice, s));
-  }
-  // uncompress W~ = U W
-  size_t o = 0;
-  for (int l = 0; l < 3; ++l) {
-    if ((st = gemm_f64((int)dims[l], R, core[l], 1.0, U[l], core[l], 0, false, Wc + o, CPD_F64, R, 0, false,
-                       0.0, Wt[l], R, 0, 1, s)))
-      return st;
-    o += (size_t)core[l] * R;
-  }
-  const double* Wtc[3] = {Wt[0], Wt[1], Wt[2]};
-  if ((st = residual_full(T, dtype, dims, Wtc, R, res, rws, residual_ws_bytes(dims), s))) return st;
-  if ((st = normalize_output(Wtc, dims, R, W_out, lambda_out, nws, normalize_ws_bytes(R), s))) return st;
-  double h_res = 0.0;
-  CPD_HIP_CHECK(hipMemcpyAsync(&h_res, res, sizeof(double), hipMemcpyDeviceToHost, s));
-  CPD_HIP_CHECK(hipStreamSynchronize(s));
   info->iters = k;
   info->stop_reason = stop;
   for (int l = 0; l < 3; ++l) info->core_dims[l] = core[l];

@@ -188,7 +188,8 @@ cpd_status jtj_v(const double* const W[3], const double* const V[3], const int32
 size_t normalize_ws_bytes(int R);
 cpd_status normalize_output(const double* const Wt[3], const int64_t dims[3], int R,
                             double* const Wout[3], double* lambda, void* ws, size_t ws_bytes,
-                            hipStream_t s);
+                            hipStream_t s,
+                            const int* skip = nullptr);   // device flag: bit 0 set -> write nothing
 size_t mttkrp_ws_bytes(const int64_t dims[3], int R, int mode);
 
 // Kernel timing (see cpd_profile_* in cpd.h).  No-ops unless enabled.

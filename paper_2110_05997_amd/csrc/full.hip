@@ -125,7 +125,7 @@ constexpr int NP_G = NP_NT / 64;
 __global__ __launch_bounds__(NP_NT) void normalize_plan_kernel(const double* __restrict__ W0, const double* __restrict__ W1,
                                                               const double* __restrict__ W2, int I1, int I2, int I3, int R,
                                                               double* __restrict__ scale, int* __restrict__ dest,
-                                                              double* __restrict__ lambda) {
+                                                              double* __restrict__ lambda, const int* __restrict__ skip) {
   __shared__ double ps[NP_G][64];
   __shared__ double pb[NP_G][64];
   __shared__ int px[NP_G][64];
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(NP_NT) void normalize_plan_kernel(const double* __r
     for (int s2 = 0; s2 < R; ++s2)
       if (lam[s2] > lam[rr] || (lam[s2] == lam[rr] && s2 < rr)) ++rank;
     dest[rr] = rank;
-    lambda[rank] = lam[rr];
+    if (!(skip && (*skip & 1))) lambda[rank] = lam[rr];
     for (int l = 0; l < 3; ++l) {
       double sc = (nrm[l][rr] > 0.0) ? 1.0 / nrm[l][rr] : 1.0;
       if (l < 2) sc *= sgn[l][rr];
@@ -184,9 +184,9 @@ __global__ __launch_bounds__(NP_NT) void normalize_plan_kernel(const double* __r
 
 __global__ void normalize_apply_kernel(const double* __restrict__ Wt, int I, int R,
                                        const double* __restrict__ scale, const int* __restrict__ dest,
-                                       double* __restrict__ Wout) {
+                                       double* __restrict__ Wout, const int* __restrict__ skip) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)I * R) return;
+  if (e >= (long long)I * R || (skip && (*skip & 1))) return;
   const int r = (int)(e % R);
   const long long i = e / R;
   Wout[i * R + dest[r]] = Wt[e] * scale[r];
@@ -274,7 +274,7 @@ size_t normalize_ws_bytes(int R) {
 
 cpd_status normalize_output(const double* const Wt[3], const int64_t dims[3], int R,
                             double* const Wout[3], double* lambda, void* ws, size_t ws_bytes,
-                            hipStream_t s) {
+                            hipStream_t s, const int* skip) {
   if (R < 1 || R > 64) {
     set_error("normalize_output: R out of range");
     return CPD_E_INVALID;
@@ -286,12 +286,12 @@ cpd_status normalize_output(const double* const Wt[3], const int64_t dims[3], in
   double* scale = (double*)ws;
   int* dest = (int*)((char*)ws + align_up(3 * 64 * sizeof(double), 256));
   hipLaunchKernelGGL(normalize_plan_kernel, dim3(1), dim3(NP_NT), 0, s, Wt[0], Wt[1], Wt[2], (int)dims[0],
-                     (int)dims[1], (int)dims[2], R, scale, dest, lambda);
+                     (int)dims[1], (int)dims[2], R, scale, dest, lambda, skip);
   CPD_LAUNCH_CHECK();
   for (int l = 0; l < 3; ++l) {
     const long long n = dims[l] * (long long)R;
     hipLaunchKernelGGL(normalize_apply_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Wt[l],
-                       (int)dims[l], R, scale + l * 64, dest, Wout[l]);
+                       (int)dims[l], R, scale + l * 64, dest, Wout[l], skip);
     CPD_LAUNCH_CHECK();
   }
   return CPD_OK;

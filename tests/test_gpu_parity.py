@@ -399,7 +399,8 @@ def test_solve_edge_cases():
     bad = [torch.full((d, 3), float("nan"), dtype=torch.float64, device=DEV) for d in core]
     with pytest.raises(lib.CpdError, match="status -4"):
         lib.DgnState(S, 3, lib.params(), W0=bad)
-    # the same start through the whole solve: reported after the dGN, before the output stage
+    # the same start through the whole solve: reported with the final read-back; the output kernels
+    # check the state's flag on the device and write nothing
     with pytest.raises(lib.CpdError, match="status -4"):
         lib.solve(Tg, 3, lib.params(init="given"), W0=bad)
 
