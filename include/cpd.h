@@ -362,6 +362,9 @@ typedef struct {
 } cpd_kernel_time;
 
 void cpd_profile_enable(int32_t on);
+/* Which kernels are timed while enabled: bit k for cpd_profile_kernel k (default: all).  Timing a
+ * few kernels keeps the event recording (host API calls) out of the rest of a measured step. */
+void cpd_profile_select(uint32_t mask);
 void cpd_profile_reset(void);
 /* Waits for the recorded events, then fills out[CPD_PK_COUNT]. */
 cpd_status cpd_profile_read(cpd_kernel_time* out);

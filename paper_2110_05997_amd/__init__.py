@@ -328,9 +328,13 @@ def residual_norm2(T, Ws):
     return out
 
 
-def profile_enable(on=True):
-    """Record HIP events around the path's main kernels (see cpd_profile_* in cpd.h)."""
-    _lib.lib().cpd_profile_enable(1 if on else 0)
+def profile_enable(on=True, kernels=None):
+    """Record HIP events around the path's main kernels (see cpd_profile_* in cpd.h); ``kernels``: a
+    list of names from _lib.PROFILE_KERNELS to time (default: all)."""
+    L = _lib.lib()
+    mask = 0xFFFFFFFF if kernels is None else sum(1 << _lib.PROFILE_KERNELS.index(k) for k in kernels)
+    L.cpd_profile_select(mask)
+    L.cpd_profile_enable(1 if on else 0)
 
 
 def profile_reset():

@@ -154,6 +154,7 @@ SIGNATURES = [
                                         ctypes.c_size_t, _P]),
     ("cpd_mlp_adam_step", ctypes.c_int, [ctypes.POINTER(Mlp), ctypes.POINTER(MlpGrads), ctypes.POINTER(Adam), _P]),
     ("cpd_profile_enable", None, [ctypes.c_int32]),
+    ("cpd_profile_select", None, [ctypes.c_uint32]),
     ("cpd_profile_reset", None, []),
     ("cpd_profile_read", ctypes.c_int, [ctypes.POINTER(KernelTime)]),
 ]

@@ -13,23 +13,30 @@ struct Pending {
 };
 
 bool g_on = false;
+uint32_t g_mask = ~0u;                 // kernels timed while enabled (bit k: cpd_profile_kernel k)
 std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_pool;        // events of finished measurements, reused
+
+bool take_event(hipEvent_t* e) {
+  if (!g_pool.empty()) { *e = g_pool.back(); g_pool.pop_back(); return true; }
+  return hipEventCreate(e) == hipSuccess;
+}
 int64_t g_launches[CPD_PK_COUNT];
 double g_ms[CPD_PK_COUNT];
 
 }  // namespace
 
 void prof_begin(int which, hipStream_t s) {
-  if (!g_on) return;
+  if (!g_on || !((g_mask >> which) & 1u)) return;
   Pending p{which, nullptr, nullptr, false};
-  if (hipEventCreate(&p.start) != hipSuccess) return;
-  if (hipEventCreate(&p.stop) != hipSuccess) { (void)hipEventDestroy(p.start); return; }
+  if (!take_event(&p.start)) return;
+  if (!take_event(&p.stop)) { g_pool.push_back(p.start); return; }
   (void)hipEventRecord(p.start, s);
   g_pending.push_back(p);
 }
 
 void prof_end(int which, hipStream_t s) {
-  if (!g_on) return;
+  if (!g_on || !((g_mask >> which) & 1u)) return;
   for (auto it = g_pending.rbegin(); it != g_pending.rend(); ++it) {
     if (it->which == which && !it->closed) {
       (void)hipEventRecord(it->stop, s);
@@ -47,11 +54,13 @@ extern "C" {
 
 void cpd_profile_enable(int32_t on) { g_on = (on != 0); }
 
+void cpd_profile_select(uint32_t mask) { g_mask = mask; }
+
 void cpd_profile_reset(void) {
   for (auto& p : g_pending) {
     if (p.closed) (void)hipEventSynchronize(p.stop);
-    (void)hipEventDestroy(p.start);
-    (void)hipEventDestroy(p.stop);
+    g_pool.push_back(p.start);
+    g_pool.push_back(p.stop);
   }
   g_pending.clear();
   for (int i = 0; i < CPD_PK_COUNT; ++i) { g_launches[i] = 0; g_ms[i] = 0.0; }
@@ -66,8 +75,8 @@ cpd_status cpd_profile_read(cpd_kernel_time* out) {
     CPD_HIP_CHECK(hipEventElapsedTime(&ms, p.start, p.stop));
     g_ms[p.which] += ms;
     g_launches[p.which] += 1;
-    (void)hipEventDestroy(p.start);
-    (void)hipEventDestroy(p.stop);
+    g_pool.push_back(p.start);
+    g_pool.push_back(p.stop);
   }
   g_pending.swap(keep);
   if (out)
