@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (CPD_BF16, CPD_F32, CPD_F64, CPD_INIT_GIVEN, CPD_INIT_MLSVD, CPD_INIT_RANDOM,
                    STOP_NAMES, CpdError, Params, SolveInfo, StepInfo)
 
-__all__ = ["params", "gram", "eig_top", "compress", "DgnState", "solve", "mttkrp", "residual_norm2",
+__all__ = ["params", "gram", "eig_top", "compress", "DgnState", "solve", "flat_w0", "mttkrp", "residual_norm2",
            "jtj_v", "Batch", "solve_mixed", "CpdError", "STOP_NAMES"]
 
 _DTYPES = {torch.float64: CPD_F64, torch.float32: CPD_F32, torch.bfloat16: CPD_BF16}
@@ -165,8 +165,26 @@ def workspace_bytes(shape, R, p=None):
     return _lib.lib().cpd_workspace_bytes((ctypes.c_int64 * 3)(*shape), R, ctypes.byref(p))
 
 
+def _flat_w0(W0, device):
+    """The three initial core factors as one contiguous FP64 device vector (a tensor that already is
+    one is used as it is, so repeated calls need no concatenation)."""
+    if W0 is None:
+        return None
+    if isinstance(W0, torch.Tensor):
+        if W0.dtype != torch.float64 or not W0.is_contiguous() or W0.device != device:
+            raise ValueError("a flat W0 must be a contiguous FP64 tensor on the tensor's device")
+        return W0
+    return torch.cat([w.reshape(-1) for w in W0]).to(device=device, dtype=torch.float64).contiguous()
+
+
+def flat_w0(W0, device):
+    """Concatenate initial core factors once, for repeated solve() calls with the same start."""
+    return _flat_w0(W0, device)
+
+
 def solve(T, R, p=None, W0=None, ws=None):
-    """Full CPD.  Returns dict(W=[3 x (I_l x R)], lam, info) with the C struct's fields."""
+    """Full CPD.  Returns dict(W=[3 x (I_l x R)], lam, info) with the C struct's fields.  W0: the three
+    initial core factors, or one flat FP64 tensor holding them in order (see flat_w0)."""
     _check_tensor(T)
     L = _lib.lib()
     if p is None:
@@ -176,9 +194,7 @@ def solve(T, R, p=None, W0=None, ws=None):
         ws = _ws(L.cpd_workspace_bytes(dims, R, ctypes.byref(p)), T.device)
     W = [torch.empty((T.shape[l], R), dtype=torch.float64, device=T.device) for l in range(3)]
     lam = torch.empty(R, dtype=torch.float64, device=T.device)
-    w0 = None
-    if W0 is not None:
-        w0 = torch.cat([w.reshape(-1) for w in W0]).to(device=T.device, dtype=torch.float64).contiguous()
+    w0 = _flat_w0(W0, T.device)
     info = SolveInfo()
     _lib.check(L.cpd_solve(_ptr(T), _dtype(T), dims, R, ctypes.byref(p), _ptr(w0),
                            (ctypes.c_void_p * 3)(*[w.data_ptr() for w in W]), _ptr(lam), ctypes.byref(info),
@@ -290,9 +306,7 @@ def solve_mixed(T_lo, T, R, p=None, W0=None, ws=None):
         ws = _ws(L.cpd_workspace_bytes(dims, R, ctypes.byref(p)), T.device)
     W = [torch.empty((T.shape[l], R), dtype=torch.float64, device=T.device) for l in range(3)]
     lam = torch.empty(R, dtype=torch.float64, device=T.device)
-    w0 = None
-    if W0 is not None:
-        w0 = torch.cat([w.reshape(-1) for w in W0]).to(device=T.device, dtype=torch.float64).contiguous()
+    w0 = _flat_w0(W0, T.device)
     info = SolveInfo()
     _lib.check(L.cpd_solve_mixed(_ptr(T_lo), CPD_BF16, _ptr(T), _dtype(T), dims, R, ctypes.byref(p), _ptr(w0),
                                  (ctypes.c_void_p * 3)(*[w.data_ptr() for w in W]), _ptr(lam), ctypes.byref(info),

@@ -415,6 +415,16 @@ def test_solve_is_deterministic():
     for wa, wb in zip(a["W"], b["W"]):
         assert torch.equal(wa, wb)
     assert a["info"]["iters"] == b["info"]["iters"]
+    # a start given as three factors and the same start concatenated once give identical solves
+    _, _, _, core = cp().compress(Td, 5)
+    W0 = [dev(w) for w in synth.init_factors(core, 5, 3)]
+    pg = cp().params(init="given")
+    c = cp().solve(Td, 5, pg, W0=W0)
+    d = cp().solve(Td, 5, pg, W0=cp().flat_w0(W0, Td.device))
+    for wc, wd in zip(c["W"], d["W"]):
+        assert torch.equal(wc, wd)
+    with pytest.raises(ValueError):
+        cp().solve(Td, 5, pg, W0=cp().flat_w0(W0, Td.device).float())
 
 
 def test_solve_mixed_bf16_grams_vs_oracle():
