@@ -76,15 +76,18 @@ void compress_sizes(const int64_t dims[3], const int P[3], Sizer& z) {
 // Runs compression with carved workspace; outputs U (compact I_l x R~_l), sigma, S.
 // T_gram / gram_dtype / gram_compute: the tensor copy and precision the Grams are formed from
 // (normally T itself); the projection always reads T.
-// chk (optional, device): the input tensor's ||T||^2 and non-finite flag from sumsq_full, read back
-// with the eigenvalues (one host round trip for both) and checked before any host decision;
-// h_tn2 receives ||T||^2.  A zero or non-finite tensor only runs the Gram and eigen kernels on
-// workspace (their loops are bounded) before the error is returned.
+// U_out[l] holds dims[l] x P_l doubles: the eigensolver writes the full basis there and only a
+// truncated mode is compacted (through workspace) afterwards.
+// chk (optional, device, 2 + P_1 + P_2 + P_3 doubles): the input tensor's ||T||^2 in chk[0] and
+// the non-finite flag (an int) in chk[1] from sumsq_full; the eigenvalues are written behind them,
+// so one copy brings all three back (one host round trip) and the checks are made before any host
+// decision; h_tn2 receives ||T||^2.  A zero or non-finite tensor only runs the Gram and eigen
+// kernels on workspace (their loops are bounded) before the error is returned.
 cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_dtype, int gram_compute,
                         const int64_t dims[3], int R, const cpd_params* p,
                         double* const U_out[3], double* const sigma_out[3], double* S_out,
-                        int core_out[3], Arena& ar, hipStream_t s, const double* chk_tn2 = nullptr,
-                        const int* chk_bad = nullptr, double* h_tn2 = nullptr) {
+                        int core_out[3], Arena& ar, hipStream_t s, double* chk = nullptr,
+                        double* h_tn2 = nullptr) {
   int P[3];
   pdims(dims, R, p, P);
   size_t gram_b = 0;
@@ -109,6 +112,7 @@ cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_d
   double* Uf[3];
   for (int l = 0; l < 3; ++l) Uf[l] = ar.take<double>((size_t)dims[l] * P[l]);
   double* lam = ar.take<double>(P[0] + P[1] + P[2]);
+  if (chk) lam = chk + 2;
   double* Y1 = ar.take<double>((size_t)P[0] * dims[1] * dims[2]);
   double* Y2 = ar.take<double>((size_t)P[0] * P[1] * dims[2]);
   if (!Y2) {
@@ -121,21 +125,20 @@ cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_d
     if ((st = gram(T_gram, gram_dtype, dims, l, gram_compute, G[l], gws, gram_b, s))) return st;
   // the three eigenproblems run side by side
   prof_begin(CPD_PK_EIG, s);
-  st = eig_top3(G, n, P, Uf, laml, 3, ews, eig_b, s);
+  st = eig_top3(G, n, P, U_out, laml, 3, ews, eig_b, s);
   prof_end(CPD_PK_EIG, s);
   if (st) return st;
   const int ptot = P[0] + P[1] + P[2];
-  std::vector<double> hlv(ptot);
-  double* hlam = hlv.data();
-  CPD_HIP_CHECK(hipMemcpyAsync(hlam, lam, sizeof(double) * ptot, hipMemcpyDeviceToHost, s));
-  double c_tn2 = 1.0;
-  int c_bad = 0;
-  if (chk_tn2) {
-    CPD_HIP_CHECK(hipMemcpyAsync(&c_tn2, chk_tn2, sizeof(double), hipMemcpyDeviceToHost, s));
-    CPD_HIP_CHECK(hipMemcpyAsync(&c_bad, chk_bad, sizeof(int), hipMemcpyDeviceToHost, s));
-  }
+  std::vector<double> hbuf(ptot + 2);
+  const int h0 = chk ? 0 : 2;   // host index of the first copied double
+  CPD_HIP_CHECK(hipMemcpyAsync(hbuf.data() + h0, chk ? chk : lam, sizeof(double) * (ptot + 2 - h0),
+                               hipMemcpyDeviceToHost, s));
   CPD_HIP_CHECK(hipStreamSynchronize(s));
-  if (chk_tn2) {
+  const double* hlam = hbuf.data() + 2;
+  if (chk) {
+    const double c_tn2 = hbuf[0];
+    int c_bad = 0;
+    memcpy(&c_bad, &hbuf[1], sizeof(int));
     if (c_bad) { set_error("cpd_solve: non-finite entries in T"); return CPD_E_NONFINITE; }
     if (!(c_tn2 > 0.0)) { set_error("cpd_solve: ||T|| = 0"); return CPD_E_ZERO_TENSOR; }
     if (h_tn2) *h_tn2 = c_tn2;
@@ -161,10 +164,13 @@ cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_d
       o += P[l];
     }
   }
-  // compact truncated U
-  for (int l = 0; l < 3; ++l)
-    CPD_HIP_CHECK(hipMemcpy2DAsync(U_out[l], sizeof(double) * rk[l], Uf[l], sizeof(double) * P[l],
+  // compact a truncated U (rows of P_l doubles to rows of R~_l) through the workspace
+  for (int l = 0; l < 3; ++l) {
+    if (rk[l] == P[l]) continue;
+    CPD_HIP_CHECK(hipMemcpy2DAsync(Uf[l], sizeof(double) * rk[l], U_out[l], sizeof(double) * P[l],
                                    sizeof(double) * rk[l], dims[l], hipMemcpyDeviceToDevice, s));
+    CPD_HIP_CHECK(hipMemcpyAsync(U_out[l], Uf[l], sizeof(double) * rk[l] * dims[l], hipMemcpyDeviceToDevice, s));
+  }
   // S = T x1 U1^T x2 U2^T x3 U3^T
   const int I1 = (int)dims[0], I2 = (int)dims[1], I3 = (int)dims[2];
   const int r1 = rk[0], r2 = rk[1], r3 = rk[2];
@@ -193,19 +199,19 @@ cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_d
 size_t solve_ws(const int64_t dims[3], int R, const cpd_params* p) {
   int P[3];
   pdims(dims, R, p, P);
+  // the carving order of solve_impl
   Sizer z;
-  z.take<double>(1);                       // ||T||^2
-  z.take<int>(1);                          // non-finite flag
+  z.take<double>(2 + P[0] + P[1] + P[2]);  // ||T||^2, non-finite flag, eigenvalues
   z.take<char>(sumsq_ws_bytes());
-  for (int l = 0; l < 3; ++l) z.take<double>((size_t)dims[l] * P[l]);   // U (compact)
+  for (int l = 0; l < 3; ++l) z.take<double>((size_t)dims[l] * P[l]);   // U
   z.take<double>((size_t)P[0] * P[1] * P[2]);                            // S
   const int32_t pc[3] = {P[0], P[1], P[2]};
+  z.take<double>(1);                                                     // final residual
   z.take<char>(state_bytes(pc, R, p ? p->maxiter : 200));
   z.take<double>((size_t)(P[0] + P[1] + P[2]) * R);                      // core factors
   for (int l = 0; l < 3; ++l) z.take<double>((size_t)dims[l] * R);       // uncompressed
   z.take<char>(normalize_ws_bytes(R));
   z.take<char>(residual_ws_bytes(dims));
-  z.take<double>(1);
   Sizer zc;
   compress_sizes(dims, P, zc);
   z.take<char>(zc.off);
@@ -329,29 +335,39 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   int P[3];
   pdims(dims, R, p, P);
   Arena ar(ws, ws_bytes);
-  double* tn2 = ar.take<double>(1);
-  int* bad = ar.take<int>(1);
+  // ||T||^2, the non-finite flag and the eigenvalues, adjacent so that one copy reads them back
+  double* chk = ar.take<double>(2 + P[0] + P[1] + P[2]);
   char* sws = ar.take<char>(sumsq_ws_bytes());
   double* U[3];
   for (int l = 0; l < 3; ++l) U[l] = ar.take<double>((size_t)dims[l] * P[l]);
   double* S = ar.take<double>((size_t)P[0] * P[1] * P[2]);
   const int32_t pc[3] = {P[0], P[1], P[2]};
+  // the final residual one 256-byte slot before the state: one copy reads it with the header
+  double* res = ar.take<double>(1);
   char* state = ar.take<char>(state_bytes(pc, R, p->maxiter));
+  if (state != (char*)res + 256) {
+    set_error("cpd_solve: workspace too small");
+    return CPD_E_WORKSPACE;
+  }
   double* Wc = ar.take<double>((size_t)(P[0] + P[1] + P[2]) * R);
   double* Wt[3];
   for (int l = 0; l < 3; ++l) Wt[l] = ar.take<double>((size_t)dims[l] * R);
   char* nws = ar.take<char>(normalize_ws_bytes(R));
   char* rws = ar.take<char>(residual_ws_bytes(dims));
-  double* res = ar.take<double>(1);
+  if (!rws) {
+    set_error("cpd_solve: workspace too small");
+    return CPD_E_WORKSPACE;
+  }
   cpd_status st;
   const int64_t n = dims[0] * dims[1] * dims[2];
-  if ((st = sumsq_full(T, dtype, n, tn2, bad, sws, sumsq_ws_bytes(), s))) return st;
+  if ((st = sumsq_full(T, dtype, n, chk, (int*)(chk + 1), sws, sumsq_ws_bytes(), s))) return st;
   // ||T||^2 and the non-finite flag come back with the eigenvalues (one host round trip)
   double h_tn2 = 0.0;
   int core[3];
-  if ((st = run_compress(T, dtype, T_gram, gram_dtype, gram_compute, dims, R, p, U, nullptr, S, core, ar, s, tn2,
-                         bad, &h_tn2)))
+  if ((st = run_compress(T, dtype, T_gram, gram_dtype, gram_compute, dims, R, p, U, nullptr, S, core, ar, s, chk,
+                         &h_tn2)))
     return st;
+  // the header and CG caps go to the device as kernel arguments: no host synchronisation here
   if ((st = state_init(state, S, core, R, W0, h_tn2, p, s, false))) return st;
   if ((st = dgn_iterate_known(state, S, core, R, p->maxiter, s))) return st;
   // no read-back here: the header is read with the final residual; the output writes check its
@@ -371,11 +387,13 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   const double* Wtc[3] = {Wt[0], Wt[1], Wt[2]};
   if ((st = residual_full(T, dtype, dims, Wtc, R, res, rws, residual_ws_bytes(dims), s))) return st;
   if ((st = normalize_output(Wtc, dims, R, W_out, lambda_out, nws, normalize_ws_bytes(R), s, flags_dev))) return st;
-  double h_res = 0.0;
-  Hdr h;
-  CPD_HIP_CHECK(hipMemcpyAsync(&h, state, sizeof(Hdr), hipMemcpyDeviceToHost, s));
-  CPD_HIP_CHECK(hipMemcpyAsync(&h_res, res, sizeof(double), hipMemcpyDeviceToHost, s));
+  char hb[256 + sizeof(Hdr)];
+  CPD_HIP_CHECK(hipMemcpyAsync(hb, res, sizeof(hb), hipMemcpyDeviceToHost, s));
   CPD_HIP_CHECK(hipStreamSynchronize(s));
+  double h_res;
+  Hdr h;
+  memcpy(&h_res, hb, sizeof(double));
+  memcpy(&h, hb + 256, sizeof(Hdr));
   if (h.flags & 1) {
     set_error("state_init: non-finite initial factors");
     return CPD_E_NONFINITE;

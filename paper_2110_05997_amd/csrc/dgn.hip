@@ -24,6 +24,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <vector>
+
 namespace cpd {
 namespace {
 
@@ -731,6 +733,30 @@ __global__ __launch_bounds__(256) void smart_init_kernel(const double* __restric
 }
 
 // N(0,1) entries by Box-Muller on SplitMix64 counters.
+// A new state's header and CG caps, built on the host and passed by value, are written by one
+// kernel together with a given start: setting up a state needs no host copy and no
+// synchronisation.  Up to SETUP_CAPS dGN iterations; longer runs copy the caps from the host.
+constexpr int SETUP_CAPS = 512;
+struct SetupArgs {
+  Hdr h;
+  int32_t caps[SETUP_CAPS];
+};
+static_assert(sizeof(SetupArgs) <= 3072, "setup arguments must fit the kernel argument segment");
+static_assert(sizeof(Hdr) % 4 == 0, "header copied in 4-byte words");
+
+__global__ __launch_bounds__(256) void state_setup_kernel(const SetupArgs a, int ncaps, char* __restrict__ st,
+                                                          size_t caps_off, const double* __restrict__ W0,
+                                                          double* __restrict__ gW, int nw) {
+  if (blockIdx.x == 0) {
+    const int32_t* hw = reinterpret_cast<const int32_t*>(&a.h);
+    int32_t* dh = reinterpret_cast<int32_t*>(st);
+    for (int i = threadIdx.x; i < (int)(sizeof(Hdr) / 4); i += 256) dh[i] = hw[i];
+    int32_t* dc = reinterpret_cast<int32_t*>(st + caps_off);
+    for (int i = threadIdx.x; i < ncaps; i += 256) dc[i] = a.caps[i];
+  }
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nw; i += gridDim.x * 256) gW[i] = W0[i];
+}
+
 __global__ void randn_kernel(double* W, int n, uint64_t seed) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
@@ -933,16 +959,18 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
   const int np = (core[0] + core[1] + core[2]) * R;
   const Layout Lo = layout_of(np, R, p->maxiter);
   char* st = (char*)state;
-  // header + caps on the host, then one copy
-  Hdr h;
-  memset(&h, 0, sizeof(h));
+  double* gW = (double*)(st + Lo.W);
+  // header and caps on the host
+  const bool inline_args = p->maxiter <= SETUP_CAPS;
+  std::vector<int32_t> caps_long(inline_args ? 0 : p->maxiter);
+  SetupArgs a;
+  memset(&a, 0, sizeof(a));
+  Hdr& h = a.h;
   h.d[0] = core[0]; h.d[1] = core[1]; h.d[2] = core[2]; h.R = R;
   h.maxiter = p->maxiter; h.np = np; h.tol_iter = -1;
   h.tol = p->tol; h.cg_tol = (p->cg_tol > 0.0) ? p->cg_tol : p->tol;
   h.init_damp = p->init_damp; h.div_ref = t_norm2;
-  CPD_HIP_CHECK(hipMemcpyAsync(st, &h, sizeof(h), hipMemcpyHostToDevice, s));
-  int* caps = (int*)malloc(sizeof(int) * p->maxiter);
-  if (!caps) { set_error("state_init: host allocation failed"); return CPD_E_INVALID; }
+  int32_t* caps = inline_args ? a.caps : caps_long.data();
   for (int k = 1; k <= p->maxiter; ++k) {
     if (p->cg_fixed > 0) {
       caps[k - 1] = p->cg_fixed;
@@ -952,14 +980,30 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
       caps[k - 1] = cg_cap_for(k, u);
     }
   }
-  hipError_t ce = hipMemcpyAsync(st + Lo.caps, caps, sizeof(int) * p->maxiter, hipMemcpyHostToDevice, s);
-  if (ce == hipSuccess) ce = hipStreamSynchronize(s);
-  free(caps);
-  if (ce != hipSuccess) {
-    set_error("state_init: copy failed: %s", hipGetErrorString(ce));
-    return CPD_E_HIP;
+  // a given start is copied by the same kernel
+  const bool given = p->init != CPD_INIT_MLSVD && W0 != nullptr;
+  const int nw = given ? np : 0;
+  int nb = (nw + 255) / 256;
+  nb = nb < 1 ? 1 : (nb > 256 ? 256 : nb);
+  if (inline_args) {
+    hipLaunchKernelGGL(state_setup_kernel, dim3(nb), dim3(256), 0, s, a, p->maxiter, st, Lo.caps, W0, gW, nw);
+    CPD_LAUNCH_CHECK();
+  } else {
+    // long runs: the caps from host memory; the synchronisation keeps the host buffers alive
+    // until the copies have read them
+    hipError_t ce = hipMemcpyAsync(st, &h, sizeof(h), hipMemcpyHostToDevice, s);
+    if (ce == hipSuccess)
+      ce = hipMemcpyAsync(st + Lo.caps, caps, sizeof(int32_t) * p->maxiter, hipMemcpyHostToDevice, s);
+    if (ce == hipSuccess) ce = hipStreamSynchronize(s);
+    if (ce != hipSuccess) {
+      set_error("state_init: copy failed: %s", hipGetErrorString(ce));
+      return CPD_E_HIP;
+    }
+    if (given) {
+      hipLaunchKernelGGL(state_setup_kernel, dim3(nb), dim3(256), 0, s, a, 0, st, Lo.caps, W0, gW, nw);
+      CPD_LAUNCH_CHECK();
+    }
   }
-  double* gW = (double*)(st + Lo.W);
   if (p->init == CPD_INIT_MLSVD) {
     hipLaunchKernelGGL(smart_init_kernel, dim3(1), dim3(256), 0, s, S, core[0], core[1], core[2],
                        R, W0, gW);
@@ -969,7 +1013,7 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
       return CPD_E_INVALID;
     }
   } else if (W0 != nullptr) {
-    CPD_HIP_CHECK(hipMemcpyAsync(gW, W0, sizeof(double) * np, hipMemcpyDeviceToDevice, s));
+    // copied above
   } else if (p->init == CPD_INIT_RANDOM) {
     hipLaunchKernelGGL(randn_kernel, dim3((np + 255) / 256), dim3(256), 0, s, gW, np, p->seed);
     CPD_LAUNCH_CHECK();
