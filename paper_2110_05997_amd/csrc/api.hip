@@ -73,6 +73,26 @@ void compress_sizes(const int64_t dims[3], const int P[3], Sizer& z) {
   z.take<double>((size_t)P[0] * P[1] * dims[2]);         // Y2
 }
 
+// Host memory for a solve's read-backs: a 4 KB pinned buffer per host thread, so the copies write
+// host memory directly instead of going through a staging copy.  Every use ends with a
+// synchronisation before the next one starts, so one buffer per thread suffices; it lives until
+// the process ends.  Falls back to `spill` (pageable) when the buffer cannot be had or is too small.
+constexpr size_t READBACK_BYTES = 4096;
+char* readback_host(size_t bytes, std::vector<char>& spill) {
+  static thread_local char* buf = nullptr;
+  static thread_local bool tried = false;
+  if (!tried) {
+    tried = true;
+    if (hipHostMalloc((void**)&buf, READBACK_BYTES, hipHostMallocPortable) != hipSuccess) {
+      buf = nullptr;
+      (void)hipGetLastError();
+    }
+  }
+  if (buf && bytes <= READBACK_BYTES) return buf;
+  spill.resize(bytes);
+  return spill.data();
+}
+
 // Runs compression with carved workspace; outputs U (compact I_l x R~_l), sigma, S.
 // T_gram / gram_dtype / gram_compute: the tensor copy and precision the Grams are formed from
 // (normally T itself); the projection always reads T.
@@ -129,12 +149,14 @@ cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_d
   prof_end(CPD_PK_EIG, s);
   if (st) return st;
   const int ptot = P[0] + P[1] + P[2];
-  std::vector<double> hbuf(ptot + 2);
+  std::vector<char> spill;
+  double* hbuf = (double*)readback_host(sizeof(double) * (ptot + 2), spill);
   const int h0 = chk ? 0 : 2;   // host index of the first copied double
-  CPD_HIP_CHECK(hipMemcpyAsync(hbuf.data() + h0, chk ? chk : lam, sizeof(double) * (ptot + 2 - h0),
+  CPD_HIP_CHECK(hipMemcpyAsync(hbuf + h0, chk ? chk : lam, sizeof(double) * (ptot + 2 - h0),
                                hipMemcpyDeviceToHost, s));
   CPD_HIP_CHECK(hipStreamSynchronize(s));
-  const double* hlam = hbuf.data() + 2;
+  const std::vector<double> hlv(hbuf + 2, hbuf + 2 + ptot);   // the buffer is reused at the end
+  const double* hlam = hlv.data();
   if (chk) {
     const double c_tn2 = hbuf[0];
     int c_bad = 0;
@@ -387,8 +409,10 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   const double* Wtc[3] = {Wt[0], Wt[1], Wt[2]};
   if ((st = residual_full(T, dtype, dims, Wtc, R, res, rws, residual_ws_bytes(dims), s))) return st;
   if ((st = normalize_output(Wtc, dims, R, W_out, lambda_out, nws, normalize_ws_bytes(R), s, flags_dev))) return st;
-  char hb[256 + sizeof(Hdr)];
-  CPD_HIP_CHECK(hipMemcpyAsync(hb, res, sizeof(hb), hipMemcpyDeviceToHost, s));
+  std::vector<char> spill;
+  const size_t hbytes = 256 + sizeof(Hdr);
+  char* hb = readback_host(hbytes, spill);
+  CPD_HIP_CHECK(hipMemcpyAsync(hb, res, hbytes, hipMemcpyDeviceToHost, s));
   CPD_HIP_CHECK(hipStreamSynchronize(s));
   double h_res;
   Hdr h;

@@ -99,12 +99,22 @@ __global__ __launch_bounds__(RNT) void sumsq_kernel(const T* __restrict__ X, lon
   if (threadIdx.x == 0) { part[blockIdx.x] = s; badp[blockIdx.x] = b; }
 }
 
-__global__ void final_flag_kernel(const double* __restrict__ badp, int n, int* __restrict__ out) {
-  __shared__ double slots[RNT / 64];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += RNT) acc += badp[i];
-  const double s = block_sum(acc, slots);
-  if (threadIdx.x == 0) *out = (s > 0.0) ? 1 : 0;
+// The sum of the per-block partials and, when `out_flag` is given, whether any block saw a
+// non-finite entry: one launch for both.
+__global__ void final_sum_flag_kernel(const double* __restrict__ part, const double* __restrict__ badp, int n,
+                                      double* __restrict__ out, int* __restrict__ out_flag) {
+  __shared__ double slots[2][RNT / 64];
+  double acc = 0.0, nb = 0.0;
+  for (int i = threadIdx.x; i < n; i += RNT) {
+    acc += part[i];
+    if (out_flag) nb += badp[i];
+  }
+  const double s = block_sum(acc, slots[0]);
+  const double b = block_sum(nb, slots[1]);
+  if (threadIdx.x == 0) {
+    *out = s;
+    if (out_flag) *out_flag = (b > 0.0) ? 1 : 0;
+  }
 }
 
 __global__ void final_sum_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
@@ -258,12 +268,8 @@ cpd_status sumsq_full(const void* T, int dtype, int64_t n, double* out, int* non
       return CPD_E_INVALID;
   }
   CPD_LAUNCH_CHECK();
-  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(RNT), 0, s, part, RB, out);
+  hipLaunchKernelGGL(final_sum_flag_kernel, dim3(1), dim3(RNT), 0, s, part, bad, RB, out, nonfinite);
   CPD_LAUNCH_CHECK();
-  if (nonfinite) {
-    hipLaunchKernelGGL(final_flag_kernel, dim3(1), dim3(RNT), 0, s, bad, RB, nonfinite);
-    CPD_LAUNCH_CHECK();
-  }
   return CPD_OK;
 }
 
