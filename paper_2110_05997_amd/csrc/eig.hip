@@ -494,12 +494,28 @@ __device__ double rayleigh_ritz(FusedLds& S, const double* G, int n, int P, int 
   return (t0 > 0.0) ? m / t0 : 0.0;
 }
 
-__global__ __launch_bounds__(FNT) void subspace_kernel(const double* __restrict__ G, int n, int P, int k,
-                                                       double* Q, double* Y, double* Z, double* Qt, double* B,
-                                                       double* Vb, double* theta, double* Uw, uint64_t seed,
-                                                       double* __restrict__ U, double* __restrict__ lam) {
+// One problem of the fused solver: its Gram, sizes, work blocks and outputs.
+struct SubspaceArgs {
+  const double* G;
+  int n, P, k;
+  double *Q, *Y, *Z, *Qt, *B, *Vb, *theta, *Uw;
+  uint64_t seed;
+  double *U, *lam;
+};
+// Up to three problems per launch, one workgroup each (the modes of one tensor).
+struct SubspaceSet {
+  SubspaceArgs p[3];
+};
+
+__global__ __launch_bounds__(FNT) void subspace_kernel(const SubspaceSet set) {
   __shared__ FusedLds S;
-  const FusedBufs b = {Q, Y, Z, Qt, B, Vb, theta, Uw};
+  const SubspaceArgs& a = set.p[blockIdx.x];
+  const double* __restrict__ G = a.G;
+  const int n = a.n, P = a.P, k = a.k;
+  const uint64_t seed = a.seed;
+  double* __restrict__ U = a.U;
+  double* __restrict__ lam = a.lam;
+  const FusedBufs b = {a.Q, a.Y, a.Z, a.Qt, a.B, a.Vb, a.theta, a.Uw};
   const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
   // start block and one Cholesky-QR pass
   for (int e = tid; e < n * k; e += FNT)
@@ -590,6 +606,16 @@ struct SubProblem {
   double r_host;
 };
 
+bool sp_fused(const SubProblem& q) { return !q.direct && q.n <= FUSED_NMAX; }
+
+SubspaceArgs subspace_args(const SubProblem& q) {
+  SubspaceArgs a;
+  a.G = q.G; a.n = q.n; a.P = q.P; a.k = q.k;
+  a.Q = q.Q; a.Y = q.Y; a.Z = q.Z; a.Qt = q.Qt; a.B = q.B; a.Vb = q.Vb; a.theta = q.theta; a.Uw = q.Uw;
+  a.seed = q.seed; a.U = q.U; a.lam = q.lam;
+  return a;
+}
+
 template <class Carver>
 void sp_carve(Carver& ar, SubProblem& q) {
   if (q.direct) {
@@ -675,8 +701,10 @@ cpd_status sp_start_phase(SubProblem& q, int ph, hipStream_t s) {
   const int n = q.n, k = q.k;
   if (n <= FUSED_NMAX) {
     if (ph != 0) return CPD_OK;
-    hipLaunchKernelGGL(subspace_kernel, dim3(1), dim3(FNT), 0, s, q.G, n, q.P, k, q.Q, q.Y, q.Z, q.Qt, q.B,
-                       q.Vb, q.theta, q.Uw, q.seed, q.U, q.lam);
+    SubspaceSet set;
+    memset(&set, 0, sizeof(set));
+    set.p[0] = subspace_args(q);
+    hipLaunchKernelGGL(subspace_kernel, dim3(1), dim3(FNT), 0, s, set);
     CPD_LAUNCH_CHECK();
     q.done = true;
     return CPD_OK;
@@ -798,6 +826,17 @@ cpd_status eig_top3(const double* const* G, const int* n, const int* P, double* 
   for (int i = 0; i < nprob; ++i) {
     sp_describe(q[i], G[i], n[i], P[i], U[i], lam[i]);
     sp_carve(ar, q[i]);
+  }
+  // every problem on the one-workgroup solver: one launch, one workgroup per problem, on s itself
+  bool all_fused = true;
+  for (int i = 0; i < nprob; ++i) all_fused = all_fused && sp_fused(q[i]);
+  if (all_fused) {
+    SubspaceSet set;
+    memset(&set, 0, sizeof(set));
+    for (int i = 0; i < nprob; ++i) set.p[i] = subspace_args(q[i]);
+    hipLaunchKernelGGL(subspace_kernel, dim3(nprob), dim3(FNT), 0, s, set);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
   }
   SideStreams* ss = side_streams();
   if (ss == nullptr) {
