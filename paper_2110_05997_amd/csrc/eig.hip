@@ -31,6 +31,45 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const double* __restrict__ 
   jacobi_block<JNT, true>(L, Ag, n, lda, lam, Vout);
 }
 
+// The direct path for up to three problems (the modes of one tensor, n <= 64), one workgroup
+// each: Jacobi eigendecomposition, the leading P eigenvalues, and the first P eigenvectors signed
+// as sign_columns_kernel signs them (one wave per column).
+struct DirectArgs {
+  const double* G;
+  int n, P;
+  double *V, *lall, *U, *lam;
+};
+struct DirectSet {
+  DirectArgs p[3];
+};
+
+__global__ __launch_bounds__(JNT) void direct_kernel(const DirectSet set) {
+  __shared__ JacobiLds L;
+  const DirectArgs& a = set.p[blockIdx.x];
+  const int n = a.n, P = a.P;
+  const double* __restrict__ V = a.V;
+  double* __restrict__ U = a.U;
+  jacobi_block<JNT, true>(L, a.G, n, n, a.lall, a.V);
+  __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
+  for (int j = tid; j < P; j += JNT) a.lam[j] = a.lall[j];
+  for (int j = w; j < P; j += JNT / 64) {
+    double best = -1.0;
+    int bi = 0;   // stays a valid index if every entry is NaN
+    for (int i = lane; i < n; i += 64) {
+      const double v = fabs(V[i * n + j]);
+      if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const double sgn = (V[bi * n + j] < 0.0) ? -1.0 : 1.0;
+    for (int i = lane; i < n; i += 64) U[i * P + j] = sgn * V[i * n + j];
+  }
+}
+
 // Copies the first P columns of X (n x ldx) into U (n x P) and signs each column so its
 // largest-|.| entry is positive (ties: lowest index).  One workgroup per column.
 __global__ void sign_columns_kernel(const double* __restrict__ X, int n, int ldx, int P,
@@ -827,9 +866,21 @@ cpd_status eig_top3(const double* const* G, const int* n, const int* P, double* 
     sp_describe(q[i], G[i], n[i], P[i], U[i], lam[i]);
     sp_carve(ar, q[i]);
   }
-  // every problem on the one-workgroup solver: one launch, one workgroup per problem, on s itself
-  bool all_fused = true;
-  for (int i = 0; i < nprob; ++i) all_fused = all_fused && sp_fused(q[i]);
+  // every problem small enough for the direct solve, or every one on the one-workgroup subspace
+  // solver: one launch, one workgroup per problem, on s itself
+  bool all_fused = true, all_direct = true;
+  for (int i = 0; i < nprob; ++i) {
+    all_fused = all_fused && sp_fused(q[i]);
+    all_direct = all_direct && q[i].direct;
+  }
+  if (all_direct) {
+    DirectSet set;
+    memset(&set, 0, sizeof(set));
+    for (int i = 0; i < nprob; ++i) set.p[i] = {q[i].G, q[i].n, q[i].P, q[i].V, q[i].lall, q[i].U, q[i].lam};
+    hipLaunchKernelGGL(direct_kernel, dim3(nprob), dim3(JNT), 0, s, set);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+  }
   if (all_fused) {
     SubspaceSet set;
     memset(&set, 0, sizeof(set));
