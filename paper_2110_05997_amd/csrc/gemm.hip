@@ -264,7 +264,11 @@ cpd_status gemm_f64(int M, int N, int K, double alpha, const double* A, int lda,
       return CPD_OK;
     }
   }
-  if (mn <= 65536 && K <= 4096 && batch <= 65535 && (mn < 16384 || K <= 1024)) {
+  // one thread per output element while the whole batch's output is small or the contraction
+  // short; a large batch of long contractions (e.g. the second mode product of a 600^3 core
+  // projection: 50 products of 50 x 600 x 600) goes to the LDS-tiled kernel
+  const bool big_batch = (long long)mn * batch >= (1LL << 20) && K >= 256;
+  if (mn <= 65536 && K <= 4096 && batch <= 65535 && (mn < 16384 || K <= 1024) && !big_batch) {
     dim3 g2((unsigned)((mn + 255) / 256), batch);
     switch (bdtype) {
       case CPD_F64:
