@@ -99,6 +99,8 @@ typedef struct {
   double gain;           /* gain ratio g */
   double mu;             /* damping parameter after the update rule */
   double cg_resid;       /* final ||r||^2 of CG */
+  int64_t t_ns;          /* device time at the end of this iteration, in ns since the state's
+                            initialisation ended (in-kernel wall-clock stamps) */
 } cpd_step_info;
 
 typedef struct {
@@ -109,6 +111,10 @@ typedef struct {
   double rel_err_core;     /* final ||S - S_k|| / ||S|| */
   double rel_err_full;     /* ||T - sum_r lambda_r w_r^(1) o w_r^(2) o w_r^(3)|| / ||T|| */
   double t_norm;           /* ||T|| */
+  int64_t time_to_tol_ns;  /* device time from the call's first kernel (T resident, compression
+                              included) to the end of iteration tol_iter, from in-kernel
+                              wall-clock stamps; -1 if the error never fell below tol.  Batched
+                              solves count from the member's dGN start (compression excluded) */
 } cpd_solve_info;
 
 /* Last error message of the calling thread (static storage, never NULL). */
@@ -231,8 +237,6 @@ cpd_status cpd_mttkrp(const void* T, int32_t dtype, const int64_t dims[3], const
                       int32_t R, int32_t mode, int32_t compute_dtype, double* M, void* ws, size_t ws_bytes,
                       void* stream);
 
-/* out (device, 1 double) = ||T - sum_r w_r^(1) o w_r^(2) o w_r^(3)||^2, fused (ch.4 "Computing the
- * residual" applied to the input tensor).  ws: cpd_residual_workspace_bytes. */
 /* ------------------------------------------------------------------------------------------ */
 /* Batched solve: many small independent CPDs (every mode <= 64), each the full path of ch.4     */
 /* (Alg. Compression, dGN with CG, uncompression) exactly as cpd_solve does it, one workgroup   */
@@ -287,6 +291,8 @@ cpd_status cpd_solve_mixed(const void* T_lo, int32_t lo_dtype, const void* T, in
                            int32_t R, const cpd_params* p, const double* W0, double* W_out[3], double* lambda_out,
                            cpd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* out (device, 1 double) = ||T - sum_r w_r^(1) o w_r^(2) o w_r^(3)||^2, fused (ch.4 "Computing the
+ * residual" applied to the input tensor).  ws: cpd_residual_workspace_bytes. */
 size_t cpd_residual_workspace_bytes(const int64_t dims[3]);
 cpd_status cpd_residual_norm2(const void* T, int32_t dtype, const int64_t dims[3],
                               const double* const W[3], int32_t R, double* out, void* ws,

@@ -48,6 +48,7 @@ class StepInfo(ctypes.Structure):
         ("gain", ctypes.c_double),
         ("mu", ctypes.c_double),
         ("cg_resid", ctypes.c_double),
+        ("t_ns", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -63,6 +64,7 @@ class SolveInfo(ctypes.Structure):
         ("rel_err_core", ctypes.c_double),
         ("rel_err_full", ctypes.c_double),
         ("t_norm", ctypes.c_double),
+        ("time_to_tol_ns", ctypes.c_int64),
     ]
 
 

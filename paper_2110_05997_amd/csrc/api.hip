@@ -382,7 +382,9 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   }
   cpd_status st;
   const int64_t n = dims[0] * dims[1] * dims[2];
-  if ((st = sumsq_full(T, dtype, n, chk, (int*)(chk + 1), sws, sumsq_ws_bytes(), s))) return st;
+  // the solve's device entry stamp goes next to the final residual (read back with it)
+  long long* t_entry = (long long*)(res + 1);
+  if ((st = sumsq_full(T, dtype, n, chk, (int*)(chk + 1), sws, sumsq_ws_bytes(), s, t_entry))) return st;
   // ||T||^2 and the non-finite flag come back with the eigenvalues (one host round trip)
   double h_tn2 = 0.0;
   int core[3];
@@ -415,8 +417,10 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   CPD_HIP_CHECK(hipMemcpyAsync(hb, res, hbytes, hipMemcpyDeviceToHost, s));
   CPD_HIP_CHECK(hipStreamSynchronize(s));
   double h_res;
+  long long h_entry;
   Hdr h;
   memcpy(&h_res, hb, sizeof(double));
+  memcpy(&h_entry, hb + sizeof(double), sizeof(long long));
   memcpy(&h, hb + 256, sizeof(Hdr));
   if (h.flags & 1) {
     set_error("state_init: non-finite initial factors");
@@ -431,6 +435,7 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   info->rel_err_core = err;
   info->t_norm = sqrt(h_tn2);
   info->rel_err_full = sqrt(h_res > 0.0 ? h_res : 0.0) / sqrt(h_tn2);
+  info->time_to_tol_ns = (ti > 0) ? (int64_t)llround((double)(h.t_tol - h_entry) * wall_ns_per_tick()) : -1;
   return CPD_OK;
 }
 }  // namespace

@@ -280,7 +280,7 @@ __global__ __launch_bounds__(PROJ_NT) void batch_project_kernel(const BItem* __r
 // ---- 5. uncompression, residual, normalisation --------------------------------------------------
 template <class TT>
 __global__ __launch_bounds__(FIN_NT) void batch_finish_kernel(const BItem* __restrict__ items, int n,
-                                                              int maxiter) {
+                                                              int maxiter, double ns_per_tick) {
   __shared__ double red[2][FIN_NT / 64];
   __shared__ double nrm[3][64];
   __shared__ double sgn[2][64];
@@ -384,6 +384,8 @@ __global__ __launch_bounds__(FIN_NT) void batch_finish_kernel(const BItem* __res
     inf->iters = h->k;
     inf->stop_reason = skipped ? -1 : h->stop;
     inf->tol_iter = h->tol_iter;
+    // per member: from its dGN start to its first iteration below tol (members run side by side)
+    inf->time_to_tol_ns = (!skipped && h->tol_iter > 0) ? llround((double)(h->t_tol - h->t_init) * ns_per_tick) : -1;
     inf->rel_err_core = skipped ? NAN : errs[h->k];
     const double tn = inf->t_norm;
     inf->rel_err_full = (tn > 0.0) ? sqrt(fmax(res, 0.0)) / tn : 0.0;
@@ -511,6 +513,7 @@ struct Launch {
   int n, dtype, variant, maxiter;
   size_t lds;
   SetupArgs setup;
+  double ns_per_tick;
 };
 
 cpd_status launch_gram(const Launch& L, hipStream_t s) {
@@ -532,9 +535,9 @@ cpd_status launch_all(const Launch& L, hipStream_t s) {
   CPD_LAUNCH_CHECK();
   if ((st = dgn_batch_launch(L.states, L.S, L.n, L.lds, s))) return st;
   if (L.dtype == CPD_F64)
-    hipLaunchKernelGGL(batch_finish_kernel<double>, dim3(L.n), dim3(FIN_NT), 0, s, L.items, L.n, L.maxiter);
+    hipLaunchKernelGGL(batch_finish_kernel<double>, dim3(L.n), dim3(FIN_NT), 0, s, L.items, L.n, L.maxiter, L.ns_per_tick);
   else
-    hipLaunchKernelGGL(batch_finish_kernel<float>, dim3(L.n), dim3(FIN_NT), 0, s, L.items, L.n, L.maxiter);
+    hipLaunchKernelGGL(batch_finish_kernel<float>, dim3(L.n), dim3(FIN_NT), 0, s, L.items, L.n, L.maxiter, L.ns_per_tick);
   CPD_LAUNCH_CHECK();
   return CPD_OK;
 }
@@ -582,6 +585,7 @@ cpd_status prepare(const cpd_batch_item* items, int n, int dtype, const cpd_para
   L.dtype = dtype;
   L.variant = 0;
   L.maxiter = p->maxiter;
+  L.ns_per_tick = wall_ns_per_tick();
   L.lds = lds;
   L.setup.caps = dc;
   L.setup.maxiter = p->maxiter;

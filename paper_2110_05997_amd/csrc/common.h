@@ -157,8 +157,11 @@ size_t sumsq_ws_bytes();
 cpd_status residual_full(const void* T, int dtype, const int64_t dims[3],
                          const double* const W[3], int R, double* out, void* ws, size_t ws_bytes,
                          hipStream_t s);
+// stamp (device, nullable): receives the device wall clock when the kernel starts.
 cpd_status sumsq_full(const void* T, int dtype, int64_t n, double* out, int* nonfinite, void* ws,
-                      size_t ws_bytes, hipStream_t s);
+                      size_t ws_bytes, hipStream_t s, long long* stamp = nullptr);
+// Nanoseconds per tick of the device wall clock (wall_clock64) of the current device.
+double wall_ns_per_tick();
 
 // dGN.
 size_t state_bytes(const int32_t core[3], int R, int maxiter);

@@ -473,6 +473,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
       h->tol_iter = -1;
       h->stop = (nb > 0.0) ? -1 : CPD_STOP_NONE;
       h->flags = (nb > 0.0) ? 1 : 0;
+      h->t_init = wall_clock64();
     }
     return;
   }
@@ -576,11 +577,14 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
       errs[k] = err;
       const int st = stop_test(errs, k, stepn, grad_inf, tol, maxiter, div_ref);
       s_stop = st;
+      const long long now = wall_clock64();
       cpd_step_info inf;
       inf.k = k; inf.cg_iters = its; inf.cg_cap = cap; inf.stop = st;
       inf.rel_err = err; inf.step_norm = stepn; inf.grad_inf = grad_inf; inf.gain = g;
       inf.mu = mu_new; inf.cg_resid = rr;
+      inf.t_ns = now - h->t_init;   // ticks here; the host converts to ns
       logp[k - 1] = inf;
+      if (tol_iter < 0 && err < tol) h->t_tol = now;
     }
     __syncthreads();
     stop = s_stop;
@@ -644,12 +648,17 @@ __global__ void dgn_tail_kernel(char* __restrict__ state) {
   const double mu_new = (g < 0.25) ? 3.0 * mu : ((g > 0.75) ? mu / 3.0 : mu);
   errs[k] = err;
   const int st = stop_test(errs, k, h->stepn, h->grad_inf, h->tol, h->maxiter, h->div_ref);
+  const long long now = wall_clock64();
   cpd_step_info inf;
   inf.k = k; inf.cg_iters = h->its; inf.cg_cap = h->cap; inf.stop = st;
   inf.rel_err = err; inf.step_norm = h->stepn; inf.grad_inf = h->grad_inf; inf.gain = g;
   inf.mu = mu_new; inf.cg_resid = h->cg_resid;
+  inf.t_ns = now - h->t_init;   // ticks here; the host converts to ns
   logp[k - 1] = inf;
-  if (h->tol_iter < 0 && err < h->tol) h->tol_iter = k;
+  if (h->tol_iter < 0 && err < h->tol) {
+    h->tol_iter = k;
+    h->t_tol = now;
+  }
   h->mu = mu_new;
   h->f2 = f2_new;
   h->stop = st;
@@ -665,6 +674,7 @@ __global__ void dgn_init_tail_kernel(char* __restrict__ state) {
   h->f2 = h->f2_new;
   h->err0 = (h->s_norm > 0.0) ? sqrt(h->f2_new) / h->s_norm : 0.0;
   errs[0] = h->err0;
+  h->t_init = wall_clock64();
 }
 
 // Batched: workgroup b initialises state b (header, caps and W already written) and iterates it
@@ -1107,6 +1117,8 @@ cpd_status state_log(void* state, int first, int count, cpd_step_info* out, hipS
     CPD_HIP_CHECK(hipMemcpyAsync(out, (char*)state + Lo.log + sizeof(cpd_step_info) * first,
                                  sizeof(cpd_step_info) * count, hipMemcpyDeviceToHost, s));
     CPD_HIP_CHECK(hipStreamSynchronize(s));
+    const double f = wall_ns_per_tick();
+    for (int i = 0; i < count; ++i) out[i].t_ns = (int64_t)llround((double)out[i].t_ns * f);
   }
   return CPD_OK;
 }

@@ -21,6 +21,9 @@ struct Hdr {
   // one iteration split over launches (large cores): values of the step awaiting its residual
   double f2_pred, stepn, grad_inf, cg_resid, f2_new;
   int32_t its, cap, pending, pad2;
+  // device wall-clock ticks (constant-rate counter): end of initialisation, and the end of the
+  // first iteration whose error fell below tol (valid when tol_iter > 0)
+  int64_t t_init, t_tol;
 };
 static_assert(sizeof(Hdr) <= 256, "header must fit its slot");
 

@@ -39,13 +39,21 @@ struct DirectArgs {
   int n, P;
   double *V, *lall, *U, *lam;
 };
-struct DirectSet {
-  DirectArgs p[3];
-};
 
-__global__ __launch_bounds__(JNT) void direct_kernel(const DirectSet set) {
+// The problem descriptors of a multi-problem launch live in a small workspace array (one slot per
+// problem); put_args_kernel writes them in stream order from three separate by-value arguments
+// (fixed indices only), and each workgroup of the solver then reads slot blockIdx.x from global
+// memory.
+template <class A>
+__global__ void put_args_kernel(const A a0, const A a1, const A a2, int nprob, A* __restrict__ out) {
+  if (threadIdx.x == 0 && nprob > 0) out[0] = a0;
+  if (threadIdx.x == 1 && nprob > 1) out[1] = a1;
+  if (threadIdx.x == 2 && nprob > 2) out[2] = a2;
+}
+
+__global__ __launch_bounds__(JNT) void direct_kernel(const DirectArgs* __restrict__ set) {
   __shared__ JacobiLds L;
-  const DirectArgs& a = set.p[blockIdx.x];
+  const DirectArgs a = set[blockIdx.x];
   const int n = a.n, P = a.P;
   const double* __restrict__ V = a.V;
   double* __restrict__ U = a.U;
@@ -541,14 +549,11 @@ struct SubspaceArgs {
   uint64_t seed;
   double *U, *lam;
 };
-// Up to three problems per launch, one workgroup each (the modes of one tensor).
-struct SubspaceSet {
-  SubspaceArgs p[3];
-};
-
-__global__ __launch_bounds__(FNT) void subspace_kernel(const SubspaceSet set) {
+// Up to three problems per launch, one workgroup each (the modes of one tensor); descriptors in a
+// workspace array written by put_args_kernel.
+__global__ __launch_bounds__(FNT) void subspace_kernel(const SubspaceArgs* __restrict__ set) {
   __shared__ FusedLds S;
-  const SubspaceArgs& a = set.p[blockIdx.x];
+  const SubspaceArgs a = set[blockIdx.x];
   const double* __restrict__ G = a.G;
   const int n = a.n, P = a.P, k = a.k;
   const uint64_t seed = a.seed;
@@ -641,9 +646,30 @@ struct SubProblem {
   double *V, *lall;                                              // direct (n <= 64)
   double *Q, *Z, *Y, *Qt, *B, *Vb, *Ri, *Dv, *theta, *Uw, *ratio;   // subspace iteration
   int* flags;
+  SubspaceArgs* desc;   // this problem's descriptor slot (single-problem launches)
   uint64_t seed;
   double r_host;
 };
+
+// Descriptor slots of one eigensolver call: NSIDE of the larger descriptor type, carved first.
+union EigDesc {
+  DirectArgs d;
+  SubspaceArgs s;
+};
+constexpr int NSIDE = 3;
+template <class Carver>
+EigDesc* carve_desc(Carver& ar) { return ar.template take<EigDesc>(NSIDE); }
+
+// Writes up to three descriptors into `out` on stream s.
+template <class A>
+cpd_status put_args(const A* a, int nprob, A* out, hipStream_t s) {
+  A z[3];
+  memset((void*)z, 0, sizeof(z));
+  for (int i = 0; i < nprob; ++i) z[i] = a[i];
+  hipLaunchKernelGGL(put_args_kernel<A>, dim3(1), dim3(64), 0, s, z[0], z[1], z[2], nprob, out);
+  CPD_LAUNCH_CHECK();
+  return CPD_OK;
+}
 
 bool sp_fused(const SubProblem& q) { return !q.direct && q.n <= FUSED_NMAX; }
 
@@ -740,10 +766,10 @@ cpd_status sp_start_phase(SubProblem& q, int ph, hipStream_t s) {
   const int n = q.n, k = q.k;
   if (n <= FUSED_NMAX) {
     if (ph != 0) return CPD_OK;
-    SubspaceSet set;
-    memset(&set, 0, sizeof(set));
-    set.p[0] = subspace_args(q);
-    hipLaunchKernelGGL(subspace_kernel, dim3(1), dim3(FNT), 0, s, set);
+    const SubspaceArgs a = subspace_args(q);
+    cpd_status st;
+    if ((st = put_args(&a, 1, q.desc, s))) return st;
+    hipLaunchKernelGGL(subspace_kernel, dim3(1), dim3(FNT), 0, s, (const SubspaceArgs*)q.desc);
     CPD_LAUNCH_CHECK();
     q.done = true;
     return CPD_OK;
@@ -785,7 +811,6 @@ cpd_status sp_continue(SubProblem& q, hipStream_t s) {
 
 // Streams (default priority) and events for running up to three problems side by side; created
 // once per host thread.
-constexpr int NSIDE = 3;
 struct SideStreams {
   hipStream_t st[NSIDE];
   hipEvent_t fork, join[NSIDE];
@@ -818,6 +843,7 @@ cpd_status eig_top(const double* G, int n, int P, double* U, double* lam, void* 
   SubProblem q;
   sp_describe(q, G, n, P, U, lam);
   Arena ar(ws, ws_bytes);
+  q.desc = &carve_desc(ar)[0].s;
   sp_carve(ar, q);
   if ((st = sp_start(q, s))) return st;
   while (!q.done) {
@@ -831,6 +857,7 @@ size_t eig_ws_bytes(int n, int P) {
   SubProblem q;
   sp_describe(q, nullptr, n, P, nullptr, nullptr);
   Sizer z;
+  carve_desc(z);
   sp_carve(z, q);
   return z.off;
 }
@@ -839,6 +866,7 @@ size_t eig_ws_bytes(int n, int P) {
 // single-workgroup kernels execute concurrently; one host loop advances them all.
 size_t eig_ws_bytes3(const int* n, const int* P, int nprob) {
   Sizer z;
+  carve_desc(z);
   for (int i = 0; i < nprob; ++i) {
     SubProblem q;
     sp_describe(q, nullptr, n[i], P[i], nullptr, nullptr);
@@ -862,8 +890,10 @@ cpd_status eig_top3(const double* const* G, const int* n, const int* P, double* 
   }
   SubProblem q[NSIDE];
   Arena ar(ws, ws_bytes);
+  EigDesc* desc = carve_desc(ar);
   for (int i = 0; i < nprob; ++i) {
     sp_describe(q[i], G[i], n[i], P[i], U[i], lam[i]);
+    q[i].desc = &desc[i].s;
     sp_carve(ar, q[i]);
   }
   // every problem small enough for the direct solve, or every one on the one-workgroup subspace
@@ -874,18 +904,21 @@ cpd_status eig_top3(const double* const* G, const int* n, const int* P, double* 
     all_direct = all_direct && q[i].direct;
   }
   if (all_direct) {
-    DirectSet set;
-    memset(&set, 0, sizeof(set));
-    for (int i = 0; i < nprob; ++i) set.p[i] = {q[i].G, q[i].n, q[i].P, q[i].V, q[i].lall, q[i].U, q[i].lam};
-    hipLaunchKernelGGL(direct_kernel, dim3(nprob), dim3(JNT), 0, s, set);
+    // contiguous DirectArgs array at the start of the descriptor block
+    DirectArgs a[NSIDE];
+    for (int i = 0; i < nprob; ++i) a[i] = {q[i].G, q[i].n, q[i].P, q[i].V, q[i].lall, q[i].U, q[i].lam};
+    DirectArgs* dev = reinterpret_cast<DirectArgs*>(desc);
+    if ((st = put_args(a, nprob, dev, s))) return st;
+    hipLaunchKernelGGL(direct_kernel, dim3(nprob), dim3(JNT), 0, s, (const DirectArgs*)dev);
     CPD_LAUNCH_CHECK();
     return CPD_OK;
   }
   if (all_fused) {
-    SubspaceSet set;
-    memset(&set, 0, sizeof(set));
-    for (int i = 0; i < nprob; ++i) set.p[i] = subspace_args(q[i]);
-    hipLaunchKernelGGL(subspace_kernel, dim3(nprob), dim3(FNT), 0, s, set);
+    SubspaceArgs a[NSIDE];
+    for (int i = 0; i < nprob; ++i) a[i] = subspace_args(q[i]);
+    SubspaceArgs* dev = reinterpret_cast<SubspaceArgs*>(desc);
+    if ((st = put_args(a, nprob, dev, s))) return st;
+    hipLaunchKernelGGL(subspace_kernel, dim3(nprob), dim3(FNT), 0, s, (const SubspaceArgs*)dev);
     CPD_LAUNCH_CHECK();
     return CPD_OK;
   }

@@ -86,8 +86,11 @@ void launch_residual(const T* X, int I1, int I2, int I3, const double* const W[3
 
 template <class T>
 __global__ __launch_bounds__(RNT) void sumsq_kernel(const T* __restrict__ X, long long n,
-                                                    double* __restrict__ part, double* __restrict__ badp) {
+                                                    double* __restrict__ part, double* __restrict__ badp,
+                                                    long long* __restrict__ stamp) {
   __shared__ double slots[2][RNT / 64];
+  // the first kernel of a solve: its start is the solve's device entry time
+  if (stamp != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *stamp = wall_clock64();
   double acc = 0.0, nf = 0.0;
   for (long long e = (long long)blockIdx.x * RNT + threadIdx.x; e < n; e += (long long)gridDim.x * RNT) {
     const double v = ldv(X, e);
@@ -246,7 +249,7 @@ cpd_status residual_full(const void* T, int dtype, const int64_t dims[3], const 
 }
 
 cpd_status sumsq_full(const void* T, int dtype, int64_t n, double* out, int* nonfinite, void* ws,
-                      size_t ws_bytes, hipStream_t s) {
+                      size_t ws_bytes, hipStream_t s, long long* stamp) {
   if (!ws || ws_bytes < sumsq_ws_bytes()) {
     set_error("sumsq_full: workspace too small");
     return CPD_E_WORKSPACE;
@@ -255,13 +258,13 @@ cpd_status sumsq_full(const void* T, int dtype, int64_t n, double* out, int* non
   double* bad = (double*)((char*)ws + align_up(RB * sizeof(double), 256));
   switch (dtype) {
     case CPD_F64:
-      hipLaunchKernelGGL(sumsq_kernel<double>, dim3(RB), dim3(RNT), 0, s, (const double*)T, (long long)n, part, bad);
+      hipLaunchKernelGGL(sumsq_kernel<double>, dim3(RB), dim3(RNT), 0, s, (const double*)T, (long long)n, part, bad, stamp);
       break;
     case CPD_F32:
-      hipLaunchKernelGGL(sumsq_kernel<float>, dim3(RB), dim3(RNT), 0, s, (const float*)T, (long long)n, part, bad);
+      hipLaunchKernelGGL(sumsq_kernel<float>, dim3(RB), dim3(RNT), 0, s, (const float*)T, (long long)n, part, bad, stamp);
       break;
     case CPD_BF16:
-      hipLaunchKernelGGL(sumsq_kernel<uint16_t>, dim3(RB), dim3(RNT), 0, s, (const uint16_t*)T, (long long)n, part, bad);
+      hipLaunchKernelGGL(sumsq_kernel<uint16_t>, dim3(RB), dim3(RNT), 0, s, (const uint16_t*)T, (long long)n, part, bad, stamp);
       break;
     default:
       set_error("sumsq_full: bad dtype");

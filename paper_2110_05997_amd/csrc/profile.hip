@@ -26,6 +26,20 @@ double g_ms[CPD_PK_COUNT];
 
 }  // namespace
 
+double wall_ns_per_tick() {
+  static thread_local int dev_cached = -1;
+  static thread_local double f = 10.0;   // 100 MHz, replaced by the device's reported rate
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return f;
+  if (dev != dev_cached) {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+      f = 1e6 / (double)khz;
+    dev_cached = dev;
+  }
+  return f;
+}
+
 void prof_begin(int which, hipStream_t s) {
   if (!g_on || !((g_mask >> which) & 1u)) return;
   Pending p{which, nullptr, nullptr, false};

@@ -399,3 +399,92 @@ def test_output_normalization():
             assert Wn[l][np.argmax(np.abs(Wn[l][:, r])), r] > 0
     rec = ml.cpd_full([Wn[0] * lam[None, :], Wn[1], Wn[2]])
     np.testing.assert_allclose(rec, ml.cpd_full(Ws), rtol=1e-12, atol=1e-12)
+
+
+def test_initial_damping_is_tau_times_mean_abs_core():
+    """ch.4 "Main parameters": mu0 = tau * E(|S|), the mean of the core's entries in absolute value
+    (not tau * max_i a_ii of the damped Gauss-Newton section, not the mean of S, not max |S|).
+    Hand-written 2x2x2 core: sum |s| = 1+2+...+8 = 36, mean 4.5; tau = 2 gives 9 exactly."""
+    S = np.array([[[1.0, -2.0], [3.0, -4.0]], [[5.0, -6.0], [7.0, -8.0]]])
+    W0 = [np.eye(2), np.eye(2), np.eye(2)]
+    st = dgn.init_state(S, W0, dgn.Params(init_damp=2.0))
+    assert st.mu == 9.0
+    st1 = dgn.init_state(S, W0, dgn.Params())          # tau = 1 is the thesis default
+    assert st1.mu == 4.5
+    # a start whose J^T J diagonal is not 1 leaves mu0 unchanged (it depends on S only)
+    st2 = dgn.init_state(S, [3.0 * np.eye(2), np.eye(2), np.eye(2)], dgn.Params())
+    assert st2.mu == 4.5
+
+
+def test_divergence_threshold_uses_max_one_and_tensor_norm_squared():
+    """ch.4 "Stopping conditions", rule 7: stop when the relative error exceeds
+    max{1, ||T||^2} / (1e-16 + tol).  The reference value is ||T||^2 of the input tensor (passed
+    in by the driver), not ||S||^2 and not ||T||; below 1 it is clamped to 1."""
+    S = np.array([[[1.0, -2.0], [3.0, -4.0]], [[5.0, -6.0], [7.0, -8.0]]])
+    W0 = [np.eye(2), np.eye(2), np.eye(2)]
+    p = dgn.Params()
+    assert dgn.init_state(S, W0, p, tnorm2=16.0).div_ref == 16.0
+    assert dgn.init_state(S, W0, p, tnorm2=0.25).div_ref == 1.0
+    assert dgn.init_state(S, W0, p).div_ref == pytest.approx(204.0, rel=1e-15)   # no T given: ||S||^2 = 204
+    # literal threshold with ||T||^2 = 16 and tol = 1e-6: 16 / (1e-16 + 1e-6)
+    thr = 16.0 / (1e-16 + 1e-6)
+    assert scripted_stop([1.0, thr * (1 + 1e-12)], div_ref=16.0) == dgn.STOP_DIVERGED
+    assert scripted_stop([1.0, thr * (1 - 1e-12)], div_ref=16.0) == dgn.STOP_NONE
+    # with ||T|| = 4 (not squared) the threshold would be 4e6; an error of 5e6 must not stop
+    assert scripted_stop([1.0, 5e6], div_ref=16.0) == dgn.STOP_NONE
+
+
+def test_windowed_rules_compare_disjoint_batches_of_c():
+    """ch.4 "Stopping conditions", rules 5 and 6 are checked every c iterations and compare "the
+    average of a batch with the next one"; the printed sums run over c + 1 indices that share the
+    endpoint k0 - c while dividing by c.  Reading kept: two disjoint batches of c errors,
+    err[k-2c+1..k-c] and err[k-c+1..k].  The sequence below separates the readings: the two batches
+    hold the same values (rule 5 fires), while the literal sums also take err[k-2c] into the old
+    batch and err[k-c] into the new one, which differ by 0.6, so the literal averages differ by
+    0.6/c and rule 5 would not fire."""
+    maxiter = 200
+    c = dgn.window_c(maxiter)
+    k = 3 * c
+    errs = [1.0] + [0.2 + 0.01 * (j % c) for j in range(1, k + 1)]   # sawtooth of period c
+    errs[k - 2 * c] = 0.8                                            # outside both kept batches
+    old = errs[k - 2 * c + 1:k - c + 1]
+    new = errs[k - c + 1:k + 1]
+    assert len(old) == len(new) == c and sorted(old) == sorted(new)
+    literal_old = sum(errs[k - 2 * c:k - c + 1]) / c
+    literal_new = sum(errs[k - c:k + 1]) / c
+    assert literal_old - literal_new > 0.6 / c - 1e-12
+    assert scripted_stop(errs, maxiter=maxiter) == dgn.STOP_AVG_ERR
+    # a lower new batch (mean 0.05 below the old one) keeps going
+    errs2 = errs[:k - c + 1] + [e - 0.05 for e in new]
+    assert scripted_stop(errs2, maxiter=maxiter) == dgn.STOP_NONE
+
+
+def test_fixed_cg_cap_replaces_random_schedule():
+    """cg_fixed > 0 (ch.4 "Conditioning": a large fixed cg_maxiter for hard tensors) sets the
+    CG cap of every iteration; with cg_tol = 0 every iteration runs exactly that many CG
+    iterations, and no uniforms are needed.  With the cap at n_p the step is the exact solution of
+    the damped normal equations (CG finite termination), checked against a dense Cholesky solve."""
+    T, _, _ = synth.planted((6, 5, 4), 3, seed=7, noise_rel=1e-2)
+    S = np.asarray(T)
+    W0 = synth.init_factors(S.shape, 3, 7)
+    p = dgn.Params(maxiter=6, cg_fixed=3, cg_tol=0.0)
+    st, infos = dgn.run_dgn(S, W0, p)
+    assert len(infos) == 6 and all(i["cg_iters"] == 3 for i in infos)
+    # exact step with cap = n_p
+    n_p = 3 * (6 + 5 + 4)
+    p2 = dgn.Params(maxiter=1, cg_fixed=n_p, cg_tol=0.0)
+    st0 = dgn.init_state(S, W0, p2)
+    Ws = st0.Ws
+    pis = dgn.grams(Ws)
+    grad = dgn.gradient(S, Ws, pis)
+    gam = dgn.regularization(Ws)
+    J = explicit_jacobian(Ws)
+    D = np.concatenate([np.repeat(g, W.shape[0]) for g, W in zip(gam, Ws)])   # column-stacked blocks
+    A = J.T @ J + st0.mu * np.diag(D)
+    x_ref = np.linalg.solve(A, -vec_blocks(grad))
+    st1, info = dgn.dgn_step(S, st0, p2, n_p)
+    # the step is w1 - w0 before balancing; recover it from the logged norm and the direction
+    M = dgn.preconditioner(pis, gam, st0.mu)
+    x, its, _ = dgn.pcg(Ws, pis, gam, st0.mu, [-g for g in grad], M, n_p, 0.0)
+    assert np.max(np.abs(vec_blocks(x) - x_ref)) < 1e-8 * np.max(np.abs(x_ref))
+    assert abs(info["step_norm"] - np.linalg.norm(x_ref)) < 1e-8 * np.linalg.norm(x_ref)
