@@ -115,7 +115,9 @@ def test_batch_graph_replays_bit_exact(members):
         float((x * x).sum())
         infos = plan.run()
         for j in range(len(idx)):
-            assert infos[j] == ref_infos[j]
+            # everything but the device time (wall-clock stamps differ run to run)
+            strip = lambda d: {k: v for k, v in d.items() if k != "time_to_tol_ns"}
+            assert strip(infos[j]) == strip(ref_infos[j])
             got = [host(w) for w in plan.W[j]] + [host(plan.lam[j])]
             for a, b in zip(got, ref_W[j]):
                 assert np.array_equal(a, b)
