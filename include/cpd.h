@@ -298,6 +298,16 @@ cpd_status cpd_residual_norm2(const void* T, int32_t dtype, const int64_t dims[3
                               const double* const W[3], int32_t R, double* out, void* ws,
                               size_t ws_bytes, void* stream);
 
+/* cpd_residual_norm2 for callers that cannot allocate or pass a workspace (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): same arguments and result, minus
+ * ws.  Its scratch (the per-block partial sums) is a static device array of 64 KiB per GPU, held
+ * until the process ends; the device address is looked up once per device on the first call made
+ * with that device current.  Calls that overlap on one GPU (several streams or threads) race on
+ * that scratch and must be serialised by the caller.  Returns CPD_E_UNSUPPORTED if the partial
+ * sums would exceed the scratch (they never do for dims <= 4096); calls no allocating routine. */
+cpd_status cpd_residual_norm2_noalloc(const void* T, int32_t dtype, const int64_t dims[3],
+                                      const double* const W[3], int32_t R, double* out, void* stream);
+
 /* out[l] (device, dims[l] x R) = block l of J^T J v (ch.3 Thm Hv) for factors W[l] and direction
  * V[l] (device, dims[l] x R each).  One workgroup; dims[l] <= 4096, R <= 64. */
 cpd_status cpd_jtj_v(const double* const W[3], const double* const V[3], const int32_t dims[3],

@@ -506,6 +506,12 @@ cpd_status cpd_residual_norm2(const void* T, int32_t dtype, const int64_t dims[3
   return residual_full(T, dtype, dims, W, R, out, ws, ws_bytes, (hipStream_t)stream);
 }
 
+cpd_status cpd_residual_norm2_noalloc(const void* T, int32_t dtype, const int64_t dims[3],
+                                      const double* const W[3], int32_t R, double* out, void* stream) {
+  CPD_REQUIRE(T && W && out && dims_ok(dims) && dtype_ok(dtype), "cpd_residual_norm2_noalloc: bad arguments");
+  return residual_full_noalloc(T, dtype, dims, W, R, out, (hipStream_t)stream);
+}
+
 cpd_status cpd_jtj_v(const double* const W[3], const double* const V[3], const int32_t dims[3],
                      int32_t R, double* const out[3], void* stream) {
   CPD_REQUIRE(W && V && dims && out, "cpd_jtj_v: null argument");

@@ -157,6 +157,10 @@ size_t sumsq_ws_bytes();
 cpd_status residual_full(const void* T, int dtype, const int64_t dims[3],
                          const double* const W[3], int R, double* out, void* ws, size_t ws_bytes,
                          hipStream_t s);
+// The same with its partial sums in the library's static device scratch (no workspace, no
+// allocation; calls that overlap on one GPU race on that scratch).
+cpd_status residual_full_noalloc(const void* T, int dtype, const int64_t dims[3], const double* const W[3],
+                                 int R, double* out, hipStream_t s);
 // stamp (device, nullable): receives the device wall clock when the kernel starts.
 cpd_status sumsq_full(const void* T, int dtype, int64_t n, double* out, int* nonfinite, void* ws,
                       size_t ws_bytes, hipStream_t s, long long* stamp = nullptr);

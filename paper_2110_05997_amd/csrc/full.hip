@@ -6,6 +6,8 @@
 // Reductions go through per-block partials summed in a fixed order (bit-reproducible).
 #include "common.h"
 
+#include <mutex>
+
 namespace cpd {
 namespace {
 
@@ -214,19 +216,13 @@ size_t residual_ws_bytes(const int64_t dims[3]) {
 
 size_t sumsq_ws_bytes() { return 2 * align_up(RB * sizeof(double), 256); }
 
-cpd_status residual_full(const void* T, int dtype, const int64_t dims[3], const double* const W[3],
-                         int R, double* out, void* ws, size_t ws_bytes, hipStream_t s) {
-  if (R < 1 || R > 64 || !T || !out || !W[0] || !W[1] || !W[2]) {
-    set_error("residual_full: bad arguments");
-    return CPD_E_INVALID;
-  }
-  if (!ws || ws_bytes < residual_ws_bytes(dims)) {
-    set_error("residual_full: workspace too small");
-    return CPD_E_WORKSPACE;
-  }
-  double* part = (double*)ws;
+namespace {
+// The two launches of the fused residual: per-block partials in `part` (RB doubles), then their sum
+// in a fixed order into *out.  Arguments already checked.
+cpd_status residual_launch(const void* T, int dtype, const int64_t dims[3], const double* const W[3], int R,
+                           double* out, double* part, hipStream_t s, bool timed) {
   const int I1 = (int)dims[0], I2 = (int)dims[1], I3 = (int)dims[2];
-  prof_begin(CPD_PK_RESIDUAL, s);
+  if (timed) prof_begin(CPD_PK_RESIDUAL, s);
   switch (dtype) {
     case CPD_F64:
       launch_residual((const double*)T, I1, I2, I3, W, R, part, s);
@@ -241,11 +237,82 @@ cpd_status residual_full(const void* T, int dtype, const int64_t dims[3], const 
       set_error("residual_full: bad dtype");
       return CPD_E_INVALID;
   }
-  prof_end(CPD_PK_RESIDUAL, s);
+  if (timed) prof_end(CPD_PK_RESIDUAL, s);
   CPD_LAUNCH_CHECK();
   hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(RNT), 0, s, part, RB, out);
   CPD_LAUNCH_CHECK();
   return CPD_OK;
+}
+
+bool residual_args_ok(const void* T, int dtype, const double* const W[3], int R, const double* out) {
+  if (R < 1 || R > 64 || !T || !out || !W[0] || !W[1] || !W[2]) {
+    set_error("residual_full: bad arguments");
+    return false;
+  }
+  if (dtype != CPD_F64 && dtype != CPD_F32 && dtype != CPD_BF16) {
+    set_error("residual_full: bad dtype");
+    return false;
+  }
+  return true;
+}
+
+// Scratch of the allocation-free residual (cpd_residual_norm2_noalloc): the per-block partial sums.
+// One copy per GPU, held until the process ends; every call on a GPU shares it.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 64 * 1024;
+__device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+// Device address of `scratch` on each GPU, looked up once per device with that device current (in
+// host code the array's name is only a stand-in for the symbol).
+constexpr int NOALLOC_MAX_DEVICES = 64;
+char* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+std::mutex g_scratch_mu;
+
+cpd_status scratch_address(char** out) {
+  int dev = 0;
+  CPD_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+    set_error("residual_norm2_noalloc: device %d beyond %d", dev, NOALLOC_MAX_DEVICES);
+    return CPD_E_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      set_error("residual_norm2_noalloc: hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+      return CPD_E_HIP;
+    }
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CPD_OK;
+}
+}  // namespace
+
+cpd_status residual_full(const void* T, int dtype, const int64_t dims[3], const double* const W[3],
+                         int R, double* out, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (!residual_args_ok(T, dtype, W, R, out)) return CPD_E_INVALID;
+  if (!ws || ws_bytes < residual_ws_bytes(dims)) {
+    set_error("residual_full: workspace too small");
+    return CPD_E_WORKSPACE;
+  }
+  return residual_launch(T, dtype, dims, W, R, out, (double*)ws, s, true);
+}
+
+cpd_status residual_full_noalloc(const void* T, int dtype, const int64_t dims[3], const double* const W[3],
+                                 int R, double* out, hipStream_t s) {
+  if (!residual_args_ok(T, dtype, W, R, out)) return CPD_E_INVALID;
+  const size_t need = residual_ws_bytes(dims);
+  if (need > NOALLOC_SCRATCH_BYTES) {
+    set_error("residual_norm2_noalloc: needs %zu scratch bytes, the static buffer holds %zu", need,
+              NOALLOC_SCRATCH_BYTES);
+    return CPD_E_UNSUPPORTED;
+  }
+  char* sp = nullptr;
+  cpd_status st = scratch_address(&sp);
+  if (st) return st;
+  // every partial is written by the first launch before the second reads it: nothing to clear
+  return residual_launch(T, dtype, dims, W, R, out, (double*)sp, s, false);
 }
 
 cpd_status sumsq_full(const void* T, int dtype, int64_t n, double* out, int* nonfinite, void* ws,
