@@ -82,6 +82,10 @@ typedef struct {
   int32_t compute_dtype;    /* precision of the compression Grams for FP32/FP64 input:
                                CPD_F64 (default, FP64 accumulation) or CPD_BF16 (BF16 MFMA with
                                FP32 accumulation; the core is still projected from the input) */
+  int32_t st_mlsvd;         /* nonzero: sequentially truncated compression (ch.2 Alg. ST-MLSVD):
+                               mode l's Gram, eigenvectors and truncation are taken on the tensor
+                               already projected in modes 1..l-1; default 0 (the classic truncated
+                               MLSVD of ch.4 Alg. Compression) */
 } cpd_params;
 
 /* Fills the thesis's defaults (maxiter 200, tol 1e-6, mlsvd_tol 1e-6, tau 1, random CG cap). */
@@ -384,6 +388,13 @@ void cpd_profile_select(uint32_t mask);
 void cpd_profile_reset(void);
 /* Waits for the recorded events, then fills out[CPD_PK_COUNT]. */
 cpd_status cpd_profile_read(cpd_kernel_time* out);
+
+/* Measured floor of the one-workgroup reductions: one workgroup of `nthreads` (a multiple of 64,
+ * <= 1024) chains `reps` block sums (wavefront shuffle, one barrier, one LDS round trip each) timed
+ * with the device wall clock; *ns_out (host) receives ns per block sum.  ws: 16 device bytes.
+ * Synchronises the stream. */
+cpd_status cpd_profile_block_sum_ns(int32_t nthreads, int32_t reps, void* ws, size_t ws_bytes, double* ns_out,
+                                    void* stream);
 
 #ifdef __cplusplus
 }

@@ -12,7 +12,7 @@ into the last mode, and terms are sorted by decreasing lambda.
 import numpy as np
 
 from . import dgn as _dgn
-from .mlsvd import compress, smart_init
+from .mlsvd import compress, compress_st, smart_init
 from .multilinear import cpd_full, frob
 
 
@@ -42,18 +42,20 @@ def normalize_output(Ws):
     return [W[:, order] for W in Ws], lam[order]
 
 
-def solve(T, R, params=None, init="random", W0=None, cg_uniforms=None, core_dims=None, log=None):
+def solve(T, R, params=None, init="random", W0=None, cg_uniforms=None, core_dims=None, log=None, st_mlsvd=False):
     """Full CPD of a third-order tensor.
 
     ``init``: "random" or "given" (W0 must hold R~_l x R matrices, drawn by
     the caller so that the GPU path can be fed the same numbers) or "mlsvd"
     (the MLSVD-energy initialisation).  ``cg_uniforms``: one uniform draw in
-    [0, 1) per dGN iteration, mapped to the random CG cap.
+    [0, 1) per dGN iteration, mapped to the random CG cap.  ``st_mlsvd``: compress with the
+    sequentially truncated MLSVD (ch.2 Alg. ST-MLSVD) instead of the classic one.
     """
     if params is None:
         params = _dgn.Params()
     T = np.asarray(T, dtype=np.float64)
-    Us, sigmas, S = compress(T, R, params.mlsvd_tol, core_dims=core_dims)
+    comp = compress_st if st_mlsvd else compress
+    Us, sigmas, S = comp(T, R, params.mlsvd_tol, core_dims=core_dims)
     core = S.shape
     if init == "mlsvd":
         Ws0 = smart_init(S, R, extra=W0)

@@ -1,7 +1,7 @@
 """Truncated MLSVD compression and the MLSVD-based initialisation (oracle; test infrastructure only).
 
 Restates ch.2 "Multilinear singular value decomposition" (Thm MLSVD,
-Alg. MLSVD, the truncation bound), the Gram-eigenvector route of App. B
+Alg. MLSVD, the truncation bound, Alg. ST-MLSVD), the Gram-eigenvector route of App. B
 (lemma relating the SVD of M to the eigendecomposition of M M^T) and ch.4
 section "Compression" (Alg. Compression, P_l = min(I_l, R)) and section
 "Initialization".
@@ -16,7 +16,7 @@ Readings taken where the thesis is silent (each listed in the design doc):
 """
 import numpy as np
 
-from .multilinear import unfold, multilinear, cpd_full, frob
+from .multilinear import unfold, multilinear, mode_product, cpd_full, frob
 
 
 def canonical_signs(U):
@@ -87,6 +87,27 @@ def compress(T, R, mlsvd_tol=1e-6, core_dims=None, route="svd"):
         ranks = list(core_dims)
     Us = [U[:, :r] for U, r in zip(Us, ranks)]
     S = multilinear(T, [U.T for U in Us])
+    return Us, sigmas, S
+
+
+def compress_st(T, R, mlsvd_tol=1e-6, core_dims=None):
+    """Sequentially truncated MLSVD (ch.2 Alg. ST-MLSVD, the variant Tensor Fox can switch to):
+    S^(0) = T; for l = 1..L the leading left singular vectors of the mode-l unfolding of the current
+    S^(l-1) (P_l = min(I_l, R) of them, signs canonical), the truncation rule of Alg. Compression on
+    those singular values, and S^(l) = S^(l-1) x_l U^(l)T, so each later mode works on the shrunk
+    tensor.  Returns ``(U, sigma, S)`` as ``compress``; sigma^(l) are the singular values of the
+    unfolding of S^(l-1)."""
+    S = np.asarray(T, dtype=np.float64)
+    L = S.ndim
+    Us, sigmas = [], []
+    for l in range(L):
+        P = min(S.shape[l], R) if core_dims is None else core_dims[l]
+        U, sg = left_singular_svd(S, l, P)
+        r = truncation_rank(sg, mlsvd_tol, L) if core_dims is None else core_dims[l]
+        U = U[:, :r]
+        Us.append(U)
+        sigmas.append(sg)
+        S = mode_product(S, U.T, l)
     return Us, sigmas, S
 
 

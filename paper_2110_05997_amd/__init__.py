@@ -48,7 +48,7 @@ def _ws(nbytes, device):
 
 
 def params(maxiter=200, tol=1e-6, mlsvd_tol=1e-6, init_damp=1.0, cg_tol=0.0, cg_fixed=0,
-           cg_uniforms=None, seed=0, init="random", core_dims=None, compute_dtype=CPD_F64):
+           cg_uniforms=None, seed=0, init="random", core_dims=None, compute_dtype=CPD_F64, st_mlsvd=False):
     """Build a cpd_params struct (defaults are the thesis's).  ``cg_uniforms`` (host floats) must
     outlive the call that uses the struct; it is kept on the returned object."""
     p = Params()
@@ -59,6 +59,7 @@ def params(maxiter=200, tol=1e-6, mlsvd_tol=1e-6, init_damp=1.0, cg_tol=0.0, cg_
     if core_dims is not None:
         p.core_dims = (ctypes.c_int32 * 3)(*core_dims)
     p.compute_dtype = int(compute_dtype)
+    p.st_mlsvd = 1 if st_mlsvd else 0
     if cg_uniforms is not None:
         arr = (ctypes.c_double * len(cg_uniforms))(*[float(u) for u in cg_uniforms])
         if len(cg_uniforms) < maxiter:
@@ -349,6 +350,15 @@ def profile_enable(on=True, kernels=None):
     mask = 0xFFFFFFFF if kernels is None else sum(1 << _lib.PROFILE_KERNELS.index(k) for k in kernels)
     L.cpd_profile_select(mask)
     L.cpd_profile_enable(1 if on else 0)
+
+
+def block_sum_ns(nthreads=512, reps=20000):
+    """Device time of one block-wide sum (one barrier + LDS round trip) in a workgroup of nthreads."""
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    out = ctypes.c_double()
+    _lib.check(_lib.lib().cpd_profile_block_sum_ns(nthreads, reps, _ptr(ws), 16, ctypes.byref(out), _stream()),
+               "cpd_profile_block_sum_ns")
+    return out.value
 
 
 def profile_reset():

@@ -33,6 +33,7 @@ class Params(ctypes.Structure):
         ("init", ctypes.c_int32),
         ("core_dims", ctypes.c_int32 * 3),
         ("compute_dtype", ctypes.c_int32),
+        ("st_mlsvd", ctypes.c_int32),
     ]
 
 
@@ -160,6 +161,8 @@ SIGNATURES = [
     ("cpd_profile_select", None, [ctypes.c_uint32]),
     ("cpd_profile_reset", None, []),
     ("cpd_profile_read", ctypes.c_int, [ctypes.POINTER(KernelTime)]),
+    ("cpd_profile_block_sum_ns", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t,
+                                                ctypes.POINTER(ctypes.c_double), _P]),
 ]
 
 _lib = None

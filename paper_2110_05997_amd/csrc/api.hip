@@ -59,11 +59,16 @@ struct CompressWs {
 
 void compress_sizes(const int64_t dims[3], const int P[3], Sizer& z) {
   size_t gram = 0;
+  const int64_t d2[3] = {P[0], dims[1], dims[2]}, d3[3] = {P[0], P[1], dims[2]};
   for (int l = 0; l < 3; ++l) {
     z.take<double>((size_t)(dims[l] * dims[l]));         // G_l
     size_t g = gram_ws_bytes(dims, l);
     gram = gram > g ? gram : g;
   }
+  // the sequentially truncated variant's Grams of the projected tensors
+  const size_t g2 = gram_ws_bytes(d2, 1), g3 = gram_ws_bytes(d3, 2);
+  gram = gram > g2 ? gram : g2;
+  gram = gram > g3 ? gram : g3;
   const int n[3] = {(int)dims[0], (int)dims[1], (int)dims[2]};
   z.take<char>(gram);                                    // gram partials
   z.take<char>(eig_ws_bytes3(n, P, 3));                  // eigensolver
@@ -91,6 +96,32 @@ char* readback_host(size_t bytes, std::vector<char>& spill) {
   if (buf && bytes <= READBACK_BYTES) return buf;
   spill.resize(bytes);
   return spill.data();
+}
+
+// The three mode products of the core projection S = T x1 U1^T x2 U2^T x3 U3^T.
+// Y1[a][i2 i3] = sum_i1 U1[i1][a] T[i1][i2 i3] (T in its own dtype)
+cpd_status project_mode1(const void* T, int dtype, int I1, int I2, int I3, const double* U1, int r1, double* Y1,
+                         hipStream_t s) {
+  cpd_status st;
+  prof_begin(CPD_PK_PROJECT, s);
+  if (mode_product_mid_fits(I1, r1))
+    st = mode_product_mid(T, dtype, 1, I1, (long long)I2 * I3, U1, r1, Y1, s);
+  else
+    st = gemm_f64(r1, I2 * I3, I1, 1.0, U1, r1, 0, true, T, dtype, (long long)I2 * I3, 0, false, 0.0, Y1,
+                  (long long)I2 * I3, 0, 1, s);
+  prof_end(CPD_PK_PROJECT, s);
+  return st;
+}
+// Y2[a][b][i3] = sum_i2 U2[i2][b] Y1[a][i2][i3]
+cpd_status project_mode2(const double* Y1, int r1, int I2, int I3, const double* U2, int r2, double* Y2,
+                         hipStream_t s) {
+  if (mode_product_mid_fits(I2, r2)) return mode_product_mid(Y1, CPD_F64, r1, I2, I3, U2, r2, Y2, s);
+  return gemm_f64(r2, I3, I2, 1.0, U2, r2, 0, true, Y1, CPD_F64, I3, (long long)I2 * I3, false, 0.0, Y2, I3,
+                  (long long)r2 * I3, r1, s);
+}
+// S[ab][c] = sum_i3 Y2[ab][i3] U3[i3][c]
+cpd_status project_mode3(const double* Y2, int r12, int I3, const double* U3, int r3, double* S, hipStream_t s) {
+  return gemm_f64(r12, r3, I3, 1.0, Y2, I3, 0, false, U3, CPD_F64, r3, 0, false, 0.0, S, r3, 0, 1, s);
 }
 
 // Runs compression with carved workspace; outputs U (compact I_l x R~_l), sigma, S.
@@ -195,25 +226,111 @@ cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_d
   }
   // S = T x1 U1^T x2 U2^T x3 U3^T
   const int I1 = (int)dims[0], I2 = (int)dims[1], I3 = (int)dims[2];
-  const int r1 = rk[0], r2 = rk[1], r3 = rk[2];
-  // Y1[a][i2 i3] = sum_i1 U1[i1][a] T[i1][i2 i3]; Y2[a][b][i3] = sum_i2 U2[i2][b] Y1[a][i2][i3]
-  prof_begin(CPD_PK_PROJECT, s);
-  if (mode_product_mid_fits(I1, r1))
-    st = mode_product_mid(T, dtype, 1, I1, (long long)I2 * I3, U_out[0], r1, Y1, s);
-  else
-    st = gemm_f64(r1, I2 * I3, I1, 1.0, U_out[0], r1, 0, true, T, dtype, (long long)I2 * I3, 0, false, 0.0, Y1,
-                  (long long)I2 * I3, 0, 1, s);
-  prof_end(CPD_PK_PROJECT, s);
-  if (st) return st;
-  if (mode_product_mid_fits(I2, r2))
-    st = mode_product_mid(Y1, CPD_F64, r1, I2, I3, U_out[1], r2, Y2, s);
-  else
-    st = gemm_f64(r2, I3, I2, 1.0, U_out[1], r2, 0, true, Y1, CPD_F64, I3, (long long)I2 * I3, false, 0.0, Y2, I3,
-                  (long long)r2 * I3, r1, s);
-  if (st) return st;
-  if ((st = gemm_f64(r1 * r2, r3, I3, 1.0, Y2, I3, 0, false, U_out[2], CPD_F64, r3, 0, false, 0.0, S_out,
-                     r3, 0, 1, s)))
-    return st;
+  if ((st = project_mode1(T, dtype, I1, I2, I3, U_out[0], rk[0], Y1, s))) return st;
+  if ((st = project_mode2(Y1, rk[0], I2, I3, U_out[1], rk[1], Y2, s))) return st;
+  if ((st = project_mode3(Y2, rk[0] * rk[1], I3, U_out[2], rk[2], S_out, s))) return st;
+  for (int l = 0; l < 3; ++l) core_out[l] = rk[l];
+  return CPD_OK;
+}
+
+// Sequentially truncated compression (ch.2 Alg. ST-MLSVD): mode l's Gram, eigenvectors and
+// truncation are taken on the tensor already projected in the modes before it, Y1 = T x1 U1^T and
+// Y2 = Y1 x2 U2^T, so the second and third Grams read R~1 I2 I3 and R~1 R~2 I3 entries instead of
+// I1 I2 I3.  Same outputs, workspace and read-back conventions as run_compress (the eigenvalues of
+// mode 1 come back with the input checks; modes 2 and 3 take one read-back each).
+cpd_status run_compress_st(const void* T, int dtype, const void* T_gram, int gram_dtype, int gram_compute,
+                           const int64_t dims[3], int R, const cpd_params* p,
+                           double* const U_out[3], double* const sigma_out[3], double* S_out,
+                           int core_out[3], Arena& ar, hipStream_t s, double* chk = nullptr,
+                           double* h_tn2 = nullptr) {
+  int P[3];
+  pdims(dims, R, p, P);
+  for (int l = 0; l < 3; ++l) {
+    if (P[l] < 1 || P[l] > dims[l]) {
+      set_error("compress: core dim %d invalid for mode %d of size %lld", P[l], l, (long long)dims[l]);
+      return CPD_E_INVALID;
+    }
+    if (dims[l] > 64 && P[l] > 56) {
+      set_error("compress: P=%d > 56 for mode size %lld > 64 is not supported", P[l], (long long)dims[l]);
+      return CPD_E_UNSUPPORTED;
+    }
+  }
+  const int I1 = (int)dims[0], I2 = (int)dims[1], I3 = (int)dims[2];
+  const int64_t d1[3] = {dims[0], dims[1], dims[2]};
+  const int64_t d2[3] = {P[0], dims[1], dims[2]};           // Y1 (at most P1 rows)
+  const int64_t d3[3] = {P[0], P[1], dims[2]};              // Y2
+  size_t gram_b = gram_ws_bytes(d1, 0);
+  const size_t g2 = gram_ws_bytes(d2, 1), g3 = gram_ws_bytes(d3, 2);
+  gram_b = gram_b > g2 ? gram_b : g2;
+  gram_b = gram_b > g3 ? gram_b : g3;
+  const int n[3] = {I1, I2, I3};
+  const size_t eig_b = eig_ws_bytes3(n, P, 3);
+  double* G[3];
+  for (int l = 0; l < 3; ++l) G[l] = ar.take<double>((size_t)(dims[l] * dims[l]));
+  char* gws = ar.take<char>(gram_b);
+  char* ews = ar.take<char>(eig_b);
+  double* Uf[3];
+  for (int l = 0; l < 3; ++l) Uf[l] = ar.take<double>((size_t)dims[l] * P[l]);
+  double* lam = ar.take<double>(P[0] + P[1] + P[2]);
+  if (chk) lam = chk + 2;
+  double* Y1 = ar.take<double>((size_t)P[0] * dims[1] * dims[2]);
+  double* Y2 = ar.take<double>((size_t)P[0] * P[1] * dims[2]);
+  if (!Y2) {
+    set_error("compress: workspace too small (%zu bytes)", ar.cap);
+    return CPD_E_WORKSPACE;
+  }
+  const bool fixed = p && p->core_dims[0] > 0 && p->core_dims[1] > 0 && p->core_dims[2] > 0;
+  const double mtol = p ? p->mlsvd_tol : 1e-6;
+  std::vector<char> spill;
+  double* hbuf = (double*)readback_host(sizeof(double) * (P[0] + P[1] + P[2] + 2), spill);
+  double* laml[3] = {lam, lam + P[0], lam + P[0] + P[1]};
+  int rk[3];
+  cpd_status st;
+  for (int l = 0; l < 3; ++l) {
+    // the tensor this mode's Gram reads: T, then Y1 (rk[0] x I2 x I3), then Y2 (rk[0] x rk[1] x I3)
+    if (l == 0) {
+      if ((st = gram(T_gram, gram_dtype, dims, 0, gram_compute, G[0], gws, gram_b, s))) return st;
+    } else if (l == 1) {
+      const int64_t dy[3] = {rk[0], dims[1], dims[2]};
+      if ((st = gram(Y1, CPD_F64, dy, 1, CPD_F64, G[1], gws, gram_b, s))) return st;
+    } else {
+      const int64_t dy[3] = {rk[0], rk[1], dims[2]};
+      if ((st = gram(Y2, CPD_F64, dy, 2, CPD_F64, G[2], gws, gram_b, s))) return st;
+    }
+    prof_begin(CPD_PK_EIG, s);
+    st = eig_top(G[l], n[l], P[l], U_out[l], laml[l], ews, eig_b, s);
+    prof_end(CPD_PK_EIG, s);
+    if (st) return st;
+    // eigenvalues of this mode (and, for mode 1 of a solve, the input checks in front of them)
+    const int h0 = (l == 0 && chk) ? 0 : 2;
+    const double* src = (l == 0 && chk) ? chk : laml[l];
+    CPD_HIP_CHECK(hipMemcpyAsync(hbuf + h0, src, sizeof(double) * (P[l] + 2 - h0), hipMemcpyDeviceToHost, s));
+    CPD_HIP_CHECK(hipStreamSynchronize(s));
+    if (l == 0 && chk) {
+      const double c_tn2 = hbuf[0];
+      int c_bad = 0;
+      memcpy(&c_bad, &hbuf[1], sizeof(int));
+      if (c_bad) { set_error("cpd_solve: non-finite entries in T"); return CPD_E_NONFINITE; }
+      if (!(c_tn2 > 0.0)) { set_error("cpd_solve: ||T|| = 0"); return CPD_E_ZERO_TENSOR; }
+      if (h_tn2) *h_tn2 = c_tn2;
+    }
+    rk[l] = fixed ? P[l] : truncation_rank(hbuf + 2, P[l], mtol);
+    if (sigma_out && sigma_out[l]) {
+      std::vector<double> tmpv(P[l]);
+      for (int r = 0; r < P[l]; ++r) tmpv[r] = sqrt(hbuf[2 + r] > 0.0 ? hbuf[2 + r] : 0.0);
+      CPD_HIP_CHECK(hipMemcpyAsync(sigma_out[l], tmpv.data(), sizeof(double) * P[l], hipMemcpyHostToDevice, s));
+      CPD_HIP_CHECK(hipStreamSynchronize(s));
+    }
+    if (rk[l] != P[l]) {
+      CPD_HIP_CHECK(hipMemcpy2DAsync(Uf[l], sizeof(double) * rk[l], U_out[l], sizeof(double) * P[l],
+                                     sizeof(double) * rk[l], dims[l], hipMemcpyDeviceToDevice, s));
+      CPD_HIP_CHECK(hipMemcpyAsync(U_out[l], Uf[l], sizeof(double) * rk[l] * dims[l], hipMemcpyDeviceToDevice, s));
+    }
+    if (l == 0) st = project_mode1(T, dtype, I1, I2, I3, U_out[0], rk[0], Y1, s);
+    else if (l == 1) st = project_mode2(Y1, rk[0], I2, I3, U_out[1], rk[1], Y2, s);
+    else st = project_mode3(Y2, rk[0] * rk[1], I3, U_out[2], rk[2], S_out, s);
+    if (st) return st;
+  }
   for (int l = 0; l < 3; ++l) core_out[l] = rk[l];
   return CPD_OK;
 }
@@ -280,8 +397,11 @@ cpd_status cpd_compress(const void* T, int32_t dtype, const int64_t dims[3], int
   if (!p) { cpd_default_params(&def); p = &def; }
   Arena ar(ws, ws_bytes);
   int core[3];
-  cpd_status st = run_compress(T, dtype, T, dtype, p->compute_dtype, dims, R, p, U_out, sigma_out, S_out, core, ar,
-                               (hipStream_t)stream);
+  cpd_status st = p->st_mlsvd
+                      ? run_compress_st(T, dtype, T, dtype, p->compute_dtype, dims, R, p, U_out, sigma_out, S_out,
+                                        core, ar, (hipStream_t)stream)
+                      : run_compress(T, dtype, T, dtype, p->compute_dtype, dims, R, p, U_out, sigma_out, S_out, core,
+                                     ar, (hipStream_t)stream);
   if (st) return st;
   CPD_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
   for (int l = 0; l < 3; ++l) core_dims_out[l] = core[l];
@@ -388,9 +508,11 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   // ||T||^2 and the non-finite flag come back with the eigenvalues (one host round trip)
   double h_tn2 = 0.0;
   int core[3];
-  if ((st = run_compress(T, dtype, T_gram, gram_dtype, gram_compute, dims, R, p, U, nullptr, S, core, ar, s, chk,
-                         &h_tn2)))
-    return st;
+  st = p->st_mlsvd ? run_compress_st(T, dtype, T_gram, gram_dtype, gram_compute, dims, R, p, U, nullptr, S, core, ar,
+                                     s, chk, &h_tn2)
+                   : run_compress(T, dtype, T_gram, gram_dtype, gram_compute, dims, R, p, U, nullptr, S, core, ar, s,
+                                  chk, &h_tn2);
+  if (st) return st;
   // the header and CG caps go to the device as kernel arguments: no host synchronisation here
   if ((st = state_init(state, S, core, R, W0, h_tn2, p, s, false))) return st;
   if ((st = dgn_iterate_known(state, S, core, R, p->maxiter, s))) return st;

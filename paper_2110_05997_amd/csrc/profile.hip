@@ -26,6 +26,24 @@ double g_ms[CPD_PK_COUNT];
 
 }  // namespace
 
+// One workgroup of `blockDim.x` threads chaining `reps` block sums (one barrier and one LDS round
+// trip each, alternating two slot arrays as the dGN kernel does): the floor under every reduction
+// of the one-workgroup dGN.
+__global__ __launch_bounds__(1024) void block_sum_probe_kernel(int reps, long long* __restrict__ ticks,
+                                                               double* __restrict__ sink) {
+  __shared__ double slots[2][16];
+  double v = (double)threadIdx.x;
+  __syncthreads();
+  const long long t0 = wall_clock64();
+  for (int i = 0; i < reps; ++i) v = block_sum(v * 1e-3, slots[i & 1]);
+  __syncthreads();
+  const long long t1 = wall_clock64();
+  if (threadIdx.x == 0) {
+    ticks[0] = t1 - t0;
+    sink[0] = v;
+  }
+}
+
 double wall_ns_per_tick() {
   static thread_local int dev_cached = -1;
   static thread_local double f = 10.0;   // 100 MHz, replaced by the device's reported rate
@@ -67,6 +85,23 @@ using namespace cpd;
 extern "C" {
 
 void cpd_profile_enable(int32_t on) { g_on = (on != 0); }
+
+cpd_status cpd_profile_block_sum_ns(int32_t nthreads, int32_t reps, void* ws, size_t ws_bytes, double* ns_out,
+                                    void* stream) {
+  CPD_REQUIRE(ws && ws_bytes >= 16 && ns_out && reps >= 1 && nthreads >= 64 && nthreads <= 1024 &&
+                  nthreads % 64 == 0,
+              "cpd_profile_block_sum_ns: bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  long long* ticks = (long long*)ws;
+  double* sink = (double*)((char*)ws + 8);
+  hipLaunchKernelGGL(block_sum_probe_kernel, dim3(1), dim3(nthreads), 0, s, reps, ticks, sink);
+  CPD_LAUNCH_CHECK();
+  long long h = 0;
+  CPD_HIP_CHECK(hipMemcpyAsync(&h, ticks, sizeof(h), hipMemcpyDeviceToHost, s));
+  CPD_HIP_CHECK(hipStreamSynchronize(s));
+  *ns_out = (double)h * wall_ns_per_tick() / (double)reps;
+  return CPD_OK;
+}
 
 void cpd_profile_select(uint32_t mask) { g_mask = mask; }
 

@@ -532,20 +532,58 @@ def test_solve_mixed_bf16_grams_vs_oracle():
     assert dT < 2.0 ** -8
 
 
-def test_solve_mixed_600cube_reaches_noise_floor():
-    """The 600^3 workload (R = 50, N(0,1) factors, 60 dB) through the BF16-Gram path. The full-tensor
-    error sits at the noise floor 1e-3 (a planted CPD is fitted to within the noise), checked against
-    the FP32 tensor the path reads. Starting point: device N(0,1) init with seed 1; from seed 0 the
-    dGN stops in a swamp near 0.2."""
-    log("solve mixed 600^3")
-    T, _, _ = synth.config3()
-    Td = dev(T, torch.float32)
-    del T
-    Tlo = Td.to(torch.bfloat16).contiguous()
-    res = cp().solve_mixed(Tlo, Td, 50, cp().params(cg_uniforms=synth.cg_uniforms(200, 0), seed=1))
+# ---------------------------------------------------------------------------------------------
+# Sequentially truncated compression (ch.2 Alg. ST-MLSVD)
+@pytest.mark.parametrize("case", ["planted_f64", "planted_f32", "config1", "truncated", "gemm_projection"])
+def test_compress_st_matches_oracle(case):
+    log("compress st", case)
+    if case == "planted_f64":
+        T, _, _ = synth.planted((40, 35, 30), 4, seed=3, noise_rel=1e-3)
+        R, dt = 4, torch.float64
+    elif case == "planted_f32":
+        T, _, _ = synth.planted((96, 80, 70), 6, seed=4, noise_rel=1e-2, dtype=np.float32)
+        R, dt = 6, torch.float32
+    elif case == "config1":
+        T, _, _ = synth.config1()
+        R, dt = 5, torch.float64
+    elif case == "truncated":
+        T, _, _ = synth.planted((30, 25, 20), 3, seed=5, noise_rel=0.0)
+        R, dt = 6, torch.float64
+    else:
+        T, _, _ = synth.planted((240, 230, 30), 20, seed=11, noise_rel=1e-3, dtype=np.float32)
+        R, dt = 20, torch.float32
+    Td = dev(T, dt)
+    p = cp().params(st_mlsvd=True)
+    Us, sg, S, core = cp().compress(Td, R, p)
+    Uo, so, So = omlsvd.compress_st(host(Td), R)
+    assert core == So.shape
+    for l in range(3):
+        assert np.max(np.abs(host(Us[l]) - Uo[l])) < 1e-10
+        c = core[l]
+        assert relmax(host(sg[l])[:c], so[l][:c]) < 1e-10
+    assert relmax(host(S), So) < 1e-10
+
+
+@pytest.mark.parametrize("case", ["config1", "planted_small"])
+def test_solve_st_matches_oracle(case):
+    log("solve st", case)
+    if case == "config1":
+        T, _, _ = synth.config1()
+        R, seed = 5, 0
+    else:
+        T, _, _ = synth.planted((23, 31, 17), 4, seed=5, noise_rel=1e-5)
+        R, seed = 4, 5
+    Td = dev(T)
+    U = synth.cg_uniforms(200, seed)
+    _, _, So = omlsvd.compress_st(T, R)
+    W0 = synth.init_factors(So.shape, R, seed)
+    ref = ocpd.solve(T, R, odgn.Params(), W0=W0, cg_uniforms=U, st_mlsvd=True)
+    res = cp().solve(Td, R, cp().params(cg_uniforms=U, st_mlsvd=True), W0=[dev(w) for w in W0])
     info = res["info"]
-    log("mixed 600^3", info)
-    assert tuple(info["core_dims"]) == (50, 50, 50)
-    assert 1 <= info["stop_reason"] <= 8
-    floor = 10 ** (-60 / 20)
-    assert info["rel_err_full"] < 1.05 * floor
+    log(info, "oracle", ref["iters"], ref["stop"])
+    assert tuple(info["core_dims"]) == ref["core_dims"]
+    That = reconstruct(res)
+    Tref = ml.cpd_full(ref["W_unnormalized"])
+    assert ml.frob(That - Tref) / ml.frob(Tref) < 1e-6
+    assert info["stop_reason"] == ref["stop"]
+    assert abs(info["iters"] - ref["iters"]) <= 1

@@ -186,3 +186,65 @@ def test_canonical_signs():
     np.testing.assert_array_equal(V[:, 0], -U[:, 0])
     # tie on |.|: the lowest index decides (-0.9 at row 0) -> flipped
     np.testing.assert_array_equal(V[:, 1], -U[:, 1])
+
+
+# ---------------------------------------------------------------------------------------------
+# Sequentially truncated MLSVD (ch.2 Alg. ST-MLSVD)
+def test_st_mlsvd_untruncated_equals_mlsvd():
+    """Without truncation every U^(l) is square orthogonal, and multiplying an unfolding on the right
+    by an orthogonal matrix keeps its left singular vectors and values: ST-MLSVD then equals the
+    MLSVD of Thm MLSVD (bases, singular values and core)."""
+    rng = np.random.default_rng(21)
+    T = rng.standard_normal((5, 4, 3))
+    Uc, sc, Sc = mlsvd.full_mlsvd(T)
+    Us, ss, Ss = mlsvd.compress_st(T, 5, core_dims=(5, 4, 3))
+    for l in range(3):
+        assert np.allclose(Us[l], Uc[l], atol=1e-12)
+        assert np.allclose(ss[l], sc[l], rtol=1e-12)
+    assert np.allclose(Ss, Sc, atol=1e-12)
+
+
+def test_st_mlsvd_recovers_exact_multilinear_rank():
+    """A tensor of multilinear rank (3, 4, 2) (random Tucker core, orthonormal bases): the truncation
+    rule keeps exactly (3, 4, 2) and the sequential truncation reconstructs T to rounding; its bases
+    span the same subspaces as the classic compression's."""
+    rng = np.random.default_rng(22)
+    G = rng.standard_normal((3, 4, 2))
+    Qs = [np.linalg.qr(rng.standard_normal((d, r)))[0] for d, r in zip((10, 9, 8), (3, 4, 2))]
+    T = ml.multilinear(G, Qs)
+    Us, _, S = mlsvd.compress_st(T, 4)
+    assert S.shape == (3, 4, 2)
+    That = ml.multilinear(S, Us)
+    assert ml.frob(T - That) < 1e-13 * ml.frob(T)
+    Uc, _, _ = mlsvd.compress(T, 4)
+    for l in range(3):
+        # equal subspaces: the projector difference vanishes
+        assert np.max(np.abs(Us[l] @ Us[l].T - Uc[l] @ Uc[l].T)) < 1e-12
+
+
+def test_st_mlsvd_error_within_truncation_bound_and_last_mode_orthogonal():
+    """ST-MLSVD satisfies the truncation bound of ch.2 (Thm energy-mlsvd, the sum of the discarded
+    squared singular values of the classic unfoldings), and its last core unfolding has orthogonal
+    rows whose norms are the last mode's singular values (S_(3) = U^(3)T S^(2)_(3))."""
+    T, _, _ = synth.planted((14, 12, 10), 6, seed=23, noise_rel=0.05)
+    core = (4, 5, 3)
+    Us, ss, S = mlsvd.compress_st(T, 6, core_dims=core)
+    err2 = ml.frob(T - ml.multilinear(S, Us)) ** 2
+    _, sc, _ = mlsvd.full_mlsvd(T)
+    bound = sum(float(np.sum(sc[l][core[l]:] ** 2)) for l in range(3))
+    assert err2 <= bound * (1 + 1e-12)
+    S3 = ml.unfold(S, 2)
+    Gm = S3 @ S3.T
+    assert np.allclose(Gm, np.diag(ss[2][:core[2]] ** 2), atol=1e-10 * Gm.max())
+
+
+def test_st_mlsvd_truncation_rule_on_planted_tensor():
+    """Noisy planted rank-4 tensor, R = 4: the sequential and classic compressions keep the same core
+    size, their bases agree to the noise level and the cores have equal norm within it."""
+    T, _, _ = synth.planted((20, 18, 16), 4, seed=24, noise_rel=1e-8)
+    Us, _, S = mlsvd.compress_st(T, 4)
+    Uc, _, Sc = mlsvd.compress(T, 4)
+    assert S.shape == Sc.shape == (4, 4, 4)
+    for l in range(3):
+        assert np.max(np.abs(Us[l] @ Us[l].T - Uc[l] @ Uc[l].T)) < 1e-6
+    assert abs(ml.frob(S) - ml.frob(Sc)) < 1e-6 * ml.frob(Sc)
