@@ -82,6 +82,10 @@ typedef struct {
   int32_t compute_dtype;    /* precision of the compression Grams for FP32/FP64 input:
                                CPD_F64 (default, FP64 accumulation) or CPD_BF16 (BF16 MFMA with
                                FP32 accumulation; the core is still projected from the input) */
+  int32_t refine_iters;     /* > 0: after uncompression, up to this many further dGN iterations on
+                               T itself (refinement in the original space, ch.4 benchmarks),
+                               continuing the compressed run's damping parameter and CG-cap schedule;
+                               the stopping rules apply with errors relative to ||T||.  Default 0 */
   int32_t st_mlsvd;         /* nonzero: sequentially truncated compression (ch.2 Alg. ST-MLSVD):
                                mode l's Gram, eigenvectors and truncation are taken on the tensor
                                already projected in modes 1..l-1; default 0 (the classic truncated
@@ -115,6 +119,8 @@ typedef struct {
   double rel_err_core;     /* final ||S - S_k|| / ||S|| */
   double rel_err_full;     /* ||T - sum_r lambda_r w_r^(1) o w_r^(2) o w_r^(3)|| / ||T|| */
   double t_norm;           /* ||T|| */
+  int32_t refine_iters;    /* refinement iterations performed (cpd_params.refine_iters) */
+  int32_t refine_stop;     /* cpd_stop of the refinement (0 if none ran) */
   int64_t time_to_tol_ns;  /* device time from the call's first kernel (T resident, compression
                               included) to the end of iteration tol_iter, from in-kernel
                               wall-clock stamps; -1 if the error never fell below tol.  Batched

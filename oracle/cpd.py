@@ -42,7 +42,39 @@ def normalize_output(Ws):
     return [W[:, order] for W in Ws], lam[order]
 
 
-def solve(T, R, params=None, init="random", W0=None, cg_uniforms=None, core_dims=None, log=None, st_mlsvd=False):
+def refine(T, Wt, params, mu, k0, n_iters, cg_uniforms=None, tnorm2=None):
+    """Refinement in the original space (the option ch.4 describes for Tensorlab and Tensor Fox:
+    the compressed solution, uncompressed, starts iterations on T itself).  Reading: n_iters further
+    iterations of the same dGN (oracle.dgn.dgn_step with T in place of the core), continuing the
+    damping parameter mu and the iteration counter of the compressed run, so iteration j takes the
+    CG cap of iteration k0 + j of the schedule (a fixed cap if params.cg_fixed); the stopping rules
+    run with maxiter = n_iters and errors relative to ||T||.  Since W~^(l)T W~^(l) = W^(l)T W^(l)
+    for orthonormal U^(l), the Grams, Pi, D and the preconditioner continue unchanged."""
+    T = np.asarray(T, dtype=np.float64)
+    p = _dgn.Params(maxiter=n_iters, tol=params.tol, mlsvd_tol=params.mlsvd_tol, init_damp=params.init_damp,
+                    cg_tol=params.cg_tol, cg_fixed=params.cg_fixed)
+    Ws = _dgn.norm_balance(Wt)
+    f = _dgn.residual(T, Ws)
+    f2 = float(np.sum(f * f))
+    t_norm = float(np.sqrt(np.sum(T * T)))
+    if tnorm2 is None:
+        tnorm2 = t_norm ** 2
+    st = _dgn.State(Ws=Ws, mu=mu, k=0, f2=f2, s_norm=t_norm, div_ref=max(1.0, tnorm2),
+                    errs=[np.sqrt(f2) / t_norm])
+    infos = []
+    while st.stop == _dgn.STOP_NONE:
+        k = k0 + st.k + 1
+        if p.cg_fixed > 0:
+            cap = p.cg_fixed
+        else:
+            cap = _dgn.cg_cap(k, cg_uniforms[min(k, len(cg_uniforms)) - 1])
+        st, info = _dgn.dgn_step(T, st, p, cap)
+        infos.append(info)
+    return st, infos
+
+
+def solve(T, R, params=None, init="random", W0=None, cg_uniforms=None, core_dims=None, log=None, st_mlsvd=False,
+          refine_iters=0):
     """Full CPD of a third-order tensor.
 
     ``init``: "random" or "given" (W0 must hold R~_l x R matrices, drawn by
@@ -68,12 +100,17 @@ def solve(T, R, params=None, init="random", W0=None, cg_uniforms=None, core_dims
     tn2 = float(np.sum(T * T))
     st, infos = _dgn.run_dgn(S, Ws0, params, cg_uniforms=cg_uniforms, tnorm2=tn2, log=log)
     Wt = uncompress(Us, st.Ws)
+    ref_st, ref_infos = None, []
+    if refine_iters > 0:
+        ref_st, ref_infos = refine(T, Wt, params, st.mu, st.k, refine_iters, cg_uniforms, tn2)
+        Wt = ref_st.Ws
     Wn, lam = normalize_output(Wt)
     that = cpd_full(Wt)
     return dict(U=Us, sigma=sigmas, S=S, core_dims=core, W_core=st.Ws, W=Wn, lam=lam,
                 W_unnormalized=Wt, iters=st.k, stop=st.stop, errs=st.errs, infos=infos,
                 rel_err_core=st.errs[-1], rel_err_full=frob(T - that) / frob(T),
-                mu=st.mu)
+                mu=st.mu, refine_iters=len(ref_infos), refine_infos=ref_infos,
+                refine_stop=ref_st.stop if ref_st is not None else 0)
 
 
 def time_to_tol_iter(errs, tol):

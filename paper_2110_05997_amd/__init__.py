@@ -48,7 +48,8 @@ def _ws(nbytes, device):
 
 
 def params(maxiter=200, tol=1e-6, mlsvd_tol=1e-6, init_damp=1.0, cg_tol=0.0, cg_fixed=0,
-           cg_uniforms=None, seed=0, init="random", core_dims=None, compute_dtype=CPD_F64, st_mlsvd=False):
+           cg_uniforms=None, seed=0, init="random", core_dims=None, compute_dtype=CPD_F64, st_mlsvd=False,
+           refine_iters=0):
     """Build a cpd_params struct (defaults are the thesis's).  ``cg_uniforms`` (host floats) must
     outlive the call that uses the struct; it is kept on the returned object."""
     p = Params()
@@ -60,6 +61,7 @@ def params(maxiter=200, tol=1e-6, mlsvd_tol=1e-6, init_damp=1.0, cg_tol=0.0, cg_
         p.core_dims = (ctypes.c_int32 * 3)(*core_dims)
     p.compute_dtype = int(compute_dtype)
     p.st_mlsvd = 1 if st_mlsvd else 0
+    p.refine_iters = int(refine_iters)
     if cg_uniforms is not None:
         arr = (ctypes.c_double * len(cg_uniforms))(*[float(u) for u in cg_uniforms])
         if len(cg_uniforms) < maxiter:

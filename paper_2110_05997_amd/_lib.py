@@ -33,6 +33,7 @@ class Params(ctypes.Structure):
         ("init", ctypes.c_int32),
         ("core_dims", ctypes.c_int32 * 3),
         ("compute_dtype", ctypes.c_int32),
+        ("refine_iters", ctypes.c_int32),
         ("st_mlsvd", ctypes.c_int32),
     ]
 
@@ -65,6 +66,8 @@ class SolveInfo(ctypes.Structure):
         ("rel_err_core", ctypes.c_double),
         ("rel_err_full", ctypes.c_double),
         ("t_norm", ctypes.c_double),
+        ("refine_iters", ctypes.c_int32),
+        ("refine_stop", ctypes.c_int32),
         ("time_to_tol_ns", ctypes.c_int64),
     ]
 

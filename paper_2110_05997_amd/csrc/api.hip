@@ -351,6 +351,7 @@ size_t solve_ws(const int64_t dims[3], int R, const cpd_params* p) {
   for (int l = 0; l < 3; ++l) z.take<double>((size_t)dims[l] * R);       // uncompressed
   z.take<char>(normalize_ws_bytes(R));
   z.take<char>(residual_ws_bytes(dims));
+  if (p && p->refine_iters > 0) z.take<char>(refine_state_bytes(dims, R, p->refine_iters));
   Sizer zc;
   compress_sizes(dims, P, zc);
   z.take<char>(zc.off);
@@ -496,7 +497,9 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   for (int l = 0; l < 3; ++l) Wt[l] = ar.take<double>((size_t)dims[l] * R);
   char* nws = ar.take<char>(normalize_ws_bytes(R));
   char* rws = ar.take<char>(residual_ws_bytes(dims));
-  if (!rws) {
+  const int n_ref = p->refine_iters > 0 ? p->refine_iters : 0;
+  char* rstate = n_ref ? ar.take<char>(refine_state_bytes(dims, R, n_ref)) : nullptr;
+  if (!rws || (n_ref && !rstate)) {
     set_error("cpd_solve: workspace too small");
     return CPD_E_WORKSPACE;
   }
@@ -522,6 +525,27 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   const int npc = (core[0] + core[1] + core[2]) * R;
   const double* Wst = (const double*)(state + layout_of(npc, R, p->maxiter).W);
   const int* flags_dev = (const int*)(state + offsetof(Hdr, flags));
+  // refinement: the compressed run's iteration count and damping parameter continue on T (one
+  // read-back of the core header)
+  int ref_k0 = 0;
+  double ref_mu = 0.0;
+  bool refining = false;
+  if (n_ref) {
+    Hdr hc;
+    CPD_HIP_CHECK(hipMemcpyAsync(&hc, state, sizeof(Hdr), hipMemcpyDeviceToHost, s));
+    CPD_HIP_CHECK(hipStreamSynchronize(s));
+    refining = !(hc.flags & 1);
+    ref_k0 = hc.k;
+    ref_mu = hc.mu;
+    if (refining) {
+      // the uncompressed start is written straight into the refinement state's factors
+      double* Wr = (double*)(rstate + refine_w_offset(dims, R, n_ref));
+      Wt[0] = Wr;
+      Wt[1] = Wr + dims[0] * R;
+      Wt[2] = Wr + (dims[0] + dims[1]) * R;
+      if ((st = refine_setup(rstate, dims, R, n_ref, h_tn2, ref_mu, ref_k0, p, s))) return st;
+    }
+  }
   // uncompress W~ = U W
   size_t o = 0;
   for (int l = 0; l < 3; ++l) {
@@ -530,6 +554,7 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
       return st;
     o += (size_t)core[l] * R;
   }
+  if (refining && (st = refine_run(rstate, T, dtype, dims, R, n_ref, s))) return st;
   const double* Wtc[3] = {Wt[0], Wt[1], Wt[2]};
   if ((st = residual_full(T, dtype, dims, Wtc, R, res, rws, residual_ws_bytes(dims), s))) return st;
   if ((st = normalize_output(Wtc, dims, R, W_out, lambda_out, nws, normalize_ws_bytes(R), s, flags_dev))) return st;
@@ -558,6 +583,15 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   info->t_norm = sqrt(h_tn2);
   info->rel_err_full = sqrt(h_res > 0.0 ? h_res : 0.0) / sqrt(h_tn2);
   info->time_to_tol_ns = (ti > 0) ? (int64_t)llround((double)(h.t_tol - h_entry) * wall_ns_per_tick()) : -1;
+  info->refine_iters = 0;
+  info->refine_stop = 0;
+  if (refining) {
+    Hdr hr;
+    CPD_HIP_CHECK(hipMemcpyAsync(&hr, rstate, sizeof(Hdr), hipMemcpyDeviceToHost, s));
+    CPD_HIP_CHECK(hipStreamSynchronize(s));
+    info->refine_iters = hr.k;
+    info->refine_stop = hr.stop;
+  }
   return CPD_OK;
 }
 }  // namespace

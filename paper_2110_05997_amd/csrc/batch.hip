@@ -386,6 +386,8 @@ __global__ __launch_bounds__(FIN_NT) void batch_finish_kernel(const BItem* __res
     inf->tol_iter = h->tol_iter;
     // per member: from its dGN start to its first iteration below tol (members run side by side)
     inf->time_to_tol_ns = (!skipped && h->tol_iter > 0) ? llround((double)(h->t_tol - h->t_init) * ns_per_tick) : -1;
+    inf->refine_iters = 0;   // batched solves do not refine
+    inf->refine_stop = 0;
     inf->rel_err_core = skipped ? NAN : errs[h->k];
     const double tn = inf->t_norm;
     inf->rel_err_full = (tn > 0.0) ? sqrt(fmax(res, 0.0)) / tn : 0.0;

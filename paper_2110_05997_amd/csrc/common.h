@@ -178,6 +178,13 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
 cpd_status dgn_iterate_known(void* state, const double* S, const int32_t core[3], int R, int max_steps,
                              hipStream_t s);
 size_t dgn_lds_bytes(int np, int R);
+// Refinement in the original space: a dGN state over the input tensor (global-memory path).
+size_t refine_state_bytes(const int64_t dims[3], int R, int n_iters);
+size_t refine_w_offset(const int64_t dims[3], int R, int n_iters);
+cpd_status refine_setup(void* state, const int64_t dims[3], int R, int n_iters, double t_norm2, double mu, int k0,
+                        const cpd_params* p, hipStream_t s);
+cpd_status refine_run(void* state, const void* T, int dtype, const int64_t dims[3], int R, int n_iters,
+                      hipStream_t s);
 // Batched persistent dGN: one workgroup per state (header, caps and W written beforehand).
 // dgn_batch_prepare sets the kernel's dynamic-LDS limit (call outside graph capture).
 cpd_status dgn_batch_prepare(size_t lds_bytes);

@@ -454,25 +454,29 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     for (int e = tid; e < c.np; e += NT) bad |= !isfinite(c.W[e]);
     const double nb = block_sum((double)bad, slotA);
     norm_balance(c);
+    // a preset header (refinement on the input tensor) already holds ||S||, mu and the divergence
+    // reference: the tensor is not read here
+    const bool preset = (h->flags & HDR_PRESET) != 0;
     const int n = d[0] * d[1] * d[2];
     double s2 = 0.0, sa = 0.0;
-    for (int e = tid; e < n; e += NT) { s2 += S[e] * S[e]; sa += fabs(S[e]); }
+    if (!preset)
+      for (int e = tid; e < n; e += NT) { s2 += S[e] * S[e]; sa += fabs(S[e]); }
     s2 = block_sum(s2, slotB);
     sa = block_sum(sa, slotA);
     const double f2 = (mode == 3) ? 0.0 : residual_mttkrp(c, slotB);
     for (int e = tid; e < c.np; e += NT) gW[e] = c.W[e];
     if (tid == 0) {
-      const double s_norm = sqrt(s2);
+      const double s_norm = preset ? h->s_norm : sqrt(s2);
       h->s_norm = s_norm;
-      h->mu = h->init_damp * (sa / (double)n);
+      if (!preset) h->mu = h->init_damp * (sa / (double)n);
       h->f2 = f2;
-      h->div_ref = fmax(1.0, (h->div_ref > 0.0) ? h->div_ref : s2);
+      if (!preset) h->div_ref = fmax(1.0, (h->div_ref > 0.0) ? h->div_ref : s2);
       h->err0 = (s_norm > 0.0) ? sqrt(f2) / s_norm : 0.0;
       errs[0] = h->err0;
       h->k = 0;
       h->tol_iter = -1;
       h->stop = (nb > 0.0) ? -1 : CPD_STOP_NONE;
-      h->flags = (nb > 0.0) ? 1 : 0;
+      h->flags = ((nb > 0.0) ? 1 : 0) | (preset ? HDR_PRESET : 0);
       h->t_init = wall_clock64();
     }
     return;
@@ -837,6 +841,8 @@ int cg_cap_for(int k, double u) {
   return (int)(lo + off);
 }
 
+size_t full_aux_bytes(const int d[3], int R);
+
 namespace {
 // LDS of the staged large-core kernel: hv_staged's operands, or W and the three Pi^(l) for the
 // gradient, whichever is larger
@@ -849,12 +855,16 @@ size_t hv_stage_doubles(const int d[3], int R) {
 
 // The persistent dGN kernel with its working set in LDS when it fits, else in the state's work
 // region.
-cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int np, int R, const int d[3],
-                      hipStream_t s) {
+// sdtype: element type of S (FP64 for a core; the input tensor's type for a refinement, which also
+// forces the global-memory path since the LDS paths read S as FP64).
+cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int np, int R, const int d[3],
+                      hipStream_t s, int sdtype = CPD_F64) {
+  const double* S = (const double*)Sv;
+  const bool lds_ok = sdtype == CPD_F64;
   const int p2 = d[2] | 1, p1 = (d[1] * p2) | 1;
   const size_t s_lds = (size_t)(d[0] - 1) * p1 + (size_t)(d[1] - 1) * p2 + d[2];   // padded core in LDS
   size_t lb;
-  if (lds_fits(np, R, &lb) && lb + (size_t)s_lds * sizeof(double) <= LDS_LIMIT) {
+  if (lds_ok && lds_fits(np, R, &lb) && lb + (size_t)s_lds * sizeof(double) <= LDS_LIMIT) {
     lb += (size_t)s_lds * sizeof(double);
     if (mode == 0) {
       CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_init_kernel<true>,
@@ -865,7 +875,7 @@ cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int
                                         (int)lb));
       hipLaunchKernelGGL(dgn_kernel<true>, dim3(1), dim3(NT), lb, s, state, S, max_steps);
     }
-  } else if (lds_fits(np, R, &lb)) {
+  } else if (lds_ok && lds_fits(np, R, &lb)) {
     if (mode == 0) {
       CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_init_kernel<false>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
@@ -890,15 +900,15 @@ cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int
     double* MK = (double*)(state + Lo.MK);
     double* MKp[3] = {MK, MK + d[0] * R, MK + (d[0] + d[1]) * R};
     char* aux = state + align_up(Lo.total, 256);
-    const size_t aux_bytes = dgn_aux_bytes(d, R);
+    const size_t aux_bytes = lds_ok ? dgn_aux_bytes(d, R) : full_aux_bytes(d, R);
     double* f2_new = (double*)(state + offsetof(Hdr, f2_new));
     if (mode == 0) {
       hipLaunchKernelGGL((dgn_kernel_g<3, false>), dim3(1), dim3(NT), 0, s, state, S, max_steps);
       CPD_LAUNCH_CHECK();
       cpd_status st;
       for (int l = 0; l < 3; ++l)
-        if ((st = mttkrp_full(S, CPD_F64, dims, Wp, R, l, CPD_F64, MKp[l], aux, aux_bytes, s))) return st;
-      if ((st = residual_full(S, CPD_F64, dims, Wp, R, f2_new, aux, aux_bytes, s))) return st;
+        if ((st = mttkrp_full(Sv, sdtype, dims, Wp, R, l, CPD_F64, MKp[l], aux, aux_bytes, s))) return st;
+      if ((st = residual_full(Sv, sdtype, dims, Wp, R, f2_new, aux, aux_bytes, s))) return st;
       hipLaunchKernelGGL(dgn_init_tail_kernel, dim3(1), dim3(64), 0, s, state);
       CPD_LAUNCH_CHECK();
       return CPD_OK;
@@ -917,8 +927,8 @@ cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int
         CPD_LAUNCH_CHECK();
         cpd_status st;
         for (int l = 0; l < 3; ++l)
-          if ((st = mttkrp_full(S, CPD_F64, dims, Wp, R, l, CPD_F64, MKp[l], aux, aux_bytes, s))) return st;
-        if ((st = residual_full(S, CPD_F64, dims, Wp, R, f2_new, aux, aux_bytes, s))) return st;
+          if ((st = mttkrp_full(Sv, sdtype, dims, Wp, R, l, CPD_F64, MKp[l], aux, aux_bytes, s))) return st;
+        if ((st = residual_full(Sv, sdtype, dims, Wp, R, f2_new, aux, aux_bytes, s))) return st;
         hipLaunchKernelGGL(dgn_tail_kernel, dim3(1), dim3(64), 0, s, state);
         CPD_LAUNCH_CHECK();
       }
@@ -940,6 +950,10 @@ cpd_status launch_dgn(char* state, const double* S, int mode, int max_steps, int
 size_t dgn_aux_bytes(const int d[3], int R) {
   const int np = (d[0] + d[1] + d[2]) * R;
   if (lds_fits(np, R, nullptr)) return 0;
+  return full_aux_bytes(d, R);
+}
+
+size_t full_aux_bytes(const int d[3], int R) {
   const int64_t dims[3] = {d[0], d[1], d[2]};
   size_t b = residual_ws_bytes(dims);
   for (int l = 0; l < 3; ++l) {
@@ -1043,6 +1057,73 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
     return CPD_E_NONFINITE;
   }
   return CPD_OK;
+}
+
+// ---- refinement on the input tensor -----------------------------------------------------------
+// A state over the input tensor's dimensions that always takes the global-memory path (the
+// full-tensor MTTKRP and residual read the tensor in its own dtype).
+size_t refine_state_bytes(const int64_t dims[3], int R, int n_iters) {
+  const int d[3] = {(int)dims[0], (int)dims[1], (int)dims[2]};
+  const int np = (d[0] + d[1] + d[2]) * R;
+  return align_up(layout_of(np, R, n_iters).total, 256) + full_aux_bytes(d, R);
+}
+
+size_t refine_w_offset(const int64_t dims[3], int R, int n_iters) {
+  const int np = (int)(dims[0] + dims[1] + dims[2]) * R;
+  return layout_of(np, R, n_iters).W;
+}
+
+// Header and CG caps of a refinement: n_iters further iterations continuing the compressed run
+// (its damping parameter mu and iteration count k0: iteration j uses the cap of iteration k0 + j),
+// errors relative to ||T|| = sqrt(t_norm2).  The caller then writes the start W~ into the state
+// (refine_w_offset) and calls refine_run.
+cpd_status refine_setup(void* state, const int64_t dims[3], int R, int n_iters, double t_norm2, double mu, int k0,
+                        const cpd_params* p, hipStream_t s) {
+  if (n_iters < 1 || n_iters > SETUP_CAPS || R < 1 || R > 64 || !(t_norm2 > 0.0)) {
+    set_error("refine: bad arguments (iterations %d, R %d)", n_iters, R);
+    return CPD_E_INVALID;
+  }
+  const int np = (int)(dims[0] + dims[1] + dims[2]) * R;
+  const Layout Lo = layout_of(np, R, n_iters);
+  SetupArgs a;
+  memset(&a, 0, sizeof(a));
+  Hdr& h = a.h;
+  h.d[0] = (int)dims[0]; h.d[1] = (int)dims[1]; h.d[2] = (int)dims[2]; h.R = R;
+  h.maxiter = n_iters; h.np = np; h.tol_iter = -1;
+  h.tol = p->tol; h.cg_tol = (p->cg_tol > 0.0) ? p->cg_tol : p->tol;
+  h.init_damp = p->init_damp;
+  h.div_ref = fmax(1.0, t_norm2);
+  h.s_norm = sqrt(t_norm2);
+  h.mu = mu;
+  h.flags = HDR_PRESET;
+  for (int j = 1; j <= n_iters; ++j) {
+    const int k = k0 + j;
+    if (p->cg_fixed > 0) {
+      a.caps[j - 1] = p->cg_fixed;
+    } else {
+      const int ku = (p->cg_uniforms && k > p->maxiter) ? p->maxiter : k;
+      const double u = p->cg_uniforms ? p->cg_uniforms[ku - 1]
+                                      : u01_from_bits(splitmix64(p->seed * 0xD1B54A32D192ED03ull + (uint64_t)k));
+      a.caps[j - 1] = cg_cap_for(k, u);
+    }
+  }
+  hipLaunchKernelGGL(state_setup_kernel, dim3(1), dim3(256), 0, s, a, n_iters, (char*)state, Lo.caps,
+                     (const double*)nullptr, (double*)nullptr, 0);
+  CPD_LAUNCH_CHECK();
+  return CPD_OK;
+}
+
+// Initialisation (balancing, residual and MTTKRP on T) and up to n_iters iterations.
+cpd_status refine_run(void* state, const void* T, int dtype, const int64_t dims[3], int R, int n_iters,
+                      hipStream_t s) {
+  const int d[3] = {(int)dims[0], (int)dims[1], (int)dims[2]};
+  const int np = (d[0] + d[1] + d[2]) * R;
+  cpd_status st;
+  if ((st = launch_dgn((char*)state, T, 0, 0, np, R, d, s, dtype))) return st;
+  prof_begin(CPD_PK_DGN, s);
+  st = launch_dgn((char*)state, T, 1, n_iters, np, R, d, s, dtype);
+  prof_end(CPD_PK_DGN, s);
+  return st;
 }
 
 size_t dgn_lds_bytes(int np, int R) { return lds_doubles(np, R) * sizeof(double); }

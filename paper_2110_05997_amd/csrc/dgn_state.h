@@ -12,6 +12,10 @@ constexpr int NT = DGN_NT;
 constexpr int NW = NT / 64;
 }  // namespace
 
+// Hdr::flags bits: 1 non-finite start (set by the initialisation), 2 rejected batch member,
+// HDR_PRESET the header arrives with ||S||, mu and the divergence reference already set (refinement)
+constexpr int32_t HDR_PRESET = 4;
+
 struct Hdr {
   int32_t d[3];
   int32_t R;

@@ -54,10 +54,10 @@ def main():
         ii = rng.integers(0, 600, NSAMP)
         rr = rng.integers(0, S.shape[l], NSAMP)
         for i, r in zip(ii, rr):
-            out.append(f"U {l} {i} {r} {res['U'][l][i, r]!r}")
+            out.append(f"U {l} {i} {r} {float(res['U'][l][i, r])!r}")
     for _ in range(NSAMP):
         a, b, c = (int(rng.integers(0, d)) for d in S.shape)
-        out.append(f"S {a} {b} {c} {S[a, b, c]!r}")
+        out.append(f"S {a} {b} {c} {float(S[a, b, c])!r}")
     for _ in range(NSAMP):
         i, j, k = (int(v) for v in rng.integers(0, 600, 3))
         v = float(np.sum(lam * W[0][i] * W[1][j] * W[2][k]))

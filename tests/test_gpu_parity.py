@@ -587,3 +587,54 @@ def test_solve_st_matches_oracle(case):
     assert ml.frob(That - Tref) / ml.frob(Tref) < 1e-6
     assert info["stop_reason"] == ref["stop"]
     assert abs(info["iters"] - ref["iters"]) <= 1
+
+
+# ---------------------------------------------------------------------------------------------
+# Refinement in the original space (further dGN iterations on T after uncompression)
+@pytest.mark.parametrize("case", ["planted_f64", "planted_f32"])
+def test_solve_refine_matches_oracle(case):
+    log("solve refine", case)
+    if case == "planted_f64":
+        T, _, _ = synth.planted((23, 31, 17), 4, seed=5, noise_rel=1e-3)
+        dt, R, seed = torch.float64, 4, 5
+    else:
+        T, _, _ = synth.planted((40, 36, 30), 5, seed=6, noise_rel=1e-2, dtype=np.float32)
+        dt, R, seed = torch.float32, 5, 6
+    Td = dev(T, dt)
+    Th = host(Td)
+    U = synth.cg_uniforms(200, seed)
+    _, _, So = omlsvd.compress(Th, R)
+    W0 = synth.init_factors(So.shape, R, seed)
+    ref = ocpd.solve(Th, R, odgn.Params(), W0=W0, cg_uniforms=U, refine_iters=3)
+    res = cp().solve(Td, R, cp().params(cg_uniforms=U, refine_iters=3), W0=[dev(w) for w in W0])
+    info = res["info"]
+    log(info, "oracle", ref["iters"], ref["refine_iters"], ref["refine_stop"], ref["rel_err_full"])
+    assert info["iters"] == ref["iters"] and info["stop_reason"] == ref["stop"]
+    assert info["refine_iters"] == ref["refine_iters"] and info["refine_stop"] == ref["refine_stop"]
+    That = reconstruct(res)
+    Tref = ml.cpd_full(ref["W_unnormalized"])
+    assert ml.frob(That - Tref) / ml.frob(Tref) < 1e-6
+    assert abs(info["rel_err_full"] - ref["rel_err_full"]) <= 1e-6 * ref["rel_err_full"]
+
+
+def test_refinement_brings_the_bf16_gram_path_to_the_fp64_solution():
+    """BF16 Grams perturb the compression bases; refinement on the FP32 tensor itself (the final FP64
+    iterations of the precision variant) removes that error: after it the reconstruction is closer to
+    the oracle's (FP64 Grams, same refinement) than before, and within 1e-5 of it."""
+    log("bf16 + refinement")
+    T, _, _ = synth.planted((96, 80, 72), 6, seed=7, noise_rel=1e-3, dtype=np.float32)
+    Td = dev(T, torch.float32)
+    Th = host(Td)
+    Tlo = Td.to(torch.bfloat16).contiguous()
+    R = 6
+    U = synth.cg_uniforms(200, 7)
+    W0 = synth.init_factors((R, R, R), R, 7)
+    ref = ocpd.solve(Th, R, odgn.Params(), W0=W0, cg_uniforms=U, refine_iters=3)
+    Tref = ml.cpd_full(ref["W_unnormalized"])
+    r0 = cp().solve_mixed(Tlo, Td, R, cp().params(cg_uniforms=U), W0=[dev(w) for w in W0])
+    r3 = cp().solve_mixed(Tlo, Td, R, cp().params(cg_uniforms=U, refine_iters=3), W0=[dev(w) for w in W0])
+    d0 = ml.frob(reconstruct(r0) - Tref) / ml.frob(Tref)
+    d3 = ml.frob(reconstruct(r3) - Tref) / ml.frob(Tref)
+    log("BF16 Grams vs oracle: unrefined", d0, "refined", d3, r3["info"])
+    assert r3["info"]["refine_iters"] >= 1
+    assert d3 < d0 and d3 < 1e-5

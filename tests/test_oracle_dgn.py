@@ -488,3 +488,43 @@ def test_fixed_cg_cap_replaces_random_schedule():
     x, its, _ = dgn.pcg(Ws, pis, gam, st0.mu, [-g for g in grad], M, n_p, 0.0)
     assert np.max(np.abs(vec_blocks(x) - x_ref)) < 1e-8 * np.max(np.abs(x_ref))
     assert abs(info["step_norm"] - np.linalg.norm(x_ref)) < 1e-8 * np.linalg.norm(x_ref)
+
+
+# ---------------------------------------------------------------------------------------------
+# Refinement in the original space
+def test_full_space_gradient_is_the_lifted_core_gradient():
+    """For T = (U1, U2, U3) . S with orthonormal U^(l), the gradient of the full-space problem at
+    W~^(l) = U^(l) W^(l) is U^(l) times the core problem's gradient at W (the MTTKRP of T against
+    the lifted factors is U^(l) S_(l) KR and the Grams of W~ equal those of W), which is what lets
+    the refinement continue the compressed iteration."""
+    rng = np.random.default_rng(31)
+    S = rng.standard_normal((4, 3, 5))
+    Us = [np.linalg.qr(rng.standard_normal((d, r)))[0] for d, r in zip((9, 7, 8), S.shape)]
+    T = ml.multilinear(S, Us)
+    W = [rng.standard_normal((r, 3)) for r in S.shape]
+    g_core = dgn.gradient(S, W)
+    g_full = dgn.gradient(T, [U @ w for U, w in zip(Us, W)])
+    for l in range(3):
+        assert np.max(np.abs(g_full[l] - Us[l] @ g_core[l])) < 1e-12 * np.max(np.abs(g_full[l]))
+
+
+def test_refinement_keeps_an_exact_solution_and_improves_a_truncated_one():
+    """Noiseless planted tensor: the compressed solve is exact, and the full-space refinement keeps it
+    (error stays at rounding, steps vanish).  A compression forced below the tensor's multilinear
+    rank loses signal; the refinement, working on T itself, lowers the full error."""
+    T, _, _ = synth.planted((12, 10, 8), 3, seed=32)
+    W0 = synth.init_factors((3, 3, 3), 3, 32)
+    U = synth.cg_uniforms(200, 32)
+    p = dgn.Params(tol=1e-13, maxiter=300)
+    r0 = cpd.solve(T, 3, p, W0=W0, cg_uniforms=U, refine_iters=0)
+    r1 = cpd.solve(T, 3, p, W0=W0, cg_uniforms=U, refine_iters=2)
+    assert r0["rel_err_full"] < 1e-10 and r1["rel_err_full"] < 1e-10
+    assert all(i["step_norm"] < 1e-8 for i in r1["refine_infos"])
+    # rank 3 in a 2 x 2 x 2 core: the compression cannot hold the tensor
+    Tn, _, _ = synth.planted((12, 10, 8), 3, seed=33, noise_rel=1e-3)
+    W0n = synth.init_factors((2, 2, 2), 3, 33)
+    pn = dgn.Params()
+    c0 = cpd.solve(Tn, 3, pn, W0=W0n, cg_uniforms=U, core_dims=(2, 2, 2))
+    c1 = cpd.solve(Tn, 3, pn, W0=W0n, cg_uniforms=U, core_dims=(2, 2, 2), refine_iters=8)
+    assert c1["refine_iters"] >= 1
+    assert c1["rel_err_full"] < 0.5 * c0["rel_err_full"]
