@@ -301,6 +301,37 @@ cpd_status cpd_solve_mixed(const void* T_lo, int32_t lo_dtype, const void* T, in
                            int32_t R, const cpd_params* p, const double* W0, double* W_out[3], double* lambda_out,
                            cpd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------------------------ */
+/* Tensors of order L >= 4: ch.4 "Tensor train and the CPD", Alg. TT-SVD (every TT-rank R) and */
+/* Alg. CPD-TTD (a rank-R CPD of the second core, a Bi-CPD with the first factor fixed to the   */
+/* inverse transpose of the previous third factor for each further core, outer factors from    */
+/* the first and last cores).                                                                   */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Workspace bytes of cpd_solve_tt; 0 if the shape is outside its limits. */
+size_t cpd_tt_workspace_bytes(int32_t L, const int64_t* dims, int32_t R, const cpd_params* p);
+
+/*
+ * cpd_solve_tt: rank-R CPD of an order-L tensor (4 <= L <= 16) through the tensor train.
+ *   T        (device) prod(dims) elements, C order, CPD_F64 or CPD_F32.
+ *   dims     (host) L sizes, each 1..4096, with R <= min(dims[0], dims[L-1]), R * dims[l] <= 4096 and
+ *            R <= 56 whenever R * dims[l] > 64 (the eigensolver's limits), and the trailing products
+ *            at least R.
+ *   W0       (device, nullable) start points of the third-order CPDs, packed: for the second core
+ *            (R x I_2 x R, compressed to R x min(I_2, R) x R) three row-major R x R, min(I_2, R) x R,
+ *            R x R matrices; then for each core l = 3..L-1 an I_l x R and an R x R matrix.  NULL:
+ *            N(0,1) starts from params.seed.
+ *   W_out[l] (device, host array of L pointers) I_l x R, unit columns, modes 1..L-1 signed so each
+ *            column's largest-|.| entry is positive, terms by decreasing lambda; lambda_out (device) R.
+ *   info     (host): iters = dGN iterations over all inner CPDs, stop_reason = the last one's,
+ *            rel_err_core = the largest inner relative error, rel_err_full = ||T - T^|| / ||T||.
+ * The inner CPDs use p's dGN parameters (classic compression, no refinement).  Synchronises the
+ * stream (once per Bi-CPD).  CPD_E_NONFINITE if a third factor to be inverted is singular.
+ */
+cpd_status cpd_solve_tt(const void* T, int32_t dtype, int32_t L, const int64_t* dims, int32_t R, const cpd_params* p,
+                        const double* W0, double* const* W_out, double* lambda_out, cpd_solve_info* info, void* ws,
+                        size_t ws_bytes, void* stream);
+
 /* out (device, 1 double) = ||T - sum_r w_r^(1) o w_r^(2) o w_r^(3)||^2, fused (ch.4 "Computing the
  * residual" applied to the input tensor).  ws: cpd_residual_workspace_bytes. */
 size_t cpd_residual_workspace_bytes(const int64_t dims[3]);

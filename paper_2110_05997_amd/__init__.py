@@ -207,6 +207,34 @@ def solve(T, R, p=None, W0=None, ws=None):
     return dict(W=W, lam=lam, info=d)
 
 
+def solve_tt(T, R, p=None, W0=None, ws=None):
+    """Rank-R CPD of a tensor of order >= 4 through the tensor train (cpd_solve_tt).  W0: None or
+    the nested start points of synth.tt_init_factors (host arrays), packed here in that order.
+    Returns dict(W=[L x (I_l x R)], lam, info)."""
+    _check_tensor(T)
+    L = _lib.lib()
+    if p is None:
+        p = params()
+    Lord = T.dim()
+    dims = (ctypes.c_int64 * Lord)(*T.shape)
+    if ws is None:
+        nb = L.cpd_tt_workspace_bytes(Lord, dims, R, ctypes.byref(p))
+        if nb == 0:
+            raise ValueError("cpd_solve_tt: shape outside the supported limits")
+        ws = _ws(nb, T.device)
+    W = [torch.empty((T.shape[l], R), dtype=torch.float64, device=T.device) for l in range(Lord)]
+    lam = torch.empty(R, dtype=torch.float64, device=T.device)
+    w0 = None
+    if W0 is not None:
+        flat = [torch.as_tensor(m, dtype=torch.float64).reshape(-1) for grp in W0 for m in grp]
+        w0 = torch.cat(flat).to(T.device)
+    info = SolveInfo()
+    Wp = (ctypes.c_void_p * Lord)(*[w.data_ptr() for w in W])
+    _lib.check(L.cpd_solve_tt(_ptr(T), _dtype(T), Lord, dims, R, ctypes.byref(p), _ptr(w0) if w0 is not None else None,
+                              Wp, _ptr(lam), ctypes.byref(info), _ptr(ws), ws.numel(), _stream()), "cpd_solve_tt")
+    return dict(W=W, lam=lam, info=_info_dict(info))
+
+
 def _info_dict(info):
     d = {f: getattr(info, f) for f, _ in SolveInfo._fields_}
     d["core_dims"] = tuple(info.core_dims)

@@ -141,6 +141,11 @@ SIGNATURES = [
     ("cpd_residual_workspace_bytes", ctypes.c_size_t, [_I64x3]),
     ("cpd_residual_norm2", ctypes.c_int, [_P, ctypes.c_int32, _I64x3, _Px3, ctypes.c_int32, _P, _P,
                                           ctypes.c_size_t, _P]),
+    ("cpd_tt_workspace_bytes", ctypes.c_size_t, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
+                                                  ctypes.POINTER(Params)]),
+    ("cpd_solve_tt", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
+                                    ctypes.POINTER(Params), _P, ctypes.POINTER(ctypes.c_void_p), _P,
+                                    ctypes.POINTER(SolveInfo), _P, ctypes.c_size_t, _P]),
     ("cpd_residual_norm2_noalloc", ctypes.c_int, [_P, ctypes.c_int32, _I64x3, _Px3, ctypes.c_int32, _P, _P]),
     ("cpd_jtj_v", ctypes.c_int, [_Px3, _Px3, _I32x3, ctypes.c_int32, _Px3, _P]),
     ("cpd_batch_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(BatchItem), ctypes.c_int32,

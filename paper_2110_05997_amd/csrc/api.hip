@@ -359,6 +359,57 @@ size_t solve_ws(const int64_t dims[3], int R, const cpd_params* p) {
 }
 
 }  // namespace
+
+size_t solve_ws_bytes(const int64_t dims[3], int R, const cpd_params* p) { return solve_ws(dims, R, p); }
+
+cpd_status solve3_raw(const double* T, const int64_t dims[3], int R, const cpd_params* p, const double* W0,
+                      double* Wt, int* iters, int* stop, double* rel_err, void* ws, size_t ws_bytes, hipStream_t s) {
+  const size_t need = solve_ws(dims, R, p);
+  if (!ws || ws_bytes < need) {
+    set_error("solve3_raw: workspace %zu < %zu", ws_bytes, need);
+    return CPD_E_WORKSPACE;
+  }
+  int P[3];
+  pdims(dims, R, p, P);
+  Arena ar(ws, ws_bytes);
+  double* chk = ar.take<double>(2 + P[0] + P[1] + P[2]);
+  char* sws = ar.take<char>(sumsq_ws_bytes());
+  double* U[3];
+  for (int l = 0; l < 3; ++l) U[l] = ar.take<double>((size_t)dims[l] * P[l]);
+  double* S = ar.take<double>((size_t)P[0] * P[1] * P[2]);
+  const int32_t pc[3] = {P[0], P[1], P[2]};
+  char* state = ar.take<char>(state_bytes(pc, R, p->maxiter));
+  if (!state) {
+    set_error("solve3_raw: workspace too small");
+    return CPD_E_WORKSPACE;
+  }
+  cpd_status st;
+  if ((st = sumsq_full(T, CPD_F64, dims[0] * dims[1] * dims[2], chk, (int*)(chk + 1), sws, sumsq_ws_bytes(), s)))
+    return st;
+  double h_tn2 = 0.0;
+  int core[3];
+  if ((st = run_compress(T, CPD_F64, T, CPD_F64, CPD_F64, dims, R, p, U, nullptr, S, core, ar, s, chk, &h_tn2)))
+    return st;
+  if ((st = state_init(state, S, core, R, W0, h_tn2, p, s, true))) return st;
+  if ((st = dgn_iterate_known(state, S, core, R, p->maxiter, s))) return st;
+  const int npc = (core[0] + core[1] + core[2]) * R;
+  const double* Wst = (const double*)(state + layout_of(npc, R, p->maxiter).W);
+  size_t o = 0, ot = 0;
+  for (int l = 0; l < 3; ++l) {
+    if ((st = gemm_f64((int)dims[l], R, core[l], 1.0, U[l], core[l], 0, false, Wst + o, CPD_F64, R, 0, false, 0.0,
+                       Wt + ot, R, 0, 1, s)))
+      return st;
+    o += (size_t)core[l] * R;
+    ot += (size_t)dims[l] * R;
+  }
+  Hdr h;
+  CPD_HIP_CHECK(hipMemcpyAsync(&h, state, sizeof(Hdr), hipMemcpyDeviceToHost, s));
+  CPD_HIP_CHECK(hipStreamSynchronize(s));
+  if (iters) *iters = h.k;
+  if (stop) *stop = h.stop;
+  if (rel_err) *rel_err = (h.s_norm > 0.0) ? sqrt(h.f2) / h.s_norm : 0.0;
+  return CPD_OK;
+}
 }  // namespace cpd
 
 using namespace cpd;
@@ -660,6 +711,25 @@ cpd_status cpd_residual_norm2(const void* T, int32_t dtype, const int64_t dims[3
                               size_t ws_bytes, void* stream) {
   CPD_REQUIRE(T && W && out && dims_ok(dims) && dtype_ok(dtype), "cpd_residual_norm2: bad arguments");
   return residual_full(T, dtype, dims, W, R, out, ws, ws_bytes, (hipStream_t)stream);
+}
+
+size_t cpd_tt_workspace_bytes(int32_t L, const int64_t* dims, int32_t R, const cpd_params* p) {
+  cpd_params def;
+  if (!p) { cpd_default_params(&def); p = &def; }
+  return tt_ws_bytes(L, dims, R, p);
+}
+
+cpd_status cpd_solve_tt(const void* T, int32_t dtype, int32_t L, const int64_t* dims, int32_t R, const cpd_params* p,
+                        const double* W0, double* const* W_out, double* lambda_out, cpd_solve_info* info, void* ws,
+                        size_t ws_bytes, void* stream) {
+  CPD_REQUIRE(T && dims && W_out && lambda_out && info && (dtype == CPD_F64 || dtype == CPD_F32),
+              "cpd_solve_tt: bad arguments");
+  CPD_REQUIRE(L >= 4 && L <= 16, "cpd_solve_tt: order L must be 4..16");
+  for (int l = 0; l < L; ++l) CPD_REQUIRE(W_out[l] != nullptr, "cpd_solve_tt: null output factor");
+  cpd_params def;
+  if (!p) { cpd_default_params(&def); p = &def; }
+  CPD_REQUIRE(p->maxiter >= 1 && p->tol >= 0.0, "cpd_solve_tt: bad parameters");
+  return solve_tt(T, dtype, L, dims, R, p, W0, W_out, lambda_out, info, ws, ws_bytes, (hipStream_t)stream);
 }
 
 cpd_status cpd_residual_norm2_noalloc(const void* T, int32_t dtype, const int64_t dims[3],

@@ -171,13 +171,27 @@ double wall_ns_per_tick();
 size_t state_bytes(const int32_t core[3], int R, int maxiter);
 size_t dgn_aux_bytes(const int d[3], int R);
 // check_flags = false leaves the non-finite-start flag in the header for the caller to read.
+// hdr_flags: initial header flags (HDR_FIX0 for a fixed first factor).
 cpd_status state_init(void* state, const double* S, const int32_t core[3], int R,
                       const double* W0, double t_norm2, const cpd_params* p, hipStream_t s,
-                      bool check_flags = true);
+                      bool check_flags = true, int32_t hdr_flags = 0);
+// A third-order CPD of a device FP64 tensor (compression, dGN, uncompression) whose factors are
+// returned unnormalised: uncompressed and balanced, in the dGN's column order, packed
+// (d0 + d1 + d2) x R in Wt.  Workspace: solve_ws_bytes(dims, R, p).  Synchronises the stream.
+size_t solve_ws_bytes(const int64_t dims[3], int R, const cpd_params* p);
+cpd_status solve3_raw(const double* T, const int64_t dims[3], int R, const cpd_params* p, const double* W0,
+                      double* Wt, int* iters, int* stop, double* rel_err, void* ws, size_t ws_bytes, hipStream_t s);
 // dgn_iterate for a state whose sizes the caller knows (no header read-back).
 cpd_status dgn_iterate_known(void* state, const double* S, const int32_t core[3], int R, int max_steps,
                              hipStream_t s);
 size_t dgn_lds_bytes(int np, int R);
+// N(0,1) entries (Box-Muller on SplitMix64 counters), the library's own random start.
+cpd_status fill_randn(double* W, int n, uint64_t seed, hipStream_t s);
+// The tensor-train route for order L >= 4 (cpd_solve_tt).
+size_t tt_ws_bytes(int L, const int64_t* dims, int R, const cpd_params* p);
+cpd_status solve_tt(const void* T, int dtype, int L, const int64_t* dims, int R, const cpd_params* p,
+                    const double* W0, double* const* W_out, double* lambda_out, cpd_solve_info* info, void* ws,
+                    size_t ws_bytes, hipStream_t s);
 // Refinement in the original space: a dGN state over the input tensor (global-memory path).
 size_t refine_state_bytes(const int64_t dims[3], int R, int n_iters);
 size_t refine_w_offset(const int64_t dims[3], int R, int n_iters);

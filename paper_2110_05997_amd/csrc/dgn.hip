@@ -276,7 +276,9 @@ __device__ double hv_staged(Ctx& c, const double* V, double* out, double mu, boo
 
 // Norm balancing (ch.4 "Updates"): every rank-one term gets equal column norms.  Uses msq as
 // scratch for the column norms.  Ends with a barrier.
-__device__ void norm_balance(Ctx& c) {
+// fix0: the first factor is held fixed; the rank-one terms are balanced over modes 2 and 3 only,
+// alpha_r = sqrt(n_r^(2) n_r^(3)).
+__device__ void norm_balance(Ctx& c, bool fix0 = false) {
   const int R = c.R;
   double* cn = c.msq;   // 3R scratch
   for (int e = threadIdx.x; e < 3 * R; e += NT) {
@@ -291,6 +293,12 @@ __device__ void norm_balance(Ctx& c) {
     int l, i, r;
     split_index(c, e, l, i, r);
     const double n0 = cn[r], n1 = cn[R + r], n2 = cn[2 * R + r];
+    if (fix0) {
+      if (l == 0 || fmin(n1, n2) == 0.0) continue;
+      const double alpha = sqrt(n1 * n2);
+      c.W[e] *= alpha / cn[l * R + r];
+      continue;
+    }
     if (fmin(n0, fmin(n1, n2)) == 0.0) continue;
     const double alpha = pow(n0 * n1 * n2, 1.0 / 3.0);
     c.W[e] *= alpha / cn[l * R + r];
@@ -446,6 +454,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
   double* slotB = c.red + NW;
 
   for (int e = tid; e < c.np; e += NT) c.W[e] = gW[e];
+  const bool fix0 = (h->flags & HDR_FIX0) != 0;
   __syncthreads();
 
   if (mode == 0 || mode == 3) {   // mode 3: the residual and MTTKRP are left to other launches
@@ -453,7 +462,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     int bad = 0;
     for (int e = tid; e < c.np; e += NT) bad |= !isfinite(c.W[e]);
     const double nb = block_sum((double)bad, slotA);
-    norm_balance(c);
+    norm_balance(c, fix0);
     // a preset header (refinement on the input tensor) already holds ||S||, mu and the divergence
     // reference: the tensor is not read here
     const bool preset = (h->flags & HDR_PRESET) != 0;
@@ -476,7 +485,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
       h->k = 0;
       h->tol_iter = -1;
       h->stop = (nb > 0.0) ? -1 : CPD_STOP_NONE;
-      h->flags = ((nb > 0.0) ? 1 : 0) | (preset ? HDR_PRESET : 0);
+      h->flags = ((nb > 0.0) ? 1 : 0) | (preset ? HDR_PRESET : 0) | (fix0 ? HDR_FIX0 : 0);
       h->t_init = wall_clock64();
     }
     return;
@@ -510,7 +519,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
       const double* Pl = gPs + l * R * R;
       double acc = 0.0;
       for (int s = 0; s < R; ++s) acc += Wi[s] * Pl[s * R + r];
-      const double g = acc - c.MK[e];
+      const double g = (fix0 && l == 0) ? 0.0 : acc - c.MK[e];   // a fixed factor has no step
       c.G[e] = g;
       gi = fmax(gi, fabs(g));
       const double r0 = c.msq[l * R + r] * (-g);
@@ -529,9 +538,10 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
       if (!(pz > 0.0)) break;
       const double alpha = rr / pz;
       double eps = 0.0;
+      const int zfree = fix0 ? c.off1 : 0;   // rows of J^T J v of a fixed factor are dropped
       for (int e = tid; e < c.np; e += NT) {
         c.X[e] += alpha * c.P[e];
-        const double rv = c.Rv[e] - alpha * c.Z[e];
+        const double rv = c.Rv[e] - alpha * ((e < zfree) ? 0.0 : c.Z[e]);
         c.Rv[e] = rv;
         eps += rv * rv;
       }
@@ -563,7 +573,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     // update, always accepted, then norm balancing
     for (int e = tid; e < c.np; e += NT) c.W[e] += c.X[e];
     __syncthreads();
-    norm_balance(c);
+    norm_balance(c, fix0);
     if (mode == 2) {
       if (tid == 0) {
         h->f2_pred = f2_pred; h->stepn = sqrt(xx); h->grad_inf = grad_inf; h->cg_resid = rr;
@@ -970,7 +980,8 @@ size_t state_bytes(const int32_t core[3], int R, int maxiter) {
 }
 
 cpd_status state_init(void* state, const double* S, const int32_t core[3], int R,
-                      const double* W0, double t_norm2, const cpd_params* p, hipStream_t s, bool check_flags) {
+                      const double* W0, double t_norm2, const cpd_params* p, hipStream_t s, bool check_flags,
+                      int32_t hdr_flags) {
   if (state == nullptr || S == nullptr || p == nullptr || R < 1 || R > 64 || p->maxiter < 1) {
     set_error("state_init: bad arguments (R=%d)", R);
     return CPD_E_INVALID;
@@ -994,6 +1005,7 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
   h.maxiter = p->maxiter; h.np = np; h.tol_iter = -1;
   h.tol = p->tol; h.cg_tol = (p->cg_tol > 0.0) ? p->cg_tol : p->tol;
   h.init_damp = p->init_damp; h.div_ref = t_norm2;
+  h.flags = hdr_flags;
   int32_t* caps = inline_args ? a.caps : caps_long.data();
   for (int k = 1; k <= p->maxiter; ++k) {
     if (p->cg_fixed > 0) {
@@ -1127,6 +1139,13 @@ cpd_status refine_run(void* state, const void* T, int dtype, const int64_t dims[
 }
 
 size_t dgn_lds_bytes(int np, int R) { return lds_doubles(np, R) * sizeof(double); }
+
+cpd_status fill_randn(double* W, int n, uint64_t seed, hipStream_t s) {
+  if (n <= 0) return CPD_OK;
+  hipLaunchKernelGGL(randn_kernel, dim3((n + 255) / 256), dim3(256), 0, s, W, n, seed);
+  CPD_LAUNCH_CHECK();
+  return CPD_OK;
+}
 
 cpd_status dgn_batch_prepare(size_t lds_bytes) {
   if (lds_bytes > LDS_LIMIT) {

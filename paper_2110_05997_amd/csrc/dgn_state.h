@@ -15,6 +15,9 @@ constexpr int NW = NT / 64;
 // Hdr::flags bits: 1 non-finite start (set by the initialisation), 2 rejected batch member,
 // HDR_PRESET the header arrives with ||S||, mu and the divergence reference already set (refinement)
 constexpr int32_t HDR_PRESET = 4;
+// HDR_FIX0: the first factor is fixed (the Bi-CPD of the tensor-train route): its block of the step,
+// gradient and CG vectors stays zero and only modes 2 and 3 are balanced
+constexpr int32_t HDR_FIX0 = 8;
 
 struct Hdr {
   int32_t d[3];

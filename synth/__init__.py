@@ -133,3 +133,31 @@ def config2(seed=0):
 def config3(seed=0, dtype=np.float32):
     """600^3, R = 50, N(0,1) factors, SNR 60 dB."""
     return planted((600, 600, 600), 50, seed=seed, snr_db=60.0, dtype=dtype)
+
+
+def tt_init_factors(dims, R, seed=0):
+    """Start points of the third-order CPDs of the tensor-train route for an order-L tensor with
+    every TT-rank R: for the second core (R x I_2 x R, compressed to P = (R, min(I_2, R), R)) three
+    P_l x R matrices, then for cores l = 3..L-1 the free factors (I_l x R, R x R); N(0,1) entries
+    from ``default_rng([seed, 4])`` in that order."""
+    rng = np.random.default_rng([seed, 4])
+    out = [[rng.standard_normal((p, R)) for p in (R, min(dims[1], R), R)]]
+    for d in dims[2:-1]:
+        out.append([rng.standard_normal((d, R)), rng.standard_normal((R, R))])
+    return out
+
+
+def planted_order_L(dims, R, seed=0, noise_rel=None, dtype=np.float64):
+    """Rank-R tensor of any order with N(0,1) factors (drawn in mode order from
+    ``default_rng(seed)``) plus optional Gaussian noise of relative Frobenius norm noise_rel."""
+    rng = np.random.default_rng(seed)
+    Fs = [rng.standard_normal((d, R)) for d in dims]
+    out = Fs[0]
+    for F in Fs[1:]:
+        out = (out[:, None, :] * F[None, :, :]).reshape(-1, R)
+    T0 = out.sum(axis=1).reshape(dims)
+    T = T0
+    if noise_rel:
+        E = rng.standard_normal(tuple(dims))
+        T = T0 + (noise_rel * math.sqrt(np.sum(T0 * T0)) / math.sqrt(np.sum(E * E))) * E
+    return np.ascontiguousarray(T.astype(dtype)), Fs
