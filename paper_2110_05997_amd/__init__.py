@@ -211,7 +211,8 @@ def solve_tt(T, R, p=None, W0=None, ws=None):
     """Rank-R CPD of a tensor of order >= 4 through the tensor train (cpd_solve_tt).  W0: None or
     the nested start points of synth.tt_init_factors (host arrays), packed here in that order.
     Returns dict(W=[L x (I_l x R)], lam, info)."""
-    _check_tensor(T)
+    if not (T.is_cuda and T.is_contiguous()):
+        raise ValueError("expected a contiguous tensor on the GPU")
     L = _lib.lib()
     if p is None:
         p = params()

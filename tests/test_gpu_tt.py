@@ -1,7 +1,10 @@
 """GPU parity of the tensor-train route (cpd_solve_tt; ch.4 "Tensor train and the CPD") against
-the oracle's Alg. CPD-TTD on the same seeded tensors, start points and CG caps.  The
-reconstructions agree to 1e-6 relative (the accuracy target of the path) and so do the full-tensor
-errors; orders 4 to 6 exercise the CPD of the second core and one to three Bi-CPDs."""
+the oracle's Alg. CPD-TTD on the same seeded tensors, start points and CG caps.  The stopping
+tolerance is 1e-10, below the 1e-6 noise, so the inner CPDs end on the improvement rule at their
+minimisers instead of on an error test within rounding of the threshold (which could move the
+stopping iteration by one between the two sides).  The reconstructions agree to 1e-6 relative (the
+accuracy target of the path) and the full errors to within their distance (triangle inequality);
+orders 4 to 6 exercise the CPD of the second core and one to three Bi-CPDs."""
 import numpy as np
 import pytest
 import torch
@@ -28,9 +31,9 @@ def test_cpd_tt_matches_oracle(dims, R, seed, dtype):
     Th = Td.double().cpu().numpy()
     U = synth.cg_uniforms(200, seed)
     W0 = synth.tt_init_factors(dims, R, seed)
-    Ws, _, logs = ott.cpd_ttd(Th, R, odgn.Params(), W0=W0, cg_uniforms=U)
+    Ws, _, logs = ott.cpd_ttd(Th, R, odgn.Params(tol=1e-10), W0=W0, cg_uniforms=U)
     ref = ott.cpd_full_L(Ws)
-    res = cp.solve_tt(Td, R, cp.params(cg_uniforms=U), W0=W0)
+    res = cp.solve_tt(Td, R, cp.params(cg_uniforms=U, tol=1e-10), W0=W0)
     W = [w.cpu().numpy() for w in res["W"]]
     lam = res["lam"].cpu().numpy()
     got = ott.cpd_full_L([W[0] * lam[None, :]] + W[1:])
@@ -38,7 +41,7 @@ def test_cpd_tt_matches_oracle(dims, R, seed, dtype):
     e_ref = np.linalg.norm(Th - ref) / np.linalg.norm(Th)
     log(res["info"], "oracle logs", logs, "That diff", d, "oracle err", e_ref)
     assert d < 1e-6
-    assert abs(res["info"]["rel_err_full"] - e_ref) <= 1e-6 * max(e_ref, 1e-12) + 1e-12
+    assert abs(res["info"]["rel_err_full"] - e_ref) <= 1.01 * d * np.linalg.norm(ref) / np.linalg.norm(Th) + 1e-12
     for w in W:
         np.testing.assert_allclose(np.linalg.norm(w, axis=0), 1.0, rtol=1e-12)
     assert np.all(lam >= 0) and np.all(np.diff(lam) <= 0)
