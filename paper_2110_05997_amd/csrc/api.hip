@@ -624,6 +624,10 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
     set_error("state_init: non-finite initial factors");
     return CPD_E_NONFINITE;
   }
+  if (h.flags & HDR_BAR_TIMEOUT) {
+    set_error("dgn: a grid barrier of the multi-workgroup CG timed out");
+    return CPD_E_HIP;
+  }
   const int k = h.k, stop = h.stop, ti = h.tol_iter;
   const double err = (h.s_norm > 0.0) ? sqrt(h.f2) / h.s_norm : 0.0;   // = the logged error of step k
   info->iters = k;
@@ -642,6 +646,10 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
     CPD_HIP_CHECK(hipStreamSynchronize(s));
     info->refine_iters = hr.k;
     info->refine_stop = hr.stop;
+    if (hr.flags & HDR_BAR_TIMEOUT) {
+      set_error("refinement: a grid barrier of the multi-workgroup CG timed out");
+      return CPD_E_HIP;
+    }
   }
   return CPD_OK;
 }

@@ -24,6 +24,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
+#include <mutex>
 #include <vector>
 
 namespace cpd {
@@ -498,6 +500,17 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
 
   for (int step_i = 0; step_i < max_steps && stop == CPD_STOP_NONE; ++step_i) {
     ++k;
+    // mode 5: the epilogue after the cooperative CG (dgn_cg_coop_kernel), which left x = M^{-1/2}
+    // x_hat in X, x^T J^T J x, the CG count and the final ||r||^2 in the header
+    double rr = 0.0, grad_inf = 0.0, xjx = 0.0;
+    int its = 0, cap = 0;
+    if (mode == 5) {
+      rr = h->cg_resid;
+      its = h->its;
+      cap = h->cap;
+      grad_inf = h->grad_inf;
+      xjx = h->xjx;
+    } else {
     grams(c);
     precond(c, mu);
     // gradient, CG start r = p = M^{-1/2}(-grad), x = 0.  With the working set in global memory, W
@@ -511,7 +524,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
       gWs = stage;
       gPs = stage + c.np;
     }
-    double rr = 0.0, gi = 0.0;
+    double gi = 0.0;
     for (int e = tid; e < c.np; e += NT) {
       int l, i, r;
       split_index(c, e, l, i, r);
@@ -529,9 +542,17 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
       rr += r0 * r0;
     }
     rr = block_sum(rr, slotA);
-    const double grad_inf = block_max(gi, slotB);
-    const int cap = caps[k - 1];
-    int its = 0;
+    grad_inf = block_max(gi, slotB);
+    cap = caps[k - 1];
+    if (mode == 4) {
+      // prologue of the cooperative CG: r_0 = p_0 and x = 0 are in the state, ||r_0||^2 in the header
+      if (tid == 0) {
+        h->cg_rr0 = rr;
+        h->grad_inf = grad_inf;
+        h->cap = cap;
+      }
+      return;
+    }
     while (its < cap) {
       if (rr == 0.0) break;
       const double pz = block_sum(GW ? hv_staged(c, c.P, c.Z, mu, true, stage) : hv(c, c.P, c.Z, mu, true), slotA);
@@ -561,7 +582,8 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     }
     __syncthreads();
     // J^T J x for the predicted residual, into Z
-    const double xjx = block_sum(GW ? hv_staged(c, c.X, c.Z, 0.0, false, stage) : hv(c, c.X, c.Z, 0.0, false), slotA);
+    xjx = block_sum(GW ? hv_staged(c, c.X, c.Z, 0.0, false, stage) : hv(c, c.X, c.Z, 0.0, false), slotA);
+    }
     double gx = 0.0, xx = 0.0;
     for (int e = tid; e < c.np; e += NT) {
       gx += c.G[e] * c.X[e];
@@ -574,7 +596,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     for (int e = tid; e < c.np; e += NT) c.W[e] += c.X[e];
     __syncthreads();
     norm_balance(c, fix0);
-    if (mode == 2) {
+    if (mode == 2 || mode == 5) {
       if (tid == 0) {
         h->f2_pred = f2_pred; h->stepn = sqrt(xx); h->grad_inf = grad_inf; h->cg_resid = rr;
         h->its = its; h->cap = cap; h->pending = 1;
@@ -676,6 +698,237 @@ __global__ void dgn_tail_kernel(char* __restrict__ state) {
   h->mu = mu_new;
   h->f2 = f2_new;
   h->stop = st;
+}
+
+// ---- cooperative CG for cores whose working set lives in global memory -------------------------
+// The CG of one dGN iteration (ch.4 Alg. "Conjugate gradient - dGN" on M^{-1/2}(J^T J + mu D)
+// M^{-1/2}, the products of Thm Hv) spread over CG_WG workgroups of one cooperative launch, then
+// x = M^{-1/2} x_hat and x^T J^T J x for the epilogue.  Per CG iteration j:
+//   A: the R x R tiles of Q_b = (M^{-1/2} p_j)_b^T W_b, one tile per wave;            grid barrier
+//   B: the tiles of z_j = M^{-1/2}(J^T J + mu D) M^{-1/2} p_j and their <p_j, z_j> partials
+//      (one per workgroup, fixed order);                                             grid barrier
+//   C: every workgroup adds the partials (same order: same alpha everywhere) and the whole of
+//      ||r_j - alpha z_j||^2 (same order everywhere: same beta), then updates its own slice of
+//      x, r_{j+1}, p_{j+1} (r and p double-buffered by the parity of j).
+// Phase A of iteration j+1 forms p_{j+1} = r_j - alpha z_j + beta p_j from the parity-j buffers, so
+// no barrier is needed after C; B reads the stored p_{j+1}, which the barrier after A publishes.
+// Every exit test is taken on values that are identical in all workgroups.
+//
+// Launch and barrier: an ordinary launch of CG_WG workgroups, few enough to be resident together
+// (a cooperative launch measured ~23 us of extra latency and slowed the kernels after it).  The grid
+// barrier counts arrivals and flips a generation word in a slot of fine-grained device memory:
+// device-scope atomics on ordinary (coarse-grained) memory are performed in the L2 of the issuing
+// XCD, which the other XCDs do not see, so a counter there can miss arrivals.  Data between the
+// workgroups goes through the state with agent-scope fences around each arrival.  The wait is
+// bounded: after BAR_SPINS polls a workgroup records HDR_BAR_TIMEOUT in the header and goes on, so
+// every wave reaches the end of the kernel, and the host reports an error.
+constexpr int CG_WG = 8;   // workgroups: a grid barrier costs ~2.2 us at 8 and ~6.4 us at 48
+constexpr long long BAR_SPINS = 1ll << 22;
+
+struct BarSlot {
+  unsigned count;
+  unsigned pad0[31];   // count and generation in separate 128-byte lines
+  unsigned gen;
+  unsigned pad1[31];
+};
+
+__device__ __forceinline__ void grid_barrier(BarSlot* b, unsigned nblocks, int* flags) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();   // this workgroup's writes, visible device-wide (release)
+    const unsigned g = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const unsigned arrived = __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    } else {
+      long long spins = 0;
+      while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) == g) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > BAR_SPINS) {
+          atomicOr(flags, HDR_BAR_TIMEOUT);
+          break;
+        }
+      }
+    }
+    __threadfence();   // the other workgroups' writes (acquire)
+  }
+  __syncthreads();
+}
+
+// p_{j+1} entry e from the parity-j buffers (alpha = 0, beta = 0 reads p_j itself)
+__device__ __forceinline__ double p_next(const double* Rj, const double* Zj, const double* Pj, int e, double alpha,
+                                         double beta, int zfree) {
+  return (Rj[e] - alpha * ((e < zfree) ? 0.0 : Zj[e])) + beta * Pj[e];
+}
+
+// Phase A: Q_b tiles for V given by vf(e) (global index); rows of Q scaled by msq when scale.
+template <class VF>
+__device__ void coop_phase_a(Ctx& c, VF vf, bool scale) {
+  const int R = c.R, RR = R * R, tr = tiles16(R);
+  const int lane = threadIdx.x & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
+  const int nA = 3 * tr * tr;
+  for (int t = blockIdx.x * NW + w; t < nA; t += gridDim.x * NW) {
+    const int b = t / (tr * tr), tt = t - b * tr * tr, tm = tt / tr, tn = tt - tm * tr;
+    const int ob = offof(c, b), db = dimof(c, b);
+    const double* Wb = c.W + ob;
+    const dbl4 acc = mfma_tile(tm * 16, tn * 16, db,
+        [&](int sidx, int i) { return sel(sidx < R && i < db, vf(ob + min(i, db - 1) * R + min(sidx, R - 1))); },
+        [&](int i, int r) { return sel(r < R && i < db, Wb[min(i, db - 1) * R + min(r, R - 1)]); });
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int sidx = tm * 16 + 4 * v + kq, r = tn * 16 + r16;
+      if (sidx < R && r < R) c.Qb[b * RR + sidx * R + r] = scale ? c.msq[b * R + sidx] * acc[v] : acc[v];
+    }
+  }
+}
+
+// Phase B: out = the scaled (or plain) structured product of V (stored), tile by tile; returns this
+// thread's partial of <V, out>.
+__device__ double coop_phase_b(Ctx& c, const double* V, double* out, double mu, bool scale) {
+  const int R = c.R, RR = R * R, tr = tiles16(R);
+  const int lane = threadIdx.x & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
+  const int t0 = tiles16(c.d0) * tr, t1 = t0 + tiles16(c.d1) * tr, t2 = t1 + tiles16(c.d2) * tr;
+  double dotp = 0.0;
+  for (int t = blockIdx.x * NW + w; t < t2; t += gridDim.x * NW) {
+    const int a = (t >= t1) ? 2 : (t >= t0 ? 1 : 0);
+    const int tt = t - (a == 0 ? 0 : (a == 1 ? t0 : t1));
+    const int tm = tt / tr, tn = tt - tm * tr;
+    const int da = dimof(c, a), oa = offof(c, a);
+    const double* Va = V + oa;
+    const double* Wa = c.W + oa;
+    const double* Pa = c.Pown + a * RR;
+    const double* ma = c.msq + a * R;
+    const int b1 = (a == 0) ? 1 : 0, b2 = (a == 2) ? 1 : 2;
+    const double* pb1 = c.pi + b1 * RR;
+    const double* pb2 = c.pi + b2 * RR;
+    const double* qb1 = c.Qb + b1 * RR;
+    const double* qb2 = c.Qb + b2 * RR;
+    const dbl4 acc1 = mfma_tile(tm * 16, tn * 16, R,
+        [&](int i, int k) {
+          const int kk = min(k, R - 1);
+          const double v = Va[min(i, da - 1) * R + kk];
+          return sel(i < da && k < R, scale ? ma[kk] * v : v);
+        },
+        [&](int k, int r) { return sel(r < R && k < R, Pa[min(k, R - 1) * R + min(r, R - 1)]); });
+    const dbl4 acc2 = mfma_tile(tm * 16, tn * 16, R,
+        [&](int i, int k) { return sel(i < da && k < R, Wa[min(i, da - 1) * R + min(k, R - 1)]); },
+        [&](int k, int r) {
+          const int q = min(k, R - 1) * R + min(r, R - 1);
+          return sel(r < R && k < R, pb2[q] * qb1[q] + pb1[q] * qb2[q]);
+        });
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = tm * 16 + 4 * v + kq, r = tn * 16 + r16;
+      if (i < da && r < R) {
+        const int e = oa + i * R + r;
+        double tv = acc1[v] + acc2[v];
+        if (scale) tv = ma[r] * (tv + mu * c.gam[a * R + r] * (ma[r] * V[e]));
+        out[e] = tv;
+        dotp += V[e] * tv;
+      }
+    }
+  }
+  return dotp;
+}
+
+// Sum of the per-workgroup partials in workgroup order (the same value in every workgroup).
+__device__ __forceinline__ double sum_parts(const double* part, int n) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += part[i];
+  return s;
+}
+
+__global__ __launch_bounds__(NT) void dgn_cg_coop_kernel(char* __restrict__ state, double* __restrict__ P1,
+                                                         double* __restrict__ R1, double* __restrict__ part,
+                                                         BarSlot* __restrict__ bar) {
+  __shared__ double slots[2][NW];
+  Hdr* h = (Hdr*)state;
+  int* hflags = &h->flags;
+  const unsigned nblk = gridDim.x;
+  auto sync_all = [&]() { grid_barrier(bar, nblk, hflags); };
+  const int R = h->R;
+  const int d[3] = {h->d[0], h->d[1], h->d[2]};
+  const int np = (d[0] + d[1] + d[2]) * R;
+  const Layout Lo = layout_of(np, R, h->maxiter);
+  Ctx c;
+  setup_ctx(c, (double*)(state + Lo.work), d, R, nullptr, (double*)(state + Lo.MK), (double*)(state + Lo.G));
+  const bool fix0 = (h->flags & HDR_FIX0) != 0;
+  const int zfree = fix0 ? c.off1 : 0;
+  const double mu = h->mu, cg_tol = h->cg_tol;
+  const int cap = h->cap;
+  double rr = h->cg_rr0;
+  double* Pb[2] = {c.P, P1};
+  double* Rb[2] = {c.Rv, R1};
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const int chunk = (np + G - 1) / G, e0 = g * chunk, e1 = min(np, e0 + chunk);
+  int its = 0, par = 0;
+  double alpha = 0.0, beta = 0.0;   // of the previous iteration (p_0 is stored)
+  bool first = true;
+  while (its < cap) {
+    if (rr == 0.0) break;
+    const double* Rj = Rb[par];
+    const double* Pj = Pb[par];
+    // A: Q from p_j (p_0 stored by the prologue; later p_j from the previous parity's buffers)
+    {
+      const double* Rq = Rb[par ^ 1];
+      const double* Pq = Pb[par ^ 1];
+      const double* Zq = c.Z;
+      const double al = alpha, be = beta;
+      if (first)
+        coop_phase_a(c, [&](int e) { return Pj[e]; }, true);
+      else
+        coop_phase_a(c, [&](int e) { return p_next(Rq, Zq, Pq, e, al, be, zfree); }, true);
+    }
+    sync_all();
+    // B: z_j and <p_j, z_j>
+    const double dp = block_sum(coop_phase_b(c, Pj, c.Z, mu, true), slots[0]);
+    if (tid == 0) part[g] = dp;
+    sync_all();
+    const double pz = sum_parts(part, G);
+    if (!(pz > 0.0)) break;
+    alpha = rr / pz;
+    // C: eps = ||r_j - alpha z_j||^2 over the whole vector, the same in every workgroup
+    double eps = 0.0;
+    for (int e = tid; e < np; e += NT) {
+      const double rv = Rj[e] - alpha * ((e < zfree) ? 0.0 : c.Z[e]);
+      eps += rv * rv;
+    }
+    eps = block_sum(eps, slots[1]);
+    beta = eps / rr;
+    double* Rn = Rb[par ^ 1];
+    double* Pn = Pb[par ^ 1];
+    for (int e = e0 + tid; e < e1; e += NT) {
+      c.X[e] += alpha * Pj[e];
+      const double rv = Rj[e] - alpha * ((e < zfree) ? 0.0 : c.Z[e]);
+      Rn[e] = rv;
+      Pn[e] = rv + beta * Pj[e];
+    }
+    rr = eps;
+    ++its;
+    par ^= 1;
+    first = false;
+    if (eps < cg_tol) break;
+  }
+  sync_all();
+  // x = M^{-1/2} x_hat on the own slice
+  for (int e = e0 + tid; e < e1; e += NT) {
+    int l, i, r;
+    split_index(c, e, l, i, r);
+    c.X[e] *= c.msq[l * R + r];
+  }
+  sync_all();
+  // x^T J^T J x: the same two phases on x, unscaled
+  coop_phase_a(c, [&](int e) { return c.X[e]; }, false);
+  sync_all();
+  const double xp = block_sum(coop_phase_b(c, c.X, c.Z, 0.0, false), slots[0]);
+  if (tid == 0) part[g] = xp;
+  sync_all();
+  if (g == 0 && tid == 0) {
+    h->xjx = sum_parts(part, G);
+    h->its = its;
+    h->cg_resid = rr;
+  }
 }
 
 // Finishes an initialisation whose residual ||S - [[W]]||^2 (into f2_new) and MTTKRP (into the
@@ -852,6 +1105,44 @@ int cg_cap_for(int k, double u) {
 }
 
 size_t full_aux_bytes(const int d[3], int R);
+size_t full_kernels_aux_bytes(const int d[3], int R);
+size_t coop_cg_bytes(int np);
+
+namespace {
+// Barrier slots of the multi-workgroup CG: one pool of fine-grained device memory per device,
+// allocated and zeroed on first use and held until the process ends (the barrier leaves a slot's
+// count at zero, so it needs no reset between launches).  A host thread keeps its own slot: calls
+// on one thread are ordered (every solve synchronises), and different threads never share one.
+constexpr int BAR_POOL = 256;
+constexpr int BAR_MAX_DEVICES = 64;
+BarSlot* g_bar_pool[BAR_MAX_DEVICES];
+std::mutex g_bar_mu;
+std::atomic<int> g_bar_next{0};
+
+cpd_status barrier_slot(BarSlot** out) {
+  int dev = 0;
+  CPD_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= BAR_MAX_DEVICES) {
+    set_error("dgn: device %d beyond %d", dev, BAR_MAX_DEVICES);
+    return CPD_E_UNSUPPORTED;
+  }
+  static thread_local int slot = -1;
+  if (slot < 0) slot = g_bar_next.fetch_add(1) % BAR_POOL;
+  std::lock_guard<std::mutex> lk(g_bar_mu);
+  if (g_bar_pool[dev] == nullptr) {
+    void* p = nullptr;
+    hipError_t e = hipExtMallocWithFlags(&p, sizeof(BarSlot) * BAR_POOL, hipDeviceMallocFinegrained);
+    if (e == hipSuccess) e = hipMemset(p, 0, sizeof(BarSlot) * BAR_POOL);
+    if (e != hipSuccess) {
+      set_error("dgn: barrier pool allocation failed: %s", hipGetErrorString(e));
+      return CPD_E_HIP;
+    }
+    g_bar_pool[dev] = (BarSlot*)p;
+  }
+  *out = g_bar_pool[dev] + slot;
+  return CPD_OK;
+}
+}  // namespace
 
 namespace {
 // LDS of the staged large-core kernel: hv_staged's operands, or W and the three Pi^(l) for the
@@ -910,7 +1201,7 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
     double* MK = (double*)(state + Lo.MK);
     double* MKp[3] = {MK, MK + d[0] * R, MK + (d[0] + d[1]) * R};
     char* aux = state + align_up(Lo.total, 256);
-    const size_t aux_bytes = lds_ok ? dgn_aux_bytes(d, R) : full_aux_bytes(d, R);
+    const size_t aux_bytes = full_kernels_aux_bytes(d, R);   // the cooperative CG's buffers follow
     double* f2_new = (double*)(state + offsetof(Hdr, f2_new));
     if (mode == 0) {
       hipLaunchKernelGGL((dgn_kernel_g<3, false>), dim3(1), dim3(NT), 0, s, state, S, max_steps);
@@ -926,14 +1217,28 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
     const size_t stage_b = hv_stage_doubles(d, R) * sizeof(double);
     const bool stg = stage_b <= LDS_LIMIT;
     if (stg && stage_b > 64 * 1024)
-      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel_g<2, true>,
+      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel_g<4, true>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)stage_b));
+    // buffers of the cooperative CG behind the full-tensor kernels' workspace
+    double* cbuf = (double*)(aux + aux_bytes);
+    double* cP1 = cbuf;
+    double* cR1 = cbuf + np;
+    double* cpart = cbuf + 2 * (size_t)np;
+    BarSlot* bar = nullptr;
+    cpd_status bst = barrier_slot(&bar);
+    if (bst) return bst;
     constexpr int CHUNK = 4;
     for (int done = 0; done < max_steps; done += CHUNK) {
       const int n = (max_steps - done < CHUNK) ? max_steps - done : CHUNK;
       for (int j = 0; j < n; ++j) {
-        if (stg) hipLaunchKernelGGL((dgn_kernel_g<2, true>), dim3(1), dim3(NT), stage_b, s, state, S, 1);
-        else hipLaunchKernelGGL((dgn_kernel_g<2, false>), dim3(1), dim3(NT), 0, s, state, S, 1);
+        // gradient and CG start (one workgroup), the CG and x^T J^T J x (CG_WG cooperative
+        // workgroups), the balanced update (one workgroup)
+        if (stg) hipLaunchKernelGGL((dgn_kernel_g<4, true>), dim3(1), dim3(NT), stage_b, s, state, S, 1);
+        else hipLaunchKernelGGL((dgn_kernel_g<4, false>), dim3(1), dim3(NT), 0, s, state, S, 1);
+        CPD_LAUNCH_CHECK();
+        hipLaunchKernelGGL(dgn_cg_coop_kernel, dim3(CG_WG), dim3(NT), 0, s, state, cP1, cR1, cpart, bar);
+        CPD_LAUNCH_CHECK();
+        hipLaunchKernelGGL((dgn_kernel_g<5, false>), dim3(1), dim3(NT), 0, s, state, S, 1);
         CPD_LAUNCH_CHECK();
         cpd_status st;
         for (int l = 0; l < 3; ++l)
@@ -964,6 +1269,13 @@ size_t dgn_aux_bytes(const int d[3], int R) {
 }
 
 size_t full_aux_bytes(const int d[3], int R) {
+  return full_kernels_aux_bytes(d, R) + coop_cg_bytes((d[0] + d[1] + d[2]) * R);
+}
+
+// The cooperative CG's second r and p buffers and its per-workgroup partials.
+size_t coop_cg_bytes(int np) { return align_up(((size_t)2 * np + 64) * sizeof(double), 256); }
+
+size_t full_kernels_aux_bytes(const int d[3], int R) {
   const int64_t dims[3] = {d[0], d[1], d[2]};
   size_t b = residual_ws_bytes(dims);
   for (int l = 0; l < 3; ++l) {
@@ -1192,6 +1504,10 @@ cpd_status state_read(void* state, int* k, int* stop, int* tol_iter, double* err
   Hdr h;
   CPD_HIP_CHECK(hipMemcpyAsync(&h, state, sizeof(h), hipMemcpyDeviceToHost, s));
   CPD_HIP_CHECK(hipStreamSynchronize(s));
+  if (h.flags & HDR_BAR_TIMEOUT) {
+    set_error("dgn: a grid barrier of the multi-workgroup CG timed out");
+    return CPD_E_HIP;
+  }
   if (k) *k = h.k;
   if (stop) *stop = h.stop;
   if (tol_iter) *tol_iter = h.tol_iter;

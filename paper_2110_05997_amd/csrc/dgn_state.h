@@ -18,6 +18,9 @@ constexpr int32_t HDR_PRESET = 4;
 // HDR_FIX0: the first factor is fixed (the Bi-CPD of the tensor-train route): its block of the step,
 // gradient and CG vectors stays zero and only modes 2 and 3 are balanced
 constexpr int32_t HDR_FIX0 = 8;
+// HDR_BAR_TIMEOUT: a grid barrier of the multi-workgroup CG stopped waiting (the results are invalid)
+constexpr int32_t HDR_BAR_TIMEOUT = 16;
+
 
 struct Hdr {
   int32_t d[3];
@@ -31,6 +34,8 @@ struct Hdr {
   // device wall-clock ticks (constant-rate counter): end of initialisation, and the end of the
   // first iteration whose error fell below tol (valid when tol_iter > 0)
   int64_t t_init, t_tol;
+  // the cooperative CG of a large core: ||r_0||^2 from the prologue, x^T J^T J x for the epilogue
+  double cg_rr0, xjx;
 };
 static_assert(sizeof(Hdr) <= 256, "header must fit its slot");
 
