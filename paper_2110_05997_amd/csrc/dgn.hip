@@ -500,17 +500,8 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
 
   for (int step_i = 0; step_i < max_steps && stop == CPD_STOP_NONE; ++step_i) {
     ++k;
-    // mode 5: the epilogue after the cooperative CG (dgn_cg_coop_kernel), which left x = M^{-1/2}
-    // x_hat in X, x^T J^T J x, the CG count and the final ||r||^2 in the header
     double rr = 0.0, grad_inf = 0.0, xjx = 0.0;
     int its = 0, cap = 0;
-    if (mode == 5) {
-      rr = h->cg_resid;
-      its = h->its;
-      cap = h->cap;
-      grad_inf = h->grad_inf;
-      xjx = h->xjx;
-    } else {
     grams(c);
     precond(c, mu);
     // gradient, CG start r = p = M^{-1/2}(-grad), x = 0.  With the working set in global memory, W
@@ -544,15 +535,6 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     rr = block_sum(rr, slotA);
     grad_inf = block_max(gi, slotB);
     cap = caps[k - 1];
-    if (mode == 4) {
-      // prologue of the cooperative CG: r_0 = p_0 and x = 0 are in the state, ||r_0||^2 in the header
-      if (tid == 0) {
-        h->cg_rr0 = rr;
-        h->grad_inf = grad_inf;
-        h->cap = cap;
-      }
-      return;
-    }
     while (its < cap) {
       if (rr == 0.0) break;
       const double pz = block_sum(GW ? hv_staged(c, c.P, c.Z, mu, true, stage) : hv(c, c.P, c.Z, mu, true), slotA);
@@ -583,7 +565,6 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     __syncthreads();
     // J^T J x for the predicted residual, into Z
     xjx = block_sum(GW ? hv_staged(c, c.X, c.Z, 0.0, false, stage) : hv(c, c.X, c.Z, 0.0, false), slotA);
-    }
     double gx = 0.0, xx = 0.0;
     for (int e = tid; e < c.np; e += NT) {
       gx += c.G[e] * c.X[e];
@@ -596,7 +577,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     for (int e = tid; e < c.np; e += NT) c.W[e] += c.X[e];
     __syncthreads();
     norm_balance(c, fix0);
-    if (mode == 2 || mode == 5) {
+    if (mode == 2) {
       if (tid == 0) {
         h->f2_pred = f2_pred; h->stepn = sqrt(xx); h->grad_inf = grad_inf; h->cg_resid = rr;
         h->its = its; h->cap = cap; h->pending = 1;
@@ -832,6 +813,9 @@ __device__ double coop_phase_b(Ctx& c, const double* V, double* out, double mu, 
   return dotp;
 }
 
+// Column-norm scratch of the iteration kernel's step 5: the M^{-1/2} slots, no longer needed then.
+__device__ __forceinline__ double* slots_cn(Ctx& c) { return c.msq; }
+
 // Sum of the per-workgroup partials in workgroup order (the same value in every workgroup).
 __device__ __forceinline__ double sum_parts(const double* part, int n) {
   double s = 0.0;
@@ -839,37 +823,112 @@ __device__ __forceinline__ double sum_parts(const double* part, int n) {
   return s;
 }
 
-__global__ __launch_bounds__(NT) void dgn_cg_coop_kernel(char* __restrict__ state, double* __restrict__ P1,
-                                                         double* __restrict__ R1, double* __restrict__ part,
-                                                         BarSlot* __restrict__ bar) {
+// One dGN iteration (ch.4 "dGN") of a core whose working set lives in global memory, on CG_WG
+// workgroups: everything but the core's residual and MTTKRPs (the full-tensor kernels compute them
+// next from the updated factors) and the scalar tail.  The factors are read and updated in the
+// state's W region; Pi, M^{-1/2} and D sit in each workgroup's LDS.
+//   1. pi^(l) = W^(l)T W^(l) tiles (one per wave);                                 barrier
+//   2. every workgroup: Pi^(l), the gammas and M^{-1/2}; gradient W Pi - MTTKRP on its own slice of
+//      the parameter vector, r_0 = p_0 = M^{-1/2}(-grad), x = 0; partials of ||r_0||^2, max|g|; barrier
+//   3. the CG described above, then x = M^{-1/2} x_hat and x^T J^T J x;
+//   4. own slice: grad.x, x.x partials, w <- w + x and that slice's part of every column norm; barrier
+//   5. every workgroup: the column norms (partials added in workgroup order), norm balancing of its
+//      slice; workgroup 0 writes the step's values to the header for the tail.
+// Dynamic LDS: 3 R^2 + 6 R doubles.
+__global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ state, double* __restrict__ P1,
+                                                           double* __restrict__ R1, double* __restrict__ part,
+                                                           BarSlot* __restrict__ bar) {
+  extern __shared__ double lds_c[];
   __shared__ double slots[2][NW];
   Hdr* h = (Hdr*)state;
+  if (h->stop != CPD_STOP_NONE) return;   // the header is the same for every workgroup
   int* hflags = &h->flags;
   const unsigned nblk = gridDim.x;
   auto sync_all = [&]() { grid_barrier(bar, nblk, hflags); };
-  const int R = h->R;
+  const int R = h->R, RR = R * R;
   const int d[3] = {h->d[0], h->d[1], h->d[2]};
   const int np = (d[0] + d[1] + d[2]) * R;
   const Layout Lo = layout_of(np, R, h->maxiter);
   Ctx c;
   setup_ctx(c, (double*)(state + Lo.work), d, R, nullptr, (double*)(state + Lo.MK), (double*)(state + Lo.G));
+  c.W = (double*)(state + Lo.W);
+  c.Pown = lds_c;
+  c.msq = lds_c + 3 * RR;
+  c.gam = c.msq + 3 * R;
+  const int* caps = (const int*)(state + Lo.caps);
   const bool fix0 = (h->flags & HDR_FIX0) != 0;
   const int zfree = fix0 ? c.off1 : 0;
   const double mu = h->mu, cg_tol = h->cg_tol;
-  const int cap = h->cap;
-  double rr = h->cg_rr0;
-  double* Pb[2] = {c.P, P1};
-  double* Rb[2] = {c.Rv, R1};
+  const int k = h->k + 1;
+  const int cap = caps[k - 1];
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int chunk = (np + G - 1) / G, e0 = g * chunk, e1 = min(np, e0 + chunk);
+  const int tr = tiles16(R);
+  const int lane = tid & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
+
+  // 1. factor Grams
+  for (int t = g * NW + w; t < 3 * tr * tr; t += G * NW) {
+    const int l = t / (tr * tr), tt = t - l * tr * tr, tm = tt / tr, tn = tt - tm * tr;
+    const double* Wl = c.W + offof(c, l);
+    const int dl = dimof(c, l);
+    const dbl4 acc = mfma_tile(tm * 16, tn * 16, dl,
+        [&](int r, int i) { return sel(r < R && i < dl, Wl[min(i, dl - 1) * R + min(r, R - 1)]); },
+        [&](int i, int q) { return sel(q < R && i < dl, Wl[min(i, dl - 1) * R + min(q, R - 1)]); });
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = tm * 16 + 4 * v + kq, q = tn * 16 + r16;
+      if (r < R && q < R) c.pi[l * RR + r * R + q] = acc[v];
+    }
+  }
+  sync_all();
+  // 2. Pi, D, M^{-1/2} (each workgroup for itself, same values), gradient and CG start on the slice
+  for (int e = tid; e < RR; e += NT) {
+    const double a = c.pi[e], b = c.pi[RR + e], dd = c.pi[2 * RR + e];
+    c.Pown[e] = b * dd;
+    c.Pown[RR + e] = a * dd;
+    c.Pown[2 * RR + e] = a * b;
+  }
+  __syncthreads();
+  precond(c, mu);
+  double rr = 0.0, gi = 0.0;
+  for (int e = e0 + tid; e < e1; e += NT) {
+    int l, i, r;
+    split_index(c, e, l, i, r);
+    const double* Wi = c.W + offof(c, l) + i * R;
+    const double* Pl = c.Pown + l * RR;
+    double acc = 0.0;
+    for (int s2 = 0; s2 < R; ++s2) acc += Wi[s2] * Pl[s2 * R + r];
+    const double gv = (fix0 && l == 0) ? 0.0 : acc - c.MK[e];   // a fixed factor has no step
+    c.G[e] = gv;
+    gi = fmax(gi, fabs(gv));
+    const double r0 = c.msq[l * R + r] * (-gv);
+    c.Rv[e] = r0;
+    c.P[e] = r0;
+    c.X[e] = 0.0;
+    rr += r0 * r0;
+  }
+  rr = block_sum(rr, slots[0]);
+  gi = block_max(gi, slots[1]);
+  if (tid == 0) {
+    part[g] = rr;
+    part[G + g] = gi;
+  }
+  sync_all();
+  rr = sum_parts(part, G);
+  double grad_inf = 0.0;
+  for (int q = 0; q < G; ++q) grad_inf = fmax(grad_inf, part[G + q]);
+
+  // 3. CG
+  double* Pb[2] = {c.P, P1};
+  double* Rb[2] = {c.Rv, R1};
   int its = 0, par = 0;
-  double alpha = 0.0, beta = 0.0;   // of the previous iteration (p_0 is stored)
+  double alpha = 0.0, beta = 0.0;   // of the previous CG iteration (p_0 is stored)
   bool first = true;
   while (its < cap) {
     if (rr == 0.0) break;
     const double* Rj = Rb[par];
     const double* Pj = Pb[par];
-    // A: Q from p_j (p_0 stored by the prologue; later p_j from the previous parity's buffers)
+    // A: Q from p_j (p_0 stored; later p_j formed from the previous parity's buffers)
     {
       const double* Rq = Rb[par ^ 1];
       const double* Pq = Pb[par ^ 1];
@@ -888,7 +947,7 @@ __global__ __launch_bounds__(NT) void dgn_cg_coop_kernel(char* __restrict__ stat
     const double pz = sum_parts(part, G);
     if (!(pz > 0.0)) break;
     alpha = rr / pz;
-    // C: eps = ||r_j - alpha z_j||^2 over the whole vector, the same in every workgroup
+    // C: ||r_j - alpha z_j||^2 over the whole vector (the same in every workgroup), own slice update
     double eps = 0.0;
     for (int e = tid; e < np; e += NT) {
       const double rv = Rj[e] - alpha * ((e < zfree) ? 0.0 : c.Z[e]);
@@ -924,10 +983,69 @@ __global__ __launch_bounds__(NT) void dgn_cg_coop_kernel(char* __restrict__ stat
   const double xp = block_sum(coop_phase_b(c, c.X, c.Z, 0.0, false), slots[0]);
   if (tid == 0) part[g] = xp;
   sync_all();
+  const double xjx = sum_parts(part, G);
+
+  // 4. own slice: grad.x, x.x, the update, and the slice's share of every column norm
+  double gx = 0.0, xx = 0.0;
+  for (int e = e0 + tid; e < e1; e += NT) {
+    const double xv = c.X[e];
+    gx += c.G[e] * xv;
+    xx += xv * xv;
+    c.W[e] += xv;
+  }
+  gx = block_sum(gx, slots[0]);
+  xx = block_sum(xx, slots[1]);
+  double* colp = part + 2 * CG_WG;   // CG_WG rows of 3R column partials
+  for (int q = tid; q < 3 * R; q += NT) {
+    const int l = q / R, r = q - l * R;
+    const int ol = offof(c, l), dl = dimof(c, l);
+    // rows i of mode l whose entry ol + i R + r lies in [e0, e1)
+    int ib = (e0 - ol - r + R - 1) / R;
+    if (e0 <= ol + r) ib = 0;
+    double acc = 0.0;
+    for (int i = ib; i < dl; ++i) {
+      const int e = ol + i * R + r;
+      if (e >= e1) break;
+      acc += c.W[e] * c.W[e];
+    }
+    colp[g * 3 * R + q] = acc;
+  }
+  if (tid == 0) {
+    part[g] = gx;
+    part[G + g] = xx;
+  }
+  sync_all();
+  // 5. column norms, balancing of the own slice, header
+  gx = sum_parts(part, G);
+  xx = sum_parts(part + G, G);
+  double* cn = slots_cn(c);   // 3R doubles of LDS (reuses msq: no longer needed)
+  for (int q = tid; q < 3 * R; q += NT) {
+    double s2 = 0.0;
+    for (int q2 = 0; q2 < G; ++q2) s2 += colp[q2 * 3 * R + q];
+    cn[q] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int e = e0 + tid; e < e1; e += NT) {
+    int l, i, r;
+    split_index(c, e, l, i, r);
+    const double n0 = cn[r], n1 = cn[R + r], n2 = cn[2 * R + r];
+    if (fix0) {
+      if (l == 0 || fmin(n1, n2) == 0.0) continue;
+      c.W[e] *= sqrt(n1 * n2) / cn[l * R + r];
+      continue;
+    }
+    if (fmin(n0, fmin(n1, n2)) == 0.0) continue;
+    c.W[e] *= pow(n0 * n1 * n2, 1.0 / 3.0) / cn[l * R + r];
+  }
   if (g == 0 && tid == 0) {
-    h->xjx = sum_parts(part, G);
-    h->its = its;
+    h->f2_pred = h->f2 + 2.0 * gx + xjx;
+    h->stepn = sqrt(xx);
+    h->grad_inf = grad_inf;
     h->cg_resid = rr;
+    h->its = its;
+    h->cap = cap;
+    h->pending = 1;
+    h->k = k;
   }
 }
 
@@ -1214,12 +1332,12 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
       CPD_LAUNCH_CHECK();
       return CPD_OK;
     }
-    const size_t stage_b = hv_stage_doubles(d, R) * sizeof(double);
-    const bool stg = stage_b <= LDS_LIMIT;
-    if (stg && stage_b > 64 * 1024)
-      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel_g<4, true>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)stage_b));
-    // buffers of the cooperative CG behind the full-tensor kernels' workspace
+    // Pi, M^{-1/2} and D of the iteration kernel in LDS
+    const size_t it_lds = ((size_t)3 * R * R + 6 * (size_t)R) * sizeof(double);
+    if (it_lds > 64 * 1024)
+      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_iter_coop_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)it_lds));
+    // buffers of the multi-workgroup iteration behind the full-tensor kernels' workspace
     double* cbuf = (double*)(aux + aux_bytes);
     double* cP1 = cbuf;
     double* cR1 = cbuf + np;
@@ -1231,14 +1349,8 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
     for (int done = 0; done < max_steps; done += CHUNK) {
       const int n = (max_steps - done < CHUNK) ? max_steps - done : CHUNK;
       for (int j = 0; j < n; ++j) {
-        // gradient and CG start (one workgroup), the CG and x^T J^T J x (CG_WG cooperative
-        // workgroups), the balanced update (one workgroup)
-        if (stg) hipLaunchKernelGGL((dgn_kernel_g<4, true>), dim3(1), dim3(NT), stage_b, s, state, S, 1);
-        else hipLaunchKernelGGL((dgn_kernel_g<4, false>), dim3(1), dim3(NT), 0, s, state, S, 1);
-        CPD_LAUNCH_CHECK();
-        hipLaunchKernelGGL(dgn_cg_coop_kernel, dim3(CG_WG), dim3(NT), 0, s, state, cP1, cR1, cpart, bar);
-        CPD_LAUNCH_CHECK();
-        hipLaunchKernelGGL((dgn_kernel_g<5, false>), dim3(1), dim3(NT), 0, s, state, S, 1);
+        // Grams, gradient, CG, x^T J^T J x and the balanced update on CG_WG workgroups
+        hipLaunchKernelGGL(dgn_iter_coop_kernel, dim3(CG_WG), dim3(NT), it_lds, s, state, cP1, cR1, cpart, bar);
         CPD_LAUNCH_CHECK();
         cpd_status st;
         for (int l = 0; l < 3; ++l)
@@ -1272,8 +1384,11 @@ size_t full_aux_bytes(const int d[3], int R) {
   return full_kernels_aux_bytes(d, R) + coop_cg_bytes((d[0] + d[1] + d[2]) * R);
 }
 
-// The cooperative CG's second r and p buffers and its per-workgroup partials.
-size_t coop_cg_bytes(int np) { return align_up(((size_t)2 * np + 64) * sizeof(double), 256); }
+// The multi-workgroup iteration's second r and p buffers and its per-workgroup partials.
+size_t coop_cg_bytes(int np) {
+  // second r and p buffers; scalar partials (2 CG_WG) and column-norm partials (CG_WG x 3R, R <= 64)
+  return align_up(((size_t)2 * np + 2 * CG_WG + (size_t)CG_WG * 3 * 64) * sizeof(double), 256);
+}
 
 size_t full_kernels_aux_bytes(const int d[3], int R) {
   const int64_t dims[3] = {d[0], d[1], d[2]};

@@ -34,8 +34,6 @@ struct Hdr {
   // device wall-clock ticks (constant-rate counter): end of initialisation, and the end of the
   // first iteration whose error fell below tol (valid when tol_iter > 0)
   int64_t t_init, t_tol;
-  // the cooperative CG of a large core: ||r_0||^2 from the prologue, x^T J^T J x for the epilogue
-  double cg_rr0, xjx;
 };
 static_assert(sizeof(Hdr) <= 256, "header must fit its slot");
 
