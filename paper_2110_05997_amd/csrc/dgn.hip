@@ -753,7 +753,7 @@ __device__ void coop_phase_a(Ctx& c, VF vf, bool scale) {
     const int b = t / (tr * tr), tt = t - b * tr * tr, tm = tt / tr, tn = tt - tm * tr;
     const int ob = offof(c, b), db = dimof(c, b);
     const double* Wb = c.W + ob;
-    const dbl4 acc = mfma_tile(tm * 16, tn * 16, db,
+    const dbl4 acc = mfma_tile_wide(tm * 16, tn * 16, db,
         [&](int sidx, int i) { return sel(sidx < R && i < db, vf(ob + min(i, db - 1) * R + min(sidx, R - 1))); },
         [&](int i, int r) { return sel(r < R && i < db, Wb[min(i, db - 1) * R + min(r, R - 1)]); });
 #pragma unroll
@@ -785,14 +785,14 @@ __device__ double coop_phase_b(Ctx& c, const double* V, double* out, double mu, 
     const double* pb2 = c.pi + b2 * RR;
     const double* qb1 = c.Qb + b1 * RR;
     const double* qb2 = c.Qb + b2 * RR;
-    const dbl4 acc1 = mfma_tile(tm * 16, tn * 16, R,
+    const dbl4 acc1 = mfma_tile_wide(tm * 16, tn * 16, R,
         [&](int i, int k) {
           const int kk = min(k, R - 1);
           const double v = Va[min(i, da - 1) * R + kk];
           return sel(i < da && k < R, scale ? ma[kk] * v : v);
         },
         [&](int k, int r) { return sel(r < R && k < R, Pa[min(k, R - 1) * R + min(r, R - 1)]); });
-    const dbl4 acc2 = mfma_tile(tm * 16, tn * 16, R,
+    const dbl4 acc2 = mfma_tile_wide(tm * 16, tn * 16, R,
         [&](int i, int k) { return sel(i < da && k < R, Wa[min(i, da - 1) * R + min(k, R - 1)]); },
         [&](int k, int r) {
           const int q = min(k, R - 1) * R + min(r, R - 1);
@@ -871,7 +871,7 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
     const int l = t / (tr * tr), tt = t - l * tr * tr, tm = tt / tr, tn = tt - tm * tr;
     const double* Wl = c.W + offof(c, l);
     const int dl = dimof(c, l);
-    const dbl4 acc = mfma_tile(tm * 16, tn * 16, dl,
+    const dbl4 acc = mfma_tile_wide(tm * 16, tn * 16, dl,
         [&](int r, int i) { return sel(r < R && i < dl, Wl[min(i, dl - 1) * R + min(r, R - 1)]); },
         [&](int i, int q) { return sel(q < R && i < dl, Wl[min(i, dl - 1) * R + min(q, R - 1)]); });
 #pragma unroll
@@ -949,6 +949,7 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
     alpha = rr / pz;
     // C: ||r_j - alpha z_j||^2 over the whole vector (the same in every workgroup), own slice update
     double eps = 0.0;
+#pragma unroll 8
     for (int e = tid; e < np; e += NT) {
       const double rv = Rj[e] - alpha * ((e < zfree) ? 0.0 : c.Z[e]);
       eps += rv * rv;
@@ -957,6 +958,7 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
     beta = eps / rr;
     double* Rn = Rb[par ^ 1];
     double* Pn = Pb[par ^ 1];
+#pragma unroll 2
     for (int e = e0 + tid; e < e1; e += NT) {
       c.X[e] += alpha * Pj[e];
       const double rv = Rj[e] - alpha * ((e < zfree) ? 0.0 : c.Z[e]);
