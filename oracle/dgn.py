@@ -169,6 +169,73 @@ def pcg(Ws, pis, gammas, mu, rhs, M, cap, cg_tol):
     return [xv * s for xv, s in zip(x, msq)], its, rr
 
 
+def block_factors(pis, gammas, mu):
+    """Block-Jacobi preconditioner (the block-diagonal preconditioner of ch.4 "Tensor Fox vs. other
+    implementations" and the Conclusions): the diagonal blocks of J^T J + mu D.  Block l acts on
+    V^(l) as V^(l) K_l with K_l = Pi^(l) + mu diag(gamma_l) (ch.3 block structure of J^T J), so it is
+    K_l (x) I in vec form.  Returns the inverses C_l^{-1} of the Cholesky factors K_l = C_l C_l^T."""
+    out = []
+    for l in range(len(pis)):
+        K = pi_own(pis, l) + mu * np.diag(gammas[l])
+        C = np.linalg.cholesky(K)
+        out.append(np.linalg.inv(C))
+    return out
+
+
+def pcg_block(Ws, pis, gammas, mu, rhs, Cinv, cap, cg_tol):
+    """The CG of ``pcg`` with the block-Jacobi split L = C (x) I: CG on
+    L^{-1} (J^T J + mu D) L^{-T} x_hat = L^{-1} rhs, x = L^{-T} x_hat.  In block form
+    L^{-1} V = V C^{-T} and L^{-T} V = V C^{-1}; same loop, same breakdown guards."""
+    lt = lambda Vs: [V @ Ci for V, Ci in zip(Vs, Cinv)]           # L^{-T}
+    li = lambda Vs: [V @ Ci.T for V, Ci in zip(Vs, Cinv)]         # L^{-1}
+    x = [np.zeros_like(W) for W in Ws]
+    r = li(rhs)
+    p = [v.copy() for v in r]
+    rr = dot(r, r)
+    its = 0
+    for _ in range(cap):
+        if rr == 0.0:
+            break
+        u = lt(p)
+        ju = jtj_v(Ws, pis, u)
+        z = li([j + mu * g * v for j, g, v in zip(ju, gammas, u)])
+        pz = dot(p, z)
+        if not pz > 0.0:
+            break
+        alpha = rr / pz
+        x = [xv + alpha * pv for xv, pv in zip(x, p)]
+        r = [rv - alpha * zv for rv, zv in zip(r, z)]
+        eps = dot(r, r)
+        beta = eps / rr
+        p = [rv + beta * pv for rv, pv in zip(r, p)]
+        rr = eps
+        its += 1
+        if eps < cg_tol:
+            break
+    return lt(x), its, rr
+
+
+def dogleg(h_gn, g, jg2, delta):
+    """Dogleg step inside the trust radius delta (Madsen, Nielsen & Tingleff, the method ch.4
+    "Conditioning" applies after a draw-back): the Gauss-Newton step h_gn if it fits; else the
+    steepest-descent step -g cut at delta when the Cauchy point a = -(|g|^2/|Jg|^2) g lies outside;
+    else a + beta (h_gn - a) with beta >= 0 putting the step on the radius."""
+    ngn = math.sqrt(dot(h_gn, h_gn))
+    if ngn <= delta:
+        return h_gn
+    gg = dot(g, g)
+    alpha = gg / jg2
+    a = [-alpha * gv for gv in g]
+    na = alpha * math.sqrt(gg)
+    if na >= delta:
+        return [-(delta / math.sqrt(gg)) * gv for gv in g]
+    d = [hv - av for hv, av in zip(h_gn, a)]
+    c = dot(a, d)
+    dd = dot(d, d)
+    beta = (-c + math.sqrt(c * c + dd * (delta * delta - na * na))) / dd
+    return [av + beta * dv for av, dv in zip(a, d)]
+
+
 # ---------------------------------------------------------------------------
 # Updates (ch.4 "Updates")
 # ---------------------------------------------------------------------------
@@ -243,6 +310,8 @@ class Params:
     init_damp: float = 1.0
     cg_tol: float = None     # None -> tol
     cg_fixed: int = 0        # > 0: fixed CG cap instead of the random schedule
+    block_precond: bool = False   # block-Jacobi preconditioner instead of the diagonal one
+    drawback: bool = False   # draw back and take a dogleg step when the error jumps 100-fold
 
     def cg_tol_value(self):
         return self.tol if self.cg_tol is None else self.cg_tol
@@ -279,23 +348,57 @@ def init_state(S, Ws0, params, tnorm2=None):
                  errs=[math.sqrt(f2) / s_norm])
 
 
-def dgn_step(S, st, params, cap):
-    """One iteration of the Tensor Fox dGN; returns (new_state, info dict)."""
-    S = np.asarray(S, dtype=np.float64)
-    Ws = st.Ws
-    k = st.k + 1
+def step_direction(S, Ws, mu, params, cap):
+    """Gradient, Grams and the preconditioned CG step at Ws (the diagonal or block-Jacobi
+    preconditioner): returns (grad, pis, x, CG iterations, final ||r||^2)."""
     pis = grams(Ws)
     grad = gradient(S, Ws, pis)
     gammas = regularization(Ws)
-    M = preconditioner(pis, gammas, st.mu)
-    x, its, cg_res = pcg(Ws, pis, gammas, st.mu, [-g for g in grad], M, cap, params.cg_tol_value())
+    rhs = [-g for g in grad]
+    if params.block_precond:
+        x, its, cg_res = pcg_block(Ws, pis, gammas, mu, rhs, block_factors(pis, gammas, mu), cap,
+                                   params.cg_tol_value())
+    else:
+        M = preconditioner(pis, gammas, mu)
+        x, its, cg_res = pcg(Ws, pis, gammas, mu, rhs, M, cap, params.cg_tol_value())
+    return grad, pis, x, its, cg_res
+
+
+def dgn_step(S, st, params, cap):
+    """One iteration of the Tensor Fox dGN; returns (new_state, info dict).
+
+    With params.drawback, an iteration whose error exceeds 100 times the previous one (the
+    divergence test of ch.4 "Conditioning") is redone from the drawn-back point N(w_k) - x (the
+    balanced bad point shifted back by the step): a new CG step there, cut by the dogleg method to
+    the trust radius |x| / 2 (reading: half the failed step), then the usual update."""
+    S = np.asarray(S, dtype=np.float64)
+    Ws = st.Ws
+    k = st.k + 1
+    grad, pis, x, its, cg_res = step_direction(S, Ws, st.mu, params, cap)
     jx = jtj_v(Ws, pis, x)
     f2_pred = st.f2 + 2.0 * dot(grad, x) + dot(x, jx)
     Wn = norm_balance([W + dx for W, dx in zip(Ws, x)])
     fn = residual(S, Wn)
     f2_new = float(np.sum(fn * fn))
     err = math.sqrt(f2_new) / st.s_norm
-    g = gain_ratio(st.f2, f2_new, f2_pred)
+    f2_base = st.f2
+    drew_back = False
+    if params.drawback and err > 100.0 * st.errs[-1]:
+        drew_back = True
+        Wd = [W - dx for W, dx in zip(Wn, x)]
+        fd = residual(S, Wd)
+        f2_base = float(np.sum(fd * fd))
+        delta = 0.5 * math.sqrt(dot(x, x))
+        grad, pis, h_gn, its, cg_res = step_direction(S, Wd, st.mu, params, cap)
+        jg2 = dot(grad, jtj_v(Wd, pis, grad))
+        x = dogleg(h_gn, grad, jg2, delta)
+        jx = jtj_v(Wd, pis, x)
+        f2_pred = f2_base + 2.0 * dot(grad, x) + dot(x, jx)
+        Wn = norm_balance([W + dx for W, dx in zip(Wd, x)])
+        fn = residual(S, Wn)
+        f2_new = float(np.sum(fn * fn))
+        err = math.sqrt(f2_new) / st.s_norm
+    g = gain_ratio(f2_base, f2_new, f2_pred)
     mu = damping_update(st.mu, g)
     step = math.sqrt(dot(x, x))
     grad_inf = max(float(np.max(np.abs(gv))) for gv in grad)
@@ -304,7 +407,7 @@ def dgn_step(S, st, params, cap):
     new = State(Ws=Wn, mu=mu, k=k, f2=f2_new, s_norm=st.s_norm, div_ref=st.div_ref,
                 errs=errs, stop=stop)
     info = dict(k=k, cg_iters=its, cg_resid=cg_res, rel_err=err, step_norm=step,
-                grad_inf=grad_inf, gain=g, mu=mu, stop=stop, f2_pred=f2_pred)
+                grad_inf=grad_inf, gain=g, mu=mu, stop=stop, f2_pred=f2_pred, drew_back=drew_back)
     return new, info
 
 

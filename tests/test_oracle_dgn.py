@@ -528,3 +528,95 @@ def test_refinement_keeps_an_exact_solution_and_improves_a_truncated_one():
     c1 = cpd.solve(Tn, 3, pn, W0=W0n, cg_uniforms=U, core_dims=(2, 2, 2), refine_iters=8)
     assert c1["refine_iters"] >= 1
     assert c1["rel_err_full"] < 0.5 * c0["rel_err_full"]
+
+
+# ---------------------------------------------------------------------------------------------
+# Robustness variants: block-Jacobi preconditioner, draw-back + dogleg
+def test_block_jacobi_split_has_identity_diagonal_blocks():
+    """L = C (x) I with K_l = C_l C_l^T the diagonal blocks of J^T J + mu D: the preconditioned
+    operator L^{-1} (J^T J + mu D) L^{-T} has identity diagonal blocks (explicit Jacobian)."""
+    rng = np.random.default_rng(41)
+    dims, R = (4, 3, 5), 3
+    Ws = [rng.standard_normal((d, R)) for d in dims]
+    mu = 0.3
+    A, _ = dense_system(np.zeros(dims), Ws, mu)
+    Ci = dgn.block_factors(dgn.grams(Ws), dgn.regularization(Ws), mu)
+    # dense L^{-1} in the column-stacked order: block l is C_l^{-1} (x) I_{d_l}
+    blocks = [np.kron(c, np.eye(d)) for c, d in zip(Ci, dims)]
+    Linv = np.zeros_like(A)
+    o = 0
+    for B in blocks:
+        Linv[o:o + B.shape[0], o:o + B.shape[0]] = B
+        o += B.shape[0]
+    P = Linv @ A @ Linv.T
+    o = 0
+    for d in dims:
+        n = d * R
+        assert np.max(np.abs(P[o:o + n, o:o + n] - np.eye(n))) < 1e-12
+        o += n
+
+
+def test_block_jacobi_pcg_full_run_equals_cholesky():
+    rng = np.random.default_rng(42)
+    dims, R = (5, 4, 3), 3
+    Ws = [rng.standard_normal((d, R)) for d in dims]
+    S = rng.standard_normal(dims)
+    mu = 0.7
+    pis = dgn.grams(Ws)
+    gam = dgn.regularization(Ws)
+    grad = dgn.gradient(S, Ws, pis)
+    A, _ = dense_system(S, Ws, mu)
+    x_ref = np.linalg.solve(A, -vec_blocks(grad))
+    n_p = sum(dims) * R
+    x, its, _ = dgn.pcg_block(Ws, pis, gam, mu, [-g for g in grad], dgn.block_factors(pis, gam, mu), n_p, 0.0)
+    assert np.max(np.abs(vec_blocks(x) - x_ref)) < 1e-9 * np.max(np.abs(x_ref))
+
+
+def test_dogleg_step_cases():
+    """Madsen-Nielsen-Tingleff dogleg: h_gn inside the radius; the cut steepest-descent step when
+    the Cauchy point is outside; otherwise a point of the segment [a, h_gn] on the radius."""
+    g = [np.array([[1.0, 2.0]])]
+    jg2 = 2.5                                  # |Jg|^2 -> Cauchy point a = -(5 / 2.5) g = -2 g, |a| = 2 sqrt(5)
+    h = [np.array([[-10.0, 1.0]])]
+    assert dgn.dogleg(h, g, jg2, 100.0) is h
+    small = dgn.dogleg(h, g, jg2, 1.0)
+    assert np.allclose(small[0], -g[0] / np.sqrt(5.0))
+    delta = 6.0
+    mid = dgn.dogleg(h, g, jg2, delta)
+    assert abs(np.linalg.norm(mid[0]) - delta) < 1e-12
+    a = -2.0 * g[0]
+    t = (mid[0] - a) / (h[0] - a)
+    assert np.allclose(t, t[0, 0]) and 0.0 <= t[0, 0] <= 1.0
+
+
+def test_drawback_fires_only_on_a_hundredfold_error_jump():
+    """Without a jump the draw-back option changes nothing; with the previous error recorded as
+    tiny (a hundredfold jump) the iteration is redone from N(w_k) - x with a dogleg step no longer
+    than half the failed one."""
+    T, _, _ = synth.planted((8, 7, 6), 3, seed=43, noise_rel=1e-2)
+    S = np.asarray(T)
+    W0 = synth.init_factors(S.shape, 3, 43)
+    U = synth.cg_uniforms(50, 43)
+    p0, p1 = dgn.Params(maxiter=10), dgn.Params(maxiter=10, drawback=True)
+    st0, inf0 = dgn.run_dgn(S, W0, p0, cg_uniforms=U)
+    st1, inf1 = dgn.run_dgn(S, W0, p1, cg_uniforms=U)
+    assert not any(i["drew_back"] for i in inf1)
+    assert [i["rel_err"] for i in inf0] == [i["rel_err"] for i in inf1]
+    st = dgn.init_state(S, W0, p1)
+    st.errs = [1e-12]                          # plant a tiny previous error: the next step is a jump
+    cap = dgn.cg_cap(1, U[0])
+    _, plain = dgn.dgn_step(S, dgn.init_state(S, W0, p0), p0, cap)
+    _, info = dgn.dgn_step(S, st, p1, cap)
+    assert info["drew_back"]
+    assert info["step_norm"] <= 0.5 * plain["step_norm"] * (1 + 1e-12)
+
+
+def test_block_jacobi_dgn_reaches_the_noise_floor():
+    """On a planted rank-4 tensor with 1e-4 relative noise the block-Jacobi dGN reaches the
+    noise floor like the diagonal one."""
+    T, _, _ = synth.planted((12, 11, 10), 4, seed=5, noise_rel=1e-4)
+    S = np.asarray(T)
+    W0 = synth.init_factors(S.shape, 4, 5)
+    _, info = dgn.run_dgn(S, W0, dgn.Params(maxiter=100, block_precond=True),
+                          cg_uniforms=synth.cg_uniforms(200, 5))
+    assert info[-1]["rel_err"] < 1.5e-4
