@@ -90,6 +90,16 @@ typedef struct {
                                mode l's Gram, eigenvectors and truncation are taken on the tensor
                                already projected in modes 1..l-1; default 0 (the classic truncated
                                MLSVD of ch.4 Alg. Compression) */
+  int32_t precond;          /* CG preconditioner: 0 (default) the diagonal M = diag(J^T J) + mu D
+                               of ch.4; 1 block-Jacobi, the diagonal blocks Pi^(l) + mu diag(gamma_l)
+                               of J^T J + mu D split by their Cholesky factors (the block-diagonal
+                               preconditioner of ch.4 "Tensor Fox vs. other implementations").
+                               Cores whose dGN runs in one workgroup's LDS only; others, the batched
+                               solver and the tensor-train route return CPD_E_UNSUPPORTED */
+  int32_t drawback;         /* nonzero: when an iteration's error exceeds 100 times the previous
+                               one (ch.4 "Conditioning"), redo it from N(w_k) - x, the balanced
+                               point drawn back by the step x, with a dogleg step inside the trust
+                               radius ||x|| / 2 (Madsen-Nielsen-Tingleff).  Same support as precond */
 } cpd_params;
 
 /* Fills the thesis's defaults (maxiter 200, tol 1e-6, mlsvd_tol 1e-6, tau 1, random CG cap). */
@@ -109,6 +119,9 @@ typedef struct {
   double cg_resid;       /* final ||r||^2 of CG */
   int64_t t_ns;          /* device time at the end of this iteration, in ns since the state's
                             initialisation ended (in-kernel wall-clock stamps) */
+  int32_t drew_back;     /* 1 if the iteration was redone from the drawn-back point
+                            (cpd_params.drawback) */
+  int32_t reserved;      /* 0 */
 } cpd_step_info;
 
 typedef struct {
@@ -193,7 +206,9 @@ cpd_status cpd_dgn_run(void* state, const double* S, const cpd_params* p, int32_
                        int32_t* stop, cpd_step_info* log, int32_t log_cap, void* stream);
 
 /* Copies the current core factors (three core_dims[l] x R matrices, packed, device) out of the
- * state, or (set = 1) into it. */
+ * state, or (set = 1) into it: the next iteration then starts from them as given (not balanced),
+ * first recomputing the residual and the MTTKRP there; mu, the iteration count and the error
+ * history continue.  Synchronises `stream`. */
 cpd_status cpd_state_factors(void* state, double* W, int32_t set, void* stream);
 
 /* ------------------------------------------------------------------------------------------ */

@@ -49,9 +49,11 @@ def _ws(nbytes, device):
 
 def params(maxiter=200, tol=1e-6, mlsvd_tol=1e-6, init_damp=1.0, cg_tol=0.0, cg_fixed=0,
            cg_uniforms=None, seed=0, init="random", core_dims=None, compute_dtype=CPD_F64, st_mlsvd=False,
-           refine_iters=0):
+           refine_iters=0, precond="jacobi", drawback=False):
     """Build a cpd_params struct (defaults are the thesis's).  ``cg_uniforms`` (host floats) must
-    outlive the call that uses the struct; it is kept on the returned object."""
+    outlive the call that uses the struct; it is kept on the returned object.  ``precond``:
+    "jacobi" (diagonal) or "block" (block-Jacobi); ``drawback``: redo a step whose error jumps
+    100-fold from the drawn-back point with a dogleg step."""
     p = Params()
     _lib.lib().cpd_default_params(ctypes.byref(p))
     p.maxiter, p.tol, p.mlsvd_tol, p.init_damp = int(maxiter), float(tol), float(mlsvd_tol), float(init_damp)
@@ -62,6 +64,8 @@ def params(maxiter=200, tol=1e-6, mlsvd_tol=1e-6, init_damp=1.0, cg_tol=0.0, cg_
     p.compute_dtype = int(compute_dtype)
     p.st_mlsvd = 1 if st_mlsvd else 0
     p.refine_iters = int(refine_iters)
+    p.precond = {"jacobi": 0, "block": 1}[precond]
+    p.drawback = 1 if drawback else 0
     if cg_uniforms is not None:
         arr = (ctypes.c_double * len(cg_uniforms))(*[float(u) for u in cg_uniforms])
         if len(cg_uniforms) < maxiter:
@@ -150,6 +154,15 @@ class DgnState:
         _lib.check(_lib.lib().cpd_dgn_run(_ptr(self.buf), _ptr(self.S), ctypes.byref(self.p), ctypes.byref(it),
                                           ctypes.byref(st), log, self.p.maxiter, _stream()), "cpd_dgn_run")
         return it.value, st.value, [log[i].as_dict() for i in range(it.value)]
+
+    def set_factors(self, W):
+        """Overwrite the state's current factors (three core_dims[l] x R matrices); the header
+        (mu, residual, error history) is left as it is."""
+        w = _flat_w0(W, self.S.device)
+        if w.numel() != sum(self.core) * self.R:
+            raise ValueError("set_factors: expected %d entries" % (sum(self.core) * self.R))
+        _lib.check(_lib.lib().cpd_state_factors(_ptr(self.buf), _ptr(w), 1, _stream()), "cpd_state_factors")
+        torch.cuda.current_stream().synchronize()
 
     def factors(self):
         n = sum(self.core) * self.R

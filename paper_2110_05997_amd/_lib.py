@@ -35,6 +35,8 @@ class Params(ctypes.Structure):
         ("compute_dtype", ctypes.c_int32),
         ("refine_iters", ctypes.c_int32),
         ("st_mlsvd", ctypes.c_int32),
+        ("precond", ctypes.c_int32),
+        ("drawback", ctypes.c_int32),
     ]
 
 
@@ -51,6 +53,8 @@ class StepInfo(ctypes.Structure):
         ("mu", ctypes.c_double),
         ("cg_resid", ctypes.c_double),
         ("t_ns", ctypes.c_int64),
+        ("drew_back", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):

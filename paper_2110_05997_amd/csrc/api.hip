@@ -391,7 +391,7 @@ cpd_status solve3_raw(const double* T, const int64_t dims[3], int R, const cpd_p
   if ((st = run_compress(T, CPD_F64, T, CPD_F64, CPD_F64, dims, R, p, U, nullptr, S, core, ar, s, chk, &h_tn2)))
     return st;
   if ((st = state_init(state, S, core, R, W0, h_tn2, p, s, true))) return st;
-  if ((st = dgn_iterate_known(state, S, core, R, p->maxiter, s))) return st;
+  if ((st = dgn_iterate_known(state, S, core, R, p->maxiter, s, dgn_opts(p)))) return st;
   const int npc = (core[0] + core[1] + core[2]) * R;
   const double* Wst = (const double*)(state + layout_of(npc, R, p->maxiter).W);
   size_t o = 0, ot = 0;
@@ -475,10 +475,10 @@ cpd_status cpd_state_init(void* state, const double* S, const int32_t core_dims[
 
 cpd_status cpd_dgn_step(void* state, const double* S, const cpd_params* p, cpd_step_info* info,
                         void* stream) {
-  (void)p;
   CPD_REQUIRE(state && S && info, "cpd_dgn_step: null argument");
+  CPD_REQUIRE(!p || p->precond == 0 || p->precond == 1, "cpd_dgn_step: precond must be 0 or 1");
   hipStream_t s = (hipStream_t)stream;
-  cpd_status st = dgn_iterate(state, S, 1, s);
+  cpd_status st = dgn_iterate(state, S, 1, s, dgn_opts(p));
   if (st) return st;
   int k = 0, stop = 0, ti = 0;
   if ((st = state_read(state, &k, &stop, &ti, nullptr, s))) return st;
@@ -493,9 +493,10 @@ cpd_status cpd_dgn_step(void* state, const double* S, const cpd_params* p, cpd_s
 cpd_status cpd_dgn_run(void* state, const double* S, const cpd_params* p, int32_t* iters,
                        int32_t* stop, cpd_step_info* log, int32_t log_cap, void* stream) {
   CPD_REQUIRE(state && S, "cpd_dgn_run: null argument");
+  CPD_REQUIRE(!p || p->precond == 0 || p->precond == 1, "cpd_dgn_run: precond must be 0 or 1");
   hipStream_t s = (hipStream_t)stream;
   const int maxiter = p ? p->maxiter : 200;
-  cpd_status st = dgn_iterate(state, S, maxiter, s);
+  cpd_status st = dgn_iterate(state, S, maxiter, s, dgn_opts(p));
   if (st) return st;
   int k = 0, sr = 0, ti = 0;
   if ((st = state_read(state, &k, &sr, &ti, nullptr, s))) return st;
@@ -520,6 +521,11 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   CPD_REQUIRE(T && W_out && W_out[0] && W_out[1] && W_out[2] && lambda_out && info, "cpd_solve: null argument");
   CPD_REQUIRE(dims_ok(dims) && dtype_ok(dtype) && R >= 1 && R <= 64, "cpd_solve: bad dims/dtype/R");
   CPD_REQUIRE(p->maxiter >= 1 && p->tol >= 0.0, "cpd_solve: bad parameters");
+  CPD_REQUIRE(p->precond == 0 || p->precond == 1, "cpd_solve: precond must be 0 or 1");
+  if (p->refine_iters > 0 && dgn_opts(p)) {
+    set_error("cpd_solve: the refinement runs the plain dGN (no block-Jacobi preconditioner or draw-back)");
+    return CPD_E_UNSUPPORTED;
+  }
   hipStream_t s = (hipStream_t)stream;
   const size_t need = solve_ws(dims, R, p);
   if (!ws || ws_bytes < need) {
@@ -569,7 +575,7 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   if (st) return st;
   // the header and CG caps go to the device as kernel arguments: no host synchronisation here
   if ((st = state_init(state, S, core, R, W0, h_tn2, p, s, false))) return st;
-  if ((st = dgn_iterate_known(state, S, core, R, p->maxiter, s))) return st;
+  if ((st = dgn_iterate_known(state, S, core, R, p->maxiter, s, dgn_opts(p)))) return st;
   // no read-back here: the header is read with the final residual; the output writes check its
   // non-finite flag on the device, so a rejected initial point leaves the outputs untouched
   (void)Wc;

@@ -461,6 +461,10 @@ cpd_status check_batch(const cpd_batch_item* items, int n, int dtype, const cpd_
     set_error("batch: bad arguments (n=%d dtype=%d)", n, dtype);
     return CPD_E_INVALID;
   }
+  if (dgn_opts(p)) {
+    set_error("batch: the batched solver runs the plain dGN (precond 0, no draw-back)");
+    return CPD_E_UNSUPPORTED;
+  }
   size_t mx = 0;
   for (int b = 0; b < n; ++b) {
     if (!item_ok(items[b])) {

@@ -181,9 +181,16 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
 size_t solve_ws_bytes(const int64_t dims[3], int R, const cpd_params* p);
 cpd_status solve3_raw(const double* T, const int64_t dims[3], int R, const cpd_params* p, const double* W0,
                       double* Wt, int* iters, int* stop, double* rel_err, void* ws, size_t ws_bytes, hipStream_t s);
+// Options of the iteration launches, from cpd_params.precond / drawback (kernel arguments; the
+// state does not record them)
+constexpr int DGN_OPT_BLOCK = 1;      // block-Jacobi preconditioner
+constexpr int DGN_OPT_DRAWBACK = 2;   // draw-back with a dogleg step on a hundredfold error jump
+inline int dgn_opts(const cpd_params* p) {
+  return p ? ((p->precond == 1 ? DGN_OPT_BLOCK : 0) | (p->drawback ? DGN_OPT_DRAWBACK : 0)) : 0;
+}
 // dgn_iterate for a state whose sizes the caller knows (no header read-back).
 cpd_status dgn_iterate_known(void* state, const double* S, const int32_t core[3], int R, int max_steps,
-                             hipStream_t s);
+                             hipStream_t s, int opts = 0);
 size_t dgn_lds_bytes(int np, int R);
 // N(0,1) entries (Box-Muller on SplitMix64 counters), the library's own random start.
 cpd_status fill_randn(double* W, int n, uint64_t seed, hipStream_t s);
@@ -204,7 +211,7 @@ cpd_status refine_run(void* state, const void* T, int dtype, const int64_t dims[
 cpd_status dgn_batch_prepare(size_t lds_bytes);
 cpd_status dgn_batch_launch(char* const* states, const double* const* S, int n, size_t lds_bytes,
                             hipStream_t s);
-cpd_status dgn_iterate(void* state, const double* S, int max_steps, hipStream_t s);
+cpd_status dgn_iterate(void* state, const double* S, int max_steps, hipStream_t s, int opts = 0);
 cpd_status state_read(void* state, int* k, int* stop, int* tol_iter, double* err,
                       hipStream_t s);
 cpd_status state_log(void* state, int first, int count, cpd_step_info* out, hipStream_t s);

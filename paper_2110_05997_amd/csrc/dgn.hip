@@ -39,6 +39,7 @@ struct Ctx {
   double *pi, *Pown, *Qb;   // 3 R^2 each
   double *msq, *gam;       // 3 R each
   double *red;             // 2 x NW
+  double *U, *Ci;          // block-Jacobi only: one more vector and the three C_l^{-1} (R x R)
   const double* S;
 };
 
@@ -80,6 +81,8 @@ __device__ void setup_ctx(Ctx& c, double* lds, const int d[3], int R, const doub
   c.msq = p; p += 3 * R;
   c.gam = p; p += 3 * R;
   c.red = p; p += 2 * NW;
+  c.U = nullptr;
+  c.Ci = nullptr;
   c.S = S;
 }
 
@@ -133,7 +136,8 @@ __device__ void precond(Ctx& c, double mu) {
 }
 
 // Structured product of Thm Hv.  With scale = true the input is v = msq * V and the output is
-// msq * (J^T J v + mu D v) (the preconditioned CG operator); with scale = false it is J^T J V.
+// msq * (J^T J v + mu D v) (the preconditioned CG operator); with scale = false it is
+// J^T J V + mu D V (mu = 0: the plain J^T J V, D not read).
 // Phase 1: Q_b = v_b^T W_b (R x R) for the three modes.  Phase 2, block a:
 //   out_a = [v_a | W_a] [Pi^(a) ; Y_a],  Y_a = pi^(b2) * Q_b1 + pi^(b1) * Q_b2 ({b1, b2} = other modes),
 // with Y formed inside the B-fragment loads (no barrier between the phases beyond the one that
@@ -195,6 +199,7 @@ __device__ double hv(Ctx& c, const double* V, double* out, double mu, bool scale
         const int e = offof(c, a) + i * R + r;
         double tv = acc1[v] + acc2[v];
         if (scale) tv = ma[r] * (tv + mu * c.gam[a * R + r] * (ma[r] * V[e]));
+        else if (mu != 0.0) tv += mu * c.gam[a * R + r] * V[e];
         out[e] = tv;
         dotp += V[e] * tv;
       }
@@ -266,6 +271,7 @@ __device__ double hv_staged(Ctx& c, const double* V, double* out, double mu, boo
           const int e = oa + i * R + r;
           double tv = acc1[v] + acc2[v];
           if (scale) tv = ma[r] * (tv + mu * c.gam[a * R + r] * (ma[r] * V[e]));
+          else if (mu != 0.0) tv += mu * c.gam[a * R + r] * V[e];
           out[e] = tv;
           dotp += V[e] * tv;
         }
@@ -274,6 +280,84 @@ __device__ double hv_staged(Ctx& c, const double* V, double* out, double mu, boo
     __syncthreads();
   }
   return dotp;
+}
+
+// Block-Jacobi preconditioner: the diagonal blocks of J^T J + mu D act on block l as
+// V^(l) -> V^(l) K_l with K_l = Pi^(l) + mu diag(gamma_l) (ch.3 block structure), split as
+// K_l = C_l C_l^T (Cholesky, lower).  C_l goes to Qb (free until the CG products), C_l^{-1} to Ci.
+// Column j of C: every thread of the column forms the pivot itself in the same order, so one
+// barrier per column suffices.  Needs Pown and gam (precond); ends with a barrier.
+__device__ void block_chol(Ctx& c, double mu) {
+  const int R = c.R, RR = R * R;
+  for (int j = 0; j < R; ++j) {
+    for (int e = threadIdx.x; e < 3 * R; e += NT) {
+      const int l = e / R, i = e - l * R;
+      if (i < j) continue;
+      const double* K = c.Pown + l * RR;
+      double* C = c.Qb + l * RR;
+      double sd = K[j * R + j] + mu * c.gam[l * R + j];
+      for (int q = 0; q < j; ++q) sd -= C[j * R + q] * C[j * R + q];
+      const double piv = sqrt(sd);
+      if (i == j) {
+        C[j * R + j] = piv;
+      } else {
+        double sv = K[i * R + j];
+        for (int q = 0; q < j; ++q) sv -= C[i * R + q] * C[j * R + q];
+        C[i * R + j] = sv / piv;
+      }
+    }
+    __syncthreads();
+  }
+  // C^{-1} (lower): column j solves C y = e_j by forward substitution, one thread per (l, j)
+  for (int e = threadIdx.x; e < 3 * R; e += NT) {
+    const int l = e / R, j = e - l * R;
+    const double* C = c.Qb + l * RR;
+    double* Y = c.Ci + l * RR;
+    for (int i = 0; i < j; ++i) Y[i * R + j] = 0.0;
+    Y[j * R + j] = 1.0 / C[j * R + j];
+    for (int i = j + 1; i < R; ++i) {
+      double sv = 0.0;
+      for (int q = j; q < i; ++q) sv += C[i * R + q] * Y[q * R + j];
+      Y[i * R + j] = -sv / C[i * R + i];
+    }
+  }
+  __syncthreads();
+}
+
+// out_a = sgn In_a C_a^{-1} (trans = false: L^{-T} in vec form) or sgn In_a C_a^{-T} (trans = true:
+// L^{-1}), block by block on the matrix cores; out2 (nullable) receives a copy.  Returns this
+// thread's partial of <out, out>; ends without a barrier.
+__device__ double tri_apply(Ctx& c, const double* In, double* out, bool trans, double sgn, double* out2) {
+  const int R = c.R, RR = R * R, tr = tiles16(R);
+  const int lane = threadIdx.x & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
+  const int t0 = tiles16(c.d0) * tr, t1 = t0 + tiles16(c.d1) * tr, t2 = t1 + tiles16(c.d2) * tr;
+  double ss = 0.0;
+  for (int t = w; t < t2; t += NW) {
+    const int a = (t >= t1) ? 2 : (t >= t0 ? 1 : 0);
+    const int tt = t - (a == 0 ? 0 : (a == 1 ? t0 : t1));
+    const int tm = tt / tr, tn = tt - tm * tr;
+    const int da = dimof(c, a), oa = offof(c, a);
+    const double* Ia = In + oa;
+    const double* Ca = c.Ci + a * RR;
+    const dbl4 acc = mfma_tile(tm * 16, tn * 16, R,
+        [&](int i, int k) { return sel(i < da && k < R, Ia[min(i, da - 1) * R + min(k, R - 1)]); },
+        [&](int k, int r) {
+          const int kk = min(k, R - 1), rr = min(r, R - 1);
+          return sel(k < R && r < R, trans ? Ca[rr * R + kk] : Ca[kk * R + rr]);
+        });
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = tm * 16 + 4 * v + kq, r = tn * 16 + r16;
+      if (i < da && r < R) {
+        const int e = oa + i * R + r;
+        const double val = sgn * acc[v];
+        out[e] = val;
+        if (out2) out2[e] = val;
+        ss += val * val;
+      }
+    }
+  }
+  return ss;
 }
 
 // Norm balancing (ch.4 "Updates"): every rank-one term gets equal column norms.  Uses msq as
@@ -420,7 +504,10 @@ __device__ int stop_test(const double* errs, int k, double step, double grad_inf
 // launches (dgn_tail_kernel finishes the step).
 // SL: the core S is copied into LDS after the working set (the caller sized the LDS for it).
 // GW: working set in global memory with hv_staged's LDS buffer at `stage`.
-template <bool SL, bool GW = false>
+// OPT (mode 1, working set in LDS): DGN_OPT_BLOCK, DGN_OPT_DRAWBACK; with DGN_OPT_BLOCK the caller
+// sized the LDS for np + 3 R^2 more doubles (block_lds_doubles), placed before the staged core.
+// SOLO: a state the host may have modified (cpd_state_factors): honours HDR_DIRTY.
+template <bool SL, bool GW = false, int OPT = 0, bool SOLO = false>
 __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double* __restrict__ S, int mode, int max_steps,
                          double* lds, int& s_stop, double* stage = nullptr) {
   Hdr* h = (Hdr*)state;
@@ -432,10 +519,13 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
   double* gW = (double*)(state + Lo.W);
   double* gMK = (double*)(state + Lo.MK);
   Ctx c;
+  constexpr bool BLK = (OPT & DGN_OPT_BLOCK) != 0 && !GW;
+  constexpr bool DRAW = (OPT & DGN_OPT_DRAWBACK) != 0 && !GW;
+  const size_t blk_lds = (BLK && mode == 1) ? block_lds_doubles(np, R) : 0;
   if (SL) {
     // rows of S padded to odd strides (in doubles): the sixteen rows a matrix-core fragment reads
     // then fall into distinct LDS banks
-    double* Sl = lds + lds_doubles(np, R);
+    double* Sl = lds + lds_doubles(np, R) + blk_lds;
     const int p2 = d[2] | 1, p1 = (d[1] * p2) | 1;
     const int n3 = d[0] * d[1] * d[2], d12 = d[1] * d[2];
     for (int e = threadIdx.x; e < n3; e += NT) {
@@ -448,6 +538,10 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
   } else {
     setup_ctx(c, lds, d, R, S, gMK, (double*)(state + Lo.G));
   }
+  if (blk_lds) {
+    c.U = lds + lds_doubles(np, R);
+    c.Ci = c.U + np;
+  }
   double* errs = (double*)(state + Lo.errs);
   const int* caps = (const int*)(state + Lo.caps);
   cpd_step_info* logp = (cpd_step_info*)(state + Lo.log);
@@ -457,6 +551,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
 
   for (int e = tid; e < c.np; e += NT) c.W[e] = gW[e];
   const bool fix0 = (h->flags & HDR_FIX0) != 0;
+  const bool dirty = SOLO && mode == 1 && (h->flags & HDR_DIRTY) != 0;   // read before any write
   __syncthreads();
 
   if (mode == 0 || mode == 3) {   // mode 3: the residual and MTTKRP are left to other launches
@@ -496,16 +591,32 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
   double mu = h->mu, f2 = h->f2;
   const double s_norm = h->s_norm, div_ref = h->div_ref, tol = h->tol, cg_tol = h->cg_tol;
   int k = h->k, stop = h->stop, tol_iter = h->tol_iter;
+  double err_prev = (k == 0) ? h->err0 : errs[k];
+  if (dirty) {
+    // factors replaced from outside: residual and MTTKRP at them; mu and the history continue
+    f2 = residual_mttkrp(c, slotB);
+    if (tid == 0) {
+      h->f2 = f2;
+      h->flags &= ~HDR_DIRTY;
+    }
+  }
+  const bool blk = BLK && !fix0;
+  const bool drawback = DRAW && !fix0;
   __syncthreads();
 
-  for (int step_i = 0; step_i < max_steps && stop == CPD_STOP_NONE; ++step_i) {
-    ++k;
-    double rr = 0.0, grad_inf = 0.0, xjx = 0.0;
-    int its = 0, cap = 0;
+  // Gradient and preconditioned CG step at the current W: Grams, D and the preconditioner first;
+  // leaves the gradient in G and the step x in X.
+  auto direction = [&](int cap, int& its, double& rr, double& grad_inf) __attribute__((always_inline)) {
+    its = 0;
+    rr = 0.0;
     grams(c);
     precond(c, mu);
-    // gradient, CG start r = p = M^{-1/2}(-grad), x = 0.  With the working set in global memory, W
-    // and the Pi^(l) are staged in LDS first (same values, same order of operations)
+    if constexpr (BLK) {
+      if (blk) block_chol(c, mu);
+    }
+    // gradient; CG start x = 0 and r = p = M^{-1/2}(-grad) (block-Jacobi: L^{-1}(-grad), below).
+    // With the working set in global memory, W and the Pi^(l) are staged in LDS first (same
+    // values, same order of operations)
     const double* gWs = c.W;
     const double* gPs = c.Pown;
     if constexpr (GW) {
@@ -526,25 +637,41 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
       const double g = (fix0 && l == 0) ? 0.0 : acc - c.MK[e];   // a fixed factor has no step
       c.G[e] = g;
       gi = fmax(gi, fabs(g));
-      const double r0 = c.msq[l * R + r] * (-g);
-      c.Rv[e] = r0;
-      c.P[e] = r0;
       c.X[e] = 0.0;
-      rr += r0 * r0;
+      if (!(BLK && blk)) {
+        const double r0 = c.msq[l * R + r] * (-g);
+        c.Rv[e] = r0;
+        c.P[e] = r0;
+        rr += r0 * r0;
+      }
+    }
+    if (BLK && blk) {
+      __syncthreads();
+      rr = tri_apply(c, c.G, c.Rv, true, -1.0, c.P);
     }
     rr = block_sum(rr, slotA);
     grad_inf = block_max(gi, slotB);
-    cap = caps[k - 1];
     while (its < cap) {
       if (rr == 0.0) break;
-      const double pz = block_sum(GW ? hv_staged(c, c.P, c.Z, mu, true, stage) : hv(c, c.P, c.Z, mu, true), slotA);
+      double pz;
+      if (BLK && blk) {
+        // z = L^{-1} (J^T J + mu D) L^{-T} p through u = L^{-T} p; <p, z> = <u, (J^T J + mu D) u>
+        tri_apply(c, c.P, c.U, false, 1.0, nullptr);
+        __syncthreads();
+        pz = block_sum(hv(c, c.U, c.Z, mu, false), slotA);
+        tri_apply(c, c.Z, c.U, true, 1.0, nullptr);
+        __syncthreads();
+      } else {
+        pz = block_sum(GW ? hv_staged(c, c.P, c.Z, mu, true, stage) : hv(c, c.P, c.Z, mu, true), slotA);
+      }
       if (!(pz > 0.0)) break;
       const double alpha = rr / pz;
+      const double* Zv = (BLK && blk) ? c.U : c.Z;
       double eps = 0.0;
       const int zfree = fix0 ? c.off1 : 0;   // rows of J^T J v of a fixed factor are dropped
       for (int e = tid; e < c.np; e += NT) {
         c.X[e] += alpha * c.P[e];
-        const double rv = c.Rv[e] - alpha * ((e < zfree) ? 0.0 : c.Z[e]);
+        const double rv = c.Rv[e] - alpha * ((e < zfree) ? 0.0 : Zv[e]);
         c.Rv[e] = rv;
         eps += rv * rv;
       }
@@ -556,27 +683,85 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
       ++its;
       if (eps < cg_tol) break;
     }
-    // x = M^{-1/2} x_hat
-    for (int e = tid; e < c.np; e += NT) {
-      int l, i, r;
-      split_index(c, e, l, i, r);
-      c.X[e] *= c.msq[l * R + r];
+    if (BLK && blk) {
+      // x = L^{-T} x_hat, into U; the two buffers swap roles
+      tri_apply(c, c.X, c.U, false, 1.0, nullptr);
+      double* t = c.X;
+      c.X = c.U;
+      c.U = t;
+    } else {
+      // x = M^{-1/2} x_hat
+      for (int e = tid; e < c.np; e += NT) {
+        int l, i, r;
+        split_index(c, e, l, i, r);
+        c.X[e] *= c.msq[l * R + r];
+      }
     }
     __syncthreads();
-    // J^T J x for the predicted residual, into Z
-    xjx = block_sum(GW ? hv_staged(c, c.X, c.Z, 0.0, false, stage) : hv(c, c.X, c.Z, 0.0, false), slotA);
-    double gx = 0.0, xx = 0.0;
+  };
+
+  // Predicted ||f + J x||^2 from the residual f2_base at the start point, then w <- w + x (always
+  // accepted) and norm balancing.
+  auto predict_update = [&](double f2_base, double& f2_pred, double& xx) __attribute__((always_inline)) {
+    const double xjx =
+        block_sum(GW ? hv_staged(c, c.X, c.Z, 0.0, false, stage) : hv(c, c.X, c.Z, 0.0, false), slotA);
+    double gx = 0.0, xs = 0.0;
     for (int e = tid; e < c.np; e += NT) {
       gx += c.G[e] * c.X[e];
-      xx += c.X[e] * c.X[e];
+      xs += c.X[e] * c.X[e];
     }
     gx = block_sum(gx, slotB);
-    xx = block_sum(xx, slotA);
-    const double f2_pred = f2 + 2.0 * gx + xjx;
-    // update, always accepted, then norm balancing
+    xx = block_sum(xs, slotA);
+    f2_pred = f2_base + 2.0 * gx + xjx;
     for (int e = tid; e < c.np; e += NT) c.W[e] += c.X[e];
     __syncthreads();
     norm_balance(c, fix0);
+  };
+
+  // Dogleg step inside the radius delta from the Gauss-Newton step in X and the gradient in G
+  // (Madsen-Nielsen-Tingleff): X itself if it fits; the steepest-descent step cut at delta when
+  // the Cauchy point a = -(|g|^2 / |J g|^2) g lies outside; else a + beta (X - a) on the radius.
+  auto dogleg = [&](double delta) __attribute__((always_inline)) {
+    const double jg2 =
+        block_sum(GW ? hv_staged(c, c.G, c.Z, 0.0, false, stage) : hv(c, c.G, c.Z, 0.0, false), slotA);
+    double hh = 0.0, gg = 0.0;
+    for (int e = tid; e < c.np; e += NT) {
+      hh += c.X[e] * c.X[e];
+      gg += c.G[e] * c.G[e];
+    }
+    hh = block_sum(hh, slotB);
+    gg = block_sum(gg, slotA);
+    if (sqrt(hh) <= delta) return;
+    const double alpha = gg / jg2, na = alpha * sqrt(gg);
+    if (na >= delta) {
+      const double sc = -(delta / sqrt(gg));
+      for (int e = tid; e < c.np; e += NT) c.X[e] = sc * c.G[e];
+      __syncthreads();
+      return;
+    }
+    double cd = 0.0, dd = 0.0;
+    for (int e = tid; e < c.np; e += NT) {
+      const double av = -alpha * c.G[e], dv = c.X[e] - av;
+      cd += av * dv;
+      dd += dv * dv;
+    }
+    cd = block_sum(cd, slotB);
+    dd = block_sum(dd, slotA);
+    const double beta = (-cd + sqrt(cd * cd + dd * (delta * delta - na * na))) / dd;
+    for (int e = tid; e < c.np; e += NT) {
+      const double av = -alpha * c.G[e];
+      c.X[e] = av + beta * (c.X[e] - av);
+    }
+    __syncthreads();
+  };
+
+  for (int step_i = 0; step_i < max_steps && stop == CPD_STOP_NONE; ++step_i) {
+    ++k;
+    int its = 0;
+    double rr = 0.0, grad_inf = 0.0, f2_pred = 0.0, xx = 0.0;
+    const int cap = caps[k - 1];
+    direction(cap, its, rr, grad_inf);
+    predict_update(f2, f2_pred, xx);
     if (mode == 2) {
       if (tid == 0) {
         h->f2_pred = f2_pred; h->stepn = sqrt(xx); h->grad_inf = grad_inf; h->cg_resid = rr;
@@ -584,10 +769,25 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
       }
       break;
     }
-    const double f2_new = residual_mttkrp(c, slotB);
-    const double err = sqrt(f2_new) / s_norm;
-    const double den = f2 - f2_pred;
-    const double g = (den > 0.0) ? (f2 - f2_new) / den : 0.0;
+    double f2_new = residual_mttkrp(c, slotB);
+    double err = sqrt(f2_new) / s_norm;
+    double f2_base = f2;
+    int drew = 0;
+    if (DRAW && drawback && err > 100.0 * err_prev) {
+      // draw back to N(w_k + x) - x, a new step there cut to half the failed one's length
+      drew = 1;
+      const double delta = 0.5 * sqrt(xx);
+      for (int e = tid; e < c.np; e += NT) c.W[e] -= c.X[e];
+      __syncthreads();
+      f2_base = residual_mttkrp(c, slotB);   // and the MTTKRP of the new gradient
+      direction(cap, its, rr, grad_inf);
+      dogleg(delta);
+      predict_update(f2_base, f2_pred, xx);
+      f2_new = residual_mttkrp(c, slotB);
+      err = sqrt(f2_new) / s_norm;
+    }
+    const double den = f2_base - f2_pred;
+    const double g = (den > 0.0) ? (f2_base - f2_new) / den : 0.0;
     const double mu_new = (g < 0.25) ? 3.0 * mu : ((g > 0.75) ? mu / 3.0 : mu);
     const double stepn = sqrt(xx);
     if (tid == 0) {
@@ -600,6 +800,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
       inf.rel_err = err; inf.step_norm = stepn; inf.grad_inf = grad_inf; inf.gain = g;
       inf.mu = mu_new; inf.cg_resid = rr;
       inf.t_ns = now - h->t_init;   // ticks here; the host converts to ns
+      inf.drew_back = drew; inf.reserved = 0;
       logp[k - 1] = inf;
       if (tol_iter < 0 && err < tol) h->t_tol = now;
     }
@@ -608,6 +809,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     if (tol_iter < 0 && err < tol) tol_iter = k;
     mu = mu_new;
     f2 = f2_new;
+    err_prev = err;
   }
   for (int e = tid; e < c.np; e += NT) gW[e] = c.W[e];
   if (tid == 0) {
@@ -624,12 +826,12 @@ __global__ __launch_bounds__(NT) void dgn_init_kernel(char* __restrict__ state, 
   dgn_body<SL>(state, S, 0, 0, lds, s_stop);
 }
 
-template <bool SL>
+template <bool SL, int OPT>
 __global__ __launch_bounds__(NT) void dgn_kernel(char* __restrict__ state, const double* __restrict__ S,
                                                  int max_steps) {
   extern __shared__ double lds[];
   __shared__ int s_stop;
-  dgn_body<SL>(state, S, 1, max_steps, lds, s_stop);
+  dgn_body<SL, false, OPT, true>(state, S, 1, max_steps, lds, s_stop);
 }
 
 // Same iteration for states too large for LDS: the working set lives in the state's own work
@@ -671,6 +873,7 @@ __global__ void dgn_tail_kernel(char* __restrict__ state) {
   inf.rel_err = err; inf.step_norm = h->stepn; inf.grad_inf = h->grad_inf; inf.gain = g;
   inf.mu = mu_new; inf.cg_resid = h->cg_resid;
   inf.t_ns = now - h->t_init;   // ticks here; the host converts to ns
+  inf.drew_back = 0; inf.reserved = 0;
   logp[k - 1] = inf;
   if (h->tol_iter < 0 && err < h->tol) {
     h->tol_iter = k;
@@ -1278,34 +1481,54 @@ size_t hv_stage_doubles(const int d[3], int R) {
 // region.
 // sdtype: element type of S (FP64 for a core; the input tensor's type for a refinement, which also
 // forces the global-memory path since the LDS paths read S as FP64).
+// The iteration kernel instantiated for the options (the plain one carries no code of the others).
+template <bool SL>
+auto dgn_kernel_for(int opts) -> void (*)(char*, const double*, int) {
+  switch (opts & (DGN_OPT_BLOCK | DGN_OPT_DRAWBACK)) {
+    case DGN_OPT_BLOCK: return dgn_kernel<SL, DGN_OPT_BLOCK>;
+    case DGN_OPT_DRAWBACK: return dgn_kernel<SL, DGN_OPT_DRAWBACK>;
+    case DGN_OPT_BLOCK | DGN_OPT_DRAWBACK: return dgn_kernel<SL, DGN_OPT_BLOCK | DGN_OPT_DRAWBACK>;
+    default: return dgn_kernel<SL, 0>;
+  }
+}
+
 cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int np, int R, const int d[3],
-                      hipStream_t s, int sdtype = CPD_F64) {
+                      hipStream_t s, int sdtype = CPD_F64, int opts = 0) {
   const double* S = (const double*)Sv;
   const bool lds_ok = sdtype == CPD_F64;
   const int p2 = d[2] | 1, p1 = (d[1] * p2) | 1;
   const size_t s_lds = (size_t)(d[0] - 1) * p1 + (size_t)(d[1] - 1) * p2 + d[2];   // padded core in LDS
+  if (mode == 0) opts = 0;
+  // the block-Jacobi factors and one more vector sit between the working set and the staged core
+  const size_t extra = (opts & DGN_OPT_BLOCK) ? block_lds_doubles(np, R) * sizeof(double) : 0;
   size_t lb;
-  if (lds_ok && lds_fits(np, R, &lb) && lb + (size_t)s_lds * sizeof(double) <= LDS_LIMIT) {
-    lb += (size_t)s_lds * sizeof(double);
+  const bool fits = lds_ok && lds_fits(np, R, &lb);
+  if (fits && lb + extra + (size_t)s_lds * sizeof(double) <= LDS_LIMIT) {
+    lb += extra + (size_t)s_lds * sizeof(double);
     if (mode == 0) {
       CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_init_kernel<true>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
       hipLaunchKernelGGL(dgn_init_kernel<true>, dim3(1), dim3(NT), lb, s, state, S);
     } else {
-      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)lb));
-      hipLaunchKernelGGL(dgn_kernel<true>, dim3(1), dim3(NT), lb, s, state, S, max_steps);
+      const auto kern = dgn_kernel_for<true>(opts);
+      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
+      hipLaunchKernelGGL(kern, dim3(1), dim3(NT), lb, s, state, S, max_steps);
     }
-  } else if (lds_ok && lds_fits(np, R, &lb)) {
+  } else if (fits && lb + extra <= LDS_LIMIT) {
+    lb += extra;
     if (mode == 0) {
       CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_init_kernel<false>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
       hipLaunchKernelGGL(dgn_init_kernel<false>, dim3(1), dim3(NT), lb, s, state, S);
     } else {
-      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)dgn_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)lb));
-      hipLaunchKernelGGL(dgn_kernel<false>, dim3(1), dim3(NT), lb, s, state, S, max_steps);
+      const auto kern = dgn_kernel_for<false>(opts);
+      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
+      hipLaunchKernelGGL(kern, dim3(1), dim3(NT), lb, s, state, S, max_steps);
     }
+  } else if (fits || (mode != 0 && opts != 0)) {
+    set_error("dgn: the block-Jacobi preconditioner and the draw-back run on cores whose working set fits "
+              "in one workgroup's LDS (np = %d, R = %d)", np, R);
+    return CPD_E_UNSUPPORTED;
   } else {
     // Large core: the core's MTTKRPs and residual run on the full-tensor kernels (spread over the
     // chip). Initialisation: the single-workgroup part (balancing, norms, header), those kernels,
@@ -1333,6 +1556,17 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
       hipLaunchKernelGGL(dgn_init_tail_kernel, dim3(1), dim3(64), 0, s, state);
       CPD_LAUNCH_CHECK();
       return CPD_OK;
+    }
+    if (hh.flags & HDR_DIRTY) {
+      // factors replaced from outside: MTTKRP and residual at them, then clear the flag
+      cpd_status st;
+      for (int l = 0; l < 3; ++l)
+        if ((st = mttkrp_full(Sv, sdtype, dims, Wp, R, l, CPD_F64, MKp[l], aux, aux_bytes, s))) return st;
+      if ((st = residual_full(Sv, sdtype, dims, Wp, R, (double*)(state + offsetof(Hdr, f2)), aux, aux_bytes, s)))
+        return st;
+      const int32_t fl = hh.flags & ~HDR_DIRTY;
+      CPD_HIP_CHECK(hipMemcpyAsync(state + offsetof(Hdr, flags), &fl, sizeof(fl), hipMemcpyHostToDevice, s));
+      CPD_HIP_CHECK(hipStreamSynchronize(s));
     }
     // Pi, M^{-1/2} and D of the iteration kernel in LDS
     const size_t it_lds = ((size_t)3 * R * R + 6 * (size_t)R) * sizeof(double);
@@ -1592,7 +1826,7 @@ cpd_status dgn_batch_launch(char* const* states, const double* const* S, int n, 
   return CPD_OK;
 }
 
-cpd_status dgn_iterate(void* state, const double* S, int max_steps, hipStream_t s) {
+cpd_status dgn_iterate(void* state, const double* S, int max_steps, hipStream_t s, int opts) {
   Hdr h;
   CPD_HIP_CHECK(hipMemcpyAsync(&h, state, sizeof(h), hipMemcpyDeviceToHost, s));
   CPD_HIP_CHECK(hipStreamSynchronize(s));
@@ -1602,17 +1836,17 @@ cpd_status dgn_iterate(void* state, const double* S, int max_steps, hipStream_t 
   }
   prof_begin(CPD_PK_DGN, s);
   const int dc[3] = {h.d[0], h.d[1], h.d[2]};
-  const cpd_status st = launch_dgn((char*)state, S, 1, max_steps, h.np, h.R, dc, s);
+  const cpd_status st = launch_dgn((char*)state, S, 1, max_steps, h.np, h.R, dc, s, CPD_F64, opts);
   prof_end(CPD_PK_DGN, s);
   return st;
 }
 
 cpd_status dgn_iterate_known(void* state, const double* S, const int32_t core[3], int R, int max_steps,
-                             hipStream_t s) {
+                             hipStream_t s, int opts) {
   const int np = (core[0] + core[1] + core[2]) * R;
   const int dc[3] = {core[0], core[1], core[2]};
   prof_begin(CPD_PK_DGN, s);
-  const cpd_status st = launch_dgn((char*)state, S, 1, max_steps, np, R, dc, s);
+  const cpd_status st = launch_dgn((char*)state, S, 1, max_steps, np, R, dc, s, CPD_F64, opts);
   prof_end(CPD_PK_DGN, s);
   return st;
 }
@@ -1662,9 +1896,13 @@ cpd_status state_factors(void* state, double* W, int set, hipStream_t s) {
   CPD_HIP_CHECK(hipStreamSynchronize(s));
   const Layout Lo = layout_of(h.np, h.R, h.maxiter);
   char* gW = (char*)state + Lo.W;
-  if (set)
+  if (set) {
     CPD_HIP_CHECK(hipMemcpyAsync(gW, W, sizeof(double) * h.np, hipMemcpyDeviceToDevice, s));
-  else
+    // the next iteration recomputes the residual and the MTTKRP at the new factors
+    const int32_t fl = h.flags | HDR_DIRTY;
+    CPD_HIP_CHECK(hipMemcpyAsync((char*)state + offsetof(Hdr, flags), &fl, sizeof(fl), hipMemcpyHostToDevice, s));
+    CPD_HIP_CHECK(hipStreamSynchronize(s));
+  } else
     CPD_HIP_CHECK(hipMemcpyAsync(W, gW, sizeof(double) * h.np, hipMemcpyDeviceToDevice, s));
   return CPD_OK;
 }

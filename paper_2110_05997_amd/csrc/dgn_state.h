@@ -20,7 +20,9 @@ constexpr int32_t HDR_PRESET = 4;
 constexpr int32_t HDR_FIX0 = 8;
 // HDR_BAR_TIMEOUT: a grid barrier of the multi-workgroup CG stopped waiting (the results are invalid)
 constexpr int32_t HDR_BAR_TIMEOUT = 16;
-
+// HDR_DIRTY: the factors were replaced from outside (cpd_state_factors); the next iteration launch
+// first recomputes the residual and the MTTKRP at them
+constexpr int32_t HDR_DIRTY = 32;
 
 struct Hdr {
   int32_t d[3];
@@ -66,5 +68,8 @@ __host__ __device__ inline Layout layout_of(int np, int R, int maxiter) {
 __host__ __device__ inline size_t lds_doubles(int np, int R) {
   return (size_t)5 * np + (size_t)9 * R * R + (size_t)6 * R + 2 * NW + 16;
 }
+
+// Extra LDS of the block-Jacobi preconditioner: one more vector and the three R x R inverse factors
+__host__ __device__ inline size_t block_lds_doubles(int np, int R) { return (size_t)np + (size_t)3 * R * R; }
 
 }  // namespace cpd

@@ -310,6 +310,10 @@ cpd_status solve_tt(const void* T, int dtype, int L, const int64_t* dims, int R,
               "R I_l > 64), R I_l <= 4096 and R <= the product of the trailing dims", TT_MAXL);
     return CPD_E_INVALID;
   }
+  if (dgn_opts(p0)) {
+    set_error("cpd_solve_tt: the tensor-train route runs the plain dGN (precond 0, no draw-back)");
+    return CPD_E_UNSUPPORTED;
+  }
   if (!ws || ws_bytes < tt_ws_bytes(L, dims, R, p0)) {
     set_error("cpd_solve_tt: workspace too small");
     return CPD_E_WORKSPACE;
