@@ -413,6 +413,41 @@ cpd_status cpd_mlp_backward(const cpd_mlp* net, const float* x, const float* dy,
 /* One Adam update of every weight and bias (host struct a: step is incremented on the host). */
 cpd_status cpd_mlp_adam_step(cpd_mlp* net, const cpd_mlp_grads* g, cpd_adam* a, void* stream);
 
+/* Encoding of the learned start.  Feature of a core S: x = S / ||S|| (FP32).  Target of a CPD of
+ * the core with unit columns W[l] and weights lambda: t = [w_r^(l) lambda_r^{1/3}] / ||S||^{1/3}
+ * (FP32, the three core_dims[l] x R row-major blocks one after the other).  The start from a
+ * network output y is W = y ||S||^{1/3}, the inverse map. */
+/* Features of n_items cores stored back to back (device FP64, n entries each) into x (device
+ * FP32, n_items x n) and their norms into norms (device FP64, n_items).  Does not synchronise. */
+cpd_status cpd_learned_features(const double* S, int32_t n_items, int64_t n, float* x, double* norms,
+                                void* stream);
+/* Target of one core's CPD (W[l] device core_dims[l] x R, lambda device R, s_norm = ||S|| > 0 on
+ * the host) into t (device FP32, R sum(core_dims) entries).  Does not synchronise. */
+cpd_status cpd_learned_target(const double* const W[3], const double* lambda, const int32_t core_dims[3],
+                              int32_t R, double s_norm, float* t, void* stream);
+size_t cpd_learned_start_workspace_bytes(const cpd_mlp* net, const int32_t core_dims[3], int32_t R,
+                                         int32_t judge_iters);
+/*
+ * cpd_learned_start: the starting point for the dGN on the core S (device FP64, core_dims C order)
+ * from the network net (n_in = prod(core_dims), n_out = R sum(core_dims)), written to W_out (device,
+ * the three core_dims[l] x R factors packed, as cpd_state_init's W0).
+ * judge_iters = 0: the network's start.  judge_iters > 0: the dGN residual judges the network:
+ * judge_iters dGN iterations (parameters p: tol, damping, CG cap from p->seed or p->cg_uniforms,
+ * precond and drawback) run from the network's start and from the fallback start, W_fallback
+ * (device, packed like W_out) or, when NULL, the library's N(0,1) start for p->seed (the start
+ * cpd_solve draws with CPD_INIT_RANDOM; the thesis's random initialisation, ch.4
+ * "Initialization"); W_out is the network's start unless its core relative error after them
+ * exceeds judge_margin (>= 1) times the fallback's (a non-finite error counts as exceeding), in
+ * which case it is the fallback.  chosen (host, nullable): 0 network, 1 fallback;
+ * judge_err (host, nullable, 2 entries): the two errors after the judge iterations (0 when
+ * judge_iters = 0).  p may be NULL (defaults).  Synchronises `stream` when judge_iters > 0; without
+ * the judge the calls are only enqueued (ws must then stay valid until the stream reaches them).
+ */
+cpd_status cpd_learned_start(const cpd_mlp* net, const double* S, const int32_t core_dims[3], int32_t R,
+                             int32_t judge_iters, double judge_margin, const cpd_params* p,
+                             const double* W_fallback, double* W_out, int32_t* chosen, double* judge_err, void* ws,
+                             size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------------------------ */
 /* Kernel timing: when enabled, HIP events are recorded on the launch stream around the main   */
 /* kernels of the path; cpd_profile_read waits for them and accumulates durations.  Intended   */

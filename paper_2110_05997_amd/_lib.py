@@ -169,6 +169,14 @@ SIGNATURES = [
     ("cpd_mlp_backward", ctypes.c_int, [ctypes.POINTER(Mlp), _P, _P, ctypes.POINTER(MlpGrads), ctypes.c_int32, _P,
                                         ctypes.c_size_t, _P]),
     ("cpd_mlp_adam_step", ctypes.c_int, [ctypes.POINTER(Mlp), ctypes.POINTER(MlpGrads), ctypes.POINTER(Adam), _P]),
+    ("cpd_learned_features", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64, _P, _P, _P]),
+    ("cpd_learned_target", ctypes.c_int, [_Px3, _P, _I32x3, ctypes.c_int32, ctypes.c_double, _P, _P]),
+    ("cpd_learned_start_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(Mlp), _I32x3, ctypes.c_int32,
+                                                            ctypes.c_int32]),
+    ("cpd_learned_start", ctypes.c_int, [ctypes.POINTER(Mlp), _P, _I32x3, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_double, ctypes.POINTER(Params), _P, _P,
+                                         ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_double), _P, ctypes.c_size_t, _P]),
     ("cpd_profile_enable", None, [ctypes.c_int32]),
     ("cpd_profile_select", None, [ctypes.c_uint32]),
     ("cpd_profile_reset", None, []),

@@ -182,6 +182,74 @@ cpd_status gemm32(bool ta, bool tb, int M, int N, int K, const float* A, int lda
   return CPD_OK;
 }
 
+// Small batches (B <= VB, inference on one or a few cores): each layer as a split-K matrix-vector
+// product streaming the weights once with coalesced loads (the tiled GEMM would run a handful of
+// workgroups over the whole K), then a fixed-order reduction of the partial sums with the bias and
+// ReLU.  part[ks][b][n] = sum over rows k of chunk ks of x[b][k] W[k][n].
+constexpr int VB = 8;
+constexpr int VNT = 256;
+constexpr int VROWS = 256;                  // rows of x staged in LDS at a time
+constexpr size_t VPART = (size_t)1024 * VNT;   // bound on KS * N (KS <= 1024 / column blocks)
+
+__global__ __launch_bounds__(VNT) void gemv_part_kernel(int B, int N, int K, int chunk, const float* __restrict__ x,
+                                                        int ldx, const float* __restrict__ W,
+                                                        float* __restrict__ part) {
+  __shared__ float xs[VB][VROWS];
+  const int n = blockIdx.x * VNT + threadIdx.x;
+  const int k0 = blockIdx.y * chunk;
+  const int k1 = min(K, k0 + chunk);
+  float acc[VB];
+#pragma unroll
+  for (int b = 0; b < VB; ++b) acc[b] = 0.f;
+  for (int kb = k0; kb < k1; kb += VROWS) {
+    const int kn = min(VROWS, k1 - kb);
+    __syncthreads();
+    for (int e = threadIdx.x; e < B * kn; e += VNT) {
+      const int b = e / kn, kk = e - b * kn;
+      xs[b][kk] = x[(long long)b * ldx + kb + kk];
+    }
+    __syncthreads();
+    if (n < N) {
+      for (int kk = 0; kk < kn; ++kk) {
+        const float w = W[(long long)(kb + kk) * N + n];
+#pragma unroll
+        for (int b = 0; b < VB; ++b)
+          if (b < B) acc[b] += xs[b][kk] * w;
+      }
+    }
+  }
+  if (n < N)
+    for (int b = 0; b < B; ++b) part[((long long)blockIdx.y * B + b) * N + n] = acc[b];
+}
+
+__global__ void gemv_reduce_kernel(int B, int N, int KS, const float* __restrict__ part,
+                                   const float* __restrict__ bias, int relu, float* __restrict__ y, int ldy) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= B * N) return;
+  const int b = e / N, n = e - b * N;
+  float s = 0.f;
+  for (int ks = 0; ks < KS; ++ks) s += part[((long long)ks * B + b) * N + n];
+  s += bias[n];
+  y[(long long)b * ldy + n] = relu ? fmaxf(s, 0.f) : s;
+}
+
+// y (B x N) = epi(x (B x K) W (K x N) + bias) for B <= VB; part holds VPART * B floats.
+cpd_status gemv32(int B, int N, int K, const float* x, const float* W, const float* bias, bool relu, float* y,
+                  float* part, hipStream_t s) {
+  const int cols = (N + VNT - 1) / VNT;
+  int ks = 1024 / cols;
+  const int kmax = (K + 7) / 8;   // at least eight rows per chunk
+  ks = ks < 1 ? 1 : (ks > kmax ? kmax : ks);
+  const int chunk = (K + ks - 1) / ks;
+  ks = (K + chunk - 1) / chunk;
+  hipLaunchKernelGGL(gemv_part_kernel, dim3(cols, ks), dim3(VNT), 0, s, B, N, K, chunk, x, K, W, part);
+  CPD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(gemv_reduce_kernel, dim3((B * N + 255) / 256), dim3(256), 0, s, B, N, ks, part, bias,
+                     relu ? 1 : 0, y, N);
+  CPD_LAUNCH_CHECK();
+  return CPD_OK;
+}
+
 bool net_ok(const cpd_mlp* net) {
   if (!net) return false;
   const int d[4] = {net->n_in, net->n_h1, net->n_h2, net->n_out};
@@ -192,13 +260,16 @@ bool net_ok(const cpd_mlp* net) {
   return true;
 }
 
-// Workspace: H1 (B x h1), H2 (B x h2), G2 (B x h2), G1 (B x h1).
+// Workspace: H1 (B x h1), H2 (B x h2), G2 (B x h2), G1 (B x h1); for B <= VB also the partial sums
+// of the small-batch forward (VPART * B).
 template <class Carver>
-void carve_mlp(Carver& z, const cpd_mlp* net, int B, float** H1, float** H2, float** G2, float** G1) {
+void carve_mlp(Carver& z, const cpd_mlp* net, int B, float** H1, float** H2, float** G2, float** G1,
+               float** part) {
   *H1 = z.template take<float>((size_t)B * net->n_h1);
   *H2 = z.template take<float>((size_t)B * net->n_h2);
   *G2 = z.template take<float>((size_t)B * net->n_h2);
   *G1 = z.template take<float>((size_t)B * net->n_h1);
+  *part = B <= VB ? z.template take<float>(VPART * B) : nullptr;
 }
 
 }  // namespace
@@ -211,8 +282,8 @@ extern "C" {
 size_t cpd_mlp_workspace_bytes(const cpd_mlp* net, int32_t B) {
   if (!net_ok(net) || B < 1) return 0;
   Sizer z;
-  float *a, *b, *c, *d;
-  carve_mlp(z, net, B, &a, &b, &c, &d);
+  float *a, *b, *c, *d, *e;
+  carve_mlp(z, net, B, &a, &b, &c, &d, &e);
   return z.off;
 }
 
@@ -225,9 +296,14 @@ cpd_status cpd_mlp_forward(const cpd_mlp* net, const float* x, float* y, int32_t
   }
   hipStream_t s = (hipStream_t)stream;
   Arena ar(ws, ws_bytes);
-  float *H1, *H2, *G2, *G1;
-  carve_mlp(ar, net, B, &H1, &H2, &G2, &G1);
+  float *H1, *H2, *G2, *G1, *part;
+  carve_mlp(ar, net, B, &H1, &H2, &G2, &G1, &part);
   cpd_status st;
+  if (B <= VB) {
+    if ((st = gemv32(B, net->n_h1, net->n_in, x, net->W[0], net->b[0], true, H1, part, s))) return st;
+    if ((st = gemv32(B, net->n_h2, net->n_h1, H1, net->W[1], net->b[1], true, H2, part, s))) return st;
+    return gemv32(B, net->n_out, net->n_h2, H2, net->W[2], net->b[2], false, y, part, s);
+  }
   if ((st = gemm32(false, false, B, net->n_h1, net->n_in, x, net->n_in, net->W[0], net->n_h1, H1, net->n_h1,
                    net->b[0], nullptr, 0, EPI_BIAS_RELU, s)))
     return st;
@@ -265,7 +341,8 @@ cpd_status cpd_mlp_backward(const cpd_mlp* net, const float* x, const float* dy,
   hipStream_t s = (hipStream_t)stream;
   Arena ar(ws, ws_bytes);
   float *H1, *H2, *G2, *G1;
-  carve_mlp(ar, net, B, &H1, &H2, &G2, &G1);
+  float* part;
+  carve_mlp(ar, net, B, &H1, &H2, &G2, &G1, &part);
   const int h1 = net->n_h1, h2 = net->n_h2, no = net->n_out, ni = net->n_in;
   cpd_status st;
   // layer 3

@@ -2,12 +2,13 @@
 initialises with random or MLSVD-energy points, ch.4 "Initialization").
 
 A network maps the compressed core S (fixed core dims, e.g. 16^3), normalised to unit Frobenius
-norm, to the R-term factors of S, balanced (equal column norms across modes), sign-fixed (modes 1
-and 2 have a positive largest entry) and ordered by decreasing weight, scaled by ||S||^{-1/3}.
-Training pairs come from the library itself: each planted tensor is compressed by cpd_compress,
-and the factors of its core are the batched solver's converged CPD of that core.  All arithmetic
-runs in libcpd (cpd_compress, cpd_solve_batched, cpd_mlp_*); this module only moves tensors and
-calls the C ABI.
+norm, to the R-term factors of S, balanced (equal column norms across modes) and scaled by
+||S||^{-1/3} (cpd_learned_features / cpd_learned_target).  Training pairs come from the library
+itself: each planted tensor is compressed by cpd_compress, and the factors of its core are the
+batched solver's converged CPD of that core.  Inference is one call, cpd_learned_start: feature,
+forward pass, rescaling and, optionally, the judge (a few dGN iterations from the network's start
+and from the fallback N(0,1) start; the better one is kept).  All arithmetic runs in libcpd; this
+module moves tensors, draws the planted inputs and calls the C ABI.
 """
 import ctypes
 import math
@@ -77,26 +78,58 @@ class MLP:
         return self._loss
 
 
-def core_feature(S):
-    """(x, scale): the core flattened and normalised to unit norm, and its norm."""
-    nrm = float(torch.linalg.vector_norm(S))
-    return (S.reshape(-1) / nrm).to(torch.float32), nrm
+def features(cores):
+    """(X, norms): FP32 features x = S / ||S|| of a list of equal-shape FP64 device cores, and their
+    norms (cpd_learned_features)."""
+    Sb = torch.stack([S.reshape(-1) for S in cores]).contiguous()
+    n_items, n = Sb.shape
+    X = torch.empty((n_items, n), dtype=torch.float32, device=Sb.device)
+    norms = torch.empty(n_items, dtype=torch.float64, device=Sb.device)
+    _lib.check(_lib.lib().cpd_learned_features(Sb.data_ptr(), n_items, n, X.data_ptr(), norms.data_ptr(), _stream()),
+               "cpd_learned_features")
+    return X, norms
 
 
-def factor_target(W, lam, scale):
-    """Flattened balanced factors (modes stacked, each core_dim x R row-major) scaled by scale^{-1/3}."""
-    c = lam.clamp(min=0.0) ** (1.0 / 3.0)
-    return torch.cat([(w * c[None, :]).reshape(-1) for w in W]).to(torch.float32) / scale ** (1.0 / 3.0)
+def factor_target(W, lam, core, R, s_norm):
+    """FP32 target of one core's CPD (unit-column factors W, weights lam) with core norm s_norm
+    (cpd_learned_target)."""
+    t = torch.empty(sum(core) * R, dtype=torch.float32, device=lam.device)
+    Wp = (ctypes.c_void_p * 3)(*[w.contiguous().data_ptr() for w in W])
+    _lib.check(_lib.lib().cpd_learned_target(Wp, lam.data_ptr(), (ctypes.c_int32 * 3)(*core), R, float(s_norm),
+                                             t.data_ptr(), _stream()), "cpd_learned_target")
+    return t
 
 
-def factors_from_output(y, core, R, scale):
-    """Inverse of factor_target: the three core_dims[l] x R initial factors (FP64)."""
-    y = y.to(torch.float64) * scale ** (1.0 / 3.0)
+def learned_start(net, S, R, judge_iters=0, p=None, W_fallback=None, margin=1.0):
+    """The starting point for the core S from the network (cpd_learned_start).  judge_iters > 0:
+    judge_iters dGN iterations from the network's start and from the fallback (W_fallback, else the
+    library's N(0,1) start for p.seed); the fallback is returned when the network's error after
+    them exceeds margin times the fallback's.  Returns (W, chosen, judge_err) with W the three
+    core_dims[l] x R factors, chosen 0 (network) or 1 (fallback)."""
+    L = _lib.lib()
+    core = tuple(int(d) for d in S.shape)
+    cd = (ctypes.c_int32 * 3)(*core)
+    S = S.contiguous()
+    p = p if p is not None else params()
+    n = L.cpd_learned_start_workspace_bytes(ctypes.byref(net.net), cd, R, judge_iters)
+    if n == 0:
+        raise ValueError("learned_start: the network does not map this core size and rank")
+    ws = torch.empty(n, dtype=torch.uint8, device=S.device)
+    W = torch.empty(sum(core) * R, dtype=torch.float64, device=S.device)
+    wf = None
+    if W_fallback is not None:
+        wf = torch.cat([w.reshape(-1) for w in W_fallback]).to(device=S.device, dtype=torch.float64).contiguous()
+    chosen = ctypes.c_int32()
+    errs = (ctypes.c_double * 2)()
+    _lib.check(L.cpd_learned_start(ctypes.byref(net.net), S.data_ptr(), cd, R, judge_iters, float(margin),
+                                   ctypes.byref(p),
+                                   wf.data_ptr() if wf is not None else None, W.data_ptr(), ctypes.byref(chosen),
+                                   errs, ws.data_ptr(), n, _stream()), "cpd_learned_start")
     out, o = [], 0
     for d in core:
-        out.append(y[o:o + d * R].reshape(d, R).contiguous())
+        out.append(W[o:o + d * R].view(d, R))
         o += d * R
-    return out
+    return out, chosen.value, (errs[0], errs[1])
 
 
 def planted_device(dims, R, gen, device="cuda"):
@@ -121,12 +154,14 @@ def make_dataset(n, seed, dims=(100, 100, 100), R=8, core=(16, 16, 16), chunk=51
             Td = planted_device(dims, R, gen, device)
             _, _, S, _ = compress(Td, R, pc)
             cores.append(S.reshape(core))
-        scales = torch.stack([torch.linalg.vector_norm(S) for S in cores]).cpu().tolist()
-        X.extend([(S.reshape(-1) / sc).to(torch.float32) for S, sc in zip(cores, scales)])
+        Xc, norms = features(cores)
+        scales = norms.cpu().tolist()
+        X.extend(list(Xc))
         b = Batch(cores, [R] * m, params(seed=seed * 7919 + done), graph=False)
         infos = b.run()
         for j in range(m):
-            Tt.append(factor_target(b.W[j], b.lam[j], scales[j]) if infos[j]["rel_err_full"] < 1e-6 else None)
+            ok = infos[j]["rel_err_full"] < 1e-6 and scales[j] > 0.0
+            Tt.append(factor_target(b.W[j], b.lam[j], core, R, scales[j]) if ok else None)
         b.close()
         done += m
         if progress is not None:
@@ -160,56 +195,73 @@ def train(X, T, sizes=None, epochs=10, batch=512, lr=1e-3, seed=0, progress=None
     return net, hist
 
 
+JUDGES = ((3, 1.0), (3, 2.0), (10, 1.0), (10, 2.0))   # (dGN iterations, margin) of the judge rules
+
+
 def evaluate(net, n_test, seed, dims=(100, 100, 100), R=8, core=(16, 16, 16), maxiter=200, progress=None):
     """Solves n_test new planted tensors from the starting points
-      learned  - the network's prediction for the compressed core,
-      fallback - the prediction unless the MLSVD-energy point has a smaller core residual
-                 (the dGN residual judges the network; the MLSVD point is the fallback),
-      mlsvd    - the MLSVD-energy point (ch.4 "Initialization"),
-      random   - N(0,1) factors,
-    and records per solve: first iteration with core rel. error below 1e-6 (0 if none), iterations
-    run, wall time of the whole cpd_solve (compression included), final and initial core error."""
-    import time
-    from . import residual_norm2, solve, DgnState
+      learned - the network's start (cpd_learned_start without the judge),
+      random  - the library's N(0,1) start (cpd_solve's default for the same seed),
+      mlsvd   - the MLSVD-energy point (ch.4 "Initialization"),
+    all with the same CG-cap stream (params seed), and records per solve: the first iteration with
+    core rel. error below 1e-6 (0 if none), iterations run, the device time from the solve's first
+    kernel to that iteration (in-kernel clock, compression included; -1 if none) and the device
+    time of the start's own inference call (cuda events; 0 for the plain starts).
+    For every judge rule (k, margin) in JUDGES, cpd_learned_start with the judge is run too and its
+    choice recorded in results["judge"][(k, margin)]: the judged start is bit-identical to the
+    network's or to the random start, so its solve is the corresponding row's."""
+    from . import solve
     gen = torch.Generator(device="cpu").manual_seed(int(seed))
-    out = {"learned": [], "fallback": [], "mlsvd": [], "random": []}
+    out = {"learned": [], "random": [], "mlsvd": [], "judge": {j: [] for j in JUDGES}}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for i in range(n_test):
         Td = planted_device(dims, R, gen, net.device)
         _, _, S, _ = compress(Td, R, params(core_dims=core))
         S3 = S.reshape(core).contiguous()
-        x, s = core_feature(S3)
-        W_l = factors_from_output(net.forward(x[None, :])[0], core, R, s)
-        st = DgnState(S3, R, params(core_dims=core, init="mlsvd"))
-        W_m = [w.clone() for w in st.factors()]
-        W_r = [torch.randn((d, R), generator=gen, dtype=torch.float64).to(net.device) for d in core]
-        e = {k: float(residual_norm2(S3, W)[0]) ** 0.5 / s for k, W in (("learned", W_l), ("mlsvd", W_m), ("random", W_r))}
-        use_l = e["learned"] <= e["mlsvd"]
-        runs = [("learned", W_l, e["learned"]), ("fallback", W_l if use_l else W_m, min(e["learned"], e["mlsvd"])),
-                ("mlsvd", W_m, e["mlsvd"]), ("random", W_r, e["random"])]
-        for name, W0, e0 in runs:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = solve(Td, R, params(core_dims=core, init="given", maxiter=maxiter), W0=W0)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
+        sd = int(seed) * 1000003 + i
+        pc = params(core_dims=core, seed=sd)
+        ev0.record()
+        W_l, _, _ = learned_start(net, S3, R, p=pc)
+        ev1.record()
+        ev1.synchronize()
+        t_l = ev0.elapsed_time(ev1)
+        for (k, m) in JUDGES:
+            ev0.record()
+            _, chosen, errs = learned_start(net, S3, R, judge_iters=k, p=pc, margin=m)
+            ev1.record()
+            ev1.synchronize()
+            out["judge"][(k, m)].append((chosen, errs[0], errs[1], ev0.elapsed_time(ev1)))
+        for name, W0, init, t_ms in (("learned", W_l, "given", t_l), ("random", None, "random", 0.0),
+                                     ("mlsvd", None, "mlsvd", 0.0)):
+            r = solve(Td, R, params(core_dims=core, init=init, maxiter=maxiter, seed=sd), W0=W0)
             inf = r["info"]
-            out[name].append((max(inf["tol_iter"], 0), inf["iters"], dt, inf["rel_err_core"], e0))
+            out[name].append((max(inf["tol_iter"], 0), inf["iters"], inf["time_to_tol_ns"], t_ms))
         if progress is not None and (i + 1) % 100 == 0:
             progress(i + 1, n_test)
     return out
 
 
 def summarize(results):
-    """Per starting point: fraction reaching 1e-6, median iterations and time to 1e-6 over those,
-    median initial core error."""
+    """Per starting point: fraction reaching 1e-6; over those, the median iterations and device ms
+    to 1e-6 of the solve, and the median total with the start's inference.  Per judge rule the
+    same figures for the start it picks, and the share of network starts it keeps."""
     import statistics
-    summ = {}
-    for name, rows in results.items():
+
+    def stats(rows):
         ok = [r for r in rows if r[0] > 0]
-        summ[name] = {"reached_1e-6": len(ok) / max(len(rows), 1),
-                      "median_iters_to_1e-6": statistics.median([r[0] for r in ok]) if ok else None,
-                      "median_s_to_1e-6": statistics.median([r[2] for r in ok]) if ok else None,
-                      "median_initial_core_err": statistics.median([r[4] for r in rows]) if rows else None}
+        return {"reached_1e-6": len(ok) / max(len(rows), 1),
+                "median_iters_to_1e-6": statistics.median([r[0] for r in ok]) if ok else None,
+                "median_solve_ms_to_1e-6": statistics.median([r[2] * 1e-6 for r in ok]) if ok else None,
+                "median_total_ms_to_1e-6": statistics.median([r[2] * 1e-6 + r[3] for r in ok]) if ok else None,
+                "median_start_ms": statistics.median([r[3] for r in rows]) if rows else None}
+
+    summ = {name: stats(results[name]) for name in ("learned", "random", "mlsvd")}
+    for (k, m), picks in results["judge"].items():
+        rows = [(results["learned"][i] if c == 0 else results["random"][i])[:3] + (t,)
+                for i, (c, _, _, t) in enumerate(picks)]
+        st = stats(rows)
+        st["network_kept"] = sum(1 for c, _, _, _ in picks if c == 0) / max(len(picks), 1)
+        summ["judged k=%d margin=%g" % (k, m)] = st
     return summ
 
 

@@ -27,7 +27,10 @@ def relmax(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30))
 
 
-@pytest.mark.parametrize("dims,B", [([37, 70, 33, 19], 45), ([4096, 1024, 1024, 384], 256)])
+# B <= 8 takes the small-batch (split-K matrix-vector) forward, larger batches the tiled GEMM
+@pytest.mark.parametrize("dims,B", [([37, 70, 33, 19], 45), ([4096, 1024, 1024, 384], 256),
+                                    ([37, 70, 33, 19], 5), ([4096, 1024, 1024, 384], 1),
+                                    ([4096, 1024, 1024, 384], 8)])
 def test_mlp_forward_backward_adam_match_oracle(dims, B):
     log("mlp", dims, B)
     L = lib()
