@@ -851,8 +851,7 @@ __global__ __launch_bounds__(NT) void dgn_kernel_g(char* __restrict__ state, con
 // Second half of an iteration split over launches: from the residual ||S - [[W]]||^2 of the
 // balanced update (f2_new, computed by the full-tensor kernels on the core, which also refreshed
 // the MTTKRP in the state) the error, gain ratio, damping update, stopping tests and log entry.
-__global__ void dgn_tail_kernel(char* __restrict__ state) {
-  if (threadIdx.x != 0) return;
+__device__ void tail_step(char* __restrict__ state) {
   Hdr* h = (Hdr*)state;
   if (h->pending != 1) return;
   h->pending = 0;
@@ -884,6 +883,10 @@ __global__ void dgn_tail_kernel(char* __restrict__ state) {
   h->stop = st;
 }
 
+__global__ void dgn_tail_kernel(char* __restrict__ state) {
+  if (threadIdx.x == 0) tail_step(state);
+}
+
 // ---- cooperative CG for cores whose working set lives in global memory -------------------------
 // The CG of one dGN iteration (ch.4 Alg. "Conjugate gradient - dGN" on M^{-1/2}(J^T J + mu D)
 // M^{-1/2}, the products of Thm Hv) spread over CG_WG workgroups of one cooperative launch, then
@@ -907,6 +910,15 @@ __global__ void dgn_tail_kernel(char* __restrict__ state) {
 // bounded: after BAR_SPINS polls a workgroup records HDR_BAR_TIMEOUT in the header and goes on, so
 // every wave reaches the end of the kernel, and the host reports an error.
 constexpr int CG_WG = 8;   // workgroups: a grid barrier costs ~2.2 us at 8 and ~6.4 us at 48
+// Partial-sum slots of the multi-workgroup iteration (doubles, after the second r, p and z
+// buffers): each group is written before a barrier and read after it, and no group is written
+// again until every workgroup has passed a later barrier.
+constexpr int SLOT_RR = 0;                          // ||r_0||^2 (CG_WG), then max|g| (CG_WG)
+constexpr int SLOT_COL = 2 * CG_WG;                 // column-norm partials, CG_WG x 3R (R <= 64)
+constexpr int SLOT_DP = SLOT_COL + CG_WG * 3 * 64;  // <p_j, z_j> by the parity of j (2 CG_WG)
+constexpr int SLOT_XJX = SLOT_DP + 2 * CG_WG;       // x^T J^T J x (CG_WG)
+constexpr int SLOT_GX = SLOT_XJX + CG_WG;           // grad.x and x.x (2 CG_WG)
+constexpr int SLOT_END = SLOT_GX + 2 * CG_WG;
 constexpr long long BAR_SPINS = 1ll << 22;
 
 struct BarSlot {
@@ -946,9 +958,12 @@ __device__ __forceinline__ double p_next(const double* Rj, const double* Zj, con
   return (Rj[e] - alpha * ((e < zfree) ? 0.0 : Zj[e])) + beta * Pj[e];
 }
 
-// Phase A: Q_b tiles for V given by vf(e) (global index); rows of Q scaled by msq when scale.
+// Phase A: the tiles of Q_b = V_b^T W_b (rows scaled by msq when scale) for V given by vf(e), written
+// as the two contributions Y_a needs, C[2a + j] = pi^(c) * Q_b for the modes a != b (j = 0 when b is
+// the lower of a's other modes, c the third mode), so that phase B reads Y_a = C[2a] + C[2a + 1]
+// without pi.  The pi entries are loaded with the tile's operands: one memory round per tile.
 template <class VF>
-__device__ void coop_phase_a(Ctx& c, VF vf, bool scale) {
+__device__ void coop_phase_a(Ctx& c, double* C, VF vf, bool scale) {
   const int R = c.R, RR = R * R, tr = tiles16(R);
   const int lane = threadIdx.x & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
   const int nA = 3 * tr * tr;
@@ -956,20 +971,40 @@ __device__ void coop_phase_a(Ctx& c, VF vf, bool scale) {
     const int b = t / (tr * tr), tt = t - b * tr * tr, tm = tt / tr, tn = tt - tm * tr;
     const int ob = offof(c, b), db = dimof(c, b);
     const double* Wb = c.W + ob;
+    // the two modes a != b, and for each the third mode whose pi weighs Q_b
+    const int a0 = (b == 0) ? 1 : 0, a1 = (b == 2) ? 1 : 2;
+    const int c0 = 3 - b - a0, c1 = 3 - b - a1;
+    double pw0[4], pw1[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = min(tm * 16 + 4 * v + kq, R - 1) * R + min(tn * 16 + r16, R - 1);
+      pw0[v] = c.pi[c0 * RR + q];
+      pw1[v] = c.pi[c1 * RR + q];
+    }
     const dbl4 acc = mfma_tile_wide(tm * 16, tn * 16, db,
         [&](int sidx, int i) { return sel(sidx < R && i < db, vf(ob + min(i, db - 1) * R + min(sidx, R - 1))); },
         [&](int i, int r) { return sel(r < R && i < db, Wb[min(i, db - 1) * R + min(r, R - 1)]); });
+    // slot of Q_b in Y_{a0} and Y_{a1}: j = 0 when b is the lower other mode of a
+    const int j0 = (b == ((a0 == 0) ? 1 : 0)) ? 0 : 1, j1 = (b == ((a1 == 0) ? 1 : 0)) ? 0 : 1;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int sidx = tm * 16 + 4 * v + kq, r = tn * 16 + r16;
-      if (sidx < R && r < R) c.Qb[b * RR + sidx * R + r] = scale ? c.msq[b * R + sidx] * acc[v] : acc[v];
+      if (sidx < R && r < R) {
+        const double qv = scale ? c.msq[b * R + sidx] * acc[v] : acc[v];
+        const int q = sidx * R + r;
+        C[(2 * a0 + j0) * RR + q] = pw0[v] * qv;
+        C[(2 * a1 + j1) * RR + q] = pw1[v] * qv;
+      }
     }
   }
 }
 
 // Phase B: out = the scaled (or plain) structured product of V (stored), tile by tile; returns this
-// thread's partial of <V, out>.
-__device__ double coop_phase_b(Ctx& c, const double* V, double* out, double mu, bool scale) {
+// thread's partial of <V, out>.  Every global operand of a tile (the V and W fragments, the two
+// contributions of Y_a at the B-fragment positions, V at the outputs) is loaded before its first
+// product, so a tile costs one memory round; Pi^(a), M^{-1/2} and D come from LDS.  R <= 64: the
+// contraction over R is a single 64-deep slice.
+__device__ double coop_phase_b(Ctx& c, const double* C, const double* V, double* out, double mu, bool scale) {
   const int R = c.R, RR = R * R, tr = tiles16(R);
   const int lane = threadIdx.x & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
   const int t0 = tiles16(c.d0) * tr, t1 = t0 + tiles16(c.d1) * tr, t2 = t1 + tiles16(c.d2) * tr;
@@ -983,33 +1018,42 @@ __device__ double coop_phase_b(Ctx& c, const double* V, double* out, double mu, 
     const double* Wa = c.W + oa;
     const double* Pa = c.Pown + a * RR;
     const double* ma = c.msq + a * R;
-    const int b1 = (a == 0) ? 1 : 0, b2 = (a == 2) ? 1 : 2;
-    const double* pb1 = c.pi + b1 * RR;
-    const double* pb2 = c.pi + b2 * RR;
-    const double* qb1 = c.Qb + b1 * RR;
-    const double* qb2 = c.Qb + b2 * RR;
-    const dbl4 acc1 = mfma_tile_wide(tm * 16, tn * 16, R,
-        [&](int i, int k) {
-          const int kk = min(k, R - 1);
-          const double v = Va[min(i, da - 1) * R + kk];
-          return sel(i < da && k < R, scale ? ma[kk] * v : v);
-        },
-        [&](int k, int r) { return sel(r < R && k < R, Pa[min(k, R - 1) * R + min(r, R - 1)]); });
-    const dbl4 acc2 = mfma_tile_wide(tm * 16, tn * 16, R,
-        [&](int i, int k) { return sel(i < da && k < R, Wa[min(i, da - 1) * R + min(k, R - 1)]); },
-        [&](int k, int r) {
-          const int q = min(k, R - 1) * R + min(r, R - 1);
-          return sel(r < R && k < R, pb2[q] * qb1[q] + pb1[q] * qb2[q]);
-        });
+    const double* ya0 = C + (2 * a) * RR;
+    const double* ya1 = C + (2 * a + 1) * RR;
+    const int irow = tm * 16 + r16, ic = min(irow, da - 1);
+    const int rcol = tn * 16 + r16, rc = min(rcol, R - 1);
+    double va[16], wa[16], y0[16], y1[16], ve[4];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int kc = min(4 * u + kq, R - 1);
+      va[u] = Va[ic * R + kc];
+      wa[u] = Wa[ic * R + kc];
+      y0[u] = ya0[kc * R + rc];
+      y1[u] = ya1[kc * R + rc];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ve[v] = Va[min(tm * 16 + 4 * v + kq, da - 1) * R + rc];
+    dbl4 acc1 = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int k = 4 * u + kq, kc = min(k, R - 1);
+      const bool okA = irow < da && k < R, okB = rcol < R && k < R;
+      const double a1 = sel(okA, scale ? ma[kc] * va[u] : va[u]);
+      const double b1 = sel(okB, Pa[kc * R + rc]);
+      const double a2 = sel(okA, wa[u]);
+      const double b2 = sel(okB, y0[u] + y1[u]);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2, acc2, 0, 0, 0);
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = tm * 16 + 4 * v + kq, r = tn * 16 + r16;
+      const int i = tm * 16 + 4 * v + kq, r = rcol;
       if (i < da && r < R) {
         const int e = oa + i * R + r;
         double tv = acc1[v] + acc2[v];
-        if (scale) tv = ma[r] * (tv + mu * c.gam[a * R + r] * (ma[r] * V[e]));
+        if (scale) tv = ma[r] * (tv + mu * c.gam[a * R + r] * (ma[r] * ve[v]));
         out[e] = tv;
-        dotp += V[e] * tv;
+        dotp += ve[v] * tv;
       }
     }
   }
@@ -1055,6 +1099,8 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
   Ctx c;
   setup_ctx(c, (double*)(state + Lo.work), d, R, nullptr, (double*)(state + Lo.MK), (double*)(state + Lo.G));
   c.W = (double*)(state + Lo.W);
+  // the work region's Pi and Q areas (adjacent, 6 R^2) hold phase A's contributions to Y
+  double* Cy = c.Pown;
   c.Pown = lds_c;
   c.msq = lds_c + 3 * RR;
   c.gam = c.msq + 3 * R;
@@ -1138,21 +1184,21 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
       const double* Zq = c.Z;
       const double al = alpha, be = beta;
       if (first)
-        coop_phase_a(c, [&](int e) { return Pj[e]; }, true);
+        coop_phase_a(c, Cy, [&](int e) { return Pj[e]; }, true);
       else
-        coop_phase_a(c, [&](int e) { return p_next(Rq, Zq, Pq, e, al, be, zfree); }, true);
+        coop_phase_a(c, Cy, [&](int e) { return p_next(Rq, Zq, Pq, e, al, be, zfree); }, true);
     }
     sync_all();
     // B: z_j and <p_j, z_j>
-    const double dp = block_sum(coop_phase_b(c, Pj, c.Z, mu, true), slots[0]);
-    if (tid == 0) part[g] = dp;
+    const double dp = block_sum(coop_phase_b(c, Cy, Pj, c.Z, mu, true), slots[0]);
+    if (tid == 0) part[SLOT_DP + g] = dp;
     sync_all();
-    const double pz = sum_parts(part, G);
+    const double pz = sum_parts(part + SLOT_DP, G);
     if (!(pz > 0.0)) break;
     alpha = rr / pz;
     // C: ||r_j - alpha z_j||^2 over the whole vector (the same in every workgroup), own slice update
     double eps = 0.0;
-#pragma unroll 8
+#pragma unroll 16
     for (int e = tid; e < np; e += NT) {
       const double rv = Rj[e] - alpha * ((e < zfree) ? 0.0 : c.Z[e]);
       eps += rv * rv;
@@ -1183,12 +1229,12 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
   }
   sync_all();
   // x^T J^T J x: the same two phases on x, unscaled
-  coop_phase_a(c, [&](int e) { return c.X[e]; }, false);
+  coop_phase_a(c, Cy, [&](int e) { return c.X[e]; }, false);
   sync_all();
-  const double xp = block_sum(coop_phase_b(c, c.X, c.Z, 0.0, false), slots[0]);
-  if (tid == 0) part[g] = xp;
+  const double xp = block_sum(coop_phase_b(c, Cy, c.X, c.Z, 0.0, false), slots[0]);
+  if (tid == 0) part[SLOT_XJX + g] = xp;
   sync_all();
-  const double xjx = sum_parts(part, G);
+  const double xjx = sum_parts(part + SLOT_XJX, G);
 
   // 4. own slice: grad.x, x.x, the update, and the slice's share of every column norm
   double gx = 0.0, xx = 0.0;
@@ -1200,7 +1246,7 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
   }
   gx = block_sum(gx, slots[0]);
   xx = block_sum(xx, slots[1]);
-  double* colp = part + 2 * CG_WG;   // CG_WG rows of 3R column partials
+  double* colp = part + SLOT_COL;   // CG_WG rows of 3R column partials
   for (int q = tid; q < 3 * R; q += NT) {
     const int l = q / R, r = q - l * R;
     const int ol = offof(c, l), dl = dimof(c, l);
@@ -1216,13 +1262,13 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
     colp[g * 3 * R + q] = acc;
   }
   if (tid == 0) {
-    part[g] = gx;
-    part[G + g] = xx;
+    part[SLOT_GX + g] = gx;
+    part[SLOT_GX + G + g] = xx;
   }
   sync_all();
   // 5. column norms, balancing of the own slice, header
-  gx = sum_parts(part, G);
-  xx = sum_parts(part + G, G);
+  gx = sum_parts(part + SLOT_GX, G);
+  xx = sum_parts(part + SLOT_GX + G, G);
   double* cn = slots_cn(c);   // 3R doubles of LDS (reuses msq: no longer needed)
   for (int q = tid; q < 3 * R; q += NT) {
     double s2 = 0.0;
@@ -1256,8 +1302,7 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
 
 // Finishes an initialisation whose residual ||S - [[W]]||^2 (into f2_new) and MTTKRP (into the
 // state's MK) were computed by the full-tensor kernels on the core.
-__global__ void dgn_init_tail_kernel(char* __restrict__ state) {
-  if (threadIdx.x != 0) return;
+__device__ void tail_init(char* __restrict__ state) {
   Hdr* h = (Hdr*)state;
   const Layout Lo = layout_of(h->np, h->R, h->maxiter);
   double* errs = (double*)(state + Lo.errs);
@@ -1265,6 +1310,182 @@ __global__ void dgn_init_tail_kernel(char* __restrict__ state) {
   h->err0 = (h->s_norm > 0.0) ? sqrt(h->f2_new) / h->s_norm : 0.0;
   errs[0] = h->err0;
   h->t_init = wall_clock64();
+}
+
+__global__ void dgn_init_tail_kernel(char* __restrict__ state) {
+  if (threadIdx.x == 0) tail_init(state);
+}
+
+// ---- residual and MTTKRPs of a large core in two launches ----------------------------------------
+// For an FP64 core whose dGN working set exceeds LDS, the MTTKRPs MK_l = S_(l) KR(other factors)
+// of the next gradient (ch.4 gradient theorem) and ||S - [[W]]||^2 (ch.4 residual) come from one
+// launch of independent wave items on the FP64 matrix cores:
+//   MTTKRP items: a 16x16 tile of MK_l over a chunk of CR_KC contraction indices (Khatri-Rao rows
+//     formed in the loads), written as a partial tile;
+//   residual items: a 16x16 tile of the model W^(1) (W^(2) kr W^(3))^T (contraction over R, one
+//     64-deep slice), whose squared differences with S are summed per wave.
+// core_finish_kernel adds the partials in a fixed order into MK and f2_new and runs the step's
+// tail (or the initialisation's), so a dGN iteration of a large core is three launches.
+constexpr int CR_KC = 256;
+
+struct CoreGeom {
+  int d0, d1, d2, R, tr;
+  int ns[3];        // contraction chunks per mode
+  int base[3];      // first partial tile of each mode
+  int nm;           // MTTKRP items (= partial tiles)
+  int nres;         // residual items
+  double inv1, inv2;
+};
+
+__host__ __device__ inline CoreGeom core_geom(const int d[3], int R) {
+  CoreGeom g;
+  g.d0 = d[0]; g.d1 = d[1]; g.d2 = d[2]; g.R = R; g.tr = (R + 15) / 16;
+  const long long K[3] = {(long long)d[1] * d[2], (long long)d[0] * d[2], (long long)d[0] * d[1]};
+  int b = 0;
+  for (int l = 0; l < 3; ++l) {
+    g.ns[l] = (int)((K[l] + CR_KC - 1) / CR_KC);
+    g.base[l] = b;
+    b += ((d[l] + 15) / 16) * g.tr * g.ns[l];
+  }
+  g.nm = b;
+  g.nres = ((d[0] + 15) / 16) * (int)(((long long)d[1] * d[2] + 15) / 16);
+  g.inv1 = 1.0 / d[1];
+  g.inv2 = 1.0 / d[2];
+  return g;
+}
+
+__global__ __launch_bounds__(NT) void core_refresh_kernel(const double* __restrict__ S, const double* __restrict__ W,
+                                                          CoreGeom g, double* __restrict__ mpart,
+                                                          double* __restrict__ rpart) {
+  const int item = blockIdx.x * NW + wave_id();
+  if (item >= g.nm + g.nres) return;
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  const int R = g.R, R1 = R - 1, d0 = g.d0, d1 = g.d1, d2 = g.d2, d12 = d1 * d2;
+  const double* W0 = W;
+  const double* W1 = W + d0 * R;
+  const double* W2 = W + (d0 + d1) * R;
+  if (item < g.nm) {
+    const int l = item >= g.base[2] ? 2 : (item >= g.base[1] ? 1 : 0);
+    const int loc = item - g.base[l];
+    const int ns = g.ns[l];
+    const int tile = loc / ns, sp = loc - tile * ns;
+    const int tm = tile / g.tr, tn = tile - tm * g.tr;
+    const int dl = l == 0 ? d0 : (l == 1 ? d1 : d2);
+    const int K = l == 0 ? d12 : (l == 1 ? d0 * d2 : d0 * d1);
+    const int kb = sp * CR_KC, kn = min(CR_KC, K - kb);
+    dbl4 acc;
+    if (l == 0) {
+      acc = mfma_tile_wide(tm * 16, tn * 16, kn,
+          [&](int i, int x) {
+            const int xx = kb + min(x, kn - 1);
+            return sel(i < d0 && x < kn, S[(long long)min(i, d0 - 1) * d12 + xx]);
+          },
+          [&](int x, int r) {
+            const int xx = kb + min(x, kn - 1), j = div_by(xx, g.inv2), k = xx - j * d2, rr = min(r, R1);
+            return sel(r < R && x < kn, W1[j * R + rr] * W2[k * R + rr]);
+          });
+    } else if (l == 1) {
+      acc = mfma_tile_wide(tm * 16, tn * 16, kn,
+          [&](int j, int x) {
+            const int xx = kb + min(x, kn - 1), i = div_by(xx, g.inv2), k = xx - i * d2;
+            return sel(j < d1 && x < kn, S[(long long)i * d12 + min(j, d1 - 1) * d2 + k]);
+          },
+          [&](int x, int r) {
+            const int xx = kb + min(x, kn - 1), i = div_by(xx, g.inv2), k = xx - i * d2, rr = min(r, R1);
+            return sel(r < R && x < kn, W0[i * R + rr] * W2[k * R + rr]);
+          });
+    } else {
+      acc = mfma_tile_wide(tm * 16, tn * 16, kn,
+          [&](int k, int x) {
+            const int xx = kb + min(x, kn - 1);
+            return sel(k < d2 && x < kn, S[(long long)xx * d2 + min(k, d2 - 1)]);
+          },
+          [&](int x, int r) {
+            const int xx = kb + min(x, kn - 1), i = div_by(xx, g.inv1), j = xx - i * d1, rr = min(r, R1);
+            return sel(r < R && x < kn, W0[i * R + rr] * W1[j * R + rr]);
+          });
+    }
+    double* out = mpart + (long long)item * 256;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[(4 * v + kq) * 16 + r16] = acc[v];
+    (void)dl;
+    return;
+  }
+  // residual item: rows tm of mode 1 times columns tn of the (j, k) index
+  const int it = item - g.nm;
+  const int tcols = (d12 + 15) / 16;
+  const int tm = it / tcols, tn = it - tm * tcols;
+  double sv[4];
+  const int x = tn * 16 + r16, xc = min(x, d12 - 1);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) sv[v] = S[(long long)min(tm * 16 + 4 * v + kq, d0 - 1) * d12 + xc];
+  const dbl4 acc = mfma_tile_wide(tm * 16, tn * 16, R,
+      [&](int i, int r) { return sel(i < d0 && r < R, W0[min(i, d0 - 1) * R + min(r, R1)]); },
+      [&](int r, int xx) {
+        const int xcl = min(xx, d12 - 1), j = div_by(xcl, g.inv2), k = xcl - j * d2, rr = min(r, R1);
+        return sel(r < R && xx < d12, W1[j * R + rr] * W2[k * R + rr]);
+      });
+  double f2 = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = tm * 16 + 4 * v + kq;
+    if (i < d0 && x < d12) {
+      const double f = sv[v] - acc[v];
+      f2 += f * f;
+    }
+  }
+  f2 = wave_sum(f2);
+  if (lane == 0) rpart[it] = f2;
+}
+
+// MK from the partial tiles and f2_new from the residual partials (fixed orders), then the tail of
+// the step (init = 0) or of the initialisation (init = 1): workgroup 0 adds the residual partials
+// and runs the tail (which reads no MK), the others one entry of MK per thread.
+__global__ __launch_bounds__(NT) void core_finish_kernel(char* __restrict__ state, CoreGeom g,
+                                                         const double* __restrict__ mpart,
+                                                         const double* __restrict__ rpart, int init) {
+  __shared__ double slots[NW];
+  Hdr* h = (Hdr*)state;
+  const int R = g.R;
+  // (a stopped state has an unchanged W: its MK is recomputed unchanged, and tail_step returns on
+  // pending == 0; workgroup 0 alone reads and clears pending)
+  if (blockIdx.x == 0) {
+    double f2 = 0.0;
+    for (int it = threadIdx.x; it < g.nres; it += NT) f2 += rpart[it];
+    f2 = block_sum(f2, slots);
+    if (threadIdx.x == 0) {
+      h->f2_new = f2;
+      if (init) tail_init(state); else tail_step(state);
+    }
+    return;
+  }
+  const Layout Lo = layout_of(h->np, R, h->maxiter);
+  double* MK = (double*)(state + Lo.MK);
+  int e = (blockIdx.x - 1) * NT + threadIdx.x;
+  if (e >= (g.d0 + g.d1 + g.d2) * R) return;
+  const int n0 = g.d0 * R, n1 = g.d1 * R;
+  const int l = e >= n0 + n1 ? 2 : (e >= n0 ? 1 : 0);
+  const int el = e - (l == 0 ? 0 : (l == 1 ? n0 : n0 + n1));
+  const int i = el / R, r = el - i * R, ns = g.ns[l];
+  const int tile = (i >> 4) * g.tr + (r >> 4);
+  const double* p = mpart + ((long long)g.base[l] + (long long)tile * ns) * 256 + (i & 15) * 16 + (r & 15);
+  double acc = 0.0;
+  for (int sp = 0; sp < ns; ++sp) acc += p[(long long)sp * 256];
+  MK[e] = acc;
+}
+
+// The fused launches serve tensors up to CR_MAXN entries (compressed cores; larger tensors, met by a
+// refinement on the input, take the full-tensor kernels).
+constexpr long long CR_MAXN = 1ll << 22;
+
+bool core_fused(const int d[3], int sdtype) {
+  return sdtype == CPD_F64 && (long long)d[0] * d[1] * d[2] <= CR_MAXN;
+}
+
+size_t core_refresh_bytes(const int d[3], int R) {
+  if ((long long)d[0] * d[1] * d[2] > CR_MAXN) return 0;
+  const CoreGeom g = core_geom(d, R);
+  return align_up(((size_t)g.nm * 256 + (size_t)g.nres) * sizeof(double), 256);
 }
 
 // Batched: workgroup b initialises state b (header, caps and W already written) and iterates it
@@ -1530,10 +1751,12 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
               "in one workgroup's LDS (np = %d, R = %d)", np, R);
     return CPD_E_UNSUPPORTED;
   } else {
-    // Large core: the core's MTTKRPs and residual run on the full-tensor kernels (spread over the
-    // chip). Initialisation: the single-workgroup part (balancing, norms, header), those kernels,
-    // and a one-thread tail. Each iteration: the single-workgroup half (gradient, CG, update),
-    // those kernels and the scalar tail; the host checks the stop flag after every few iterations.
+    // Large core: the MTTKRPs and the residual run over the chip, on the fused core launches
+    // (core_refresh_kernel + core_finish_kernel, which also runs the tail) or, for tensors too large
+    // for them or not FP64 (a refinement on the input), on the full-tensor kernels and a one-thread
+    // tail.  Initialisation: the single-workgroup part (balancing, norms, header), then those.  Each
+    // iteration: the multi-workgroup half (Grams, gradient, CG, update), then those; the host checks
+    // the stop flag after every few iterations.
     const int64_t dims[3] = {d[0], d[1], d[2]};
     Hdr hh;
     CPD_HIP_CHECK(hipMemcpyAsync(&hh, state, sizeof(Hdr), hipMemcpyDeviceToHost, s));
@@ -1546,16 +1769,39 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
     char* aux = state + align_up(Lo.total, 256);
     const size_t aux_bytes = full_kernels_aux_bytes(d, R);   // the cooperative CG's buffers follow
     double* f2_new = (double*)(state + offsetof(Hdr, f2_new));
-    if (mode == 0) {
-      hipLaunchKernelGGL((dgn_kernel_g<3, false>), dim3(1), dim3(NT), 0, s, state, S, max_steps);
-      CPD_LAUNCH_CHECK();
+    // the fused core launches' partials follow the cooperative CG's buffers
+    const bool fused = core_fused(d, sdtype);
+    const CoreGeom cg = core_geom(d, R);
+    double* mpart = (double*)(aux + aux_bytes + coop_cg_bytes(np));
+    double* rpart = mpart + (size_t)cg.nm * 256;
+    const int cr_blocks = (cg.nm + cg.nres + NW - 1) / NW;
+    // residual and MTTKRPs at the current W, then the step's (or the initialisation's) tail
+    auto refresh = [&](int init) -> cpd_status {
+      if (fused) {
+        hipLaunchKernelGGL(core_refresh_kernel, dim3(cr_blocks), dim3(NT), 0, s, S, (const double*)(state + Lo.W),
+                           cg, mpart, rpart);
+        CPD_LAUNCH_CHECK();
+        const int fin_blocks = 1 + (np + NT - 1) / NT;
+        hipLaunchKernelGGL(core_finish_kernel, dim3(fin_blocks), dim3(NT), 0, s, state, cg, (const double*)mpart,
+                           (const double*)rpart, init);
+        CPD_LAUNCH_CHECK();
+        return CPD_OK;
+      }
       cpd_status st;
       for (int l = 0; l < 3; ++l)
         if ((st = mttkrp_full(Sv, sdtype, dims, Wp, R, l, CPD_F64, MKp[l], aux, aux_bytes, s))) return st;
       if ((st = residual_full(Sv, sdtype, dims, Wp, R, f2_new, aux, aux_bytes, s))) return st;
-      hipLaunchKernelGGL(dgn_init_tail_kernel, dim3(1), dim3(64), 0, s, state);
+      if (init)
+        hipLaunchKernelGGL(dgn_init_tail_kernel, dim3(1), dim3(64), 0, s, state);
+      else
+        hipLaunchKernelGGL(dgn_tail_kernel, dim3(1), dim3(64), 0, s, state);
       CPD_LAUNCH_CHECK();
       return CPD_OK;
+    };
+    if (mode == 0) {
+      hipLaunchKernelGGL((dgn_kernel_g<3, false>), dim3(1), dim3(NT), 0, s, state, S, max_steps);
+      CPD_LAUNCH_CHECK();
+      return refresh(1);
     }
     if (hh.flags & HDR_DIRTY) {
       // factors replaced from outside: MTTKRP and residual at them, then clear the flag
@@ -1589,11 +1835,7 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
         hipLaunchKernelGGL(dgn_iter_coop_kernel, dim3(CG_WG), dim3(NT), it_lds, s, state, cP1, cR1, cpart, bar);
         CPD_LAUNCH_CHECK();
         cpd_status st;
-        for (int l = 0; l < 3; ++l)
-          if ((st = mttkrp_full(Sv, sdtype, dims, Wp, R, l, CPD_F64, MKp[l], aux, aux_bytes, s))) return st;
-        if ((st = residual_full(Sv, sdtype, dims, Wp, R, f2_new, aux, aux_bytes, s))) return st;
-        hipLaunchKernelGGL(dgn_tail_kernel, dim3(1), dim3(64), 0, s, state);
-        CPD_LAUNCH_CHECK();
+        if ((st = refresh(0))) return st;
       }
       if (done + n < max_steps) {
         CPD_HIP_CHECK(hipMemcpyAsync(&hh, state, sizeof(Hdr), hipMemcpyDeviceToHost, s));
@@ -1617,13 +1859,12 @@ size_t dgn_aux_bytes(const int d[3], int R) {
 }
 
 size_t full_aux_bytes(const int d[3], int R) {
-  return full_kernels_aux_bytes(d, R) + coop_cg_bytes((d[0] + d[1] + d[2]) * R);
+  return full_kernels_aux_bytes(d, R) + coop_cg_bytes((d[0] + d[1] + d[2]) * R) + core_refresh_bytes(d, R);
 }
 
 // The multi-workgroup iteration's second r and p buffers and its per-workgroup partials.
 size_t coop_cg_bytes(int np) {
-  // second r and p buffers; scalar partials (2 CG_WG) and column-norm partials (CG_WG x 3R, R <= 64)
-  return align_up(((size_t)2 * np + 2 * CG_WG + (size_t)CG_WG * 3 * 64) * sizeof(double), 256);
+  return align_up(((size_t)2 * np + SLOT_END) * sizeof(double), 256);
 }
 
 size_t full_kernels_aux_bytes(const int d[3], int R) {

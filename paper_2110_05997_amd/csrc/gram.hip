@@ -397,6 +397,157 @@ __global__ __launch_bounds__(GB_NT) void gram_bf16_big_kernel(const uint16_t* __
 }
 
 // Unfolding view of mode `mode` (variant, sizes and strides; no tiling).
+// FP64 Gram for large modes from FP64 or FP32 input: 128x128 tiles of G (twice the 64x64 tile's
+// flops per staged element and per converted value), each of the four waves a 64x64 quarter
+// (sixteen 16x16 accumulators on v_mfma_f64_16x16x4f64), 16 contraction indices per stage.  Staging
+// moves 16-byte vectors: along the contraction index for modes 1 and 2, along the row index for
+// mode 3 (stored transposed); values are promoted to FP64 at the LDS store.  On diagonal tiles the
+// 16x16 blocks below the diagonal are skipped (the reduction reads the upper triangle only), and
+// blocks past the last row are skipped everywhere.
+constexpr int GF_T = 128;
+constexpr int GF_NT = 256;
+constexpr int GF_KC = 16;
+constexpr int GF_LD = GF_KC + 1;   // LDS row pitch in doubles
+
+constexpr size_t GF_LDS = (size_t)2 * 2 * GF_T * GF_LD * sizeof(double);   // two stages, two operands
+
+template <class T>
+__global__ __launch_bounds__(GF_NT) void gram_f64_big_kernel(const T* __restrict__ src, GramGeom g,
+                                                             double* __restrict__ part) {
+  constexpr int VW = 16 / (int)sizeof(T);                 // elements per 16-byte vector
+  constexpr int NV = GF_T * GF_KC / VW / GF_NT;           // vectors per thread and operand
+  typedef T vec_t __attribute__((ext_vector_type(VW)));
+  // double-buffered stages: stage s + 1 is stored while stage s is multiplied, one barrier a stage
+  extern __shared__ double gf_lds[];
+  typedef double row_t[GF_LD];
+  auto Xbuf = [&](int b, int op) { return (row_t*)(gf_lds + (2 * b + op) * (GF_T * GF_LD)); };
+  const int L = blockIdx.x;
+  const int xcd = L & 7, idx = L >> 3;
+  const int tile = idx % g.nupper;
+  const int split = (idx / g.nupper) * 8 + xcd;
+  if (split >= g.nsplit) return;
+  int tm, tn;
+  tile_of(tile, g.ntile, tm, tn);
+  const bool diag = (tm == tn);
+  const int kbeg = split * g.kchunk, kend = min(g.Ktot, kbeg + g.kchunk);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // wave quarters; on a diagonal tile the quarter below the diagonal has nothing to do, so its wave
+  // takes the lower half of the off-diagonal quarter's rows (10, 8, 8 and 10 blocks instead of 10,
+  // 0, 16 and 10)
+  int wm = (w & 1) * 64, wn = (w >> 1) * 64, ilim = 4;
+  if (diag && w == 1) { wm = 32; wn = 64; ilim = 2; }
+  if (diag && w == 2) ilim = 2;
+  const bool v0 = g.variant == 0;
+  const int gM = g.M, gK = g.K, sm = g.sm, sk = g.sk;
+  const long long sb = g.sb;
+  const double invK = 1.0 / (double)(v0 ? gK : 1);
+  // vector v of this thread: variant 0 -> (row, VW consecutive contraction indices); variant 1 ->
+  // (VW consecutive rows, one contraction index)
+  auto vrow = [=](int v) {
+    const int e = tid + v * GF_NT;
+    return v0 ? e / (GF_KC / VW) : (e % (GF_T / VW)) * VW;
+  };
+  auto vk = [=](int v) {
+    const int e = tid + v * GF_NT;
+    return v0 ? (e % (GF_KC / VW)) * VW : e / (GF_T / VW);
+  };
+  auto addr = [=](int m, int kp) -> long long {
+    if (v0) {
+      const int b = (int)(((double)kp + 0.5) * invK);
+      return (long long)b * sb + (long long)m * sm + (kp - b * gK);
+    }
+    return (long long)kp * sk + m;
+  };
+  vec_t rm[NV], rn[NV];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int r = vrow(v), kp = k0 + vk(v);
+      const bool okk = kp < kend;
+      const int gm = tm * GF_T + r, gn = tn * GF_T + r;
+      rm[v] = *(const vec_t*)(src + addr(gm < gM && okk ? gm : 0, okk ? kp : 0));
+      if (!diag) rn[v] = *(const vec_t*)(src + addr(gn < gM && okk ? gn : 0, okk ? kp : 0));
+    }
+  };
+  auto store = [&](row_t* X, const vec_t* rv, int row0, int k0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int r = vrow(v), kq = vk(v);
+      const bool okk = k0 + kq < kend;
+#pragma unroll
+      for (int u = 0; u < VW; ++u) {
+        if (v0) {
+          X[r][kq + u] = (okk && row0 + r < gM) ? (double)rv[v][u] : 0.0;
+        } else {
+          X[r + u][kq] = (okk && row0 + r + u < gM) ? (double)rv[v][u] : 0.0;
+        }
+      }
+    }
+  };
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  // 16x16 blocks this wave computes: inside the matrix, and on or above the diagonal of a diagonal
+  // tile (a whole quarter below it idles in the products)
+  bool on[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r0 = wm + 16 * i, c0 = wn + 16 * j;
+      on[i][j] = i < ilim && tm * GF_T + r0 < gM && tn * GF_T + c0 < gM && (!diag || r0 <= c0);
+    }
+  if (kbeg < kend) {
+    fetch(kbeg);
+    store(Xbuf(0, 0), rm, tm * GF_T, kbeg);
+    if (!diag) store(Xbuf(0, 1), rn, tn * GF_T, kbeg);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += GF_KC) {
+    const bool more = k0 + GF_KC < kend;
+    if (more) fetch(k0 + GF_KC);
+    row_t* Am = Xbuf(cur, 0);
+    row_t* Bn = diag ? Xbuf(cur, 0) : Xbuf(cur, 1);
+#pragma unroll
+    for (int kk = 0; kk < GF_KC; kk += 4) {
+      // A fragment: lane holds A[lane%16][lane/16] (16x4); B fragment: B[lane/16][lane%16] (4x16)
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = Am[wm + 16 * i + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bn[wn + 16 * j + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (on[i][j]) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    // the other buffer was last read before the previous barrier
+    if (more) {
+      store(Xbuf(cur ^ 1, 0), rm, tm * GF_T, k0 + GF_KC);
+      if (!diag) store(Xbuf(cur ^ 1, 1), rn, tn * GF_T, k0 + GF_KC);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  // every block of the upper triangle is written by exactly one wave (the reduction reads no other)
+  double* out = part + ((long long)tile * g.nsplit + split) * (GF_T * GF_T);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (i < ilim)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = wm + 16 * i + 4 * v + (lane >> 4);
+          const int c = wn + 16 * j + (lane & 15);
+          out[r * GF_T + c] = acc[i][j][v];
+        }
+}
+
 GramGeom make_geom_base(const int64_t dims[3], int mode) {
   GramGeom g{};
   const long long I1 = dims[0], I2 = dims[1], I3 = dims[2];
@@ -614,6 +765,53 @@ GramGeom make_big_geom(const int64_t dims[3], int mode) {
   return g;
 }
 
+// 128x128 FP64 tiles: the split count is a multiple of 8 (XCD order), chunks hold at least 32
+// stages, and the workgroup count fills GF_SLOTS resident workgroups (two per compute unit on the
+// 256 units) in whole rounds: the first count of at least four rounds within 2 % of full, else the
+// fullest one seen.
+constexpr int GF_SLOTS = 512;
+
+GramGeom make_f64_big_geom(const int64_t dims[3], int mode) {
+  GramGeom g = make_geom_base(dims, mode);
+  g.ntile = (g.M + GF_T - 1) / GF_T;
+  g.nupper = g.ntile * (g.ntile + 1) / 2;
+  const long long maxsplit = (g.Ktot + 32 * GF_KC - 1) / (32 * GF_KC);
+  long long best_ns = 8, best_chunk = (g.Ktot + 7) / 8;
+  best_chunk = (best_chunk + GF_KC - 1) / GF_KC * GF_KC;
+  double best_eff = -1.0;
+  for (long long want = 8; want <= 1024; want += 8) {
+    long long chunk = (g.Ktot + want - 1) / want;
+    chunk = (chunk + GF_KC - 1) / GF_KC * GF_KC;
+    long long ns = (g.Ktot + chunk - 1) / chunk;
+    ns = (ns + 7) / 8 * 8;
+    const long long n = (long long)g.nupper * ns;
+    const long long rounds = (n + GF_SLOTS - 1) / GF_SLOTS;
+    const double eff = (double)n / (double)(rounds * GF_SLOTS);
+    if (eff > best_eff + 1e-12) {
+      best_eff = eff;
+      best_ns = ns;
+      best_chunk = chunk;
+    }
+    if (rounds >= 4 && eff >= 0.98) {
+      best_ns = ns;
+      best_chunk = chunk;
+      break;
+    }
+    if (want >= maxsplit) break;
+  }
+  g.nsplit = (int)best_ns;
+  g.kchunk = (int)best_chunk;
+  return g;
+}
+
+// The 128x128 FP64 kernel moves whole 16-byte vectors of the input type.
+bool big_f64_ok(const GramGeom& g, const void* T, int dtype) {
+  if ((dtype != CPD_F64 && dtype != CPD_F32) || g.M <= GT_MAXM || ((uintptr_t)T & 15)) return false;
+  const int vw = dtype == CPD_F64 ? 2 : 4;
+  if (g.variant == 0) return g.K % vw == 0 && g.sm % vw == 0 && g.sb % vw == 0;
+  return g.sk % vw == 0 && g.M % vw == 0;
+}
+
 // The large BF16 kernel moves whole 16-byte vectors: every vector must be in one slab and aligned.
 bool big_bf16_ok(const GramGeom& g, const void* T) {
   if (g.M <= GT_MAXM || ((uintptr_t)T & 15)) return false;
@@ -642,6 +840,9 @@ size_t gram_ws_bytes(const int64_t dims[3], int mode) {
     const GramGeom gb = make_big_geom(dims, mode);
     const size_t bb = align_up((size_t)gb.nupper * gb.nsplit * GB_T * GB_T * sizeof(double), 256);
     b = b > bb ? b : bb;
+    const GramGeom gf = make_f64_big_geom(dims, mode);
+    const size_t bf = align_up((size_t)gf.nupper * gf.nsplit * GF_T * GF_T * sizeof(double), 256);
+    b = b > bf ? b : bf;
   }
   if (g.M <= GT_MAXM) {
     int mp;
@@ -685,6 +886,26 @@ cpd_status gram(const void* T, int dtype, const int64_t dims[3], int mode, int c
     const long long nel = (long long)ntri * 256;
     hipLaunchKernelGGL(gram_tri_reduce_kernel, dim3((unsigned)((nel + 31) / 32)), dim3(256), 0, s, part, t.M, mp,
                        t.nsplit, G);
+    prof_end(CPD_PK_GRAM, s);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+  }
+  if (!bf && big_f64_ok(make_geom_base(dims, mode), T, dtype)) {
+    const GramGeom gf = make_f64_big_geom(dims, mode);
+    const int nb = gf.nupper * gf.nsplit;
+    prof_begin(CPD_PK_GRAM, s);
+    if (dtype == CPD_F64) {
+      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)gram_f64_big_kernel<double>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)GF_LDS));
+      hipLaunchKernelGGL(gram_f64_big_kernel<double>, dim3(nb), dim3(GF_NT), GF_LDS, s, (const double*)T, gf, part);
+    } else {
+      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)gram_f64_big_kernel<float>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)GF_LDS));
+      hipLaunchKernelGGL(gram_f64_big_kernel<float>, dim3(nb), dim3(GF_NT), GF_LDS, s, (const float*)T, gf, part);
+    }
+    CPD_LAUNCH_CHECK();
+    const long long nelf = (long long)gf.nupper * GF_T * GF_T;
+    hipLaunchKernelGGL(gram_reduce_kernel<GF_T>, dim3((unsigned)((nelf + 255) / 256)), dim3(256), 0, s, part, gf, G);
     prof_end(CPD_PK_GRAM, s);
     CPD_LAUNCH_CHECK();
     return CPD_OK;

@@ -51,12 +51,17 @@ def log(*a):
 
 
 # ---------------------------------------------------------------------------------------------
-# Gram sizes <= 208 take the whole-triangle kernel, larger ones the 64x64-tile kernel (230, 209);
-# bf16 input is promoted exactly on the FP64 path
+# Gram sizes <= 208 take the whole-triangle kernel; larger ones the 128x128-tile kernel when the
+# rows allow 16-byte vectors of the input type (230 and 600: mode 1; 260: mode 2 on slabs of 24;
+# 300 and 262: mode 3, row-contiguous), else the 64x64-tile kernel (209, 301, BF16 input, which is
+# promoted exactly on the FP64 path)
 @pytest.mark.parametrize("dims,dtype", [((70, 45, 130), torch.float64), ((33, 97, 20), torch.float32),
                                         ((5, 4, 3), torch.float64), ((130, 1, 65), torch.float64),
                                         ((230, 20, 9), torch.float32), ((7, 209, 208), torch.bfloat16),
-                                        ((200, 200, 200), torch.float32), ((600, 36, 50), torch.float32)])
+                                        ((200, 200, 200), torch.float32), ((600, 36, 50), torch.float32),
+                                        ((12, 260, 24), torch.float64), ((9, 10, 300), torch.float32),
+                                        ((10, 7, 262), torch.float64), ((9, 10, 301), torch.float32),
+                                        ((7, 209, 208), torch.float32)])
 def test_gram_matches_unfolding_gram(dims, dtype):
     log("gram", dims, dtype)
     rng = np.random.default_rng(sum(dims))
@@ -248,8 +253,10 @@ def oracle_steps(S, W0, params, uniforms, nsteps):
     return st, infos
 
 
+# (30, 30, 30) R = 30, (50, 50, 50) R = 50 and (20, 25, 30) R = 60 exceed one workgroup's LDS: the
+# multi-workgroup iteration
 @pytest.mark.parametrize("dims,R,seed", [((5, 5, 5), 5, 0), ((12, 9, 10), 6, 1), ((20, 20, 20), 20, 2),
-                                         ((30, 30, 30), 30, 3), ((50, 50, 50), 50, 4)])
+                                         ((30, 30, 30), 30, 3), ((50, 50, 50), 50, 4), ((20, 25, 30), 60, 5)])
 def test_dgn_steps_match_oracle(dims, R, seed):
     log("dgn_step", dims, R)
     rng = np.random.default_rng(seed)
