@@ -104,7 +104,9 @@ cpd_status project_mode1(const void* T, int dtype, int I1, int I2, int I3, const
                          hipStream_t s) {
   cpd_status st;
   prof_begin(CPD_PK_PROJECT, s);
-  if (mode_product_mid_fits(I1, r1))
+  if (r1 <= 64)
+    st = project_mfma(T, dtype, I1, (long long)I2 * I3, 1, 0, U1, r1, Y1, 0, s);
+  else if (mode_product_mid_fits(I1, r1))
     st = mode_product_mid(T, dtype, 1, I1, (long long)I2 * I3, U1, r1, Y1, s);
   else
     st = gemm_f64(r1, I2 * I3, I1, 1.0, U1, r1, 0, true, T, dtype, (long long)I2 * I3, 0, false, 0.0, Y1,
@@ -115,6 +117,8 @@ cpd_status project_mode1(const void* T, int dtype, int I1, int I2, int I3, const
 // Y2[a][b][i3] = sum_i2 U2[i2][b] Y1[a][i2][i3]
 cpd_status project_mode2(const double* Y1, int r1, int I2, int I3, const double* U2, int r2, double* Y2,
                          hipStream_t s) {
+  if (r2 <= 64 && r1 <= 65535)
+    return project_mfma(Y1, CPD_F64, I2, I3, r1, (long long)I2 * I3, U2, r2, Y2, (long long)r2 * I3, s);
   if (mode_product_mid_fits(I2, r2)) return mode_product_mid(Y1, CPD_F64, r1, I2, I3, U2, r2, Y2, s);
   return gemm_f64(r2, I3, I2, 1.0, U2, r2, 0, true, Y1, CPD_F64, I3, (long long)I2 * I3, false, 0.0, Y2, I3,
                   (long long)r2 * I3, r1, s);

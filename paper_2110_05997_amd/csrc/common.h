@@ -130,6 +130,10 @@ __host__ __device__ __forceinline__ double u01_from_bits(uint64_t x) {
 cpd_status mode_product_mid(const void* X, int xdtype, int A, int J, long long K, const double* U, int nb,
                             double* Y, hipStream_t s);
 bool mode_product_mid_fits(int J, int nb);   // whether mode_product_mid supports J rows of U
+// Y[b] (r x N) = U^T X[b] for U (K x r, r <= 64) and row-major X[b] (K x N), b < batch, on the FP64
+// matrix cores (the first two mode products of the core projection).
+cpd_status project_mfma(const void* X, int xdtype, int K, long long N, int batch, long long sX, const double* U,
+                        int r, double* Y, long long sY, hipStream_t s);
 cpd_status gemm_f64(int M, int N, int K, double alpha, const double* A, int lda, long long sA,
                     bool ta, const void* B, int bdtype, long long ldb, long long sB, bool tb,
                     double beta, double* C, long long ldc, long long sC, int batch,

@@ -316,6 +316,158 @@ cpd_status gemm_f64(int M, int N, int K, double alpha, const double* A, int lda,
   return CPD_OK;
 }
 
+// Mode product Y[b] (r x N) = U^T (r x K) X[b] (K x N) for a tall-skinny U (K x r, r <= 64) and
+// row-major X (the unfolding whose contraction index is the slowest: the first mode product of the
+// core projection, ch.2 multilinear multiplication): FP64 matrix cores, X promoted exactly.  A wave
+// owns 16 columns and all r rows (up to four 16-row tiles); the contraction advances four rows of X
+// per step, U fragments come from L1/L2 and each element of X is read once.
+typedef double pdbl4 __attribute__((ext_vector_type(4)));
+
+template <class TB>
+__device__ __forceinline__ double tod(TB x) { return (double)x; }
+template <>
+__device__ __forceinline__ double tod<uint16_t>(uint16_t x) { return bf16_bits_to_f64(x); }
+
+template <class TB>
+__global__ __launch_bounds__(256) void proj_mfma_kernel(const TB* __restrict__ X, int K, long long N, long long sX,
+                                                        const double* __restrict__ U, int r,
+                                                        double* __restrict__ Y, long long sY) {
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4, w = threadIdx.x >> 6;
+  const long long n0 = ((long long)blockIdx.x * 4 + w) * 16;
+  if (n0 >= N) return;
+  X += (long long)blockIdx.y * sX;
+  Y += (long long)blockIdx.y * sY;
+  const long long n = n0 + r16;
+  const bool nok = n < N;
+  const long long nc = nok ? n : N - 1;
+  const int mt = (r + 15) / 16;
+  pdbl4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = pdbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int k = k0 + kq;
+    const bool kok = k < K;
+    const int kc = kok ? k : K - 1;
+    const double xv = loadB(X + (long long)kc * N + nc);
+    const double b = (kok && nok) ? xv : 0.0;   // B[k][n]
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t < mt) {
+        const int m = t * 16 + r16;
+        const double uv = U[(long long)kc * r + (m < r ? m : r - 1)];
+        const double a = (kok && m < r) ? uv : 0.0;   // A[m][k] = U[k][m]
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  // acc[t][v] = Y[t 16 + 4 v + kq][n0 + r16]
+  if (!nok) return;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    if (t < mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = t * 16 + 4 * v + kq;
+        if (m < r) Y[(long long)m * N + n] = acc[t][v];
+      }
+}
+
+// The same product for long rows: a workgroup owns 256 columns and all r <= 64 rows of Y and
+// streams X through LDS sixteen rows at a time (each row of a stage one contiguous 16-byte-vector
+// run, so X is read in long bursts), U^T alongside; four waves, each 64 x 64 of the tile as sixteen
+// 16x16 FP64 matrix-core accumulators.  Needs N and the batch stride to be multiples of the
+// vector width and X 16-byte aligned.
+constexpr int PB_N = 256, PB_KC = 16, PB_LD = PB_KC + 1;
+
+template <class TB>
+__global__ __launch_bounds__(256) void proj_big_kernel(const TB* __restrict__ X, int K, long long N, long long sX,
+                                                       const double* __restrict__ U, int r,
+                                                       double* __restrict__ Y, long long sY) {
+  constexpr int VW = 16 / (int)sizeof(TB);
+  constexpr int NVX = PB_KC * PB_N / VW / 256;   // X vectors per thread and stage
+  typedef TB vec_t __attribute__((ext_vector_type(VW)));
+  __shared__ double Xm[64][PB_LD];      // U^T: row m, stage index k
+  __shared__ double Xn[PB_N][PB_LD];    // X^T: column n, stage index k
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, r16 = lane & 15, kq = lane >> 4;
+  const long long n0 = (long long)blockIdx.x * PB_N;
+  X += (long long)blockIdx.y * sX;
+  Y += (long long)blockIdx.y * sY;
+  const int wn = w * 64;
+  pdbl4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = pdbl4{0.0, 0.0, 0.0, 0.0};
+  const int mt = (r + 15) / 16;
+  vec_t rx[NVX];
+  double ru[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int v = 0; v < NVX; ++v) {
+      const int e = tid + v * 256;
+      const int kk = e / (PB_N / VW), nq = (e % (PB_N / VW)) * VW;
+      const int k = k0 + kk;
+      const long long n = n0 + nq;
+      const bool ok = k < K && n < N;
+      rx[v] = *(const vec_t*)(X + (ok ? (long long)k * N + n : 0ll));
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int e = tid + v * 256, kk = e / 64, m = e % 64, k = k0 + kk;
+      const bool ok = k < K && m < r;
+      ru[v] = U[ok ? (long long)k * r + m : 0ll];
+    }
+  };
+  auto store = [&](int k0) {
+#pragma unroll
+    for (int v = 0; v < NVX; ++v) {
+      const int e = tid + v * 256;
+      const int kk = e / (PB_N / VW), nq = (e % (PB_N / VW)) * VW;
+      const bool okk = k0 + kk < K;
+#pragma unroll
+      for (int u = 0; u < VW; ++u) Xn[nq + u][kk] = (okk && n0 + nq + u < N) ? tod<TB>(rx[v][u]) : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int e = tid + v * 256, kk = e / 64, m = e % 64;
+      Xm[m][kk] = (k0 + kk < K && m < r) ? ru[v] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += PB_KC) {
+    store(k0);
+    __syncthreads();
+    if (k0 + PB_KC < K) fetch(k0 + PB_KC);
+#pragma unroll
+    for (int kk = 0; kk < PB_KC; kk += 4) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = Xm[16 * i + r16][kk + kq];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Xn[wn + 16 * j + r16][kk + kq];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i < mt)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // acc[i][j][v] = Y[16 i + 4 v + kq][n0 + wn + 16 j + r16]
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (i < mt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * i + 4 * v + kq;
+          const long long n = n0 + wn + 16 * j + r16;
+          if (m < r && n < N) Y[(long long)m * N + n] = acc[i][j][v];
+        }
+}
+
 }  // namespace cpd
 
 namespace cpd {
@@ -342,6 +494,52 @@ cpd_status mode_product_mid(const void* X, int xdtype, int A, int J, long long K
     case CPD_F32: mprod_launch<float>((const float*)X, A, J, K, U, nb, Y, s); break;
     case CPD_BF16: mprod_launch<uint16_t>((const uint16_t*)X, A, J, K, U, nb, Y, s); break;
     default: set_error("mode_product_mid: bad dtype %d", xdtype); return CPD_E_INVALID;
+  }
+  CPD_LAUNCH_CHECK();
+  return CPD_OK;
+}
+
+cpd_status project_mfma(const void* X, int xdtype, int K, long long N, int batch, long long sX, const double* U,
+                        int r, double* Y, long long sY, hipStream_t s) {
+  if (K <= 0 || N <= 0 || batch <= 0) return CPD_OK;
+  if (X == nullptr || U == nullptr || Y == nullptr || r < 1 || r > 64 || batch > 65535 ||
+      (N + 63) / 64 > 0x7fffffffLL || (xdtype != CPD_F64 && xdtype != CPD_F32 && xdtype != CPD_BF16)) {
+    set_error("project_mfma: bad arguments");
+    return CPD_E_INVALID;
+  }
+  const int vw = xdtype == CPD_F64 ? 2 : (xdtype == CPD_F32 ? 4 : 8);
+  if (N % vw == 0 && sX % vw == 0 && ((uintptr_t)X & 15) == 0 && (N + PB_N - 1) / PB_N <= 0x7fffffffLL) {
+    const dim3 gb((unsigned)((N + PB_N - 1) / PB_N), (unsigned)batch);
+    switch (xdtype) {
+      case CPD_F64:
+        hipLaunchKernelGGL(proj_big_kernel<double>, gb, dim3(256), 0, s, (const double*)X, K, N, sX, U, r, Y, sY);
+        break;
+      case CPD_F32:
+        hipLaunchKernelGGL(proj_big_kernel<float>, gb, dim3(256), 0, s, (const float*)X, K, N, sX, U, r, Y, sY);
+        break;
+      default:
+        hipLaunchKernelGGL(proj_big_kernel<uint16_t>, gb, dim3(256), 0, s, (const uint16_t*)X, K, N, sX, U, r, Y,
+                           sY);
+        break;
+    }
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+  }
+  const dim3 grid((unsigned)((N + 63) / 64), (unsigned)batch);
+  switch (xdtype) {
+    case CPD_F64:
+      hipLaunchKernelGGL(proj_mfma_kernel<double>, grid, dim3(256), 0, s, (const double*)X, K, N, sX, U, r, Y, sY);
+      break;
+    case CPD_F32:
+      hipLaunchKernelGGL(proj_mfma_kernel<float>, grid, dim3(256), 0, s, (const float*)X, K, N, sX, U, r, Y, sY);
+      break;
+    case CPD_BF16:
+      hipLaunchKernelGGL(proj_mfma_kernel<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)X, K, N, sX, U, r, Y,
+                         sY);
+      break;
+    default:
+      set_error("project_mfma: bad dtype %d", xdtype);
+      return CPD_E_INVALID;
   }
   CPD_LAUNCH_CHECK();
   return CPD_OK;
