@@ -892,11 +892,12 @@ __global__ void dgn_tail_kernel(char* __restrict__ state) {
 // M^{-1/2}, the products of Thm Hv) spread over CG_WG workgroups of one cooperative launch, then
 // x = M^{-1/2} x_hat and x^T J^T J x for the epilogue.  Per CG iteration j:
 //   A: the R x R tiles of Q_b = (M^{-1/2} p_j)_b^T W_b, one tile per wave;            grid barrier
-//   B: the tiles of z_j = M^{-1/2}(J^T J + mu D) M^{-1/2} p_j and their <p_j, z_j> partials
-//      (one per workgroup, fixed order);                                             grid barrier
-//   C: every workgroup adds the partials (same order: same alpha everywhere) and the whole of
-//      ||r_j - alpha z_j||^2 (same order everywhere: same beta), then updates its own slice of
-//      x, r_{j+1}, p_{j+1} (r and p double-buffered by the parity of j).
+//   B: the tiles of z_j = M^{-1/2}(J^T J + mu D) M^{-1/2} p_j and their <p_j, z_j>, <r_j, z_j>
+//      and <z_j, z_j> partials (one set per workgroup);                               grid barrier
+//   C: every workgroup adds the partials in workgroup order (same alpha everywhere) and forms
+//      ||r_j - alpha z_j||^2 = ||r_j||^2 - 2 alpha <r_j, z_j> + alpha^2 <z_j, z_j> (same beta
+//      everywhere), then updates its own slice of x, r_{j+1}, p_{j+1} (r and p double-buffered by
+//      the parity of j).
 // Phase A of iteration j+1 forms p_{j+1} = r_j - alpha z_j + beta p_j from the parity-j buffers, so
 // no barrier is needed after C; B reads the stored p_{j+1}, which the barrier after A publishes.
 // Every exit test is taken on values that are identical in all workgroups.
@@ -916,7 +917,9 @@ constexpr int CG_WG = 8;   // workgroups: a grid barrier costs ~2.2 us at 8 and 
 constexpr int SLOT_RR = 0;                          // ||r_0||^2 (CG_WG), then max|g| (CG_WG)
 constexpr int SLOT_COL = 2 * CG_WG;                 // column-norm partials, CG_WG x 3R (R <= 64)
 constexpr int SLOT_DP = SLOT_COL + CG_WG * 3 * 64;  // <p_j, z_j> by the parity of j (2 CG_WG)
-constexpr int SLOT_XJX = SLOT_DP + 2 * CG_WG;       // x^T J^T J x (CG_WG)
+constexpr int SLOT_RZ = SLOT_DP + 2 * CG_WG;        // <r_j, z_j> (CG_WG)
+constexpr int SLOT_ZZ = SLOT_RZ + CG_WG;            // <z_j, z_j> (CG_WG)
+constexpr int SLOT_XJX = SLOT_ZZ + CG_WG;           // x^T J^T J x (CG_WG)
 constexpr int SLOT_GX = SLOT_XJX + CG_WG;           // grad.x and x.x (2 CG_WG)
 constexpr int SLOT_END = SLOT_GX + 2 * CG_WG;
 constexpr long long BAR_SPINS = 1ll << 22;
@@ -1004,7 +1007,12 @@ __device__ void coop_phase_a(Ctx& c, double* C, VF vf, bool scale) {
 // contributions of Y_a at the B-fragment positions, V at the outputs) is loaded before its first
 // product, so a tile costs one memory round; Pi^(a), M^{-1/2} and D come from LDS.  R <= 64: the
 // contraction over R is a single 64-deep slice.
-__device__ double coop_phase_b(Ctx& c, const double* C, const double* V, double* out, double mu, bool scale) {
+// With Rv (the stored r_j) also this thread's partials of <r_j, z> and <z, z> over the entries past
+// zfree, from which every workgroup forms ||r_j - alpha z||^2 = ||r_j||^2 - 2 alpha <r_j, z> +
+// alpha^2 <z, z> without a pass over the whole vector.
+__device__ double coop_phase_b(Ctx& c, const double* C, const double* V, double* out, double mu, bool scale,
+                               const double* Rv = nullptr, double* rz = nullptr, double* zz = nullptr,
+                               int zfree = 0) {
   const int R = c.R, RR = R * R, tr = tiles16(R);
   const int lane = threadIdx.x & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
   const int t0 = tiles16(c.d0) * tr, t1 = t0 + tiles16(c.d1) * tr, t2 = t1 + tiles16(c.d2) * tr;
@@ -1022,7 +1030,7 @@ __device__ double coop_phase_b(Ctx& c, const double* C, const double* V, double*
     const double* ya1 = C + (2 * a + 1) * RR;
     const int irow = tm * 16 + r16, ic = min(irow, da - 1);
     const int rcol = tn * 16 + r16, rc = min(rcol, R - 1);
-    double va[16], wa[16], y0[16], y1[16], ve[4];
+    double va[16], wa[16], y0[16], y1[16], ve[4], re[4];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int kc = min(4 * u + kq, R - 1);
@@ -1032,7 +1040,11 @@ __device__ double coop_phase_b(Ctx& c, const double* C, const double* V, double*
       y1[u] = ya1[kc * R + rc];
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) ve[v] = Va[min(tm * 16 + 4 * v + kq, da - 1) * R + rc];
+    for (int v = 0; v < 4; ++v) {
+      const int q = min(tm * 16 + 4 * v + kq, da - 1) * R + rc;
+      ve[v] = Va[q];
+      re[v] = Rv ? Rv[oa + q] : 0.0;
+    }
     dbl4 acc1 = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -1054,6 +1066,10 @@ __device__ double coop_phase_b(Ctx& c, const double* C, const double* V, double*
         if (scale) tv = ma[r] * (tv + mu * c.gam[a * R + r] * (ma[r] * ve[v]));
         out[e] = tv;
         dotp += ve[v] * tv;
+        if (Rv && e >= zfree) {
+          *rz += re[v] * tv;
+          *zz += tv * tv;
+        }
       }
     }
   }
@@ -1189,21 +1205,24 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
         coop_phase_a(c, Cy, [&](int e) { return p_next(Rq, Zq, Pq, e, al, be, zfree); }, true);
     }
     sync_all();
-    // B: z_j and <p_j, z_j>
-    const double dp = block_sum(coop_phase_b(c, Cy, Pj, c.Z, mu, true), slots[0]);
-    if (tid == 0) part[SLOT_DP + g] = dp;
+    // B: z_j, and the partials of <p_j, z_j>, <r_j, z_j> and <z_j, z_j>
+    double rzp = 0.0, zzp = 0.0;
+    const double dp = block_sum(coop_phase_b(c, Cy, Pj, c.Z, mu, true, Rj, &rzp, &zzp, zfree), slots[0]);
+    rzp = block_sum(rzp, slots[1]);
+    zzp = block_sum(zzp, slots[0]);
+    if (tid == 0) {
+      part[SLOT_DP + g] = dp;
+      part[SLOT_RZ + g] = rzp;
+      part[SLOT_ZZ + g] = zzp;
+    }
     sync_all();
     const double pz = sum_parts(part + SLOT_DP, G);
     if (!(pz > 0.0)) break;
     alpha = rr / pz;
-    // C: ||r_j - alpha z_j||^2 over the whole vector (the same in every workgroup), own slice update
-    double eps = 0.0;
-#pragma unroll 16
-    for (int e = tid; e < np; e += NT) {
-      const double rv = Rj[e] - alpha * ((e < zfree) ? 0.0 : c.Z[e]);
-      eps += rv * rv;
-    }
-    eps = block_sum(eps, slots[1]);
+    // C: ||r_j - alpha z_j||^2 from the partials (the same in every workgroup; rounding can only
+    // make a vanishing value slightly negative, read as 0), own slice update
+    const double rzs = sum_parts(part + SLOT_RZ, G), zzs = sum_parts(part + SLOT_ZZ, G);
+    const double eps = fmax(rr - 2.0 * alpha * rzs + alpha * alpha * zzs, 0.0);
     beta = eps / rr;
     double* Rn = Rb[par ^ 1];
     double* Pn = Pb[par ^ 1];
