@@ -50,9 +50,9 @@ def parse():
 # for a plain copy of known size (`bench.py --copy-calibration`).  A figure is reported only while
 # the kernel's sources hash to the digest it was taken with.
 TRAFFIC = {
-    # dgn_kernel on the 200^3 R = 20 workload (20^3 core, 19 iterations): FETCH_SIZE 72.5 KiB x 2.0,
-    # WRITE_SIZE 29.56 KiB x 1.0 (profiles/dgn_kernel_200cube_traffic.md)
-    "dgn": {"bytes": 148480 + 30272, "sources": ['dgn.hip', 'dgn_state.h', 'mfma_f64.h', 'common.h'], "digest": 'ad823d5eb81f4c75'},
+    # gram_f64_big_kernel<float> on the 600^3 FP32 tensor, per mode: FETCH_SIZE 1178769 KiB x 2.0,
+    # WRITE_SIZE 239360 KiB x 1.0 (profiles/solve_600cube_fp64_r50.md)
+    "gram": {"bytes": 2414119040 + 245104640, "sources": ['gram.hip', 'common.h'], "digest": '1d2be558e061a948'},
 }
 
 
