@@ -410,6 +410,7 @@ def bench_600cube(cp, synth, torch, dev, Td):
         out[name]["seeds_0_to_7"] = {"reached_noise_floor": ok, "of": 8, "median_s": statistics.median(ts),
                                          "median_iters": float(np.median(its))}
     out["reconstruction_diff_bf16_vs_fp64_gpu"] = cpd_diff(res["bf16_grams"], res["fp64_grams"], torch)
+    out["variants"] = variants_600cube(cp, synth, torch, dev, Td, Tlo, U, idx, val)
     # full-tensor MTTKRP (2 R N flop per mode) and Gram (N (I+1) per mode) on the FP32 tensor and
     # its BF16 copy
     Wf = [torch.randn(600, 50, dtype=torch.float64, device=dev) for _ in range(3)]
@@ -420,6 +421,52 @@ def bench_600cube(cp, synth, torch, dev, Td):
     out["mttkrp"] = {**m32, **m16}
     out["gram"] = {**gram_rates(cp, torch, Td, [("fp32_in_f64_mfma", cp.CPD_F64)]),
                    **gram_rates(cp, torch, Tlo, [("bf16_in_bf16_mfma", cp.CPD_BF16)])}
+    return out
+
+
+def variants_600cube(cp, synth, torch, dev, Td, Tlo, U, idx, val):
+    """At full size: the device time of cpd_compress with the classic and with the sequentially
+    truncated MLSVD (HIP events around the call, the host's truncation read-back included), then
+    whole solves from the headline start with the ST-MLSVD and with three refinement iterations on
+    T (FP64 and BF16 Grams), each against the FP64 oracle's sampled reconstruction (whose solve uses
+    the classic MLSVD and no refinement)."""
+    R = 50
+    out = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for name, kw in (("classic", {}), ("st_mlsvd", {"st_mlsvd": True})):
+        pc = cp.params(cg_uniforms=U, **kw)
+        cp.compress(Td, R, pc)
+        ts = []
+        for _ in range(3):
+            e0.record()
+            _, _, _, core = cp.compress(Td, R, pc)
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        out["compress_ms_" + name] = statistics.median(ts)
+        out["core_" + name] = list(core)
+    W0 = cp.flat_w0([torch.as_tensor(w).to(dev) for w in synth.init_factors((R, R, R), R, 2)], Td.device)
+    for name, mixed, kw in (("st_mlsvd_fp64_grams", False, {"st_mlsvd": True}),
+                            ("refine3_fp64_grams", False, {"refine_iters": 3}),
+                            ("refine3_bf16_grams", True, {"refine_iters": 3})):
+        pv = cp.params(cg_uniforms=U, **kw)
+        try:
+            wsv = torch.empty(cp.workspace_bytes(Td.shape, R, pv), dtype=torch.uint8, device=dev)
+            times = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                r = (cp.solve_mixed(Tlo, Td, R, pv, W0=W0, ws=wsv) if mixed else cp.solve(Td, R, pv, W0=W0, ws=wsv))
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - a)
+            inf = r["info"]
+            out[name] = {"s_per_solve": statistics.median(times[1:]), "iters": inf["iters"],
+                         "refine_iters": inf["refine_iters"], "stop": cp.STOP_NAMES[inf["stop_reason"]],
+                         "rel_err_core": inf["rel_err_core"], "rel_err_full": inf["rel_err_full"],
+                         "that_vs_oracle_sampled": that_vs_oracle(r, idx, val)}
+            del wsv
+        except Exception as exc:   # recorded, so that the rest of the line is still printed
+            out[name] = {"error": str(exc)}
     return out
 
 

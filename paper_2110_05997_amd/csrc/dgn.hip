@@ -1100,7 +1100,7 @@ __device__ __forceinline__ double sum_parts(const double* part, int n) {
 // Dynamic LDS: 3 R^2 + 6 R doubles.
 __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ state, double* __restrict__ P1,
                                                            double* __restrict__ R1, double* __restrict__ part,
-                                                           BarSlot* __restrict__ bar) {
+                                                           BarSlot* __restrict__ bar, int grams_ready) {
   extern __shared__ double lds_c[];
   __shared__ double slots[2][NW];
   Hdr* h = (Hdr*)state;
@@ -1131,7 +1131,8 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
   const int tr = tiles16(R);
   const int lane = tid & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
 
-  // 1. factor Grams
+  // 1. factor Grams (unless the previous launch, core_finish_kernel, left them in the state)
+  if (!grams_ready) {
   for (int t = g * NW + w; t < 3 * tr * tr; t += G * NW) {
     const int l = t / (tr * tr), tt = t - l * tr * tr, tm = tt / tr, tn = tt - tm * tr;
     const double* Wl = c.W + offof(c, l);
@@ -1146,6 +1147,7 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
     }
   }
   sync_all();
+  }
   // 2. Pi, D, M^{-1/2} (each workgroup for itself, same values), gradient and CG start on the slice
   for (int e = tid; e < RR; e += NT) {
     const double a = c.pi[e], b = c.pi[RR + e], dd = c.pi[2 * RR + e];
@@ -1239,8 +1241,8 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
     first = false;
     if (eps < cg_tol) break;
   }
-  sync_all();
-  // x = M^{-1/2} x_hat on the own slice
+  // x = M^{-1/2} x_hat on the own slice (no barrier before it: after the last barrier of the CG
+  // every workgroup reads and writes only its own slice of x, r, p and z)
   for (int e = e0 + tid; e < e1; e += NT) {
     int l, i, r;
     split_index(c, e, l, i, r);
@@ -1479,9 +1481,34 @@ __global__ __launch_bounds__(NT) void core_finish_kernel(char* __restrict__ stat
     return;
   }
   const Layout Lo = layout_of(h->np, R, h->maxiter);
+  const int np = (g.d0 + g.d1 + g.d2) * R;
+  const int nmk = (np + NT - 1) / NT;   // workgroups 1..nmk: MTTKRP entries; then the Grams
+  if ((int)blockIdx.x > nmk) {
+    // pi^(l) = W^(l)T W^(l) of the factors this step's residual was taken at, for the next
+    // iteration launch (one 16x16 tile per wave)
+    const int d[3] = {g.d0, g.d1, g.d2};
+    Ctx c;
+    setup_ctx(c, (double*)(state + Lo.work), d, R, nullptr, nullptr, nullptr);
+    const double* W = (const double*)(state + Lo.W);
+    const int tr = g.tr, lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+    const int t = ((int)blockIdx.x - 1 - nmk) * NW + wave_id();
+    if (t >= 3 * tr * tr) return;
+    const int l = t / (tr * tr), tt = t - l * tr * tr, tm = tt / tr, tn = tt - tm * tr;
+    const double* Wl = W + offof(c, l);
+    const int dl = dimof(c, l);
+    const dbl4 acc = mfma_tile_wide(tm * 16, tn * 16, dl,
+        [&](int r, int i) { return sel(r < R && i < dl, Wl[min(i, dl - 1) * R + min(r, R - 1)]); },
+        [&](int i, int q) { return sel(q < R && i < dl, Wl[min(i, dl - 1) * R + min(q, R - 1)]); });
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = tm * 16 + 4 * v + kq, q = tn * 16 + r16;
+      if (r < R && q < R) c.pi[l * R * R + r * R + q] = acc[v];
+    }
+    return;
+  }
   double* MK = (double*)(state + Lo.MK);
   int e = (blockIdx.x - 1) * NT + threadIdx.x;
-  if (e >= (g.d0 + g.d1 + g.d2) * R) return;
+  if (e >= np) return;
   const int n0 = g.d0 * R, n1 = g.d1 * R;
   const int l = e >= n0 + n1 ? 2 : (e >= n0 ? 1 : 0);
   const int el = e - (l == 0 ? 0 : (l == 1 ? n0 : n0 + n1));
@@ -1800,7 +1827,7 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
         hipLaunchKernelGGL(core_refresh_kernel, dim3(cr_blocks), dim3(NT), 0, s, S, (const double*)(state + Lo.W),
                            cg, mpart, rpart);
         CPD_LAUNCH_CHECK();
-        const int fin_blocks = 1 + (np + NT - 1) / NT;
+        const int fin_blocks = 1 + (np + NT - 1) / NT + (3 * cg.tr * cg.tr + NW - 1) / NW;
         hipLaunchKernelGGL(core_finish_kernel, dim3(fin_blocks), dim3(NT), 0, s, state, cg, (const double*)mpart,
                            (const double*)rpart, init);
         CPD_LAUNCH_CHECK();
@@ -1822,6 +1849,9 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
       CPD_LAUNCH_CHECK();
       return refresh(1);
     }
+    // the fused refresh leaves the Grams of the current factors in the state; the first launch after
+    // replaced factors (or after the full-tensor kernels) forms them itself
+    int grams_ready = (fused && !(hh.flags & HDR_DIRTY)) ? 1 : 0;
     if (hh.flags & HDR_DIRTY) {
       // factors replaced from outside: MTTKRP and residual at them, then clear the flag
       cpd_status st;
@@ -1851,8 +1881,10 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
       const int n = (max_steps - done < CHUNK) ? max_steps - done : CHUNK;
       for (int j = 0; j < n; ++j) {
         // Grams, gradient, CG, x^T J^T J x and the balanced update on CG_WG workgroups
-        hipLaunchKernelGGL(dgn_iter_coop_kernel, dim3(CG_WG), dim3(NT), it_lds, s, state, cP1, cR1, cpart, bar);
+        hipLaunchKernelGGL(dgn_iter_coop_kernel, dim3(CG_WG), dim3(NT), it_lds, s, state, cP1, cR1, cpart, bar,
+                           grams_ready);
         CPD_LAUNCH_CHECK();
+        grams_ready = fused ? 1 : 0;
         cpd_status st;
         if ((st = refresh(0))) return st;
       }

@@ -174,65 +174,62 @@ __global__ __launch_bounds__(ONT) void orth_kernel(double* __restrict__ Z, int n
 }
 
 // Cholesky of the column-scaled Gram D C D = R^T R, D = diag(C)^{-1/2}, of a k x k SPD matrix
-// (k <= 64).  One wavefront, lane = column; right-looking, the trailing update of each column
-// runs down the column without dependences between its entries.  Writes R (upper triangular,
-// row-major k x k) and D.  A pivot below 1e-13 sets *bad = 1 (or-ed with *prev when given).
-__global__ __launch_bounds__(64) void chol_scaled_kernel(const double* __restrict__ C, int k,
-                                                         double* __restrict__ Rout, double* __restrict__ Dout,
-                                                         const int* __restrict__ prev, int* __restrict__ bad) {
+// (k <= 64).  Four wavefronts, lane = column, waves interleaved over rows; right-looking without
+// forming the pivot row first: at step j row j is final, and every thread subtracts
+// a_jr a_jc / a_jj from its entries of the rows below (one barrier per step).  At the end row r is
+// scaled by a_rr^{-1/2}.  Writes R (upper triangular, row-major k x k) and D.  A pivot below 1e-13
+// sets *bad = 1 (or-ed with *prev when given).
+constexpr int CH_NT = 256;
+__global__ __launch_bounds__(CH_NT) void chol_scaled_kernel(const double* __restrict__ C, int k,
+                                                            double* __restrict__ Rout, double* __restrict__ Dout,
+                                                            const int* __restrict__ prev, int* __restrict__ bad) {
   __shared__ double A[JMAX][JMAX + 1];   // A[row][col], upper triangle used
   __shared__ double dsc[JMAX];
-  const int c = threadIdx.x;
-  if (c < k) {
+  constexpr int CW = CH_NT / 64;
+  const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x < k) {
     const double cc = C[c * k + c];
     dsc[c] = (cc > 0.0) ? 1.0 / sqrt(cc) : 1.0;
   }
   __syncthreads();
   if (c < k)
-    for (int r = 0; r <= c; ++r) A[r][c] = dsc[r] * C[r * k + c] * dsc[c];
+    for (int r = w; r <= c; r += CW) A[r][c] = dsc[r] * C[r * k + c] * dsc[c];
   __syncthreads();
-  int fail = 0;
-  for (int j = 0; j < k; ++j) {
-    const double piv = A[j][j];
-    if (!(piv > 1e-13)) fail = 1;
-    const double d = sqrt(fmax(piv, 1e-300));
-    __syncthreads();
-    // row j of R: lane c >= j scales its entry
-    if (c >= j && c < k) A[j][c] = (c == j) ? d : A[j][c] / d;
-    __syncthreads();
-    // trailing update of column c > j: A[r][c] -= R[j][r] R[j][c] for j < r <= c
+  for (int j = 0; j + 1 < k; ++j) {
     if (c > j && c < k) {
-      const double rjc = A[j][c];
-      int r = j + 1;
-      for (; r + 3 <= c; r += 4) {
-        const double x0 = A[j][r], x1 = A[j][r + 1], x2 = A[j][r + 2], x3 = A[j][r + 3];
-        const double y0 = A[r][c], y1 = A[r + 1][c], y2 = A[r + 2][c], y3 = A[r + 3][c];
-        A[r][c] = y0 - x0 * rjc;
-        A[r + 1][c] = y1 - x1 * rjc;
-        A[r + 2][c] = y2 - x2 * rjc;
-        A[r + 3][c] = y3 - x3 * rjc;
-      }
-      for (; r <= c; ++r) A[r][c] -= A[j][r] * rjc;
+      const double t = A[j][c] / fmax(A[j][j], 1e-300);
+      for (int r = j + 1 + w; r <= c; r += CW) A[r][c] -= A[j][r] * t;
     }
     __syncthreads();
   }
+  int fail = 0;
   if (c < k) {
-    for (int r = 0; r < k; ++r) Rout[r * k + c] = (r <= c) ? A[r][c] : 0.0;
-    Dout[c] = dsc[c];
+    for (int r = w; r < k; r += CW) {
+      const double piv = A[r][r];
+      if (c == r && !(piv > 1e-13)) fail = 1;
+      Rout[r * k + c] = (r <= c) ? A[r][c] / sqrt(fmax(piv, 1e-300)) : 0.0;
+    }
+    if (w == 0) Dout[c] = dsc[c];
   }
-  if (c == 0) *bad = fail | (prev ? *prev : 0);
+  fail = __syncthreads_or(fail);
+  if (threadIdx.x == 0) *bad = (fail ? 1 : 0) | (prev ? *prev : 0);
 }
 
-// Q[i, :] = (Y[i, :] D) R^{-1} by forward substitution along the row (thread per row, R and D
-// staged in LDS); skipped when the factorisation failed.
+// Q[i, :] = (Y[i, :] D) R^{-1} by forward substitution along the row (thread per row, R, D and
+// 1 / diag(R) staged in LDS).  Entry c subtracts its c earlier terms in four interleaved partial
+// sums (loops unrolled at compile time, so the loads of R run ahead of the arithmetic).  Skipped
+// when the factorisation failed.
 __global__ __launch_bounds__(128) void rowsolve_kernel(const double* __restrict__ Y, const double* __restrict__ Rm,
                                                        const double* __restrict__ D, int n, int k,
                                                        const int* __restrict__ bad, double* __restrict__ Q) {
   __shared__ double Rs[JMAX * JMAX];
-  __shared__ double Ds[JMAX];
+  __shared__ double Ds[JMAX], Ri[JMAX];
   if (*bad) return;
   for (int e = threadIdx.x; e < k * k; e += blockDim.x) Rs[e] = Rm[e];
-  for (int e = threadIdx.x; e < k; e += blockDim.x) Ds[e] = D[e];
+  for (int e = threadIdx.x; e < k; e += blockDim.x) {
+    Ds[e] = D[e];
+    Ri[e] = 1.0 / Rm[e * k + e];
+  }
   __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -242,34 +239,52 @@ __global__ __launch_bounds__(128) void rowsolve_kernel(const double* __restrict_
 #pragma unroll
   for (int c = 0; c < JMAX; ++c) {
     if (c < k) {
-      double v = y[c] * Ds[c];
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-      for (int t = 0; t < c; ++t) v -= qv[t] * Rs[t * k + c];
-      qv[c] = v / Rs[c * k + c];
+      for (int t = 0; t + 3 < c; t += 4) {
+        s0 = fma(qv[t], Rs[t * k + c], s0);
+        s1 = fma(qv[t + 1], Rs[(t + 1) * k + c], s1);
+        s2 = fma(qv[t + 2], Rs[(t + 2) * k + c], s2);
+        s3 = fma(qv[t + 3], Rs[(t + 3) * k + c], s3);
+      }
+#pragma unroll
+      for (int t = c & ~3; t < c; ++t) s0 = fma(qv[t], Rs[t * k + c], s0);
+      qv[c] = (y[c] * Ds[c] - ((s0 + s1) + (s2 + s3))) * Ri[c];
       q[c] = qv[c];
     }
   }
 }
 
-// max_j ||ZV[:,j] - theta_j U[:,j]|| / |theta_0| over the P wanted pairs (one workgroup).
-__global__ void ritz_residual_kernel(const double* __restrict__ ZV, int ldz, const double* __restrict__ U,
-                                     const double* __restrict__ theta, int n, int P,
-                                     double* __restrict__ out) {
-  __shared__ double red[2][256 / 64];
-  double worst = 0.0;
-  int flip = 0;
-  for (int j = 0; j < P; ++j) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const double r = ZV[(long long)i * ldz + j] - theta[j] * U[(long long)i * P + j];
+// max_j ||ZV[:,j] - theta_j U[:,j]|| / |theta_0| over the P <= 64 wanted pairs (one workgroup):
+// lane = column (coalesced along the rows), waves interleaved over rows, the waves' column sums
+// added in a fixed order.
+constexpr int RR_NT = 1024;
+__global__ __launch_bounds__(RR_NT) void ritz_residual_kernel(const double* __restrict__ ZV, int ldz,
+                                                              const double* __restrict__ U,
+                                                              const double* __restrict__ theta, int n, int P,
+                                                              double* __restrict__ out) {
+  constexpr int RW = RR_NT / 64;
+  __shared__ double part[RW][64];
+  const int j = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double s = 0.0;
+  if (j < P) {
+    const double th = theta[j];
+    for (int i = w; i < n; i += RW) {
+      const double r = ZV[(long long)i * ldz + j] - th * U[(long long)i * P + j];
       s += r * r;
     }
-    s = block_sum(s, red[flip]); flip ^= 1;
-    worst = fmax(worst, sqrt(s));
   }
-  if (threadIdx.x == 0) {
-    const double t0 = fabs(theta[0]);
-    *out = (t0 > 0.0) ? worst / t0 : 0.0;
+  part[w][j] = s;
+  __syncthreads();
+  if (w == 0) {
+    double t = 0.0;
+    for (int q = 0; q < RW; ++q) t += part[q][j];
+    double worst = (j < P) ? sqrt(t) : 0.0;
+    for (int off = 32; off > 0; off >>= 1) worst = fmax(worst, __shfl_xor(worst, off));
+    if (j == 0) {
+      const double t0 = fabs(theta[0]);
+      *out = (t0 > 0.0) ? worst / t0 : 0.0;
+    }
   }
 }
 
@@ -615,7 +630,7 @@ cpd_status chol_qr(const double* Y, int n, int k, double* Q, double* C, double* 
   cpd_status st;
   const unsigned nb = (unsigned)((n + 127) / 128);
   if ((st = gemm_f64(k, k, n, 1.0, Y, k, 0, true, Y, CPD_F64, k, 0, false, 0.0, C, k, 0, 1, s))) return st;
-  hipLaunchKernelGGL(chol_scaled_kernel, dim3(1), dim3(64), 0, s, C, k, Rm, D, (const int*)nullptr, flags);
+  hipLaunchKernelGGL(chol_scaled_kernel, dim3(1), dim3(CH_NT), 0, s, C, k, Rm, D, (const int*)nullptr, flags);
   CPD_LAUNCH_CHECK();
   double* out1 = twice ? Qtmp : Q;
   hipLaunchKernelGGL(rowsolve_kernel, dim3(nb), dim3(128), 0, s, Y, Rm, D, n, k, flags, out1);
@@ -623,7 +638,7 @@ cpd_status chol_qr(const double* Y, int n, int k, double* Q, double* C, double* 
   int* last = flags;
   if (twice) {
     if ((st = gemm_f64(k, k, n, 1.0, Qtmp, k, 0, true, Qtmp, CPD_F64, k, 0, false, 0.0, C, k, 0, 1, s))) return st;
-    hipLaunchKernelGGL(chol_scaled_kernel, dim3(1), dim3(64), 0, s, C, k, Rm, D, flags, flags + 1);
+    hipLaunchKernelGGL(chol_scaled_kernel, dim3(1), dim3(CH_NT), 0, s, C, k, Rm, D, flags, flags + 1);
     CPD_LAUNCH_CHECK();
     hipLaunchKernelGGL(rowsolve_kernel, dim3(nb), dim3(128), 0, s, Qtmp, Rm, D, n, k, flags + 1, Q);
     CPD_LAUNCH_CHECK();
@@ -648,7 +663,8 @@ struct SubProblem {
   int* flags;
   SubspaceArgs* desc;   // this problem's descriptor slot (single-problem launches)
   uint64_t seed;
-  double r_host;
+  double* r_host;   // the Ritz residual ratio read back by the host (pinned when possible)
+  double r_own;     // pageable fallback for r_host
 };
 
 // Descriptor slots of one eigensolver call: NSIDE of the larger descriptor type, carved first.
@@ -723,18 +739,25 @@ cpd_status sp_check(int n, int P, const double* G, const double* U, const double
   return CPD_OK;
 }
 
-cpd_status sp_finish(SubProblem& q, hipStream_t s) {
+// Writes the current pairs (eigenvalues, signed vectors) into the outputs.
+cpd_status sp_emit(SubProblem& q, hipStream_t s) {
   const double* X = q.direct ? q.V : q.Uw;
   const int ldx = q.direct ? q.n : q.P;
   CPD_HIP_CHECK(hipMemcpyAsync(q.lam, q.direct ? q.lall : q.theta, sizeof(double) * q.P, hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(sign_columns_kernel, dim3(q.P), dim3(256), 0, s, X, q.n, ldx, q.P, q.U);
   CPD_LAUNCH_CHECK();
-  q.done = true;
   return CPD_OK;
 }
 
-// One Rayleigh-Ritz step; the Ritz residual ratio is copied to q.r_host (valid after the stream
-// has been synchronised).
+cpd_status sp_finish(SubProblem& q, hipStream_t s) {
+  q.done = true;
+  return sp_emit(q, s);
+}
+
+// One Rayleigh-Ritz step; the Ritz residual ratio is copied to *q.r_host (valid after the stream
+// has been synchronised).  The Ritz pairs are written to the outputs right away: if the ratio passes
+// the test they are the result and the host launches nothing more; otherwise the next step
+// overwrites them.
 cpd_status sp_rr(SubProblem& q, hipStream_t s) {
   const int n = q.n, k = q.k, P = q.P;
   cpd_status st;
@@ -746,10 +769,10 @@ cpd_status sp_rr(SubProblem& q, hipStream_t s) {
   // Ritz vectors U = Q Vb[:, :P]; Y = Z Vb = G (Q Vb) (its first P columns give the residuals)
   if ((st = gemm_f64(n, P, k, 1.0, q.Q, k, 0, false, q.Vb, CPD_F64, k, 0, false, 0.0, q.Uw, P, 0, 1, s))) return st;
   if ((st = gemm_f64(n, k, k, 1.0, q.Z, k, 0, false, q.Vb, CPD_F64, k, 0, false, 0.0, q.Y, k, 0, 1, s))) return st;
-  hipLaunchKernelGGL(ritz_residual_kernel, dim3(1), dim3(256), 0, s, q.Y, k, q.Uw, q.theta, n, P, q.ratio);
+  hipLaunchKernelGGL(ritz_residual_kernel, dim3(1), dim3(RR_NT), 0, s, q.Y, k, q.Uw, q.theta, n, P, q.ratio);
   CPD_LAUNCH_CHECK();
-  CPD_HIP_CHECK(hipMemcpyAsync(&q.r_host, q.ratio, sizeof(double), hipMemcpyDeviceToHost, s));
-  return CPD_OK;
+  CPD_HIP_CHECK(hipMemcpyAsync(q.r_host, q.ratio, sizeof(double), hipMemcpyDeviceToHost, s));
+  return sp_emit(q, s);
 }
 
 // Enqueues phase `ph` (0..5) of the first part of the problem: 0 the whole direct solve, or the
@@ -800,13 +823,38 @@ cpd_status sp_start(SubProblem& q, hipStream_t s) {
 
 // After the stream has been synchronised: finish, or enqueue the next basis and Ritz step.
 cpd_status sp_continue(SubProblem& q, hipStream_t s) {
-  if (q.r_host <= 1e-13 || q.it >= 199) return sp_finish(q, s);
+  if (*q.r_host <= 1e-13 || q.it >= 199) {
+    q.done = true;   // the outputs were written by the last Rayleigh-Ritz step
+    return CPD_OK;
+  }
   // next basis: orthonormalised G (Q Vb); its columns are nearly orthogonal (G times Ritz
   // vectors), but a second pass keeps the Rayleigh-Ritz basis orthonormal to rounding
   cpd_status st;
   if ((st = chol_qr(q.Y, q.n, q.k, q.Q, q.B, q.Ri, q.Dv, q.Qt, q.flags, true, q.seed + 2 + q.it, s))) return st;
   ++q.it;
   return sp_rr(q, s);
+}
+
+// Pinned host slots for the Ritz residual ratios of up to NSIDE problems, one set per host thread,
+// kept until the process ends.  A copy into pageable memory returns only when the stream reaches
+// it, which would serialise the problems' Rayleigh-Ritz steps behind the host.  Every use ends
+// with a synchronisation of the problem's stream before the next call on the thread.
+double* ratio_slots() {
+  static thread_local double* buf = nullptr;
+  static thread_local bool tried = false;
+  if (!tried) {
+    tried = true;
+    if (hipHostMalloc((void**)&buf, NSIDE * sizeof(double), hipHostMallocPortable) != hipSuccess) {
+      buf = nullptr;
+      (void)hipGetLastError();
+    }
+  }
+  return buf;
+}
+
+void sp_bind_ratio(SubProblem& q, int slot) {
+  double* b = ratio_slots();
+  q.r_host = b ? b + slot : &q.r_own;
 }
 
 // Streams (default priority) and events for running up to three problems side by side; created
@@ -842,6 +890,7 @@ cpd_status eig_top(const double* G, int n, int P, double* U, double* lam, void* 
   }
   SubProblem q;
   sp_describe(q, G, n, P, U, lam);
+  sp_bind_ratio(q, 0);
   Arena ar(ws, ws_bytes);
   q.desc = &carve_desc(ar)[0].s;
   sp_carve(ar, q);
@@ -893,6 +942,7 @@ cpd_status eig_top3(const double* const* G, const int* n, const int* P, double* 
   EigDesc* desc = carve_desc(ar);
   for (int i = 0; i < nprob; ++i) {
     sp_describe(q[i], G[i], n[i], P[i], U[i], lam[i]);
+    sp_bind_ratio(q[i], i);
     q[i].desc = &desc[i].s;
     sp_carve(ar, q[i]);
   }

@@ -176,6 +176,42 @@ void launch_residual(const T* X, int I1, int I2, int I3, const double* const W[3
   }
 }
 
+// Squares of the 16 / sizeof(T) entries packed in one 16-byte word, added in order; a
+// non-finite entry sets nf.
+template <class T>
+__device__ __forceinline__ void sumsq_word(const uint4& q, double& acc, double& nf) {
+  const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double v = __builtin_bit_cast(double, ((uint64_t)w[2 * i + 1] << 32) | w[2 * i]);
+      if (!isfinite(v)) nf = 1.0;
+      acc += v * v;
+    }
+  } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double v = (double)__builtin_bit_cast(float, w[i]);
+      if (!isfinite(v)) nf = 1.0;
+      acc += v * v;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double lo = (double)__builtin_bit_cast(float, w[i] << 16);
+      const double hi = (double)__builtin_bit_cast(float, w[i] & 0xffff0000u);
+      if (!isfinite(lo) || !isfinite(hi)) nf = 1.0;
+      acc += lo * lo;
+      acc += hi * hi;
+    }
+  }
+}
+
+// ||X||^2 partials, one per block: the 16-byte words of the aligned body are strided over the
+// grid with SQ_U loads in flight per thread; the unaligned head and the tail (fewer than one
+// word per thread of the grid) go entry by entry.  Fixed grid, fixed order: bit-reproducible.
+constexpr int SQ_U = 4;
+
 template <class T>
 __global__ __launch_bounds__(RNT) void sumsq_kernel(const T* __restrict__ X, long long n,
                                                     double* __restrict__ part, double* __restrict__ badp,
@@ -183,11 +219,34 @@ __global__ __launch_bounds__(RNT) void sumsq_kernel(const T* __restrict__ X, lon
   __shared__ double slots[2][RNT / 64];
   // the first kernel of a solve: its start is the solve's device entry time
   if (stamp != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *stamp = wall_clock64();
+  constexpr int EPW = 16 / (int)sizeof(T);   // entries per word
+  const long long head = (long long)((16 - ((uintptr_t)X & 15)) & 15) / (long long)sizeof(T);
+  const bool aligned = ((uintptr_t)X % sizeof(T)) == 0;
+  const long long h = aligned ? (head < n ? head : n) : n;
+  const long long nw = (n - h) / EPW;        // whole words of the body
+  const uint4* Xw = reinterpret_cast<const uint4*>(X + h);
+  const long long gid = (long long)blockIdx.x * RNT + threadIdx.x;
+  const long long stride = (long long)gridDim.x * RNT;
   double acc = 0.0, nf = 0.0;
-  for (long long e = (long long)blockIdx.x * RNT + threadIdx.x; e < n; e += (long long)gridDim.x * RNT) {
-    const double v = ldv(X, e);
-    if (!isfinite(v)) nf = 1.0;
-    acc += v * v;
+  long long v = gid;
+  for (; v + (SQ_U - 1) * stride < nw; v += SQ_U * stride) {
+    uint4 q[SQ_U];
+#pragma unroll
+    for (int u = 0; u < SQ_U; ++u) q[u] = Xw[v + u * stride];
+#pragma unroll
+    for (int u = 0; u < SQ_U; ++u) sumsq_word<T>(q[u], acc, nf);
+  }
+  for (; v < nw; v += stride) sumsq_word<T>(Xw[v], acc, nf);
+  // head entries, then the tail entries after the last whole word
+  for (long long e = gid; e < h; e += stride) {
+    const double x = ldv(X, e);
+    if (!isfinite(x)) nf = 1.0;
+    acc += x * x;
+  }
+  for (long long e = h + nw * EPW + gid; e < n; e += stride) {
+    const double x = ldv(X, e);
+    if (!isfinite(x)) nf = 1.0;
+    acc += x * x;
   }
   const double s = block_sum(acc, slots[0]);
   const double b = block_sum(nf, slots[1]);

@@ -86,54 +86,125 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, double al
   }
 }
 
-// C = A^T B for narrow operands (A: K x M, B: K x N, M, N <= 64): one workgroup per output row m,
-// lane = column n, the four waves split the K rows; partial sums combined in a fixed order.
-template <class TB>
-__global__ __launch_bounds__(256) void atb_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
-                                                  int lda, const TB* __restrict__ B, long long ldb, double beta,
-                                                  double* __restrict__ C, long long ldc) {
-  __shared__ double part[4][64];
-  const int m = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  if (lane < N) {
-    int k = w;
-    for (; k + 12 < K; k += 16) {
-      a0 = fma(A[(long long)k * lda + m], loadB(B + (long long)k * ldb + lane), a0);
-      a1 = fma(A[(long long)(k + 4) * lda + m], loadB(B + (long long)(k + 4) * ldb + lane), a1);
-      a2 = fma(A[(long long)(k + 8) * lda + m], loadB(B + (long long)(k + 8) * ldb + lane), a2);
-      a3 = fma(A[(long long)(k + 12) * lda + m], loadB(B + (long long)(k + 12) * ldb + lane), a3);
+typedef double sdbl4 __attribute__((ext_vector_type(4)));
+
+// v where ok, else +0.0, by a bit mask: the load of v stays unconditional (a select on a loaded
+// value may be turned into a branch around the load, which serialises the loads of a batch).
+__device__ __forceinline__ double keep_if(bool ok, double v) {
+  const unsigned long long m = ok ? ~0ull : 0ull;
+  return __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, v) & m);
+}
+
+// C = alpha A B + beta C for row-major A (M x K) and B (K x N), N <= 64, on the FP64 matrix cores
+// (tall-skinny products: a subspace block times the Gram, the last mode product of the core
+// projection, the uncompression).  A workgroup owns 16 rows and all N columns; wave w takes the
+// 4-deep contraction slices w, w + 4, ..., with SK_U slices of loads in flight before their MFMAs;
+// the four partial tiles are added in LDS in a fixed order.  Fragments: A[row r16][k kq],
+// B[k kq][col r16], result row 4 v + kq, column r16 in acc[v].
+constexpr int SK_NT = 256;
+constexpr int SK_U = 8;
+__global__ __launch_bounds__(SK_NT) void skinny_mfma_kernel(int M, int N, int K, double alpha,
+                                                            const double* __restrict__ A, int lda,
+                                                            const double* __restrict__ B, long long ldb, double beta,
+                                                            double* __restrict__ C, long long ldc) {
+  constexpr int NWV = SK_NT / 64;
+  __shared__ double part[NWV][16][65];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r16 = lane & 15, kq = lane >> 4;
+  const int m0 = blockIdx.x * 16;
+  const int nt = (N + 15) >> 4;
+  const int row = m0 + r16;
+  const bool rok = row < M;
+  const double* ar = A + (long long)(rok ? row : 0) * lda;
+  sdbl4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = sdbl4{0.0, 0.0, 0.0, 0.0};
+  const int nsl = (K + 3) >> 2;
+  for (int s0 = w; s0 < nsl; s0 += NWV * SK_U) {
+    double a[SK_U], b[SK_U][4];
+#pragma unroll
+    for (int u = 0; u < SK_U; ++u) {
+      const int k = (s0 + NWV * u) * 4 + kq;
+      const bool kok = k < K;
+      const long long kc = kok ? k : 0;
+      a[u] = keep_if(rok && kok, ar[kc]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int col = t * 16 + r16;
+        b[u][t] = keep_if(kok && col < N, B[kc * ldb + (col < N ? col : 0)]);
+      }
     }
-    for (; k < K; k += 4) a0 = fma(A[(long long)k * lda + m], loadB(B + (long long)k * ldb + lane), a0);
+    __builtin_amdgcn_sched_barrier(0);   // every load of the batch is issued before its MFMAs
+#pragma unroll
+    for (int u = 0; u < SK_U; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < nt) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][t], acc[t], 0, 0, 0);
   }
-  part[w][lane] = (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[w][4 * v + kq][t * 16 + r16] = acc[t][v];
   __syncthreads();
-  if (w == 0 && lane < N) {
-    const double v = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
-    double* c = C + (long long)m * ldc + lane;
-    *c = (beta == 0.0) ? alpha * v : alpha * v + beta * *c;
+  for (int e = threadIdx.x; e < 16 * 64; e += SK_NT) {
+    const int r = e >> 6, c = e & 63, gm = m0 + r;
+    if (gm < M && c < N) {
+      double v = part[0][r][c];
+#pragma unroll
+      for (int q = 1; q < NWV; ++q) v += part[q][r][c];
+      double* cp = C + (long long)gm * ldc + c;
+      *cp = (beta == 0.0) ? alpha * v : alpha * v + beta * *cp;
+    }
   }
 }
 
-// C = A B with N <= 64 (no transposes): one wavefront per output row, lane = column.
-template <class TB>
-__global__ __launch_bounds__(256) void rowgemm_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
-                                                      int lda, const TB* __restrict__ B, long long ldb, double beta,
-                                                      double* __restrict__ C, long long ldc) {
-  const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (m >= M || lane >= N) return;
-  const double* a = A + (long long)m * lda;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int k = 0;
-  for (; k + 3 < K; k += 4) {
-    a0 = fma(a[k], loadB(B + (long long)k * ldb + lane), a0);
-    a1 = fma(a[k + 1], loadB(B + (long long)(k + 1) * ldb + lane), a1);
-    a2 = fma(a[k + 2], loadB(B + (long long)(k + 2) * ldb + lane), a2);
-    a3 = fma(a[k + 3], loadB(B + (long long)(k + 3) * ldb + lane), a3);
+// C = alpha A^T B + beta C for A (K x M) and B (K x N), M, N <= 64 (Grams of subspace blocks) on
+// the FP64 matrix cores: workgroup (x, y) owns output tile (16 x, 16 y); its four waves take
+// interleaved 4-deep slices of the contraction (SK_U in flight) and add their tiles in LDS in a
+// fixed order.  Fragments: A^T[m r16][k kq] = A[k][m], B[k kq][n r16].
+__global__ __launch_bounds__(SK_NT) void atb_mfma_kernel(int M, int N, int K, double alpha,
+                                                         const double* __restrict__ A, int lda,
+                                                         const double* __restrict__ B, long long ldb, double beta,
+                                                         double* __restrict__ C, long long ldc) {
+  constexpr int NWV = SK_NT / 64;
+  __shared__ double part[NWV][16][17];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r16 = lane & 15, kq = lane >> 4;
+  const int m = blockIdx.x * 16 + r16, n = blockIdx.y * 16 + r16;
+  const bool mok = m < M, nok = n < N;
+  const int mc = mok ? m : 0, nc = nok ? n : 0;
+  sdbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  const int nsl = (K + 3) >> 2;
+  for (int s0 = w; s0 < nsl; s0 += NWV * SK_U) {
+    double a[SK_U], b[SK_U];
+#pragma unroll
+    for (int u = 0; u < SK_U; ++u) {
+      const int k = (s0 + NWV * u) * 4 + kq;
+      const bool kok = k < K;
+      const long long kc = kok ? k : 0;
+      a[u] = keep_if(kok && mok, A[kc * lda + mc]);
+      b[u] = keep_if(kok && nok, B[kc * ldb + nc]);
+    }
+    __builtin_amdgcn_sched_barrier(0);   // every load of the batch is issued before its MFMAs
+#pragma unroll
+    for (int u = 0; u < SK_U; u += 2) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u + 1], b[u + 1], acc1, 0, 0, 0);
+    }
   }
-  for (; k < K; ++k) a0 = fma(a[k], loadB(B + (long long)k * ldb + lane), a0);
-  const double acc = (a0 + a1) + (a2 + a3);
-  double* c = C + (long long)m * ldc + lane;
-  *c = (beta == 0.0) ? alpha * acc : alpha * acc + beta * *c;
+  const sdbl4 acc = acc0 + acc1;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) part[w][4 * v + kq][r16] = acc[v];
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+    const int gm = blockIdx.x * 16 + r, gn = blockIdx.y * 16 + c;
+    if (gm < M && gn < N) {
+      double v = part[0][r][c];
+#pragma unroll
+      for (int q = 1; q < NWV; ++q) v += part[q][r][c];
+      double* cp = C + (long long)gm * ldc + gn;
+      *cp = (beta == 0.0) ? alpha * v : alpha * v + beta * *cp;
+    }
+  }
 }
 
 // One thread per output element, for small products where 64x64 tiles would leave the chip idle.
@@ -252,14 +323,14 @@ cpd_status gemm_f64(int M, int N, int K, double alpha, const double* A, int lda,
   const long long mn = (long long)M * N;
   if (bdtype == CPD_F64 && batch == 1 && !tc && !tb && N <= 64) {
     if (ta && M <= 64 && K >= 128) {
-      hipLaunchKernelGGL(atb_kernel<double>, dim3(M), dim3(256), 0, s, M, N, K, alpha, A, lda, (const double*)B,
-                         ldb, beta, C, ldc);
+      hipLaunchKernelGGL(atb_mfma_kernel, dim3((M + 15) / 16, (N + 15) / 16), dim3(SK_NT), 0, s, M, N, K, alpha, A,
+                         lda, (const double*)B, ldb, beta, C, ldc);
       CPD_LAUNCH_CHECK();
       return CPD_OK;
     }
-    if (!ta && K <= 4096) {
-      hipLaunchKernelGGL(rowgemm_kernel<double>, dim3((M + 3) / 4), dim3(256), 0, s, M, N, K, alpha, A, lda,
-                         (const double*)B, ldb, beta, C, ldc);
+    if (!ta && M <= 0x7fffffff - 15) {
+      hipLaunchKernelGGL(skinny_mfma_kernel, dim3((unsigned)((M + 15) / 16)), dim3(SK_NT), 0, s, M, N, K, alpha, A,
+                         lda, (const double*)B, ldb, beta, C, ldc);
       CPD_LAUNCH_CHECK();
       return CPD_OK;
     }

@@ -482,6 +482,33 @@ def test_solve_edge_cases():
         lib.solve(Tg, 3, lib.params(init="given"), W0=bad)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+def test_tensor_norm_and_nonfinite_check_at_any_alignment(dtype):
+    """||T||^2 and the non-finite check read the tensor in 16-byte words after an unaligned head
+    and before a ragged tail: for views starting 0..7 entries into a buffer, the reported full error
+    equals ||T - T^||/||T|| computed on the host from the returned factors, and a NaN at the first,
+    a middle or the last entry is reported (status -4)."""
+    log("norm / non-finite check", dtype)
+    lib = cp()
+    dims, R = (7, 9, 11), 3
+    n = int(np.prod(dims))
+    T, _, _ = synth.planted(dims, R, seed=4, noise_rel=1e-2)
+    for off in range(8):
+        buf = torch.zeros(n + 8, dtype=dtype, device=DEV)
+        view = buf[off:off + n]
+        view.copy_(dev(T.reshape(-1), dtype))
+        Tv = view.view(dims)
+        res = lib.solve(Tv, R, lib.params(seed=1))
+        Th = host(Tv)
+        err = ml.frob(Th - reconstruct(res)) / ml.frob(Th)
+        assert abs(res["info"]["rel_err_full"] - err) <= 1e-10 * err, (off, res["info"]["rel_err_full"], err)
+        for pos in (0, n // 2, n - 1):
+            view.copy_(dev(T.reshape(-1), dtype))
+            view[pos] = float("nan")
+            with pytest.raises(lib.CpdError, match="status -4"):
+                lib.solve(Tv, R, lib.params(seed=1))
+
+
 def test_solve_is_deterministic():
     log("determinism")
     T, _, _ = synth.planted((40, 41, 42), 5, seed=8, noise_rel=1e-3)
