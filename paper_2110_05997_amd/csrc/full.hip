@@ -16,6 +16,10 @@ constexpr int RNT = 256;
 
 template <class T>
 __device__ __forceinline__ double ldv(const T* p, long long i) { return (double)p[i]; }
+template <class T>
+__device__ __forceinline__ double to_f64(T v) { return (double)v; }
+template <>
+__device__ __forceinline__ double to_f64<uint16_t>(uint16_t v) { return bf16_bits_to_f64(v); }
 template <>
 __device__ __forceinline__ double ldv<uint16_t>(const uint16_t* p, long long i) { return bf16_bits_to_f64(p[i]); }
 
@@ -70,12 +74,15 @@ __global__ __launch_bounds__(RNT) void residual_kernel(const T* __restrict__ X, 
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// The same sum on the FP64 matrix cores: the model is the product of A = [w^(1)_i * w^(2)_j] ((I1 I2)
-// x R, Khatri-Rao rows formed in the loads) and B = W^(3)T (R x I3).  A wave owns RM_KW columns k
-// (four 16-wide tiles whose B fragments stay in registers for all its rows) and walks 16-row blocks
-// of (i, j); the workgroups of one column range split the row blocks.
-// Every difference T - model is squared and summed in FP64; fixed grid, fixed order.
+// Residual on the FP64 matrix cores (R <= 64), work in tasks (row i of mode 1, RM_KW columns k of
+// mode 3): the task's B[r][kk] = W0[i][r] W2[k0 + kk][r] is staged in LDS once, and the model of
+// 16 rows (i, j0..j0+15) by RM_KW columns is the product of the W1 rows j (the A fragments, one
+// load each) with B, a 16 x 64 MFMA tile over the R <= 64 contraction.  Each wave takes every
+// fourth block of rows j and loads the next block's tensor values and W1 rows into a second register
+// set before the current block's products.  The grid is fixed (RB workgroups, tasks strided over
+// it) and every sum runs in a fixed order: bit-reproducible.
 constexpr int RM_KW = 64;
+typedef double rdbl4 __attribute__((ext_vector_type(4)));
 
 template <class T>
 __global__ __launch_bounds__(RNT) void residual_mfma_kernel(const T* __restrict__ X, int I1, int I2, int I3,
@@ -83,72 +90,83 @@ __global__ __launch_bounds__(RNT) void residual_mfma_kernel(const T* __restrict_
                                                             const double* __restrict__ W1,
                                                             const double* __restrict__ W2, int R,
                                                             double* __restrict__ part) {
-  typedef double dbl4 __attribute__((ext_vector_type(4)));
   __shared__ double slots[RNT / 64];
-  __shared__ double Bs[64][RM_KW + 1];   // B[r][k - k0] = W2[k][r] of this workgroup's columns
+  __shared__ double Bs[64][RM_KW + 1];
   const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4, w = threadIdx.x >> 6;
-  // XCD-aware order: workgroup L runs on XCD L mod 8; the consecutive workgroups of one XCD take
-  // every column range of the same row blocks, so each row of X is read by one XCD at about the
-  // same time (whole rows from DRAM, the overlaps from its L2)
+  constexpr int NWV = RNT / 64;
   const int nkr = (I3 + RM_KW - 1) / RM_KW;
-  const int G = (RB / 8 / nkr) * 8;
-  const int q = blockIdx.x >> 3, xcd = blockIdx.x & 7;
-  const int kr = q % nkr, gi = (q / nkr) * 8 + xcd;
+  const long long ntask = (long long)I1 * nkr;
+  const int njb = (I2 + 15) / 16;
+  const int nu = (R + 3) / 4;   // contraction steps of four (at most 16)
   double acc = 0.0;
-  if (G > 0 && gi < G) {
-    const int k0 = kr * RM_KW;
-    const int nu = (R + 3) / 4;   // contraction steps of four (R <= 64: at most 16)
+  // one block: tensor values tv[v][n] at row j0 + 4 v + kq, column k0 + 16 n + r16, and the A
+  // fragments av[u] = W1[j0 + r16][4 u + kq] (zero outside the matrices; addresses clamped)
+  auto load = [&](int i, int k0, int jb, T (&tv)[4][4], double (&av)[16]) {
+    const int j = jb * 16 + r16;
+    const bool jok = j < I2;
+    const double* w1 = W1 + (long long)(jok ? j : I2 - 1) * R;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int r = 4 * u + kq;
+      const double x = w1[r < R ? r : R - 1];
+      av[u] = (jok && r < R) ? x : 0.0;
+    }
+    // raw tensor values (converted at the products): in the input's own width, so the prefetched
+    // set costs half the registers for FP32 input
+    const T* xr = X + ((long long)i * I2 + (long long)jb * 16) * I3 + k0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        const int jr = jb * 16 + 4 * v + kq, k = k0 + 16 * n + r16;
+        const bool ok = jr < I2 && k < I3;
+        tv[v][n] = xr[ok ? (long long)(4 * v + kq) * I3 + 16 * n + r16 : 0ll];
+      }
+  };
+  auto compute = [&](int jb, int k0, const T (&tv)[4][4], const double (&av)[16]) {
+    // B is reread from LDS for every block (kept in registers it would leave room for one wave per
+    // SIMD only)
+    asm volatile("" ::: "memory");
+    rdbl4 am[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) am[n] = rdbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if (u < nu) {
+        double bf[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) bf[n] = Bs[4 * u + kq][16 * n + r16];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) am[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bf[n], am[n], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);   // one step's B fragments in registers at a time
+    }
+    // am[n][v] is the model at row 4 v + kq of the block, column 16 n + r16 (zero where tv is)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        const int jr = jb * 16 + 4 * v + kq, k = k0 + 16 * n + r16;
+        const double d = (jr < I2 && k < I3) ? to_f64(tv[v][n]) - am[n][v] : 0.0;
+        acc += d * d;
+      }
+  };
+  T tA[4][4], tB[4][4];
+  double aA[16], aB[16];
+  for (long long t = blockIdx.x; t < ntask; t += gridDim.x) {
+    const int i = (int)(t / nkr), kr = (int)(t - (long long)i * nkr), k0 = kr * RM_KW;
+    __syncthreads();   // the previous task's products no longer read Bs
+    const double* w0 = W0 + (long long)i * R;
     for (int e = threadIdx.x; e < 64 * RM_KW; e += RNT) {
       const int kk = e / 64, r = e - kk * 64, k = k0 + kk;
       const bool ok = r < R && k < I3;
-      Bs[r][kk] = ok ? W2[(long long)(ok ? k : 0) * R + (ok ? r : 0)] : 0.0;
+      const double x = W2[(long long)(ok ? k : 0) * R + (ok ? r : 0)] * w0[ok ? r : 0];
+      Bs[r][kk] = ok ? x : 0.0;
     }
     __syncthreads();
-    const int nij = I1 * I2;
-    const int nblk = (nij + 15) / 16;
-    for (int b = gi * (RNT / 64) + w; b < nblk; b += G * (RNT / 64)) {
-      const int ij = b * 16 + r16;
-      const bool rok = ij < nij;
-      const int ijc = rok ? ij : nij - 1;
-      const int i = ijc / I2, j = ijc - i * I2;
-      double tv[4][4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          const int row = b * 16 + 4 * v + kq, k = k0 + 16 * n + r16;
-          const bool ok = row < nij && k < I3;
-          const double xv = ldv(X, ok ? (long long)row * I3 + k : 0ll);   // address clamped in range
-          tv[v][n] = ok ? xv : 0.0;
-        }
-      // the A fragments (Khatri-Rao rows) loaded together, before the products
-      double av[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int r = 4 * u + kq, rc = r < R ? r : R - 1;
-        const double wa = W0[(long long)i * R + rc] * W1[(long long)j * R + rc];
-        av[u] = (rok && r < R) ? wa : 0.0;
-      }
-      dbl4 am[4];
-#pragma unroll
-      for (int n = 0; n < 4; ++n) am[n] = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        if (u < nu) {
-#pragma unroll
-          for (int n = 0; n < 4; ++n)
-            am[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], Bs[4 * u + kq][16 * n + r16], am[n], 0, 0, 0);
-        }
-      }
-      // am[n][v] is the model at row b 16 + 4 v + kq, column k0 + 16 n + r16
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          const int row = b * 16 + 4 * v + kq, k = k0 + 16 * n + r16;
-          const double d = tv[v][n] - am[n][v];
-          acc += (row < nij && k < I3) ? d * d : 0.0;
-        }
+    for (int jb = w; jb < njb; jb += NWV) {
+      load(i, k0, jb, tA, aA);
+      compute(jb, k0, tA, aA);
     }
   }
   const double sres = block_sum(acc, slots);
@@ -158,7 +176,7 @@ __global__ __launch_bounds__(RNT) void residual_mfma_kernel(const T* __restrict_
 template <class T>
 void launch_residual(const T* X, int I1, int I2, int I3, const double* const W[3], int R, double* part,
                      hipStream_t s) {
-  if (R <= 64 && (I3 + RM_KW - 1) / RM_KW <= RB / 8 && (long long)I1 * I2 < (1ll << 31) - 16) {
+  if (R <= 64 && (long long)I1 * I2 < (1ll << 31) - 16) {
     hipLaunchKernelGGL(residual_mfma_kernel<T>, dim3(RB), dim3(RNT), 0, s, X, I1, I2, I3, W[0], W[1], W[2], R,
                        part);
     return;

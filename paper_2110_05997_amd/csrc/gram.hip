@@ -458,8 +458,10 @@ __global__ __launch_bounds__(GF_NT) void gram_f64_big_kernel(const T* __restrict
     }
     return (long long)kp * sk + m;
   };
-  vec_t rm[NV], rn[NV];
-  auto fetch = [&](int k0) {
+  // two register sets: the loads of stage s + 2 are issued while stage s is multiplied and stage
+  // s + 1 waits in the other set, so a load has two stages of MFMAs to land
+  vec_t rm0[NV], rn0[NV], rm1[NV], rn1[NV];
+  auto fetch = [&](vec_t* rm, vec_t* rn, int k0) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int r = vrow(v), kp = k0 + vk(v);
@@ -500,15 +502,20 @@ __global__ __launch_bounds__(GF_NT) void gram_f64_big_kernel(const T* __restrict
       on[i][j] = i < ilim && tm * GF_T + r0 < gM && tn * GF_T + c0 < gM && (!diag || r0 <= c0);
     }
   if (kbeg < kend) {
-    fetch(kbeg);
-    store(Xbuf(0, 0), rm, tm * GF_T, kbeg);
-    if (!diag) store(Xbuf(0, 1), rn, tn * GF_T, kbeg);
+    fetch(rm0, rn0, kbeg);
+    store(Xbuf(0, 0), rm0, tm * GF_T, kbeg);
+    if (!diag) store(Xbuf(0, 1), rn0, tn * GF_T, kbeg);
+    fetch(rm1, rn1, kbeg + GF_KC);
   }
   __syncthreads();
   int cur = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += GF_KC) {
+  // stage at k0 from LDS buffer cur; its successor's data waits in (nrm, nrn); the stage after that
+  // is fetched into (frm, frn)
+  auto stage = [&](int k0, vec_t* frm, vec_t* frn, const vec_t* nrm, const vec_t* nrn) {
     const bool more = k0 + GF_KC < kend;
-    if (more) fetch(k0 + GF_KC);
+    // unconditional (past the chunk the addresses are clamped and the values unused): a fixed
+    // number of loads per stage lets the wait before the store count only the older set
+    fetch(frm, frn, k0 + 2 * GF_KC);
     row_t* Am = Xbuf(cur, 0);
     row_t* Bn = diag ? Xbuf(cur, 0) : Xbuf(cur, 1);
 #pragma unroll
@@ -527,11 +534,15 @@ __global__ __launch_bounds__(GF_NT) void gram_f64_big_kernel(const T* __restrict
     }
     // the other buffer was last read before the previous barrier
     if (more) {
-      store(Xbuf(cur ^ 1, 0), rm, tm * GF_T, k0 + GF_KC);
-      if (!diag) store(Xbuf(cur ^ 1, 1), rn, tn * GF_T, k0 + GF_KC);
+      store(Xbuf(cur ^ 1, 0), nrm, tm * GF_T, k0 + GF_KC);
+      if (!diag) store(Xbuf(cur ^ 1, 1), nrn, tn * GF_T, k0 + GF_KC);
     }
     __syncthreads();
     cur ^= 1;
+  };
+  for (int k0 = kbeg; k0 < kend; k0 += 2 * GF_KC) {
+    stage(k0, rm0, rn0, rm1, rn1);
+    if (k0 + GF_KC < kend) stage(k0 + GF_KC, rm1, rn1, rm0, rn0);
   }
   // every block of the upper triangle is written by exactly one wave (the reduction reads no other)
   double* out = part + ((long long)tile * g.nsplit + split) * (GF_T * GF_T);
