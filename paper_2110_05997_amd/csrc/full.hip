@@ -78,9 +78,8 @@ __global__ __launch_bounds__(RNT) void residual_kernel(const T* __restrict__ X, 
 // mode 3): the task's B[r][kk] = W0[i][r] W2[k0 + kk][r] is staged in LDS once, and the model of
 // 16 rows (i, j0..j0+15) by RM_KW columns is the product of the W1 rows j (the A fragments, one
 // load each) with B, a 16 x 64 MFMA tile over the R <= 64 contraction.  Each wave takes every
-// fourth block of rows j and loads the next block's tensor values and W1 rows into a second register
-// set before the current block's products.  The grid is fixed (RB workgroups, tasks strided over
-// it) and every sum runs in a fixed order: bit-reproducible.
+// fourth block of rows j.  The grid is fixed (RB workgroups, each a contiguous run of tasks) and
+// every sum runs in a fixed order: bit-reproducible.
 constexpr int RM_KW = 64;
 typedef double rdbl4 __attribute__((ext_vector_type(4)));
 
@@ -151,9 +150,13 @@ __global__ __launch_bounds__(RNT) void residual_mfma_kernel(const T* __restrict_
         acc += d * d;
       }
   };
-  T tA[4][4], tB[4][4];
-  double aA[16], aB[16];
-  for (long long t = blockIdx.x; t < ntask; t += gridDim.x) {
+  T tA[4][4];
+  double aA[16];
+  // a contiguous run of tasks per workgroup: neighbouring column ranges of one row i follow each
+  // other on the same compute unit, so the cache lines they share (rows are not line-aligned) are
+  // read from memory once
+  const long long tb = ntask * blockIdx.x / gridDim.x, te = ntask * (blockIdx.x + 1) / gridDim.x;
+  for (long long t = tb; t < te; ++t) {
     const int i = (int)(t / nkr), kr = (int)(t - (long long)i * nkr), k0 = kr * RM_KW;
     __syncthreads();   // the previous task's products no longer read Bs
     const double* w0 = W0 + (long long)i * R;
