@@ -563,6 +563,7 @@ struct SubspaceArgs {
   double *Q, *Y, *Z, *Qt, *B, *Vb, *theta, *Uw;
   uint64_t seed;
   double *U, *lam;
+  double *V, *lall;   // orders n <= 64: the full Jacobi's outputs, used when the iteration stalls
 };
 // Up to three problems per launch, one workgroup each (the modes of one tensor); descriptors in a
 // workspace array written by put_args_kernel.
@@ -589,18 +590,29 @@ __global__ __launch_bounds__(FNT) void subspace_kernel(const SubspaceArgs* __res
     __syncthreads();
     cholqr(S, b.Y, n, k, b.Q, b.Qt, it == 3, seed + 100 + it);
   }
+  // orders n <= 64 (few wanted pairs) give the iteration eight Rayleigh-Ritz steps, then fall back
+  // to the full Jacobi of G (a spectrum without a gap after the P-th eigenvalue converges slowly)
+  const int max_rr = (a.V != nullptr) ? 8 : 199;
   double ratio = rayleigh_ritz(S, G, n, P, k, b);
-  for (int it = 0; ratio > 1e-13 && it < 199; ++it) {
+  for (int it = 0; ratio > 1e-13 && it < max_rr; ++it) {
     cholqr(S, b.Y, n, k, b.Q, b.Qt, true, seed + 2 + it);
     ratio = rayleigh_ritz(S, G, n, P, k, b);
   }
+  const bool full = a.V != nullptr && ratio > 1e-13;
+  if (full) {
+    __syncthreads();
+    jacobi_block<FNT, true>(S.u.jac, G, n, n, a.lall, a.V);
+    __syncthreads();
+  }
+  const double* X = full ? a.V : b.Uw;
+  const int ldx = full ? n : P;
   // eigenvalues and signed eigenvectors (largest-|.| entry positive, ties: lowest index)
-  for (int j = tid; j < P; j += FNT) lam[j] = b.theta[j];
+  for (int j = tid; j < P; j += FNT) lam[j] = full ? a.lall[j] : b.theta[j];
   for (int j = w; j < P; j += FNW) {
     double best = -1.0;
     int bi = 0;
     for (int i = lane; i < n; i += 64) {
-      const double a = fabs(b.Uw[i * P + j]);
+      const double a = fabs(X[i * ldx + j]);
       if (a > best || (a == best && i < bi)) { best = a; bi = i; }
     }
     for (int off = 32; off >= 1; off >>= 1) {
@@ -608,8 +620,8 @@ __global__ __launch_bounds__(FNT) void subspace_kernel(const SubspaceArgs* __res
       const int oi = __shfl_xor(bi, off, 64);
       if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
     }
-    const double sgn = (b.Uw[bi * P + j] < 0.0) ? -1.0 : 1.0;
-    for (int i = lane; i < n; i += 64) U[i * P + j] = sgn * b.Uw[i * P + j];
+    const double sgn = (X[bi * ldx + j] < 0.0) ? -1.0 : 1.0;
+    for (int i = lane; i < n; i += 64) U[i * P + j] = sgn * X[i * ldx + j];
   }
 }
 
@@ -694,6 +706,8 @@ SubspaceArgs subspace_args(const SubProblem& q) {
   a.G = q.G; a.n = q.n; a.P = q.P; a.k = q.k;
   a.Q = q.Q; a.Y = q.Y; a.Z = q.Z; a.Qt = q.Qt; a.B = q.B; a.Vb = q.Vb; a.theta = q.theta; a.Uw = q.Uw;
   a.seed = q.seed; a.U = q.U; a.lam = q.lam;
+  a.V = q.n <= JMAX ? q.V : nullptr;
+  a.lall = q.n <= JMAX ? q.lall : nullptr;
   return a;
 }
 
@@ -703,6 +717,10 @@ void sp_carve(Carver& ar, SubProblem& q) {
     q.V = ar.template take<double>((size_t)q.n * q.n);
     q.lall = ar.template take<double>(q.n);
     return;
+  }
+  if (q.n <= JMAX) {   // the fused iteration's fallback
+    q.V = ar.template take<double>((size_t)q.n * q.n);
+    q.lall = ar.template take<double>(q.n);
   }
   const size_t nk = (size_t)q.n * q.k, kk = (size_t)q.k * q.k;
   q.Q = ar.template take<double>(nk);
@@ -722,7 +740,8 @@ void sp_carve(Carver& ar, SubProblem& q) {
 void sp_describe(SubProblem& q, const double* G, int n, int P, double* U, double* lam) {
   memset(&q, 0, sizeof(q));
   q.G = G; q.n = n; q.P = P; q.U = U; q.lam = lam;
-  q.direct = n <= JMAX;
+  // orders up to 64: the full Jacobi unless few pairs are wanted (subspace block at most n / 2)
+  q.direct = n <= JMAX && 2 * subspace_k(n, P) > n;
   q.k = q.direct ? n : subspace_k(n, P);
   q.seed = 0xC0FFEEull + (uint64_t)n * 131 + (uint64_t)P;
 }
