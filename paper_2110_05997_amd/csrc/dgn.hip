@@ -890,7 +890,8 @@ __global__ void dgn_tail_kernel(char* __restrict__ state) {
 // ---- cooperative CG for cores whose working set lives in global memory -------------------------
 // The CG of one dGN iteration (ch.4 Alg. "Conjugate gradient - dGN" on M^{-1/2}(J^T J + mu D)
 // M^{-1/2}, the products of Thm Hv) spread over CG_WG workgroups of one cooperative launch, then
-// x = M^{-1/2} x_hat and x^T J^T J x for the epilogue.  Per CG iteration j:
+// x = M^{-1/2} x_hat and x^T J^T J x (from the CG coefficients) for the epilogue.  Per CG
+// iteration j:
 //   A: the R x R tiles of Q_b = (M^{-1/2} p_j)_b^T W_b, one tile per wave;            grid barrier
 //   B: the tiles of z_j = M^{-1/2}(J^T J + mu D) M^{-1/2} p_j and their <p_j, z_j>, <r_j, z_j>
 //      and <z_j, z_j> partials (one set per workgroup);                               grid barrier
@@ -919,7 +920,7 @@ constexpr int SLOT_COL = 2 * CG_WG;                 // column-norm partials, CG_
 constexpr int SLOT_DP = SLOT_COL + CG_WG * 3 * 64;  // <p_j, z_j> by the parity of j (2 CG_WG)
 constexpr int SLOT_RZ = SLOT_DP + 2 * CG_WG;        // <r_j, z_j> (CG_WG)
 constexpr int SLOT_ZZ = SLOT_RZ + CG_WG;            // <z_j, z_j> (CG_WG)
-constexpr int SLOT_XJX = SLOT_ZZ + CG_WG;           // x^T J^T J x (CG_WG)
+constexpr int SLOT_XJX = SLOT_ZZ + CG_WG;           // x^T D x (CG_WG)
 constexpr int SLOT_GX = SLOT_XJX + CG_WG;           // grad.x and x.x (2 CG_WG)
 constexpr int SLOT_END = SLOT_GX + 2 * CG_WG;
 constexpr long long BAR_SPINS = 1ll << 22;
@@ -1090,11 +1091,12 @@ __device__ __forceinline__ double sum_parts(const double* part, int n) {
 // workgroups: everything but the core's residual and MTTKRPs (the full-tensor kernels compute them
 // next from the updated factors) and the scalar tail.  The factors are read and updated in the
 // state's W region; Pi, M^{-1/2} and D sit in each workgroup's LDS.
-//   1. pi^(l) = W^(l)T W^(l) tiles (one per wave);                                 barrier
+//   1. pi^(l) = W^(l)T W^(l) tiles (one per wave), unless the previous launch left them; barrier
 //   2. every workgroup: Pi^(l), the gammas and M^{-1/2}; gradient W Pi - MTTKRP on its own slice of
 //      the parameter vector, r_0 = p_0 = M^{-1/2}(-grad), x = 0; partials of ||r_0||^2, max|g|; barrier
-//   3. the CG described above, then x = M^{-1/2} x_hat and x^T J^T J x;
-//   4. own slice: grad.x, x.x partials, w <- w + x and that slice's part of every column norm; barrier
+//   3. the CG described above;
+//   4. own slice: x = M^{-1/2} x_hat, grad.x, x.x and x^T D x partials, w <- w + x and that
+//      slice's part of every column norm; barrier (x^T J^T J x then follows from the CG coefficients)
 //   5. every workgroup: the column norms (partials added in workgroup order), norm balancing of its
 //      slice; workgroup 0 writes the step's values to the header for the tail.
 // Dynamic LDS: 3 R^2 + 6 R doubles.
@@ -1190,6 +1192,7 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
   double* Rb[2] = {c.Rv, R1};
   int its = 0, par = 0;
   double alpha = 0.0, beta = 0.0;   // of the previous CG iteration (p_0 is stored)
+  double aff = 0.0;                 // sum over the CG iterations of alpha_j ||r_j||^2
   bool first = true;
   while (its < cap) {
     if (rr == 0.0) break;
@@ -1221,6 +1224,7 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
     const double pz = sum_parts(part + SLOT_DP, G);
     if (!(pz > 0.0)) break;
     alpha = rr / pz;
+    aff += alpha * rr;
     // C: ||r_j - alpha z_j||^2 from the partials (the same in every workgroup; rounding can only
     // make a vanishing value slightly negative, read as 0), own slice update
     const double rzs = sum_parts(part + SLOT_RZ, G), zzs = sum_parts(part + SLOT_ZZ, G);
@@ -1241,32 +1245,26 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
     first = false;
     if (eps < cg_tol) break;
   }
-  // x = M^{-1/2} x_hat on the own slice (no barrier before it: after the last barrier of the CG
-  // every workgroup reads and writes only its own slice of x, r, p and z)
+  // 4. own slice (no barrier before it: after the last barrier of the CG every workgroup reads and
+  // writes only its own slice): x = M^{-1/2} x_hat, grad.x, x.x, x^T D x, the update, and the
+  // slice's share of every column norm.  x^T J^T J x needs no product of its own: with A the CG
+  // operator, b = -M^{-1/2} grad its right-hand side and x_hat_0 = 0, the CG iterates satisfy
+  // x_hat^T A x_hat = 2 b^T x_hat - sum_j alpha_j ||r_j||^2 (a relation that persists in finite
+  // precision), b^T x_hat = -grad.x, and x_hat^T A x_hat = x^T (J^T J + mu D) x.
+  double gx = 0.0, xx = 0.0, xdx = 0.0;
   for (int e = e0 + tid; e < e1; e += NT) {
     int l, i, r;
     split_index(c, e, l, i, r);
-    c.X[e] *= c.msq[l * R + r];
-  }
-  sync_all();
-  // x^T J^T J x: the same two phases on x, unscaled
-  coop_phase_a(c, Cy, [&](int e) { return c.X[e]; }, false);
-  sync_all();
-  const double xp = block_sum(coop_phase_b(c, Cy, c.X, c.Z, 0.0, false), slots[0]);
-  if (tid == 0) part[SLOT_XJX + g] = xp;
-  sync_all();
-  const double xjx = sum_parts(part + SLOT_XJX, G);
-
-  // 4. own slice: grad.x, x.x, the update, and the slice's share of every column norm
-  double gx = 0.0, xx = 0.0;
-  for (int e = e0 + tid; e < e1; e += NT) {
-    const double xv = c.X[e];
+    const double xv = c.X[e] * c.msq[l * R + r];
+    c.X[e] = xv;
     gx += c.G[e] * xv;
     xx += xv * xv;
+    xdx += c.gam[l * R + r] * xv * xv;
     c.W[e] += xv;
   }
   gx = block_sum(gx, slots[0]);
   xx = block_sum(xx, slots[1]);
+  xdx = block_sum(xdx, slots[0]);
   double* colp = part + SLOT_COL;   // CG_WG rows of 3R column partials
   for (int q = tid; q < 3 * R; q += NT) {
     const int l = q / R, r = q - l * R;
@@ -1285,11 +1283,14 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
   if (tid == 0) {
     part[SLOT_GX + g] = gx;
     part[SLOT_GX + G + g] = xx;
+    part[SLOT_XJX + g] = xdx;
   }
   sync_all();
   // 5. column norms, balancing of the own slice, header
   gx = sum_parts(part + SLOT_GX, G);
   xx = sum_parts(part + SLOT_GX + G, G);
+  xdx = sum_parts(part + SLOT_XJX, G);
+  const double xjx = -2.0 * gx - aff - mu * xdx;
   double* cn = slots_cn(c);   // 3R doubles of LDS (reuses msq: no longer needed)
   for (int q = tid; q < 3 * R; q += NT) {
     double s2 = 0.0;
