@@ -604,11 +604,14 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
   const bool drawback = DRAW && !fix0;
   __syncthreads();
 
+  // sum over the CG iterations of alpha_j ||r_j||^2 (x^T J^T J x of the step follows from it)
+  double aff = 0.0;
   // Gradient and preconditioned CG step at the current W: Grams, D and the preconditioner first;
   // leaves the gradient in G and the step x in X.
   auto direction = [&](int cap, int& its, double& rr, double& grad_inf) __attribute__((always_inline)) {
     its = 0;
     rr = 0.0;
+    aff = 0.0;
     grams(c);
     precond(c, mu);
     if constexpr (BLK) {
@@ -666,6 +669,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
       }
       if (!(pz > 0.0)) break;
       const double alpha = rr / pz;
+      aff += alpha * rr;
       const double* Zv = (BLK && blk) ? c.U : c.Z;
       double eps = 0.0;
       const int zfree = fix0 ? c.off1 : 0;   // rows of J^T J v of a fixed factor are dropped
@@ -702,16 +706,28 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
 
   // Predicted ||f + J x||^2 from the residual f2_base at the start point, then w <- w + x (always
   // accepted) and norm balancing.
-  auto predict_update = [&](double f2_base, double& f2_pred, double& xx) __attribute__((always_inline)) {
-    const double xjx =
-        block_sum(GW ? hv_staged(c, c.X, c.Z, 0.0, false, stage) : hv(c, c.X, c.Z, 0.0, false), slotA);
-    double gx = 0.0, xs = 0.0;
+  // Predicted residual of the linearisation, the update and the balancing.  For the CG's own step
+  // (from_cg) x^T J^T J x comes from the CG coefficients: with A the preconditioned operator, b its
+  // right-hand side and x_hat_0 = 0, x_hat^T A x_hat = 2 b^T x_hat - sum_j alpha_j ||r_j||^2 (a
+  // relation that persists in finite precision), b^T x_hat = -grad.x and x_hat^T A x_hat =
+  // x^T (J^T J + mu D) x; a step changed after the CG (the dogleg) takes the product.
+  auto predict_update = [&](double f2_base, double& f2_pred, double& xx, bool from_cg) __attribute__((always_inline)) {
+    double xjx = 0.0;
+    if (!from_cg)
+      xjx = block_sum(GW ? hv_staged(c, c.X, c.Z, 0.0, false, stage) : hv(c, c.X, c.Z, 0.0, false), slotA);
+    double gx = 0.0, xs = 0.0, xd = 0.0;
     for (int e = tid; e < c.np; e += NT) {
       gx += c.G[e] * c.X[e];
       xs += c.X[e] * c.X[e];
+      if (from_cg) {
+        int l, i, r;
+        split_index(c, e, l, i, r);
+        xd += c.gam[l * R + r] * c.X[e] * c.X[e];
+      }
     }
     gx = block_sum(gx, slotB);
     xx = block_sum(xs, slotA);
+    if (from_cg) xjx = -2.0 * gx - aff - mu * block_sum(xd, slotB);
     f2_pred = f2_base + 2.0 * gx + xjx;
     for (int e = tid; e < c.np; e += NT) c.W[e] += c.X[e];
     __syncthreads();
@@ -761,7 +777,8 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
     double rr = 0.0, grad_inf = 0.0, f2_pred = 0.0, xx = 0.0;
     const int cap = caps[k - 1];
     direction(cap, its, rr, grad_inf);
-    predict_update(f2, f2_pred, xx);
+    // the batched kernel keeps the product (its registers are at the limit)
+    predict_update(f2, f2_pred, xx, SOLO);
     if (mode == 2) {
       if (tid == 0) {
         h->f2_pred = f2_pred; h->stepn = sqrt(xx); h->grad_inf = grad_inf; h->cg_resid = rr;
@@ -782,7 +799,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
       f2_base = residual_mttkrp(c, slotB);   // and the MTTKRP of the new gradient
       direction(cap, its, rr, grad_inf);
       dogleg(delta);
-      predict_update(f2_base, f2_pred, xx);
+      predict_update(f2_base, f2_pred, xx, false);
       f2_new = residual_mttkrp(c, slotB);
       err = sqrt(f2_new) / s_norm;
     }
