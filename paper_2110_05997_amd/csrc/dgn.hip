@@ -135,6 +135,80 @@ __device__ void precond(Ctx& c, double mu) {
   __syncthreads();
 }
 
+// The structured product of Thm Hv (same contract as hv below) on the vector units, for ranks whose
+// 16 x 16 matrix-core tiles would be mostly padding.  Phase 1: the thread of position (s, r) forms
+// Q_b[s][r] = v_b[:, s] . W_b[:, r] of all three modes and stores Y_0, Y_1, Y_2 in their place in Qb
+// (one barrier).  Phase 2: the thread of entry (a, i, r) forms
+// v_a[i, :] Pi^(a)[:, r] + W_a[i, :] Y_a[:, r].
+constexpr int HV_VALU_RMAX = 24;
+__device__ double hv_valu(Ctx& c, const double* V, double* out, double mu, bool scale) {
+  const int R = c.R, RR = R * R, tid = threadIdx.x;
+  const int d0 = c.d0, d1 = c.d1, d2 = c.d2;
+  const double* V0 = V;
+  const double* V1 = V + c.off1;
+  const double* V2 = V + c.off2;
+  const double* W0 = c.W;
+  const double* W1 = c.W + c.off1;
+  const double* W2 = c.W + c.off2;
+  // column dot products in four interleaved partial sums (their loads overlap)
+  auto coldot = [&](const double* Vb, const double* Wb, int db, int s, int r) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = 0;
+    for (; i + 3 < db; i += 4) {
+      a0 = fma(Vb[i * R + s], Wb[i * R + r], a0);
+      a1 = fma(Vb[(i + 1) * R + s], Wb[(i + 1) * R + r], a1);
+      a2 = fma(Vb[(i + 2) * R + s], Wb[(i + 2) * R + r], a2);
+      a3 = fma(Vb[(i + 3) * R + s], Wb[(i + 3) * R + r], a3);
+    }
+    for (; i < db; ++i) a0 = fma(Vb[i * R + s], Wb[i * R + r], a0);
+    return (a0 + a1) + (a2 + a3);
+  };
+  for (int sr = tid; sr < RR; sr += NT) {
+    const int s = sr / R, r = sr - s * R;
+    double q0 = coldot(V0, W0, d0, s, r);
+    double q1 = coldot(V1, W1, d1, s, r);
+    double q2 = coldot(V2, W2, d2, s, r);
+    if (scale) {
+      q0 *= c.msq[s];
+      q1 *= c.msq[R + s];
+      q2 *= c.msq[2 * R + s];
+    }
+    const double p0 = c.pi[sr], p1 = c.pi[RR + sr], p2 = c.pi[2 * RR + sr];
+    c.Qb[sr] = p2 * q1 + p1 * q2;
+    c.Qb[RR + sr] = p2 * q0 + p0 * q2;
+    c.Qb[2 * RR + sr] = p1 * q0 + p0 * q1;
+  }
+  __syncthreads();
+  double dotp = 0.0;
+  for (int e = tid; e < c.np; e += NT) {
+    int a, i, r;
+    split_index(c, e, a, i, r);
+    const double* Va = V + offof(c, a) + i * R;
+    const double* Wa = c.W + offof(c, a) + i * R;
+    const double* Pa = c.Pown + a * RR + r;
+    const double* Ya = c.Qb + a * RR + r;
+    const double* ma = c.msq + a * R;
+    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+    int s2 = 0;
+    for (; s2 + 1 < R; s2 += 2) {
+      a0 = fma(scale ? ma[s2] * Va[s2] : Va[s2], Pa[s2 * R], a0);
+      b0 = fma(Wa[s2], Ya[s2 * R], b0);
+      a1 = fma(scale ? ma[s2 + 1] * Va[s2 + 1] : Va[s2 + 1], Pa[(s2 + 1) * R], a1);
+      b1 = fma(Wa[s2 + 1], Ya[(s2 + 1) * R], b1);
+    }
+    if (s2 < R) {
+      a0 = fma(scale ? ma[s2] * Va[s2] : Va[s2], Pa[s2 * R], a0);
+      b0 = fma(Wa[s2], Ya[s2 * R], b0);
+    }
+    double tv = (a0 + a1) + (b0 + b1);
+    if (scale) tv = ma[r] * (tv + mu * c.gam[a * R + r] * (ma[r] * V[e]));
+    else if (mu != 0.0) tv += mu * c.gam[a * R + r] * V[e];
+    out[e] = tv;
+    dotp += V[e] * tv;
+  }
+  return dotp;
+}
+
 // Structured product of Thm Hv.  With scale = true the input is v = msq * V and the output is
 // msq * (J^T J v + mu D v) (the preconditioned CG operator); with scale = false it is
 // J^T J V + mu D V (mu = 0: the plain J^T J V, D not read).
@@ -143,7 +217,11 @@ __device__ void precond(Ctx& c, double mu) {
 // with Y formed inside the B-fragment loads (no barrier between the phases beyond the one that
 // publishes Q).  Returns this thread's partial of <V, out>; ends
 // without a barrier after phase 2.
+// HVM 0: the vector-unit product for R <= HV_VALU_RMAX, the matrix cores above; 1: the matrix
+// cores at any R (the batched kernel: carrying both paths spills its registers).
+template <int HVM = 0>
 __device__ double hv(Ctx& c, const double* V, double* out, double mu, bool scale) {
+  if (HVM == 0 && c.R <= HV_VALU_RMAX) return hv_valu(c, V, out, mu, scale);
   const int R = c.R, RR = R * R, tr = tiles16(R);
   const int lane = threadIdx.x & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
   for (int t = w; t < 3 * tr * tr; t += NW) {
@@ -510,6 +588,7 @@ __device__ int stop_test(const double* errs, int k, double step, double grad_inf
 template <bool SL, bool GW = false, int OPT = 0, bool SOLO = false>
 __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double* __restrict__ S, int mode, int max_steps,
                          double* lds, int& s_stop, double* stage = nullptr) {
+  constexpr int HVM = SOLO ? 0 : 1;   // structured-product path (see hv)
   Hdr* h = (Hdr*)state;
   const int R = h->R;
   int d[3] = {h->d[0], h->d[1], h->d[2]};
@@ -661,11 +740,11 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
         // z = L^{-1} (J^T J + mu D) L^{-T} p through u = L^{-T} p; <p, z> = <u, (J^T J + mu D) u>
         tri_apply(c, c.P, c.U, false, 1.0, nullptr);
         __syncthreads();
-        pz = block_sum(hv(c, c.U, c.Z, mu, false), slotA);
+        pz = block_sum(hv<HVM>(c, c.U, c.Z, mu, false), slotA);
         tri_apply(c, c.Z, c.U, true, 1.0, nullptr);
         __syncthreads();
       } else {
-        pz = block_sum(GW ? hv_staged(c, c.P, c.Z, mu, true, stage) : hv(c, c.P, c.Z, mu, true), slotA);
+        pz = block_sum(GW ? hv_staged(c, c.P, c.Z, mu, true, stage) : hv<HVM>(c, c.P, c.Z, mu, true), slotA);
       }
       if (!(pz > 0.0)) break;
       const double alpha = rr / pz;
@@ -714,7 +793,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
   auto predict_update = [&](double f2_base, double& f2_pred, double& xx, bool from_cg) __attribute__((always_inline)) {
     double xjx = 0.0;
     if (!from_cg)
-      xjx = block_sum(GW ? hv_staged(c, c.X, c.Z, 0.0, false, stage) : hv(c, c.X, c.Z, 0.0, false), slotA);
+      xjx = block_sum(GW ? hv_staged(c, c.X, c.Z, 0.0, false, stage) : hv<HVM>(c, c.X, c.Z, 0.0, false), slotA);
     double gx = 0.0, xs = 0.0, xd = 0.0;
     for (int e = tid; e < c.np; e += NT) {
       gx += c.G[e] * c.X[e];
@@ -739,7 +818,7 @@ __device__ __forceinline__ void dgn_body(char* __restrict__ state, const double*
   // the Cauchy point a = -(|g|^2 / |J g|^2) g lies outside; else a + beta (X - a) on the radius.
   auto dogleg = [&](double delta) __attribute__((always_inline)) {
     const double jg2 =
-        block_sum(GW ? hv_staged(c, c.G, c.Z, 0.0, false, stage) : hv(c, c.G, c.Z, 0.0, false), slotA);
+        block_sum(GW ? hv_staged(c, c.G, c.Z, 0.0, false, stage) : hv<HVM>(c, c.G, c.Z, 0.0, false), slotA);
     double hh = 0.0, gg = 0.0;
     for (int e = tid; e < c.np; e += NT) {
       hh += c.X[e] * c.X[e];
