@@ -1007,7 +1007,9 @@ __global__ void dgn_tail_kernel(char* __restrict__ state) {
 // workgroups goes through the state with agent-scope fences around each arrival.  The wait is
 // bounded: after BAR_SPINS polls a workgroup records HDR_BAR_TIMEOUT in the header and goes on, so
 // every wave reaches the end of the kernel, and the host reports an error.
-constexpr int CG_WG = 8;   // workgroups: a grid barrier costs ~2.2 us at 8 and ~6.4 us at 48
+// workgroups: a grid barrier costs ~2.2 us at 8 and ~6.4 us at 48; at R = 50 (48 tiles per phase,
+// one per wave at 6) the 600^3 solve's dGN takes 7.68 ms with 6, 7.79 ms with 8, 10.8 ms with 4
+constexpr int CG_WG = 6;
 // Partial-sum slots of the multi-workgroup iteration (doubles, after the second r, p and z
 // buffers): each group is written before a barrier and read after it, and no group is written
 // again until every workgroup has passed a later barrier.
