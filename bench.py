@@ -50,9 +50,10 @@ def parse():
 # for a plain copy of known size (`bench.py --copy-calibration`).  A figure is reported only while
 # the kernel's sources hash to the digest it was taken with.
 TRAFFIC = {
-    # gram_f64_big_kernel<float> on the 600^3 FP32 tensor, per mode: FETCH_SIZE 1186007 KiB x 2.0,
-    # WRITE_SIZE 239360 KiB x 1.0 (profiles/solve_600cube_fp64_r50.md)
-    "gram": {"bytes": 2428941952 + 245104640, "sources": ['gram.hip', 'common.h'], "digest": '61519f49bd8da0a0'},
+    # gram_f64_direct_kernel<float, *> on the 600^3 FP32 tensor, mean over the three modes: FETCH_SIZE
+    # 1793918 KiB x 2.0 (modes 1 and 2: 1769939, mode 3: 1841876), WRITE_SIZE 478720 KiB x 1.0
+    # (profiles/solve_600cube_fp64_r50.md)
+    "gram": {"bytes": 3673943680 + 490209280, "sources": ['gram.hip', 'common.h'], "digest": '09e325ce764c4ca8'},
 }
 
 

@@ -9,8 +9,8 @@
 //   mode 2: sum over i1 of the I2 x I3 slab T[i1] times its transpose (contraction contiguous)
 //   mode 3: columns of the (I1 I2) x I3 matrix                 (rows m contiguous)
 // FP32 input is promoted exactly to FP64 before the MFMA, so all three precisions accumulate in
-// FP64.  Work split: 64x64 tiles of the upper triangle of G times split-K chunks; each workgroup
-// writes a partial tile and a second kernel sums the partials in a fixed order (bit-reproducible).
+// FP64.  Work split: tiles of the upper triangle of G (64x64; 128x128 for large modes) times split-K
+// chunks; each workgroup writes a partial tile and a second kernel sums the partials in a fixed order (bit-reproducible).
 #include "common.h"
 
 namespace cpd {
@@ -396,31 +396,114 @@ __global__ __launch_bounds__(GB_NT) void gram_bf16_big_kernel(const uint16_t* __
         out[(wm + 16 * a + 4 * q + v) * GB_T + wn + 16 * b + i] = (double)acc[a][b][v];
 }
 
-// Unfolding view of mode `mode` (variant, sizes and strides; no tiling).
-// FP64 Gram for large modes from FP64 or FP32 input: 128x128 tiles of G (twice the 64x64 tile's
-// flops per staged element and per converted value), each of the four waves a 64x64 quarter
-// (sixteen 16x16 accumulators on v_mfma_f64_16x16x4f64), 16 contraction indices per stage.  Staging
-// moves 16-byte vectors: along the contraction index for modes 1 and 2, along the row index for
-// mode 3 (stored transposed); values are promoted to FP64 at the LDS store.  On diagonal tiles the
-// 16x16 blocks below the diagonal are skipped (the reduction reads the upper triangle only), and
-// blocks past the last row are skipped everywhere.
+// FP64 Gram for large modes from FP64 or FP32 input: 128x128 tiles of G, each of the four waves a
+// 64x64 quarter (sixteen 16x16 accumulators on v_mfma_f64_16x16x4f64); on diagonal tiles the 16x16
+// blocks below the diagonal are skipped (the reduction reads the upper triangle only) and the
+// quarter below the diagonal takes the lower half of the off-diagonal quarter's rows (10, 8, 8 and
+// 10 blocks instead of 10, 0, 16 and 10); blocks past the last row are skipped everywhere.
 constexpr int GF_T = 128;
 constexpr int GF_NT = 256;
-constexpr int GF_KC = 16;
-constexpr int GF_LD = GF_KC + 1;   // LDS row pitch in doubles
+constexpr int GF_KC = 16;   // contraction indices per stage
 
-constexpr size_t GF_LDS = (size_t)2 * 2 * GF_T * GF_LD * sizeof(double);   // two stages, two operands
+// The operands go straight from memory into registers: no LDS and no barrier.  The contraction is
+// a sum, so any order of its indices that both operands share gives the same products: within a
+// stage of 16 indices, lane (p, q) of a 16x4 fragment holds index k0 + 4q + e at MFMA step e for
+// modes 1 and 2 (one 16-byte load of four consecutive indices per row block), and index
+// k0 + 4e + q for mode 3, whose unfolding is contiguous along the row (one element per row block
+// and step).  Each wave loads its own rows (its partner wave's copy of the same rows comes from the
+// cache), keeps the next stage's loads in flight in a second register set while the current one
+// is multiplied, and promotes to FP64 just before the MFMAs.  Full stages run without masks; the
+// chunk's last partial stage zeroes the indices past its end.
+template <class T, bool FULL>
+__device__ __forceinline__ void gd_stage(dbl4 (&acc)[4][4], const T (&ra)[4][4], const T (&rb)[4][4],
+                                         const bool (&on)[4][4]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    double a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = (double)ra[i][e];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = (double)rb[j][e];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (FULL || on[i][j]) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+}
 
-template <class T>
-__global__ __launch_bounds__(GF_NT) void gram_f64_big_kernel(const T* __restrict__ src, GramGeom g,
-                                                             double* __restrict__ part) {
-  constexpr int VW = 16 / (int)sizeof(T);                 // elements per 16-byte vector
-  constexpr int NV = GF_T * GF_KC / VW / GF_NT;           // vectors per thread and operand
+template <class T, int VAR, bool FULL>
+__device__ __forceinline__ void gd_chunk(const T* __restrict__ src, const GramGeom& g, const int (&gra)[4],
+                                         const int (&grb)[4], int kbeg, int kend, dbl4 (&acc)[4][4],
+                                         const bool (&on)[4][4]) {
+  constexpr int VW = 16 / (int)sizeof(T);
   typedef T vec_t __attribute__((ext_vector_type(VW)));
-  // double-buffered stages: stage s + 1 is stored while stage s is multiplied, one barrier a stage
-  extern __shared__ double gf_lds[];
-  typedef double row_t[GF_LD];
-  auto Xbuf = [&](int b, int op) { return (row_t*)(gf_lds + (2 * b + op) * (GF_T * GF_LD)); };
+  const int lane = threadIdx.x & 63, q = lane >> 4;
+  constexpr bool v0 = VAR == 0;
+  const double invK = 1.0 / (double)(v0 ? g.K : 1);
+  const int kmaxv = g.Ktot - VW, kmax1 = g.Ktot - 1;
+  // one operand's stage at k0 into r; `mask` zeroes indices >= kend (the chunk's last stage only)
+  auto load = [&](T (&r)[4][4], const int (&gr)[4], int k0, bool mask) {
+    if constexpr (v0) {
+#pragma unroll
+      for (int u = 0; u < 4 / VW; ++u) {
+        const int kk = k0 + 4 * q + u * VW;
+        const int ks = min(kk, kmaxv);
+        const int b = (int)(((double)ks + 0.5) * invK);
+        const long long off = (long long)b * g.sb + (ks - b * g.K);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const vec_t v = *(const vec_t*)(src + off + (long long)gr[i] * g.sm);
+#pragma unroll
+          for (int t = 0; t < VW; ++t) r[i][u * VW + t] = (mask && kk + t >= kend) ? (T)0 : v[t];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int kk = k0 + 4 * e + q;
+        const long long off = (long long)min(kk, kmax1) * g.sk;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const T v = src[off + gr[i]];
+          r[i][e] = (mask && kk >= kend) ? (T)0 : v;
+        }
+      }
+    }
+  };
+  T ra0[4][4], rb0[4][4], ra1[4][4], rb1[4][4];
+  const int nst = (kend - kbeg) / GF_KC, kfull = kbeg + GF_KC * nst;
+  if (nst > 0) {
+    load(ra0, gra, kbeg, false);
+    load(rb0, grb, kbeg, false);
+  }
+  int s = 0;
+  for (; s + 2 <= nst; s += 2) {
+    const int k0 = kbeg + GF_KC * s;
+    load(ra1, gra, k0 + GF_KC, false);
+    load(rb1, grb, k0 + GF_KC, false);
+    __builtin_amdgcn_sched_barrier(0);
+    gd_stage<T, FULL>(acc, ra0, rb0, on);
+    __builtin_amdgcn_sched_barrier(0);
+    // stage s + 2 (clamped indices and unused when the chunk ends at s + 2)
+    load(ra0, gra, k0 + 2 * GF_KC, false);
+    load(rb0, grb, k0 + 2 * GF_KC, false);
+    __builtin_amdgcn_sched_barrier(0);
+    gd_stage<T, FULL>(acc, ra1, rb1, on);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (s < nst) gd_stage<T, FULL>(acc, ra0, rb0, on);
+  if (kfull < kend) {
+    load(ra1, gra, kfull, true);
+    load(rb1, grb, kfull, true);
+    gd_stage<T, FULL>(acc, ra1, rb1, on);
+  }
+}
+
+// FP32 input fits two waves per SIMD (240 registers); FP64 input's stages take one.
+template <class T, int VAR>
+__global__ __launch_bounds__(GF_NT, sizeof(T) == 4 ? 2 : 1) void gram_f64_direct_kernel(
+    const T* __restrict__ src, GramGeom g, double* __restrict__ part) {
   const int L = blockIdx.x;
   const int xcd = L & 7, idx = L >> 3;
   const int tile = idx % g.nupper;
@@ -430,121 +513,39 @@ __global__ __launch_bounds__(GF_NT) void gram_f64_big_kernel(const T* __restrict
   tile_of(tile, g.ntile, tm, tn);
   const bool diag = (tm == tn);
   const int kbeg = split * g.kchunk, kend = min(g.Ktot, kbeg + g.kchunk);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  // wave quarters; on a diagonal tile the quarter below the diagonal has nothing to do, so its wave
-  // takes the lower half of the off-diagonal quarter's rows (10, 8, 8 and 10 blocks instead of 10,
-  // 0, 16 and 10)
+  // the wave index as a wave-uniform value: the quarter's geometry stays in scalar registers
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // wave quarters (diagonal tiles: 10, 8, 8 and 10 blocks)
   int wm = (w & 1) * 64, wn = (w >> 1) * 64, ilim = 4;
   if (diag && w == 1) { wm = 32; wn = 64; ilim = 2; }
   if (diag && w == 2) ilim = 2;
-  const bool v0 = g.variant == 0;
-  const int gM = g.M, gK = g.K, sm = g.sm, sk = g.sk;
-  const long long sb = g.sb;
-  const double invK = 1.0 / (double)(v0 ? gK : 1);
-  // vector v of this thread: variant 0 -> (row, VW consecutive contraction indices); variant 1 ->
-  // (VW consecutive rows, one contraction index)
-  auto vrow = [=](int v) {
-    const int e = tid + v * GF_NT;
-    return v0 ? e / (GF_KC / VW) : (e % (GF_T / VW)) * VW;
-  };
-  auto vk = [=](int v) {
-    const int e = tid + v * GF_NT;
-    return v0 ? (e % (GF_KC / VW)) * VW : e / (GF_T / VW);
-  };
-  auto addr = [=](int m, int kp) -> long long {
-    if (v0) {
-      const int b = (int)(((double)kp + 0.5) * invK);
-      return (long long)b * sb + (long long)m * sm + (kp - b * gK);
-    }
-    return (long long)kp * sk + m;
-  };
-  // two register sets: the loads of stage s + 2 are issued while stage s is multiplied and stage
-  // s + 1 waits in the other set, so a load has two stages of MFMAs to land
-  vec_t rm0[NV], rn0[NV], rm1[NV], rn1[NV];
-  auto fetch = [&](vec_t* rm, vec_t* rn, int k0) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int r = vrow(v), kp = k0 + vk(v);
-      const bool okk = kp < kend;
-      const int gm = tm * GF_T + r, gn = tn * GF_T + r;
-      rm[v] = *(const vec_t*)(src + addr(gm < gM && okk ? gm : 0, okk ? kp : 0));
-      if (!diag) rn[v] = *(const vec_t*)(src + addr(gn < gM && okk ? gn : 0, okk ? kp : 0));
-    }
-  };
-  auto store = [&](row_t* X, const vec_t* rv, int row0, int k0) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int r = vrow(v), kq = vk(v);
-      const bool okk = k0 + kq < kend;
-#pragma unroll
-      for (int u = 0; u < VW; ++u) {
-        if (v0) {
-          X[r][kq + u] = (okk && row0 + r < gM) ? (double)rv[v][u] : 0.0;
-        } else {
-          X[r + u][kq] = (okk && row0 + r + u < gM) ? (double)rv[v][u] : 0.0;
-        }
-      }
-    }
-  };
-  dbl4 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  // 16x16 blocks this wave computes: inside the matrix, and on or above the diagonal of a diagonal
-  // tile (a whole quarter below it idles in the products)
   bool on[4][4];
+  bool full = true;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r0 = wm + 16 * i, c0 = wn + 16 * j;
-      on[i][j] = i < ilim && tm * GF_T + r0 < gM && tn * GF_T + c0 < gM && (!diag || r0 <= c0);
+      on[i][j] = i < ilim && tm * GF_T + r0 < g.M && tn * GF_T + c0 < g.M && (!diag || r0 <= c0);
+      full = full && on[i][j];
     }
-  if (kbeg < kend) {
-    fetch(rm0, rn0, kbeg);
-    store(Xbuf(0, 0), rm0, tm * GF_T, kbeg);
-    if (!diag) store(Xbuf(0, 1), rn0, tn * GF_T, kbeg);
-    fetch(rm1, rn1, kbeg + GF_KC);
+  // rows of this lane in each row block (clamped into the matrix: rows past the end only feed
+  // partial entries that the reduction never reads)
+  int gra[4], grb[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    gra[i] = min(tm * GF_T + wm + 16 * i + (lane & 15), g.M - 1);
+    grb[i] = min(tn * GF_T + wn + 16 * i + (lane & 15), g.M - 1);
   }
-  __syncthreads();
-  int cur = 0;
-  // stage at k0 from LDS buffer cur; its successor's data waits in (nrm, nrn); the stage after that
-  // is fetched into (frm, frn)
-  auto stage = [&](int k0, vec_t* frm, vec_t* frn, const vec_t* nrm, const vec_t* nrn) {
-    const bool more = k0 + GF_KC < kend;
-    // unconditional (past the chunk the addresses are clamped and the values unused): a fixed
-    // number of loads per stage lets the wait before the store count only the older set
-    fetch(frm, frn, k0 + 2 * GF_KC);
-    row_t* Am = Xbuf(cur, 0);
-    row_t* Bn = diag ? Xbuf(cur, 0) : Xbuf(cur, 1);
+  dbl4 acc[4][4];
 #pragma unroll
-    for (int kk = 0; kk < GF_KC; kk += 4) {
-      // A fragment: lane holds A[lane%16][lane/16] (16x4); B fragment: B[lane/16][lane%16] (4x16)
-      double a[4], b[4];
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = Am[wm + 16 * i + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bn[wn + 16 * j + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (on[i][j]) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    // the other buffer was last read before the previous barrier
-    if (more) {
-      store(Xbuf(cur ^ 1, 0), nrm, tm * GF_T, k0 + GF_KC);
-      if (!diag) store(Xbuf(cur ^ 1, 1), nrn, tn * GF_T, k0 + GF_KC);
-    }
-    __syncthreads();
-    cur ^= 1;
-  };
-  for (int k0 = kbeg; k0 < kend; k0 += 2 * GF_KC) {
-    stage(k0, rm0, rn0, rm1, rn1);
-    if (k0 + GF_KC < kend) stage(k0 + GF_KC, rm1, rn1, rm0, rn0);
-  }
-  // every block of the upper triangle is written by exactly one wave (the reduction reads no other)
+    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  if (full)
+    gd_chunk<T, VAR, true>(src, g, gra, grb, kbeg, kend, acc, on);
+  else
+    gd_chunk<T, VAR, false>(src, g, gra, grb, kbeg, kend, acc, on);
   double* out = part + ((long long)tile * g.nsplit + split) * (GF_T * GF_T);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -778,8 +779,9 @@ GramGeom make_big_geom(const int64_t dims[3], int mode) {
 
 // 128x128 FP64 tiles: the split count is a multiple of 8 (XCD order), chunks hold at least 32
 // stages, and the workgroup count fills GF_SLOTS resident workgroups (two per compute unit on the
-// 256 units) in whole rounds: the first count of at least four rounds within 2 % of full, else the
-// fullest one seen.
+// 256 units) in whole rounds: the first count of at least eight rounds within 2 % of full, else the
+// fullest one seen.  Diagonal tiles finish early and the last round is ragged, so more, shorter
+// rounds pay for the larger partials (600^3: 272 splits, 2.53 ms per mode against 2.61 ms with 136).
 constexpr int GF_SLOTS = 512;
 
 GramGeom make_f64_big_geom(const int64_t dims[3], int mode) {
@@ -803,7 +805,7 @@ GramGeom make_f64_big_geom(const int64_t dims[3], int mode) {
       best_ns = ns;
       best_chunk = chunk;
     }
-    if (rounds >= 4 && eff >= 0.98) {
+    if (rounds >= 8 && eff >= 0.98) {
       best_ns = ns;
       best_chunk = chunk;
       break;
@@ -905,15 +907,12 @@ cpd_status gram(const void* T, int dtype, const int64_t dims[3], int mode, int c
     const GramGeom gf = make_f64_big_geom(dims, mode);
     const int nb = gf.nupper * gf.nsplit;
     prof_begin(CPD_PK_GRAM, s);
-    if (dtype == CPD_F64) {
-      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)gram_f64_big_kernel<double>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)GF_LDS));
-      hipLaunchKernelGGL(gram_f64_big_kernel<double>, dim3(nb), dim3(GF_NT), GF_LDS, s, (const double*)T, gf, part);
-    } else {
-      CPD_HIP_CHECK(hipFuncSetAttribute((const void*)gram_f64_big_kernel<float>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)GF_LDS));
-      hipLaunchKernelGGL(gram_f64_big_kernel<float>, dim3(nb), dim3(GF_NT), GF_LDS, s, (const float*)T, gf, part);
-    }
+    auto k = dtype == CPD_F64 ? (gf.variant == 0 ? (const void*)gram_f64_direct_kernel<double, 0>
+                                                 : (const void*)gram_f64_direct_kernel<double, 1>)
+                              : (gf.variant == 0 ? (const void*)gram_f64_direct_kernel<float, 0>
+                                                 : (const void*)gram_f64_direct_kernel<float, 1>);
+    void* args[] = {(void*)&T, (void*)&gf, (void*)&part};
+    CPD_HIP_CHECK(hipLaunchKernel(k, dim3(nb), dim3(GF_NT), args, 0, s));
     CPD_LAUNCH_CHECK();
     const long long nelf = (long long)gf.nupper * GF_T * GF_T;
     hipLaunchKernelGGL(gram_reduce_kernel<GF_T>, dim3((unsigned)((nelf + 255) / 256)), dim3(256), 0, s, part, gf, G);
