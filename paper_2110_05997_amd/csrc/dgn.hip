@@ -999,16 +999,24 @@ __global__ void dgn_tail_kernel(char* __restrict__ state) {
 // no barrier is needed after C; B reads the stored p_{j+1}, which the barrier after A publishes.
 // Every exit test is taken on values that are identical in all workgroups.
 //
-// Launch and barrier: an ordinary launch of CG_WG workgroups, few enough to be resident together
-// (a cooperative launch measured ~23 us of extra latency and slowed the kernels after it).  The grid
-// barrier counts arrivals and flips a generation word in a slot of fine-grained device memory:
-// device-scope atomics on ordinary (coarse-grained) memory are performed in the L2 of the issuing
-// XCD, which the other XCDs do not see, so a counter there can miss arrivals.  Data between the
-// workgroups goes through the state with agent-scope fences around each arrival.  The wait is
-// bounded: after BAR_SPINS polls a workgroup records HDR_BAR_TIMEOUT in the header and goes on, so
-// every wave reaches the end of the kernel, and the host reports an error.
-// workgroups: a grid barrier costs ~2.2 us at 8 and ~6.4 us at 48; at R = 50 (48 tiles per phase,
-// one per wave at 6) the 600^3 solve's dGN takes 7.68 ms with 6, 7.79 ms with 8, 10.8 ms with 4
+// Launch and barrier: an ordinary launch of CG_WG x COOP_STRIDE workgroups, of which every
+// COOP_STRIDE-th one works (few enough to be resident together; a cooperative launch measured
+// ~23 us of extra latency and slowed the kernels after it).  The barriers up to the one after
+// step 2 count arrivals and flip a generation word in a slot of fine-grained device memory, with
+// agent-scope fences around each arrival (device-scope atomics on ordinary, coarse-grained memory
+// are performed in the L2 of the issuing XCD, which the other XCDs do not see).  Before the one
+// after step 2 each workgroup records its hardware XCD; when all share one (the dispatch hands
+// workgroups to the eight XCDs in turn), every later barrier is XCD-local: counter and generation
+// in ordinary memory with agent-scope atomics, which that XCD's L2 performs; each wave's stores
+// are acknowledged by the L2 before the arrival, and the device-scope invalidate after it drops
+// the L1 and the L2's clean lines but keeps the dirty lines the workgroups just wrote, with no L2
+// write-back (the agent-scope fence's write-back left every CG phase starting from memory).  The
+// workgroup-scope invalidate is not enough: the L1 keeps stale lines (wrong CG sums).  Every wait
+// is bounded: after BAR_SPINS polls a workgroup records HDR_BAR_TIMEOUT in the header and goes on,
+// so every wave reaches the end of the kernel, and the host reports an error.
+// workgroups: at R = 50 (48 tiles per phase, one per wave at 6) the 600^3 solve's dGN takes
+// 7.27 ms with 6 and 7.35 ms with 8 (memory-coherent barriers throughout: 7.68 ms with 6, 7.79 ms
+// with 8, 10.8 ms with 4)
 constexpr int CG_WG = 6;
 // Partial-sum slots of the multi-workgroup iteration (doubles, after the second r, p and z
 // buffers): each group is written before a barrier and read after it, and no group is written
@@ -1027,8 +1035,48 @@ struct BarSlot {
   unsigned count;
   unsigned pad0[31];   // count and generation in separate 128-byte lines
   unsigned gen;
-  unsigned pad1[31];
+  unsigned xcc[8];     // the hardware XCD of each workgroup of the current launch
+  unsigned pad1[23];
 };
+static_assert(CG_WG <= 8, "one XCD id slot per workgroup");
+
+// The iteration kernel runs on every COOP_STRIDE-th workgroup of its launch: workgroups go to the
+// eight XCDs in turn, so these normally share one XCD, whose L2 is then their common coherence
+// point.  The others leave at once.
+constexpr int COOP_STRIDE = 8;
+__device__ __forceinline__ int coop_g() { return blockIdx.x / COOP_STRIDE; }
+__device__ __forceinline__ int coop_G() { return gridDim.x / COOP_STRIDE; }
+
+// Grid barrier for workgroups on one XCD: counter and generation in ordinary device memory, whose
+// agent-scope atomics are performed in that XCD's L2.  Release: every wave waits until its stores
+// are acknowledged (the L1 writes through to the L2).  Acquire: a device-scope invalidate, which
+// drops the compute unit's L1 and the L2's clean lines and keeps its dirty ones, the data the
+// group exchanges; there is no L2 write-back.  Same bounded wait as grid_barrier.
+__device__ __forceinline__ void xcd_barrier(BarSlot* b, unsigned nblocks, int* flags) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned g = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // read before this arrival is counted
+    const unsigned arrived = __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the reset lands before the release
+      __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long long spins = 0;
+      while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > BAR_SPINS) {
+          atomicOr(flags, HDR_BAR_TIMEOUT);
+          break;
+        }
+      }
+    }
+    asm volatile("s_waitcnt vmcnt(0)\n\tbuffer_inv sc1" ::: "memory");
+  }
+  __syncthreads();
+}
 
 __device__ __forceinline__ void grid_barrier(BarSlot* b, unsigned nblocks, int* flags) {
   __syncthreads();
@@ -1069,7 +1117,7 @@ __device__ void coop_phase_a(Ctx& c, double* C, VF vf, bool scale) {
   const int R = c.R, RR = R * R, tr = tiles16(R);
   const int lane = threadIdx.x & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
   const int nA = 3 * tr * tr;
-  for (int t = blockIdx.x * NW + w; t < nA; t += gridDim.x * NW) {
+  for (int t = coop_g() * NW + w; t < nA; t += coop_G() * NW) {
     const int b = t / (tr * tr), tt = t - b * tr * tr, tm = tt / tr, tn = tt - tm * tr;
     const int ob = offof(c, b), db = dimof(c, b);
     const double* Wb = c.W + ob;
@@ -1116,7 +1164,7 @@ __device__ double coop_phase_b(Ctx& c, const double* C, const double* V, double*
   const int lane = threadIdx.x & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
   const int t0 = tiles16(c.d0) * tr, t1 = t0 + tiles16(c.d1) * tr, t2 = t1 + tiles16(c.d2) * tr;
   double dotp = 0.0;
-  for (int t = blockIdx.x * NW + w; t < t2; t += gridDim.x * NW) {
+  for (int t = coop_g() * NW + w; t < t2; t += coop_G() * NW) {
     const int a = (t >= t1) ? 2 : (t >= t0 ? 1 : 0);
     const int tt = t - (a == 0 ? 0 : (a == 1 ? t0 : t1));
     const int tm = tt / tr, tn = tt - tm * tr;
@@ -1200,14 +1248,26 @@ __device__ __forceinline__ double sum_parts(const double* part, int n) {
 // Dynamic LDS: 3 R^2 + 6 R doubles.
 __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ state, double* __restrict__ P1,
                                                            double* __restrict__ R1, double* __restrict__ part,
-                                                           BarSlot* __restrict__ bar, int grams_ready) {
+                                                           BarSlot* __restrict__ bar, BarSlot* __restrict__ xbar,
+                                                           int grams_ready) {
   extern __shared__ double lds_c[];
   __shared__ double slots[2][NW];
+  __shared__ int s_same_xcd;
+  if (blockIdx.x % COOP_STRIDE) return;
   Hdr* h = (Hdr*)state;
   if (h->stop != CPD_STOP_NONE) return;   // the header is the same for every workgroup
   int* hflags = &h->flags;
-  const unsigned nblk = gridDim.x;
-  auto sync_all = [&]() { grid_barrier(bar, nblk, hflags); };
+  const unsigned nblk = coop_G();
+  // the barriers up to the one after step 2 are the memory-coherent kind; each workgroup publishes
+  // its XCD before that one, and when all share one XCD the later barriers are XCD-local (the same
+  // decision in every workgroup)
+  bool same_xcd = false;
+  auto sync_all = [&]() {
+    if (same_xcd)
+      xcd_barrier(xbar, nblk, hflags);
+    else
+      grid_barrier(bar, nblk, hflags);
+  };
   const int R = h->R, RR = R * R;
   const int d[3] = {h->d[0], h->d[1], h->d[2]};
   const int np = (d[0] + d[1] + d[2]) * R;
@@ -1226,7 +1286,7 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
   const double mu = h->mu, cg_tol = h->cg_tol;
   const int k = h->k + 1;
   const int cap = caps[k - 1];
-  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const int G = coop_G(), g = coop_g(), tid = threadIdx.x;
   const int chunk = (np + G - 1) / G, e0 = g * chunk, e1 = min(np, e0 + chunk);
   const int tr = tiles16(R);
   const int lane = tid & 63, w = wave_id(), r16 = lane & 15, kq = lane >> 4;
@@ -1279,8 +1339,20 @@ __global__ __launch_bounds__(NT) void dgn_iter_coop_kernel(char* __restrict__ st
   if (tid == 0) {
     part[g] = rr;
     part[G + g] = gi;
+    unsigned x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+    __hip_atomic_store(&bar->xcc[g], x & 0xfu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
-  sync_all();
+  grid_barrier(bar, nblk, hflags);
+  if (tid == 0) {
+    const unsigned x0 = __hip_atomic_load(&bar->xcc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    int same = 1;
+    for (unsigned i = 1; i < nblk; ++i)
+      same &= __hip_atomic_load(&bar->xcc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == x0;
+    s_same_xcd = same;
+  }
+  __syncthreads();
+  same_xcd = __builtin_amdgcn_readfirstlane(s_same_xcd) != 0;
   rr = sum_parts(part, G);
   double grad_inf = 0.0;
   for (int q = 0; q < G; ++q) grad_inf = fmax(grad_inf, part[G + q]);
@@ -1798,17 +1870,19 @@ size_t full_kernels_aux_bytes(const int d[3], int R);
 size_t coop_cg_bytes(int np);
 
 namespace {
-// Barrier slots of the multi-workgroup CG: one pool of fine-grained device memory per device,
-// allocated and zeroed on first use and held until the process ends (the barrier leaves a slot's
-// count at zero, so it needs no reset between launches).  A host thread keeps its own slot: calls
-// on one thread are ordered (every solve synchronises), and different threads never share one.
+// Barrier slots of the multi-workgroup CG: per device one pool of fine-grained device memory (the
+// memory-coherent barrier) and one of ordinary device memory (the XCD-local one), allocated and
+// zeroed on first use and held until the process ends (both barriers leave a slot's count at zero,
+// so it needs no reset between launches).  A host thread keeps its own slot: calls on one thread
+// are ordered (every solve synchronises), and different threads never share one.
 constexpr int BAR_POOL = 256;
 constexpr int BAR_MAX_DEVICES = 64;
 BarSlot* g_bar_pool[BAR_MAX_DEVICES];
+BarSlot* g_xbar_pool[BAR_MAX_DEVICES];
 std::mutex g_bar_mu;
 std::atomic<int> g_bar_next{0};
 
-cpd_status barrier_slot(BarSlot** out) {
+cpd_status barrier_slot(BarSlot** out, BarSlot** xout) {
   int dev = 0;
   CPD_HIP_CHECK(hipGetDevice(&dev));
   if (dev < 0 || dev >= BAR_MAX_DEVICES) {
@@ -1828,7 +1902,18 @@ cpd_status barrier_slot(BarSlot** out) {
     }
     g_bar_pool[dev] = (BarSlot*)p;
   }
+  if (g_xbar_pool[dev] == nullptr) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(BarSlot) * BAR_POOL);
+    if (e == hipSuccess) e = hipMemset(p, 0, sizeof(BarSlot) * BAR_POOL);
+    if (e != hipSuccess) {
+      set_error("dgn: barrier pool allocation failed: %s", hipGetErrorString(e));
+      return CPD_E_HIP;
+    }
+    g_xbar_pool[dev] = (BarSlot*)p;
+  }
   *out = g_bar_pool[dev] + slot;
+  *xout = g_xbar_pool[dev] + slot;
   return CPD_OK;
 }
 }  // namespace
@@ -1972,16 +2057,16 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
     double* cP1 = cbuf;
     double* cR1 = cbuf + np;
     double* cpart = cbuf + 2 * (size_t)np;
-    BarSlot* bar = nullptr;
-    cpd_status bst = barrier_slot(&bar);
+    BarSlot *bar = nullptr, *xbar = nullptr;
+    cpd_status bst = barrier_slot(&bar, &xbar);
     if (bst) return bst;
     constexpr int CHUNK = 4;
     for (int done = 0; done < max_steps; done += CHUNK) {
       const int n = (max_steps - done < CHUNK) ? max_steps - done : CHUNK;
       for (int j = 0; j < n; ++j) {
         // Grams, gradient, CG, x^T J^T J x and the balanced update on CG_WG workgroups
-        hipLaunchKernelGGL(dgn_iter_coop_kernel, dim3(CG_WG), dim3(NT), it_lds, s, state, cP1, cR1, cpart, bar,
-                           grams_ready);
+        hipLaunchKernelGGL(dgn_iter_coop_kernel, dim3(CG_WG * COOP_STRIDE), dim3(NT), it_lds, s, state, cP1, cR1,
+                           cpart, bar, xbar, grams_ready);
         CPD_LAUNCH_CHECK();
         grams_ready = fused ? 1 : 0;
         cpd_status st;

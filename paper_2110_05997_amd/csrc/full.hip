@@ -77,35 +77,43 @@ __global__ __launch_bounds__(RNT) void residual_kernel(const T* __restrict__ X, 
 // Residual on the FP64 matrix cores (R <= 64), work in tasks (row i of mode 1, RM_KW columns k of
 // mode 3): the task's B[r][kk] = W0[i][r] W2[k0 + kk][r] is staged in LDS once, and the model of
 // 16 rows (i, j0..j0+15) by RM_KW columns is the product of the W1 rows j (the A fragments, one
-// load each) with B, a 16 x 64 MFMA tile over the R <= 64 contraction.  Each wave takes every
-// fourth block of rows j.  The grid is fixed (RB workgroups, each a contiguous run of tasks) and
-// every sum runs in a fixed order: bit-reproducible.
+// load each) with B, a 16 x 64 MFMA tile over the R <= 4 NU contraction.  Each wave takes every
+// fourth block of rows j, and for up to 13 contraction steps (NU, fixed at compile time) loads the
+// tensor values and A fragments of its next block while it multiplies the current one.  The grid is fixed (RB workgroups, each a contiguous run
+// of tasks) and every sum runs in a fixed order: bit-reproducible.
 constexpr int RM_KW = 64;
 typedef double rdbl4 __attribute__((ext_vector_type(4)));
 
-template <class T>
-__global__ __launch_bounds__(RNT) void residual_mfma_kernel(const T* __restrict__ X, int I1, int I2, int I3,
+// two waves per SIMD where the register sets fit in 256 registers (FP32/BF16 input, or up to 8
+// contraction steps), else one
+template <class T, int NU>
+constexpr int res_waves() { return sizeof(T) <= 4 || NU <= 8 ? 2 : 1; }
+
+template <class T, int NU>
+__global__ __launch_bounds__(RNT, (res_waves<T, NU>())) void residual_mfma_kernel(const T* __restrict__ X, int I1, int I2, int I3,
                                                             const double* __restrict__ W0,
                                                             const double* __restrict__ W1,
                                                             const double* __restrict__ W2, int R,
                                                             double* __restrict__ part) {
   __shared__ double slots[RNT / 64];
-  __shared__ double Bs[64][RM_KW + 1];
+  // row pitch 80 doubles: the four rows kq of a fragment read fall 32 banks apart, so the 64 lanes'
+  // 8-byte reads are free of bank conflicts
+  __shared__ double Bs[64][RM_KW + 16];
   const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4, w = threadIdx.x >> 6;
   constexpr int NWV = RNT / 64;
   const int nkr = (I3 + RM_KW - 1) / RM_KW;
   const long long ntask = (long long)I1 * nkr;
   const int njb = (I2 + 15) / 16;
-  const int nu = (R + 3) / 4;   // contraction steps of four (at most 16)
+  const int nu = (R + 3) / 4;   // contraction steps of four (at most NU)
   double acc = 0.0;
   // one block: tensor values tv[v][n] at row j0 + 4 v + kq, column k0 + 16 n + r16, and the A
   // fragments av[u] = W1[j0 + r16][4 u + kq] (zero outside the matrices; addresses clamped)
-  auto load = [&](int i, int k0, int jb, T (&tv)[4][4], double (&av)[16]) {
+  auto load = [&](int i, int k0, int jb, T (&tv)[4][4], double (&av)[NU]) {
     const int j = jb * 16 + r16;
     const bool jok = j < I2;
     const double* w1 = W1 + (long long)(jok ? j : I2 - 1) * R;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < NU; ++u) {
       const int r = 4 * u + kq;
       const double x = w1[r < R ? r : R - 1];
       av[u] = (jok && r < R) ? x : 0.0;
@@ -122,23 +130,28 @@ __global__ __launch_bounds__(RNT) void residual_mfma_kernel(const T* __restrict_
         tv[v][n] = xr[ok ? (long long)(4 * v + kq) * I3 + 16 * n + r16 : 0ll];
       }
   };
-  auto compute = [&](int jb, int k0, const T (&tv)[4][4], const double (&av)[16]) {
+  auto compute = [&](int jb, int k0, const T (&tv)[4][4], const double (&av)[NU]) {
     // B is reread from LDS for every block (kept in registers it would leave room for one wave per
-    // SIMD only)
+    // SIMD only); the next step's fragments are read while the current step's MFMAs run
     asm volatile("" ::: "memory");
     rdbl4 am[4];
 #pragma unroll
     for (int n = 0; n < 4; ++n) am[n] = rdbl4{0.0, 0.0, 0.0, 0.0};
+    double bf[4], bn[4];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int n = 0; n < 4; ++n) bf[n] = Bs[kq][16 * n + r16];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
       if (u < nu) {
-        double bf[4];
+        const int un = u + 1 < NU ? u + 1 : u;
 #pragma unroll
-        for (int n = 0; n < 4; ++n) bf[n] = Bs[4 * u + kq][16 * n + r16];
+        for (int n = 0; n < 4; ++n) bn[n] = Bs[4 * un + kq][16 * n + r16];
 #pragma unroll
         for (int n = 0; n < 4; ++n) am[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bf[n], am[n], 0, 0, 0);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) bf[n] = bn[n];
       }
-      __builtin_amdgcn_sched_barrier(0);   // one step's B fragments in registers at a time
+      __builtin_amdgcn_sched_barrier(0);   // two steps' B fragments in registers at a time
     }
     // am[n][v] is the model at row 4 v + kq of the block, column 16 n + r16 (zero where tv is)
 #pragma unroll
@@ -150,8 +163,8 @@ __global__ __launch_bounds__(RNT) void residual_mfma_kernel(const T* __restrict_
         acc += d * d;
       }
   };
-  T tA[4][4];
-  double aA[16];
+  T tA[4][4], tB[4][4];
+  double aA[NU], aB[NU];
   // a contiguous run of tasks per workgroup: neighbouring column ranges of one row i follow each
   // other on the same compute unit, so the cache lines they share (rows are not line-aligned) are
   // read from memory once
@@ -161,15 +174,32 @@ __global__ __launch_bounds__(RNT) void residual_mfma_kernel(const T* __restrict_
     __syncthreads();   // the previous task's products no longer read Bs
     const double* w0 = W0 + (long long)i * R;
     for (int e = threadIdx.x; e < 64 * RM_KW; e += RNT) {
-      const int kk = e / 64, r = e - kk * 64, k = k0 + kk;
+      const int r = e / RM_KW, kk = e - r * RM_KW, k = k0 + kk;   // lanes along a row of B
       const bool ok = r < R && k < I3;
       const double x = W2[(long long)(ok ? k : 0) * R + (ok ? r : 0)] * w0[ok ? r : 0];
       Bs[r][kk] = ok ? x : 0.0;
     }
     __syncthreads();
-    for (int jb = w; jb < njb; jb += NWV) {
-      load(i, k0, jb, tA, aA);
+    if constexpr (NU > 13) {
+      // one register set (two would not fit two waves per SIMD)
+      for (int jb = w; jb < njb; jb += NWV) {
+        load(i, k0, jb, tA, aA);
+        compute(jb, k0, tA, aA);
+      }
+      continue;
+    }
+    // two register sets in turn; the loads of a block past the last are clamped and unused
+    if (w < njb) load(i, k0, w, tA, aA);
+    for (int jb = w; jb < njb; jb += 2 * NWV) {
+      load(i, k0, min(jb + NWV, njb - 1), tB, aB);
+      __builtin_amdgcn_sched_barrier(0);
       compute(jb, k0, tA, aA);
+      __builtin_amdgcn_sched_barrier(0);
+      if (jb + NWV >= njb) break;
+      load(i, k0, min(jb + 2 * NWV, njb - 1), tA, aA);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(jb + NWV, k0, tB, aB);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   const double sres = block_sum(acc, slots);
@@ -180,8 +210,9 @@ template <class T>
 void launch_residual(const T* X, int I1, int I2, int I3, const double* const W[3], int R, double* part,
                      hipStream_t s) {
   if (R <= 64 && (long long)I1 * I2 < (1ll << 31) - 16) {
-    hipLaunchKernelGGL(residual_mfma_kernel<T>, dim3(RB), dim3(RNT), 0, s, X, I1, I2, I3, W[0], W[1], W[2], R,
-                       part);
+    auto k = R <= 16 ? residual_mfma_kernel<T, 4> : R <= 32 ? residual_mfma_kernel<T, 8>
+           : R <= 52 ? residual_mfma_kernel<T, 13> : residual_mfma_kernel<T, 16>;
+    hipLaunchKernelGGL(k, dim3(RB), dim3(RNT), 0, s, X, I1, I2, I3, W[0], W[1], W[2], R, part);
     return;
   }
   switch ((R + 7) / 8) {
