@@ -539,6 +539,114 @@ __global__ __launch_bounds__(256) void proj_big_kernel(const TB* __restrict__ X,
         }
 }
 
+
+// The same product with the operands straight from memory into registers: no LDS and no barrier.
+// A workgroup owns all r <= 64 rows of Y and 256 columns, a wave 64 of them.  Lane (p, q) loads
+// four consecutive columns 4p .. 4p + 3 of row k of X in one vector load; element b of the four
+// feeds the MFMA of column block b, which therefore holds the columns 4p + b (p = 0..15) of the
+// wave's 64, and the lane ends up with four consecutive columns of Y per accumulator row, written
+// as one 32-byte store.  Within a stage of 16 contraction indices, lane group q holds index
+// k0 + 4t + q at MFMA step t in both operands; U^T's fragments are loaded per step (U is small and
+// stays in the caches).  The next stage's loads are in flight in a second register set while the
+// current one is multiplied; full stages carry no masks.
+template <class TB>
+__device__ __forceinline__ void load4(const TB* p, TB (&v)[4]) {
+  typedef TB v4 __attribute__((ext_vector_type(4)));
+  const v4 x = *(const v4*)p;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = x[u];
+}
+
+template <class TB>
+constexpr int pd_waves() { return sizeof(TB) <= 4 ? 2 : 1; }
+
+template <class TB>
+__global__ __launch_bounds__(256, (pd_waves<TB>())) void proj_direct_kernel(const TB* __restrict__ X, int K, long long N,
+                                                                            long long sX, const double* __restrict__ U,
+                                                                            int r, double* __restrict__ Y, long long sY) {
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int p16 = lane & 15, q = lane >> 4;
+  X += (long long)blockIdx.y * sX;
+  Y += (long long)blockIdx.y * sY;
+  const long long nc = (long long)blockIdx.x * PB_N + w * 64 + 4 * p16;   // this lane's first column
+  const long long ncl = nc < N ? nc : N - 4;                             // clamped for the loads
+  const int mt = (r + 15) / 16;
+  pdbl4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[i][b] = pdbl4{0.0, 0.0, 0.0, 0.0};
+  // one stage at k0: xb[t][b] = X[k0 + 4t + q][nc + b], ua[t][i] = U[k0 + 4t + q][16 i + p16]
+  // (indices clamped into the matrices; with `mask`, values past K or r are zero)
+  auto load = [&](TB (&xb)[4][4], double (&ua)[4][4], int k0, bool mask) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = k0 + 4 * t + q, kc = k < K ? k : K - 1;
+      load4<TB>(X + (long long)kc * N + ncl, xb[t]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = 16 * i + p16;
+        const double u = U[(long long)kc * r + (m < r ? m : r - 1)];
+        ua[t][i] = (mask && (k >= K || m >= r)) ? 0.0 : u;
+      }
+      if (mask && k >= K) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) xb[t][b] = (TB)0;
+      }
+    }
+  };
+  auto stage = [&](const TB (&xb)[4][4], const double (&ua)[4][4]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      double bv[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = tod<TB>(xb[t][b]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i < mt)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[i][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[t][i], bv[b], acc[i][b], 0, 0, 0);
+    }
+  };
+  // rows m >= r of U only feed rows of Y that are not written, so full stages need no masks
+  TB x0[4][4], x1[4][4];
+  double u0[4][4], u1[4][4];
+  const int nst = K / PB_KC, kfull = nst * PB_KC;
+  if (nst > 0) load(x0, u0, 0, false);
+  int st = 0;
+  for (; st + 2 <= nst; st += 2) {
+    const int k0 = st * PB_KC;
+    load(x1, u1, k0 + PB_KC, false);
+    __builtin_amdgcn_sched_barrier(0);
+    stage(x0, u0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(x0, u0, k0 + 2 * PB_KC, false);   // clamped and unused when the last full stage was st + 1
+    __builtin_amdgcn_sched_barrier(0);
+    stage(x1, u1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (st < nst) stage(x0, u0);
+  if (kfull < K) {
+    load(x1, u1, kfull, true);
+    stage(x1, u1);
+  }
+  // acc[i][b][v] = Y[16 i + 4 v + q][nc + b]
+  if (nc < N) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i < mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * i + 4 * v + q;
+          if (m < r) {
+            pdbl4 o;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) o[b] = acc[i][b][v];
+            *(pdbl4*)(Y + (long long)m * N + nc) = o;
+          }
+        }
+  }
+}
 }  // namespace cpd
 
 namespace cpd {
@@ -579,6 +687,18 @@ cpd_status project_mfma(const void* X, int xdtype, int K, long long N, int batch
     return CPD_E_INVALID;
   }
   const int vw = xdtype == CPD_F64 ? 2 : (xdtype == CPD_F32 ? 4 : 8);
+  const size_t esz = xdtype == CPD_F64 ? 8 : (xdtype == CPD_F32 ? 4 : 2);
+  if (xdtype != CPD_BF16 && N % 4 == 0 && sX % 4 == 0 && sY % 4 == 0 && ((uintptr_t)X & (4 * esz - 1)) == 0 &&
+      ((uintptr_t)Y & 31) == 0 && (N + PB_N - 1) / PB_N <= 0x7fffffffLL) {
+    // four consecutive columns per lane: rows of X and Y aligned to four elements
+    const dim3 gb((unsigned)((N + PB_N - 1) / PB_N), (unsigned)batch);
+    if (xdtype == CPD_F64)
+      hipLaunchKernelGGL(proj_direct_kernel<double>, gb, dim3(256), 0, s, (const double*)X, K, N, sX, U, r, Y, sY);
+    else
+      hipLaunchKernelGGL(proj_direct_kernel<float>, gb, dim3(256), 0, s, (const float*)X, K, N, sX, U, r, Y, sY);
+    CPD_LAUNCH_CHECK();
+    return CPD_OK;
+  }
   if (N % vw == 0 && sX % vw == 0 && ((uintptr_t)X & 15) == 0 && (N + PB_N - 1) / PB_N <= 0x7fffffffLL) {
     const dim3 gb((unsigned)((N + PB_N - 1) / PB_N), (unsigned)batch);
     switch (xdtype) {

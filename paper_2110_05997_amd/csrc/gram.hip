@@ -506,11 +506,26 @@ __global__ __launch_bounds__(GF_NT, sizeof(T) == 4 ? 2 : 1) void gram_f64_direct
     const T* __restrict__ src, GramGeom g, double* __restrict__ part) {
   const int L = blockIdx.x;
   const int xcd = L & 7, idx = L >> 3;
-  const int tile = idx % g.nupper;
-  const int split = (idx / g.nupper) * 8 + xcd;
+  // launch order: every off-diagonal tile's workgroups first, then the diagonal tiles' (at most 10
+  // of 16 blocks per wave), so that the last round, which runs ragged, holds the shorter ones
+  // (600^3: 2.52 against 2.58 ms per mode); within each class consecutive workgroups of one XCD
+  // take the tiles of one split, whose rows they then share in that XCD's L2
+  const int nd = g.ntile, no = g.nupper - nd, per = g.nsplit / 8;
+  int tm, tn, split;
+  if (idx < no * per) {
+    const int to = idx % no;
+    split = (idx / no) * 8 + xcd;
+    int row = 0, start = 0;   // the to-th off-diagonal tile of the upper triangle, row by row
+    while (to >= start + (g.ntile - 1 - row)) { start += g.ntile - 1 - row; ++row; }
+    tm = row;
+    tn = row + 1 + (to - start);
+  } else {
+    const int id = idx - no * per;
+    tm = tn = id % nd;
+    split = (id / nd) * 8 + xcd;
+  }
   if (split >= g.nsplit) return;
-  int tm, tn;
-  tile_of(tile, g.ntile, tm, tn);
+  const int tile = tm * g.ntile - tm * (tm - 1) / 2 + (tn - tm);
   const bool diag = (tm == tn);
   const int kbeg = split * g.kchunk, kend = min(g.Ktot, kbeg + g.kchunk);
   // the wave index as a wave-uniform value: the quarter's geometry stays in scalar registers
