@@ -53,7 +53,7 @@ TRAFFIC = {
     # gram_f64_direct_kernel<float, *> on the 600^3 FP32 tensor, mean over the three modes: FETCH_SIZE
     # 2483416 KiB x 2.0 (modes 1 and 2: 2434726, mode 3: 2580796), WRITE_SIZE 478720 KiB x 1.0
     # (profiles/solve_600cube_fp64_r50.md)
-    "gram": {"bytes": 5086036139 + 490209280, "sources": ['gram.hip', 'common.h'], "digest": '0ac09d76a25e8259'},
+    "gram": {"bytes": 5086036139 + 490209280, "sources": ['gram.hip', 'common.h'], "digest": 'afdf508370b78c43'},
 }
 
 

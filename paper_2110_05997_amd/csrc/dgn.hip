@@ -1548,7 +1548,9 @@ __host__ __device__ inline CoreGeom core_geom(const int d[3], int R) {
 
 __global__ __launch_bounds__(NT) void core_refresh_kernel(const double* __restrict__ S, const double* __restrict__ W,
                                                           CoreGeom g, double* __restrict__ mpart,
-                                                          double* __restrict__ rpart) {
+                                                          double* __restrict__ rpart, const Hdr* __restrict__ h) {
+  // a stopped solve's W is unchanged: nothing to recompute (iterations enqueued past the stop)
+  if (h->stop != CPD_STOP_NONE) return;
   const int item = blockIdx.x * NW + wave_id();
   if (item >= g.nm + g.nres) return;
   const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
@@ -1919,6 +1921,39 @@ cpd_status barrier_slot(BarSlot** out, BarSlot** xout) {
 }  // namespace
 
 namespace {
+// Two pinned header slots and two events per host thread for the pipelined stop test of the
+// multi-workgroup dGN, created on first use on the thread's current device and held until the
+// process ends; nullptr (the synchronous test) when they cannot be had or the thread has moved to
+// another device.  Calls on one thread are ordered, so one pair per thread suffices.
+struct HeaderSlots {
+  Hdr* h[2];
+  hipEvent_t ev[2];
+  int dev;
+};
+HeaderSlots* header_slots() {
+  static thread_local HeaderSlots hs = {};
+  static thread_local int state = 0;   // 0 untried, 1 ready, -1 unavailable
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  if (state == 0) {
+    state = -1;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, 2 * sizeof(Hdr), hipHostMallocPortable) == hipSuccess) {
+      hs.h[0] = (Hdr*)p;
+      hs.h[1] = hs.h[0] + 1;
+      if (hipEventCreateWithFlags(&hs.ev[0], hipEventDisableTiming) == hipSuccess &&
+          hipEventCreateWithFlags(&hs.ev[1], hipEventDisableTiming) == hipSuccess) {
+        hs.dev = dev;
+        state = 1;
+      }
+    }
+    if (state < 0) (void)hipGetLastError();
+  }
+  return state == 1 && hs.dev == dev ? &hs : nullptr;
+}
+}  // namespace
+
+namespace {
 // LDS of the staged large-core kernel: hv_staged's operands, or W and the three Pi^(l) for the
 // gradient, whichever is larger
 size_t hv_stage_doubles(const int d[3], int R) {
@@ -2009,7 +2044,7 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
     auto refresh = [&](int init) -> cpd_status {
       if (fused) {
         hipLaunchKernelGGL(core_refresh_kernel, dim3(cr_blocks), dim3(NT), 0, s, S, (const double*)(state + Lo.W),
-                           cg, mpart, rpart);
+                           cg, mpart, rpart, (const Hdr*)state);
         CPD_LAUNCH_CHECK();
         const int fin_blocks = 1 + (np + NT - 1) / NT + (3 * cg.tr * cg.tr + NW - 1) / NW;
         hipLaunchKernelGGL(core_finish_kernel, dim3(fin_blocks), dim3(NT), 0, s, state, cg, (const double*)mpart,
@@ -2060,8 +2095,13 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
     BarSlot *bar = nullptr, *xbar = nullptr;
     cpd_status bst = barrier_slot(&bar, &xbar);
     if (bst) return bst;
+    // Chunks of CHUNK iterations; the stop test reads the header after each chunk.  With the
+    // pinned slots the copy of chunk c's header is waited for only once chunk c + 1 is enqueued,
+    // so the device never idles on the host (a chunk enqueued past the stop returns at once).
     constexpr int CHUNK = 4;
-    for (int done = 0; done < max_steps; done += CHUNK) {
+    HeaderSlots* hs = header_slots();
+    int pending = -1;   // chunk whose header copy is in flight
+    for (int done = 0, c = 0; done < max_steps; done += CHUNK, ++c) {
       const int n = (max_steps - done < CHUNK) ? max_steps - done : CHUNK;
       for (int j = 0; j < n; ++j) {
         // Grams, gradient, CG, x^T J^T J x and the balanced update on CG_WG workgroups
@@ -2072,11 +2112,20 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
         cpd_status st;
         if ((st = refresh(0))) return st;
       }
-      if (done + n < max_steps) {
+      if (done + n >= max_steps) break;
+      if (hs == nullptr) {
         CPD_HIP_CHECK(hipMemcpyAsync(&hh, state, sizeof(Hdr), hipMemcpyDeviceToHost, s));
         CPD_HIP_CHECK(hipStreamSynchronize(s));
         if (hh.stop != CPD_STOP_NONE) break;
+        continue;
       }
+      CPD_HIP_CHECK(hipMemcpyAsync(hs->h[c & 1], state, sizeof(Hdr), hipMemcpyDeviceToHost, s));
+      CPD_HIP_CHECK(hipEventRecord(hs->ev[c & 1], s));
+      if (pending >= 0) {
+        CPD_HIP_CHECK(hipEventSynchronize(hs->ev[pending & 1]));
+        if (hs->h[pending & 1]->stop != CPD_STOP_NONE) break;
+      }
+      pending = c;
     }
     return CPD_OK;
   }

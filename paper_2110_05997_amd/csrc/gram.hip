@@ -256,6 +256,8 @@ __global__ void gram_reduce_kernel(const double* __restrict__ part, GramGeom g, 
   if (m >= g.M || n >= g.M) return;
   const double* p = part + (long long)tile * g.nsplit * (TE * TE) + rc;
   double s = 0.0;
+  // sixteen loads in flight per thread; the additions stay in split order
+#pragma unroll 16
   for (int k = 0; k < g.nsplit; ++k) s += p[(long long)k * TE * TE];
   G[(long long)m * g.M + n] = s;
   G[(long long)n * g.M + m] = s;
