@@ -98,6 +98,27 @@ char* readback_host(size_t bytes, std::vector<char>& spill) {
   return spill.data();
 }
 
+// An event per host thread for waiting on one read-back while later work stays enqueued, created
+// on first use on the thread's current device and held until the process ends; nullptr (wait for
+// the stream instead) when it cannot be had or the thread has moved to another device.
+hipEvent_t readback_event() {
+  static thread_local hipEvent_t ev = nullptr;
+  static thread_local int dev_of = -1;
+  static thread_local bool tried = false;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  if (!tried) {
+    tried = true;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+      dev_of = dev;
+    } else {
+      ev = nullptr;
+      (void)hipGetLastError();
+    }
+  }
+  return ev != nullptr && dev_of == dev ? ev : nullptr;
+}
+
 // The three mode products of the core projection S = T x1 U1^T x2 U2^T x3 U3^T.
 // Y1[a][i2 i3] = sum_i1 U1[i1][a] T[i1][i2 i3] (T in its own dtype)
 cpd_status project_mode1(const void* T, int dtype, int I1, int I2, int I3, const double* U1, int r1, double* Y1,
@@ -189,7 +210,22 @@ cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_d
   const int h0 = chk ? 0 : 2;   // host index of the first copied double
   CPD_HIP_CHECK(hipMemcpyAsync(hbuf + h0, chk ? chk : lam, sizeof(double) * (ptot + 2 - h0),
                                hipMemcpyDeviceToHost, s));
-  CPD_HIP_CHECK(hipStreamSynchronize(s));
+  // the core projection at the full ranks P goes in behind the copy, so that the device works
+  // while the host waits for the eigenvalues (only the copy is waited for); a truncation below P
+  // repeats it at the truncated ranks
+  const int I1 = (int)dims[0], I2 = (int)dims[1], I3 = (int)dims[2];
+  hipEvent_t ev = readback_event();
+  bool speculated = false;
+  if (ev != nullptr) {
+    CPD_HIP_CHECK(hipEventRecord(ev, s));
+    if ((st = project_mode1(T, dtype, I1, I2, I3, U_out[0], P[0], Y1, s))) return st;
+    if ((st = project_mode2(Y1, P[0], I2, I3, U_out[1], P[1], Y2, s))) return st;
+    if ((st = project_mode3(Y2, P[0] * P[1], I3, U_out[2], P[2], S_out, s))) return st;
+    speculated = true;
+    CPD_HIP_CHECK(hipEventSynchronize(ev));
+  } else {
+    CPD_HIP_CHECK(hipStreamSynchronize(s));
+  }
   const std::vector<double> hlv(hbuf + 2, hbuf + 2 + ptot);   // the buffer is reused at the end
   const double* hlam = hlv.data();
   if (chk) {
@@ -228,11 +264,12 @@ cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_d
                                    sizeof(double) * rk[l], dims[l], hipMemcpyDeviceToDevice, s));
     CPD_HIP_CHECK(hipMemcpyAsync(U_out[l], Uf[l], sizeof(double) * rk[l] * dims[l], hipMemcpyDeviceToDevice, s));
   }
-  // S = T x1 U1^T x2 U2^T x3 U3^T
-  const int I1 = (int)dims[0], I2 = (int)dims[1], I3 = (int)dims[2];
-  if ((st = project_mode1(T, dtype, I1, I2, I3, U_out[0], rk[0], Y1, s))) return st;
-  if ((st = project_mode2(Y1, rk[0], I2, I3, U_out[1], rk[1], Y2, s))) return st;
-  if ((st = project_mode3(Y2, rk[0] * rk[1], I3, U_out[2], rk[2], S_out, s))) return st;
+  // S = T x1 U1^T x2 U2^T x3 U3^T (already enqueued when no mode was truncated)
+  if (!(speculated && rk[0] == P[0] && rk[1] == P[1] && rk[2] == P[2])) {
+    if ((st = project_mode1(T, dtype, I1, I2, I3, U_out[0], rk[0], Y1, s))) return st;
+    if ((st = project_mode2(Y1, rk[0], I2, I3, U_out[1], rk[1], Y2, s))) return st;
+    if ((st = project_mode3(Y2, rk[0] * rk[1], I3, U_out[2], rk[2], S_out, s))) return st;
+  }
   for (int l = 0; l < 3; ++l) core_out[l] = rk[l];
   return CPD_OK;
 }

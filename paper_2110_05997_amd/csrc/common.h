@@ -192,7 +192,8 @@ constexpr int DGN_OPT_DRAWBACK = 2;   // draw-back with a dogleg step on a hundr
 inline int dgn_opts(const cpd_params* p) {
   return p ? ((p->precond == 1 ? DGN_OPT_BLOCK : 0) | (p->drawback ? DGN_OPT_DRAWBACK : 0)) : 0;
 }
-// dgn_iterate for a state whose sizes the caller knows (no header read-back).
+// dgn_iterate for a state just set up by state_init with maxiter = max_steps and no factors
+// replaced since: the caller knows its sizes, so there is no header read-back.
 cpd_status dgn_iterate_known(void* state, const double* S, const int32_t core[3], int R, int max_steps,
                              hipStream_t s, int opts = 0);
 size_t dgn_lds_bytes(int np, int R);

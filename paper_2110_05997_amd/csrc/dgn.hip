@@ -1978,8 +1978,10 @@ auto dgn_kernel_for(int opts) -> void (*)(char*, const double*, int) {
   }
 }
 
+// known_maxiter >= 0: the header was just written by state_init with that maxiter and no factors
+// replaced since, so the large-core path takes both from the caller instead of a blocking read.
 cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int np, int R, const int d[3],
-                      hipStream_t s, int sdtype = CPD_F64, int opts = 0) {
+                      hipStream_t s, int sdtype = CPD_F64, int opts = 0, int known_maxiter = -1) {
   const double* S = (const double*)Sv;
   const bool lds_ok = sdtype == CPD_F64;
   const int p2 = d[2] | 1, p1 = (d[1] * p2) | 1;
@@ -2023,9 +2025,13 @@ cpd_status launch_dgn(char* state, const void* Sv, int mode, int max_steps, int 
     // iteration: the multi-workgroup half (Grams, gradient, CG, update), then those; the host checks
     // the stop flag after every few iterations.
     const int64_t dims[3] = {d[0], d[1], d[2]};
-    Hdr hh;
-    CPD_HIP_CHECK(hipMemcpyAsync(&hh, state, sizeof(Hdr), hipMemcpyDeviceToHost, s));
-    CPD_HIP_CHECK(hipStreamSynchronize(s));
+    Hdr hh{};
+    if (known_maxiter >= 0) {
+      hh.maxiter = known_maxiter;   // flags: no HDR_DIRTY
+    } else {
+      CPD_HIP_CHECK(hipMemcpyAsync(&hh, state, sizeof(Hdr), hipMemcpyDeviceToHost, s));
+      CPD_HIP_CHECK(hipStreamSynchronize(s));
+    }
     const Layout Lo = layout_of(np, R, hh.maxiter);
     const double* Wp[3] = {(const double*)(state + Lo.W), (const double*)(state + Lo.W) + d[0] * R,
                            (const double*)(state + Lo.W) + (d[0] + d[1]) * R};
@@ -2247,7 +2253,7 @@ cpd_status state_init(void* state, const double* S, const int32_t core[3], int R
   }
   cpd_status lst;
   const int dc[3] = {core[0], core[1], core[2]};
-  if ((lst = launch_dgn(st, S, 0, 0, np, R, dc, s))) return lst;
+  if ((lst = launch_dgn(st, S, 0, 0, np, R, dc, s, CPD_F64, 0, p->maxiter))) return lst;
   if (!check_flags) return CPD_OK;
   int flags = 0;
   CPD_HIP_CHECK(hipMemcpyAsync(&flags, st + offsetof(Hdr, flags), sizeof(int), hipMemcpyDeviceToHost, s));
@@ -2371,7 +2377,7 @@ cpd_status dgn_iterate_known(void* state, const double* S, const int32_t core[3]
   const int np = (core[0] + core[1] + core[2]) * R;
   const int dc[3] = {core[0], core[1], core[2]};
   prof_begin(CPD_PK_DGN, s);
-  const cpd_status st = launch_dgn((char*)state, S, 1, max_steps, np, R, dc, s, CPD_F64, opts);
+  const cpd_status st = launch_dgn((char*)state, S, 1, max_steps, np, R, dc, s, CPD_F64, opts, max_steps);
   prof_end(CPD_PK_DGN, s);
   return st;
 }
