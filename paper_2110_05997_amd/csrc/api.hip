@@ -163,7 +163,7 @@ cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_d
                         const int64_t dims[3], int R, const cpd_params* p,
                         double* const U_out[3], double* const sigma_out[3], double* S_out,
                         int core_out[3], Arena& ar, hipStream_t s, double* chk = nullptr,
-                        double* h_tn2 = nullptr) {
+                        double* h_tn2 = nullptr, bool chk_from_gram = false) {
   int P[3];
   pdims(dims, R, p, P);
   size_t gram_b = 0;
@@ -197,8 +197,10 @@ cpd_status run_compress(const void* T, int dtype, const void* T_gram, int gram_d
   }
   double* laml[3] = {lam, lam + P[0], lam + P[0] + P[1]};
   cpd_status st;
-  for (int l = 0; l < 3; ++l)
+  for (int l = 0; l < 3; ++l) {
     if ((st = gram(T_gram, gram_dtype, dims, l, gram_compute, G[l], gws, gram_b, s))) return st;
+    if (l == 0 && chk && chk_from_gram && (st = gram_trace_check(G[0], n[0], chk, (int*)(chk + 1), s))) return st;
+  }
   // the three eigenproblems run side by side
   prof_begin(CPD_PK_EIG, s);
   st = eig_top3(G, n, P, U_out, laml, 3, ews, eig_b, s);
@@ -283,7 +285,7 @@ cpd_status run_compress_st(const void* T, int dtype, const void* T_gram, int gra
                            const int64_t dims[3], int R, const cpd_params* p,
                            double* const U_out[3], double* const sigma_out[3], double* S_out,
                            int core_out[3], Arena& ar, hipStream_t s, double* chk = nullptr,
-                           double* h_tn2 = nullptr) {
+                           double* h_tn2 = nullptr, bool chk_from_gram = false) {
   int P[3];
   pdims(dims, R, p, P);
   for (int l = 0; l < 3; ++l) {
@@ -331,6 +333,7 @@ cpd_status run_compress_st(const void* T, int dtype, const void* T_gram, int gra
     // the tensor this mode's Gram reads: T, then Y1 (rk[0] x I2 x I3), then Y2 (rk[0] x rk[1] x I3)
     if (l == 0) {
       if ((st = gram(T_gram, gram_dtype, dims, 0, gram_compute, G[0], gws, gram_b, s))) return st;
+      if (chk && chk_from_gram && (st = gram_trace_check(G[0], (int)dims[0], chk, (int*)(chk + 1), s))) return st;
     } else if (l == 1) {
       const int64_t dy[3] = {rk[0], dims[1], dims[2]};
       if ((st = gram(Y1, CPD_F64, dy, 1, CPD_F64, G[1], gws, gram_b, s))) return st;
@@ -605,14 +608,21 @@ cpd_status solve_impl(const void* T_gram, int32_t gram_dtype, int gram_compute, 
   const int64_t n = dims[0] * dims[1] * dims[2];
   // the solve's device entry stamp goes next to the final residual (read back with it)
   long long* t_entry = (long long*)(res + 1);
-  if ((st = sumsq_full(T, dtype, n, chk, (int*)(chk + 1), sws, sumsq_ws_bytes(), s, t_entry))) return st;
+  // ||T||^2 and the non-finite check: from the mode-1 Gram's trace when that Gram is the FP64 one
+  // of T itself, else a pass over T (which also takes the entry stamp)
+  const bool chk_from_gram = T_gram == T && gram_dtype == dtype && gram_compute != CPD_BF16;
+  if (chk_from_gram) {
+    if ((st = device_stamp(t_entry, s))) return st;
+  } else if ((st = sumsq_full(T, dtype, n, chk, (int*)(chk + 1), sws, sumsq_ws_bytes(), s, t_entry))) {
+    return st;
+  }
   // ||T||^2 and the non-finite flag come back with the eigenvalues (one host round trip)
   double h_tn2 = 0.0;
   int core[3];
   st = p->st_mlsvd ? run_compress_st(T, dtype, T_gram, gram_dtype, gram_compute, dims, R, p, U, nullptr, S, core, ar,
-                                     s, chk, &h_tn2)
+                                     s, chk, &h_tn2, chk_from_gram)
                    : run_compress(T, dtype, T_gram, gram_dtype, gram_compute, dims, R, p, U, nullptr, S, core, ar, s,
-                                  chk, &h_tn2);
+                                  chk, &h_tn2, chk_from_gram);
   if (st) return st;
   // the header and CG caps go to the device as kernel arguments: no host synchronisation here
   if ((st = state_init(state, S, core, R, W0, h_tn2, p, s, false))) return st;

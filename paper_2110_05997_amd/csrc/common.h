@@ -168,6 +168,10 @@ cpd_status residual_full_noalloc(const void* T, int dtype, const int64_t dims[3]
 // stamp (device, nullable): receives the device wall clock when the kernel starts.
 cpd_status sumsq_full(const void* T, int dtype, int64_t n, double* out, int* nonfinite, void* ws,
                       size_t ws_bytes, hipStream_t s, long long* stamp = nullptr);
+// ||T||^2 and the non-finite flag from the trace of an FP64 Gram of T's mode-1 unfolding.
+cpd_status gram_trace_check(const double* G, int n, double* out, int* nonfinite, hipStream_t s);
+// writes the device wall clock to t
+cpd_status device_stamp(long long* t, hipStream_t s);
 // Nanoseconds per tick of the device wall clock (wall_clock64) of the current device.
 double wall_ns_per_tick();
 

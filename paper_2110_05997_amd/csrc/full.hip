@@ -544,6 +544,42 @@ cpd_status sumsq_full(const void* T, int dtype, int64_t n, double* out, int* non
   return CPD_OK;
 }
 
+// ||T||^2 and the non-finite flag from the mode-1 Gram when it was formed from T in FP64: its
+// trace is the sum of the squared entries (each product exact, FP64 accumulation), and a NaN or
+// infinite entry leaves a non-finite diagonal entry.  Saves a pass over T; the sum runs in a
+// fixed order (bit-reproducible).
+__global__ void gram_trace_flag_kernel(const double* __restrict__ G, int n, double* __restrict__ out,
+                                       int* __restrict__ out_flag) {
+  __shared__ double slots[2][RNT / 64];
+  double acc = 0.0, nb = 0.0;
+  for (int i = threadIdx.x; i < n; i += RNT) {
+    const double d = G[(long long)i * n + i];
+    acc += d;
+    nb += isfinite(d) ? 0.0 : 1.0;
+  }
+  const double sum = block_sum(acc, slots[0]);
+  const double b = block_sum(nb, slots[1]);
+  if (threadIdx.x == 0) {
+    *out = sum;
+    *out_flag = (b > 0.0 || !isfinite(sum)) ? 1 : 0;
+  }
+}
+
+// The device wall clock at the start of a solve (its entry stamp).
+__global__ void stamp_kernel(long long* __restrict__ t) { *t = wall_clock64(); }
+
+cpd_status gram_trace_check(const double* G, int n, double* out, int* nonfinite, hipStream_t s) {
+  hipLaunchKernelGGL(gram_trace_flag_kernel, dim3(1), dim3(RNT), 0, s, G, n, out, nonfinite);
+  CPD_LAUNCH_CHECK();
+  return CPD_OK;
+}
+
+cpd_status device_stamp(long long* t, hipStream_t s) {
+  hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(1), 0, s, t);
+  CPD_LAUNCH_CHECK();
+  return CPD_OK;
+}
+
 size_t normalize_ws_bytes(int R) {
   (void)R;
   return align_up(3 * 64 * sizeof(double), 256) + align_up(64 * sizeof(int), 256);
