@@ -416,7 +416,8 @@ constexpr int GF_KC = 16;   // contraction indices per stage
 // cache), keeps the next stage's loads in flight in a second register set while the current one
 // is multiplied, and promotes to FP64 just before the MFMAs.  Full stages run without masks; the
 // chunk's last partial stage zeroes the indices past its end.
-template <class T, bool FULL>
+// PAT: the wave's 16x16 blocks (bit 4i + j) fixed at compile time, or 0 for the runtime mask `on`
+template <class T, unsigned PAT>
 __device__ __forceinline__ void gd_stage(dbl4 (&acc)[4][4], const T (&ra)[4][4], const T (&rb)[4][4],
                                          const bool (&on)[4][4]) {
 #pragma unroll
@@ -430,11 +431,12 @@ __device__ __forceinline__ void gd_stage(dbl4 (&acc)[4][4], const T (&ra)[4][4],
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (FULL || on[i][j]) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (PAT ? ((PAT >> (4 * i + j)) & 1u) != 0 : on[i][j])
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
   }
 }
 
-template <class T, int VAR, bool FULL>
+template <class T, int VAR, unsigned PAT>
 __device__ __forceinline__ void gd_chunk(const T* __restrict__ src, const GramGeom& g, const int (&gra)[4],
                                          const int (&grb)[4], int kbeg, int kend, dbl4 (&acc)[4][4],
                                          const bool (&on)[4][4]) {
@@ -485,20 +487,20 @@ __device__ __forceinline__ void gd_chunk(const T* __restrict__ src, const GramGe
     load(ra1, gra, k0 + GF_KC, false);
     load(rb1, grb, k0 + GF_KC, false);
     __builtin_amdgcn_sched_barrier(0);
-    gd_stage<T, FULL>(acc, ra0, rb0, on);
+    gd_stage<T, PAT>(acc, ra0, rb0, on);
     __builtin_amdgcn_sched_barrier(0);
     // stage s + 2 (clamped indices and unused when the chunk ends at s + 2)
     load(ra0, gra, k0 + 2 * GF_KC, false);
     load(rb0, grb, k0 + 2 * GF_KC, false);
     __builtin_amdgcn_sched_barrier(0);
-    gd_stage<T, FULL>(acc, ra1, rb1, on);
+    gd_stage<T, PAT>(acc, ra1, rb1, on);
     __builtin_amdgcn_sched_barrier(0);
   }
-  if (s < nst) gd_stage<T, FULL>(acc, ra0, rb0, on);
+  if (s < nst) gd_stage<T, PAT>(acc, ra0, rb0, on);
   if (kfull < kend) {
     load(ra1, gra, kfull, true);
     load(rb1, grb, kfull, true);
-    gd_stage<T, FULL>(acc, ra1, rb1, on);
+    gd_stage<T, PAT>(acc, ra1, rb1, on);
   }
 }
 
@@ -537,15 +539,17 @@ __global__ __launch_bounds__(GF_NT, sizeof(T) == 4 ? 2 : 1) void gram_f64_direct
   if (diag && w == 1) { wm = 32; wn = 64; ilim = 2; }
   if (diag && w == 2) ilim = 2;
   bool on[4][4];
-  bool full = true;
+  unsigned mask = 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int r0 = wm + 16 * i, c0 = wn + 16 * j;
       on[i][j] = i < ilim && tm * GF_T + r0 < g.M && tn * GF_T + c0 < g.M && (!diag || r0 <= c0);
-      full = full && on[i][j];
+      mask |= on[i][j] ? 1u << (4 * i + j) : 0u;
     }
+  // nothing inside the matrix: no loads, no partial entries the reduction reads
+  if (mask == 0) return;
   // rows of this lane in each row block (clamped into the matrix: rows past the end only feed
   // partial entries that the reduction never reads)
   int gra[4], grb[4];
@@ -559,10 +563,16 @@ __global__ __launch_bounds__(GF_NT, sizeof(T) == 4 ? 2 : 1) void gram_f64_direct
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-  if (full)
-    gd_chunk<T, VAR, true>(src, g, gra, grb, kbeg, kend, acc, on);
-  else
-    gd_chunk<T, VAR, false>(src, g, gra, grb, kbeg, kend, acc, on);
+  // the block patterns of whole quarters, upper triangles of diagonal quarters and the two-row
+  // and two-column quarters at the edges run without per-MFMA masks (and without the loads of
+  // operand blocks they do not use)
+  switch (mask) {
+    case 0xffffu: gd_chunk<T, VAR, 0xffffu>(src, g, gra, grb, kbeg, kend, acc, on); break;
+    case 0x8cefu: gd_chunk<T, VAR, 0x8cefu>(src, g, gra, grb, kbeg, kend, acc, on); break;
+    case 0x00ffu: gd_chunk<T, VAR, 0x00ffu>(src, g, gra, grb, kbeg, kend, acc, on); break;
+    case 0x3333u: gd_chunk<T, VAR, 0x3333u>(src, g, gra, grb, kbeg, kend, acc, on); break;
+    default: gd_chunk<T, VAR, 0u>(src, g, gra, grb, kbeg, kend, acc, on); break;
+  }
   double* out = part + ((long long)tile * g.nsplit + split) * (GF_T * GF_T);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
