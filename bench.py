@@ -51,9 +51,9 @@ def parse():
 # the kernel's sources hash to the digest it was taken with.
 TRAFFIC = {
     # gram_f64_direct_kernel<float, *> on the 600^3 FP32 tensor, mean over the three modes: FETCH_SIZE
-    # 2491789 KiB x 2.0 (modes 1 and 2: 2445927, mode 3: 2583514), WRITE_SIZE 478720 KiB x 1.0
+    # 2471040 KiB x 2.0 (modes 1 and 2: 2350948, mode 3: 2711224), WRITE_SIZE 478720 KiB x 1.0
     # (profiles/solve_600cube_fp64_r50.md)
-    "gram": {"bytes": 5103184384 + 490209280, "sources": ['gram.hip', 'common.h'], "digest": 'bf9f741f0baca12d'},
+    "gram": {"bytes": 5060690133 + 490209280, "sources": ['gram.hip', 'common.h'], "digest": '5357c74747e2494d'},
 }
 
 
