@@ -89,7 +89,8 @@ typedef double rdbl4 __attribute__((ext_vector_type(4)));
 template <class T, int NU>
 constexpr int res_waves() { return sizeof(T) <= 4 || NU <= 8 ? 2 : 1; }
 
-template <class T, int NU>
+// EXACT: the contraction takes all NU steps ((R + 3) / 4 == NU), so no step needs its test
+template <class T, int NU, bool EXACT>
 __global__ __launch_bounds__(RNT, (res_waves<T, NU>())) void residual_mfma_kernel(const T* __restrict__ X, int I1, int I2, int I3,
                                                             const double* __restrict__ W0,
                                                             const double* __restrict__ W1,
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(RNT, (res_waves<T, NU>())) void residual_mfma_kerne
     for (int n = 0; n < 4; ++n) bf[n] = Bs[kq][16 * n + r16];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-      if (u < nu) {
+      if (EXACT || u < nu) {
         const int un = u + 1 < NU ? u + 1 : u;
 #pragma unroll
         for (int n = 0; n < 4; ++n) bn[n] = Bs[4 * un + kq][16 * n + r16];
@@ -210,8 +211,10 @@ template <class T>
 void launch_residual(const T* X, int I1, int I2, int I3, const double* const W[3], int R, double* part,
                      hipStream_t s) {
   if (R <= 64 && (long long)I1 * I2 < (1ll << 31) - 16) {
-    auto k = R <= 16 ? residual_mfma_kernel<T, 4> : R <= 32 ? residual_mfma_kernel<T, 8>
-           : R <= 52 ? residual_mfma_kernel<T, 13> : residual_mfma_kernel<T, 16>;
+    const int nu = (R + 3) / 4;
+    auto k = nu == 13 ? residual_mfma_kernel<T, 13, true> : nu == 16 ? residual_mfma_kernel<T, 16, true>
+           : R <= 16 ? residual_mfma_kernel<T, 4, false> : R <= 32 ? residual_mfma_kernel<T, 8, false>
+           : R <= 52 ? residual_mfma_kernel<T, 13, false> : residual_mfma_kernel<T, 16, false>;
     hipLaunchKernelGGL(k, dim3(RB), dim3(RNT), 0, s, X, I1, I2, I3, W[0], W[1], W[2], R, part);
     return;
   }

@@ -560,7 +560,8 @@ __device__ __forceinline__ void load4(const TB* p, TB (&v)[4]) {
 template <class TB>
 constexpr int pd_waves() { return sizeof(TB) <= 4 ? 2 : 1; }
 
-template <class TB>
+// MT4: r > 48, all four row blocks of U^T in use (no per-block test)
+template <class TB, bool MT4>
 __global__ __launch_bounds__(256, (pd_waves<TB>())) void proj_direct_kernel(const TB* __restrict__ X, int K, long long N,
                                                                             long long sX, const double* __restrict__ U,
                                                                             int r, double* __restrict__ Y, long long sY) {
@@ -570,7 +571,7 @@ __global__ __launch_bounds__(256, (pd_waves<TB>())) void proj_direct_kernel(cons
   Y += (long long)blockIdx.y * sY;
   const long long nc = (long long)blockIdx.x * PB_N + w * 64 + 4 * p16;   // this lane's first column
   const long long ncl = nc < N ? nc : N - 4;                             // clamped for the loads
-  const int mt = (r + 15) / 16;
+  const int mt = MT4 ? 4 : (r + 15) / 16;
   pdbl4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -692,10 +693,13 @@ cpd_status project_mfma(const void* X, int xdtype, int K, long long N, int batch
       ((uintptr_t)Y & 31) == 0 && (N + PB_N - 1) / PB_N <= 0x7fffffffLL) {
     // four consecutive columns per lane: rows of X and Y aligned to four elements
     const dim3 gb((unsigned)((N + PB_N - 1) / PB_N), (unsigned)batch);
-    if (xdtype == CPD_F64)
-      hipLaunchKernelGGL(proj_direct_kernel<double>, gb, dim3(256), 0, s, (const double*)X, K, N, sX, U, r, Y, sY);
-    else
-      hipLaunchKernelGGL(proj_direct_kernel<float>, gb, dim3(256), 0, s, (const float*)X, K, N, sX, U, r, Y, sY);
+    if (xdtype == CPD_F64) {
+      auto kd = r > 48 ? proj_direct_kernel<double, true> : proj_direct_kernel<double, false>;
+      hipLaunchKernelGGL(kd, gb, dim3(256), 0, s, (const double*)X, K, N, sX, U, r, Y, sY);
+    } else {
+      auto kf = r > 48 ? proj_direct_kernel<float, true> : proj_direct_kernel<float, false>;
+      hipLaunchKernelGGL(kf, gb, dim3(256), 0, s, (const float*)X, K, N, sX, U, r, Y, sY);
+    }
     CPD_LAUNCH_CHECK();
     return CPD_OK;
   }
